@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of 1WQC pattern execution on one MI355X.
+
+Workload (the large plain configuration): a random circuit on 24 logical
+qubits of 2000 J(alpha) gates (alpha uniform in [0, 2pi)) and 300 CZ gates on
+random pairs, translated into a measurement pattern (J(alpha) = N w; E u w;
+M u^(-alpha); X w^(s_u), CZ = E) with live width 24 <-> 25 (2^25 complex64
+amplitudes, 256 MiB), seeded forced outcomes and a normalised complex Gaussian
+input state already resident in device memory.
+
+One step = one whole run of the pattern (every N, E, M, X command as HIP
+kernels, FP64 probability reductions) plus the read-out of the 2^24 output
+amplitudes into a device buffer.
+
+Printed: one JSON line with the metric (non-trivial pattern commands per
+second), the roofline of the dominant kernel (HIP events around every launch
+of one extra profiled step), the fused-window executor's figures, and the FP64
+oracle timed on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(n_logical=24, n_j=2000, n_cz=300)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("owqs_kernels.hip", "owqs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1604_05659_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_exec(owqs, torch, pat, inp, out, exec_, steps, warmup):
+    pat.set_exec(exec_)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        pat.run(inp)
+        pat.read_state(out, check=False)
+    pat.check()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        pat.run(inp)
+        pat.read_state(out, check=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pat.check()
+    ev_ms = ev0.elapsed_time(ev1)
+    prof = pat.run_profiled(inp)
+    return wall, ev_ms, prof
+
+
+def roofline_of(prof, kernel_names):
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    e = prof[dom]
+    avg_s = e["ms"] / e["launches"] / 1e3
+    per_launch = e["bytes"] / e["launches"]
+    achieved = per_launch / avg_s / 1e9
+    tr = measured_traffic(kernel_names.get(dom, dom))
+    return dom, {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": tr,
+        "kernel": dom,
+        "bytes_per_launch": per_launch,
+        "avg_launch_us": round(avg_s * 1e6, 2),
+        "launches_per_step": e["launches"],
+    }
+
+
+def cpu_baseline(wl_gates, psi_in, seconds_hint):
+    """Oracle (complex128, OpenMP over all host cores) on the first gates of
+    the same circuit at the same width; returns the JSON object."""
+    import owqs_workloads as W
+    from oracle import core as oc
+
+    threads = os.cpu_count() or 1
+    threads = oc.set_threads(threads)
+    n_gates = 12
+    gates = wl_gates[:n_gates]
+    pat = W.circuit_to_pattern(WORKLOAD["n_logical"], gates, prepare_zero=False)
+    outc = W.outcome_bits(pat.n_meas(), W.rng(2, W.P_OUTCOME, 0))
+    x = psi_in.astype(np.complex128)
+    t0 = time.perf_counter()
+    oc.run(pat, outc, x, oc.MODE_OWQS)
+    dt = time.perf_counter() - t0
+    nt = pat.nontrivial_count(outc)
+    return {
+        "value": round(nt / dt, 3),
+        "unit": "commands/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"first {n_gates} gates ({len(pat.cmds)} commands, {nt} non-trivial) of the same circuit "
+                   f"at live width 24<->25, complex128, {dt:.1f} s wall"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fused", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs a pattern on a single MI355X "
+              "(no multi-GPU path); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import owqs_workloads as W
+    import paper_1604_05659_amd as owqs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    log("[bench] generating workload")
+    wl = W.plain_large(**WORKLOAD)
+    pat_def = wl.pattern
+    counts = pat_def.counts()
+    n_all = len(pat_def.cmds)
+    n_nontriv = pat_def.nontrivial_count(wl.outcomes)
+
+    ctx = owqs.Context(0)
+    pat = owqs.Pattern(ctx, pat_def)
+    pat.set_mode(owqs.MODE_OWQS)
+    pat.set_outcomes(wl.outcomes)
+    inp = torch.as_tensor(wl.input_state).cuda()
+    out = torch.empty(1 << len(pat_def.outputs), dtype=torch.complex64, device="cuda")
+
+    log("[bench] plain executor")
+    wall, ev_ms, prof = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_PLAIN, args.steps, args.warmup)
+    probs = pat.read_probs()
+    ms_step = 1e3 * wall / args.steps
+    names = {"measure(M)": "k_measure", "prepare(N)": "k_prepare", "cz(E)": "k_cz", "pauli_x(X)": "k_x",
+             "jwindow(NEMX)": "k_jwindow"}
+    dom, roof = roofline_of(prof, names)
+    step_bytes = sum(v["bytes"] for v in prof.values())
+    kernels = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                   "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in prof.items()}
+    result = {
+        "metric": "pattern commands/s & HBM GB/s at 2^25 amps; batched vs plain at err<=1e-5",
+        "value": round(n_nontriv / (ms_step / 1e3), 1),
+        "unit": "commands/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("plain_large: random J/CZ circuit on 24 logical qubits, 2000 J(alpha) + 300 CZ, "
+                         "pattern of 8300 commands, live width 24<->25 (2^25 complex64 amplitudes), "
+                         "complex Gaussian input, seeded forced outcomes, OWQS mode (FP64 probabilities)"),
+            "exec": "plain (one kernel per non-trivial command)",
+            "commands_listed": n_all,
+            "commands_nontrivial": n_nontriv,
+            "counts": counts,
+        },
+        "commands_all_per_s": round(n_all / (ms_step / 1e3), 1),
+        "hbm_gbs_step": round(step_bytes / (ms_step / 1e3) / 1e9, 1),
+        "event_ms_per_step": round(ev_ms / args.steps, 3),
+        "roofline": roof,
+        "kernels": kernels,
+        "checks": {"max_abs_p_minus_half": float(np.max(np.abs(probs - 0.5)))},
+    }
+
+    if not args.no_fused:
+        log("[bench] fused executor")
+        wall_f, ev_f, prof_f = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_FUSED, args.steps, args.warmup)
+        probs_f = pat.read_probs()
+        fused_out = out.clone()
+        pat.set_exec(owqs.EXEC_PLAIN)
+        pat.run(inp)
+        pat.read_state(out)
+        diff = float((fused_out - out).abs().max().item())
+        ms_f = 1e3 * wall_f / args.steps
+        _, roof_f = roofline_of(prof_f, names)
+        result["fused"] = {
+            "value": round(n_nontriv / (ms_f / 1e3), 1),
+            "unit": "commands/s",
+            "ms_per_step": round(ms_f, 3),
+            "live_width": 24,
+            "roofline": roof_f,
+            "kernels": {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                            "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in prof_f.items()},
+            "max_abs_diff_vs_plain": diff,
+            "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
+        }
+
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(wl.meta["gates"], wl.input_state, 20)
+    else:
+        result["cpu_baseline"] = None
+    pat.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

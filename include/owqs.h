@@ -1,0 +1,206 @@
+/*
+ * owqs.h -- C ABI of libowqs: state-vector execution of one-way quantum
+ * computer (1WQC) measurement patterns on an AMD Instinct MI355X (gfx950).
+ *
+ * The library takes a pattern (Sec. 2.2 of "One-Way Quantum Computer
+ * Simulation": qubits, inputs, outputs and a command list of N, E, M, X, Z)
+ * together with the state of the input qubits, applies the commands in the
+ * given order with qubit elimination after every measurement (Sec. 4.2) and
+ * implicit actions (Sec. 4.4), and reports the state of the output qubits
+ * (Sec. 4, overview of the simulator).  Measurement outcomes are forced by the
+ * caller, so runs are reproducible.
+ *
+ * Conventions used by every entry point:
+ *   - Commands are given in EXECUTION order (first command first); the paper
+ *     writes patterns right to left.
+ *   - Amplitudes are complex64, interleaved (float re, float im).  Bit k of an
+ *     input index is the k-th listed input qubit; bit k of an output index is
+ *     the k-th listed output qubit (the paper's qubit v <-> 2^(v-1) of
+ *     Figs. 5-6; its kets print the most significant qubit first, Eq. 8).
+ *   - M with angle alpha and signal domains s, t measures at
+ *     theta = (-1)^s alpha + t pi (Eq. 2).  Outcome o keeps the branch of the
+ *     elimination operator of Eq. 11 (o = 0) or Eq. 12 (o = 1):
+ *     new = (psi_0 + (-1)^o e^{-i theta} psi_1) / sqrt(2), whose squared norm
+ *     is the outcome probability (Eq. 13).
+ *   - X_v^s and Z_v^s apply when the XOR of the outcomes in s is 1.
+ *   - Ownership: every *_create has a matching *_destroy.  Host arrays passed
+ *     in are copied before the call returns; the library never frees caller
+ *     memory.  Device pointers (flag *_on_device = 1) are borrowed until the
+ *     work enqueued on the given stream has finished.
+ *   - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls that
+ *     take a stream enqueue work and return without waiting, except where a
+ *     host buffer is read or written, which waits for the stream.
+ *   - Errors: every call returns an owqs_status; negative values are errors.
+ *     owqs_last_error() gives a human-readable detail (command index, HIP
+ *     error string).  After OWQS_E_ZERO_PROB the state is undefined.
+ *   - Thread safety: a context and its patterns must be used from one host
+ *     thread at a time.
+ */
+#ifndef OWQS_H
+#define OWQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OWQS_OK = 0,
+  OWQS_E_INVALID_ARG = -1,       /* null pointer, size mismatch, bad enum */
+  OWQS_E_PATTERN = -2,           /* pattern breaks rule D0, D1, D2 or D3 (Sec. 2.2) */
+  OWQS_E_ZERO_PROB = -3,         /* a forced outcome has probability < 1e-10 */
+  OWQS_E_WIDTH = -4,             /* live width above OWQS_MAX_WIDTH */
+  OWQS_E_NOMEM = -5,             /* device or host allocation failed */
+  OWQS_E_HIP = -6,               /* a HIP runtime call failed */
+  OWQS_E_NOT_DETERMINISTIC = -7, /* EOWQS check mode saw |p - 1/2| > 1e-4 */
+  OWQS_E_STATE = -8              /* call out of order, e.g. read before run */
+} owqs_status;
+
+/* Largest live width (number of qubits held in the state vector at once). */
+#define OWQS_MAX_WIDTH 34
+
+/* Command opcodes (Sec. 2.2). */
+enum {
+  OWQS_OP_N = 0, /* N_v: prepare v in |+> = (|0> + |1>)/sqrt 2 */
+  OWQS_OP_E = 1, /* E_uv: controlled-Z between u (q0) and v (q1) */
+  OWQS_OP_M = 2, /* M_v^alpha with s- and t-domains (Eqs. 1-2) */
+  OWQS_OP_X = 3, /* X_v^s: Pauli X when the s signal is 1 */
+  OWQS_OP_Z = 4  /* Z_v^s: Pauli Z when the s signal is 1 */
+};
+
+/* One command.  Qubit ids are non-negative integers.  Domains are ranges in
+ * the `domain_ids` array given to owqs_pattern_create; the t-domain is read
+ * for M only.  40 bytes, no implicit padding. */
+typedef struct {
+  int32_t op;     /* OWQS_OP_* */
+  int32_t q0;     /* qubit acted on (E: first qubit) */
+  int32_t q1;     /* E: second qubit; ignored otherwise */
+  int32_t s_off;  /* s-domain = domain_ids[s_off .. s_off + s_len) */
+  int32_t s_len;
+  int32_t t_off;  /* t-domain = domain_ids[t_off .. t_off + t_len) (M only) */
+  int32_t t_len;
+  int32_t reserved; /* must be 0 */
+  double angle;   /* M: alpha in radians; ignored otherwise */
+} owqs_cmd;
+
+/* OWQS (Sec. 4): each M computes its outcome probability in FP64 and the
+ * state is renormalised by it.  EOWQS (Sec. 4.5): for patterns with a
+ * (generalised) flow every outcome has probability 1/2, so no probability is
+ * computed and the scale is fixed.  EOWQS_CHECK: as EOWQS, but every M still
+ * computes p and the run fails with OWQS_E_NOT_DETERMINISTIC if
+ * |p - 1/2| > 1e-4. */
+typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 2 } owqs_mode;
+
+/* Execution plan.  PLAIN: one kernel per non-trivial command, the live width
+ * growing on N and shrinking on M.  FUSED (default): windows of commands are
+ * merged into single passes over the state (N w; E u w; M u; corrections on
+ * w becomes one 2x2 update in place; runs of E/Z become one diagonal pass).
+ * Both give the same result to FP32 rounding. */
+typedef enum { OWQS_EXEC_PLAIN = 0, OWQS_EXEC_FUSED = 1 } owqs_exec;
+
+typedef struct owqs_ctx owqs_ctx;
+typedef struct owqs_pattern owqs_pattern;
+
+/* Name of a status code (static string). */
+const char *owqs_status_str(owqs_status s);
+
+/* Create a context bound to HIP device `device`.  *out receives the handle.
+ * device = -1 makes a host-only context: patterns can be created, parsed and
+ * validated, but owqs_run returns OWQS_E_STATE. */
+owqs_status owqs_ctx_create(int device, owqs_ctx **out);
+void owqs_ctx_destroy(owqs_ctx *ctx);
+/* Detail of the last error raised through this context (static until the
+ * next call on the context).  Never NULL. */
+const char *owqs_last_error(const owqs_ctx *ctx);
+
+/* Build a pattern from commands in execution order (Sec. 2.2, P = (V,I,O,A)).
+ * inputs[k] is bit k of the input state, outputs[k] bit k of the read-out.
+ * The pattern is validated against D0-D3 (no dependence on an unmeasured
+ * outcome; no action on a measured qubit; no action on an unprepared
+ * non-input; exactly the non-outputs are measured) and its largest live width
+ * is computed; no device memory is allocated yet.  Every M starts with its
+ * outcome forced to 0. */
+owqs_status owqs_pattern_create(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds,
+                                const int32_t *domain_ids, size_t ndom,
+                                const int32_t *inputs, int32_t nin,
+                                const int32_t *outputs, int32_t nout,
+                                owqs_pattern **out);
+
+/* Same, from text format v1: lines "inputs q...", "outputs q...", then one
+ * command per line in execution order: "N q", "E u v",
+ * "M q alpha [s: ids] [t: ids]", "X q [s: ids]", "Z q [s: ids]"; '#' starts a
+ * comment.  `len` is the number of bytes in `text`. */
+owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len,
+                                   owqs_pattern **out);
+
+/* Frees the pattern and its device buffers (waits for its streams' work). */
+void owqs_pattern_destroy(owqs_pattern *pat);
+
+/* Sizes of the pattern: number of M commands, largest live width (plain
+ * execution), number of inputs and outputs, number of commands.  Any output
+ * pointer may be NULL. */
+owqs_status owqs_pattern_info(const owqs_pattern *pat, int32_t *n_meas, int32_t *max_live,
+                              int32_t *n_in, int32_t *n_out, size_t *ncmds);
+
+owqs_status owqs_set_mode(owqs_pattern *pat, owqs_mode mode);
+owqs_status owqs_set_exec(owqs_pattern *pat, owqs_exec exec);
+
+/* Replace the angles of the M commands (alpha[m] for the m-th M in execution
+ * order, radians).  n_meas must equal the pattern's M count. */
+owqs_status owqs_set_angles(owqs_pattern *pat, const double *alpha, size_t n_meas);
+
+/* Force the outcomes of the M commands (bits[m] in {0,1} for the m-th M). */
+owqs_status owqs_set_outcomes(owqs_pattern *pat, const uint8_t *bits, size_t n_meas);
+
+/* Run the whole pattern on `stream`.  input_c64 holds 2^nin complex64
+ * amplitudes (n_amps must equal 2^nin; when nin = 0 pass n_amps = 1 and
+ * input NULL for the empty product state).  The input need not be
+ * normalised: OWQS renormalises at every M, EOWQS keeps its norm.  The live
+ * state stays in device memory owned by the pattern until the next run. */
+owqs_status owqs_run(owqs_pattern *pat, const void *input_c64, size_t n_amps,
+                     int input_on_device, void *stream);
+
+/* Copy the output state (2^nout complex64, outputs[k] at bit k, scaled to the
+ * true state) to out_c64.  With out_on_device = 0 the call waits for the
+ * stream and also reports a pending OWQS_E_ZERO_PROB /
+ * OWQS_E_NOT_DETERMINISTIC from the run. */
+owqs_status owqs_read_state(owqs_pattern *pat, void *out_c64, size_t n_amps,
+                            int out_on_device, void *stream);
+
+/* Waits for `stream` and reports errors detected on the device by the last
+ * run (zero probability, non-determinism in EOWQS_CHECK mode). */
+owqs_status owqs_check(owqs_pattern *pat, void *stream);
+
+/* Kernel kinds reported by owqs_run_profiled. */
+enum {
+  OWQS_KIND_N = 0,      /* prepare: 16 * 2^n algorithmic bytes at live width n */
+  OWQS_KIND_E = 1,      /* controlled-Z: 4 * 2^n (the quarter read and written) */
+  OWQS_KIND_M = 2,      /* measure + eliminate: 12 * 2^n (read all, write half) */
+  OWQS_KIND_X = 3,      /* 16 * 2^n */
+  OWQS_KIND_Z = 4,      /* 8 * 2^n */
+  OWQS_KIND_J = 5,      /* fused window N w; E u w; M u; X/Z w: 16 * 2^n */
+  OWQS_KIND_FINISH = 6, /* one-block FP64 finish of an M/window probability (bytes not counted) */
+  OWQS_NUM_KINDS = 8
+};
+
+/* As owqs_run, and also times every kernel of the run with HIP events
+ * recorded on `stream` between consecutive launches; waits for the stream.
+ * For each kind k, adds the number of launches to counts[k], their summed
+ * event time to ms[k] and their algorithmic bytes (amplitudes that the
+ * command must read plus those it must write, 8 bytes each) to bytes[k].
+ * The three arrays hold OWQS_NUM_KINDS entries each and are not cleared. */
+owqs_status owqs_run_profiled(owqs_pattern *pat, const void *input_c64, size_t n_amps,
+                              int input_on_device, void *stream, int64_t *counts, double *ms,
+                              double *bytes);
+
+/* FP64 outcome probability of every M of the last run (OWQS and EOWQS_CHECK
+ * modes; 0.5 in EOWQS mode).  Waits for `stream`. */
+owqs_status owqs_read_probs(owqs_pattern *pat, double *p, size_t n_meas, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OWQS_H */

@@ -478,6 +478,52 @@ def ansatz(index: int = 0, n_logical: int = 16, layers: int = 25, batch: int = 6
     return Workload(pat, out, None, {"n_logical": n_logical, "layers": layers}), sets
 
 
+def random_pattern(g: np.random.Generator, max_qubits: int = 10) -> Pattern:
+    """A random pattern obeying D0-D3: random inputs, lazily prepared qubits,
+    E between live qubits, M with random domains over measured qubits, and
+    X/Z corrections with random domains."""
+    nin = int(g.integers(0, 3))
+    ids = list(range(max_qubits))
+    inputs = ids[:nin]
+    live = list(inputs)
+    fresh = ids[nin:]
+    measured = []
+    cmds = []
+    n_out = int(g.integers(1, 3))
+    steps = 0
+    while steps < 60:
+        steps += 1
+        r = g.random()
+        if (r < 0.25 or len(live) < 2) and fresh:
+            q = fresh.pop(0)
+            cmds.append(("N", q))
+            live.append(q)
+        elif r < 0.55 and len(live) >= 2:
+            a, b = g.choice(len(live), size=2, replace=False)
+            cmds.append(("E", live[a], live[b]))
+        elif r < 0.8 and len(live) > n_out:
+            q = live.pop(int(g.integers(len(live))))
+            def dom():
+                if not measured:
+                    return ()
+                k = int(g.integers(0, min(3, len(measured)) + 1))
+                return tuple(int(x) for x in g.choice(measured, size=k, replace=False))
+            cmds.append(("M", q, float(g.uniform(0, 2 * math.pi)), dom(), dom()))
+            measured.append(q)
+        elif live and measured:
+            q = live[int(g.integers(len(live)))]
+            k = int(g.integers(1, min(2, len(measured)) + 1))
+            d = tuple(int(x) for x in g.choice(measured, size=k, replace=False))
+            cmds.append(("X" if g.random() < 0.5 else "Z", q, d))
+        if not fresh and len(live) <= n_out:
+            break
+    while len(live) > n_out:
+        q = live.pop(0)
+        cmds.append(("M", q, float(g.uniform(0, 2 * math.pi)), (), ()))
+        measured.append(q)
+    return Pattern(inputs, list(live), cmds)
+
+
 def basis_state(n_qubits: int, k: int) -> np.ndarray:
     v = np.zeros(1 << n_qubits, dtype=np.complex64)
     v[k] = 1.0

@@ -1,0 +1,275 @@
+"""Python binding of libowqs: 1WQC pattern execution on an MI355X (gfx950).
+
+Argument marshalling only: every step of a run executes in the HIP kernels of
+``libowqs.so`` (see ``include/owqs.h``).  PyTorch supplies device memory and
+the current stream.  Importing this package fails loudly when the library has
+not been built; there is no CPU fallback.
+
+Typical use::
+
+    import paper_1604_05659_amd as owqs
+    ctx = owqs.Context(0)
+    pat = owqs.Pattern(ctx, pattern)          # pattern: .inputs/.outputs/.cmds
+    pat.set_outcomes(bits)
+    pat.run(psi_in)                           # complex64 CUDA tensor
+    psi_out = pat.read_state()                # complex64 CUDA tensor
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libowqs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python paper_1604_05659_amd/build.py` "
+        "(or __graft_entry__.build()) first. There is no CPU fallback.")
+
+# PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Import it first
+# so that libowqs binds to that same runtime instead of loading a second copy
+# from /opt/rocm: device pointers and streams are then shared with torch.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+E_INVALID_ARG, E_PATTERN, E_ZERO_PROB, E_WIDTH, E_NOMEM, E_HIP, E_NOT_DETERMINISTIC, E_STATE = range(-1, -9, -1)
+MODE_OWQS, MODE_EOWQS, MODE_EOWQS_CHECK = 0, 1, 2
+EXEC_PLAIN, EXEC_FUSED = 0, 1
+OPS = {"N": 0, "E": 1, "M": 2, "X": 3, "Z": 4}
+KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)"}
+NUM_KINDS = 8
+
+
+class OwqsCmd(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("s_off", ctypes.c_int32), ("s_len", ctypes.c_int32),
+                ("t_off", ctypes.c_int32), ("t_len", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("angle", ctypes.c_double)]
+
+
+assert ctypes.sizeof(OwqsCmd) == 40
+
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_sig = {
+    "owqs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "owqs_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "owqs_ctx_destroy": (None, [_vp]),
+    "owqs_last_error": (ctypes.c_char_p, [_vp]),
+    "owqs_pattern_create": (ctypes.c_int, [_vp, ctypes.POINTER(OwqsCmd), ctypes.c_size_t, _i32p,
+                                           ctypes.c_size_t, _i32p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                           ctypes.POINTER(_vp)]),
+    "owqs_pattern_from_text": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "owqs_pattern_destroy": (None, [_vp]),
+    "owqs_pattern_info": (ctypes.c_int, [_vp, _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_size_t)]),
+    "owqs_set_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "owqs_set_exec": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "owqs_set_angles": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "owqs_set_outcomes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
+    "owqs_run": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "owqs_read_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "owqs_check": (ctypes.c_int, [_vp, _vp]),
+    "owqs_read_probs": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _vp]),
+    "owqs_run_profiled": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class OwqsError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        name = _lib.owqs_status_str(status).decode()
+        super().__init__(f"{name}: {detail}" if detail else name)
+        self.status = status
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """A libowqs context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        st = _lib.owqs_ctx_create(int(device), ctypes.byref(h))
+        if st != OK:
+            raise OwqsError(st, f"device {device}")
+        self._h = h
+        self.device = int(device)
+
+    def check(self, status: int):
+        if status != OK:
+            raise OwqsError(status, _lib.owqs_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.owqs_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _marshal(pattern):
+    cmds = (OwqsCmd * max(len(pattern.cmds), 1))()
+    dom = []
+    for i, c in enumerate(pattern.cmds):
+        x = cmds[i]
+        x.op = OPS[c[0]]
+        x.q0 = int(c[1])
+        if c[0] == "E":
+            x.q1 = int(c[2])
+        elif c[0] == "M":
+            x.angle = float(c[2])
+            x.s_off, x.s_len = len(dom), len(c[3])
+            dom.extend(int(j) for j in c[3])
+            x.t_off, x.t_len = len(dom), len(c[4])
+            dom.extend(int(j) for j in c[4])
+        elif c[0] in ("X", "Z"):
+            x.s_off, x.s_len = len(dom), len(c[2])
+            dom.extend(int(j) for j in c[2])
+    dom_a = np.array(dom if dom else [0], np.int32)
+    ins = np.array(list(pattern.inputs) or [0], np.int32)
+    outs = np.array(list(pattern.outputs) or [0], np.int32)
+    return cmds, dom_a, len(dom), ins, outs
+
+
+class Pattern:
+    """A pattern loaded into libowqs (owns its device state buffer)."""
+
+    def __init__(self, ctx: Context, pattern=None, text: Optional[str] = None):
+        self.ctx = ctx
+        h = _vp()
+        if text is not None:
+            b = text.encode()
+            ctx.check(_lib.owqs_pattern_from_text(ctx._h, b, len(b), ctypes.byref(h)))
+        else:
+            cmds, dom, ndom, ins, outs = _marshal(pattern)
+            ctx.check(_lib.owqs_pattern_create(
+                ctx._h, cmds, len(pattern.cmds), dom.ctypes.data_as(_i32p), ndom,
+                ins.ctypes.data_as(_i32p), len(pattern.inputs), outs.ctypes.data_as(_i32p),
+                len(pattern.outputs), ctypes.byref(h)))
+        self._h = h
+        nm, ml, ni, no = (ctypes.c_int32() for _ in range(4))
+        nc = ctypes.c_size_t()
+        ctx.check(_lib.owqs_pattern_info(h, ctypes.byref(nm), ctypes.byref(ml), ctypes.byref(ni),
+                                         ctypes.byref(no), ctypes.byref(nc)))
+        self.n_meas, self.max_live, self.n_in, self.n_out, self.ncmds = nm.value, ml.value, ni.value, no.value, nc.value
+
+    def set_mode(self, mode: int):
+        self.ctx.check(_lib.owqs_set_mode(self._h, int(mode)))
+
+    def set_exec(self, exec_: int):
+        self.ctx.check(_lib.owqs_set_exec(self._h, int(exec_)))
+
+    def set_angles(self, alphas: Sequence[float]):
+        a = np.ascontiguousarray(alphas, np.float64)
+        self.ctx.check(_lib.owqs_set_angles(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
+
+    def set_outcomes(self, bits: Sequence[int]):
+        b = np.ascontiguousarray(bits, np.uint8)
+        self.ctx.check(_lib.owqs_set_outcomes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), b.size))
+
+    def run(self, psi_in=None, stream=None):
+        """psi_in: complex64 CUDA tensor of 2^n_in amplitudes (None when n_in = 0)."""
+        if psi_in is None:
+            if self.n_in:
+                raise ValueError("this pattern needs an input state")
+            self.ctx.check(_lib.owqs_run(self._h, None, 1, 1, _stream_handle(stream)))
+            return
+        import torch
+        if psi_in.dtype != torch.complex64 or not psi_in.is_cuda or not psi_in.is_contiguous():
+            raise TypeError("input must be a contiguous complex64 CUDA tensor")
+        self.ctx.check(_lib.owqs_run(self._h, psi_in.data_ptr(), psi_in.numel(), 1, _stream_handle(stream)))
+
+    def run_profiled(self, psi_in=None, stream=None) -> dict:
+        """Run once with HIP events between launches; returns, per kernel kind,
+        {"launches", "ms", "bytes"} (algorithmic bytes, element level)."""
+        counts = np.zeros(NUM_KINDS, np.int64)
+        ms = np.zeros(NUM_KINDS, np.float64)
+        by = np.zeros(NUM_KINDS, np.float64)
+        ptr, n = None, 1
+        if psi_in is not None:
+            ptr, n = psi_in.data_ptr(), psi_in.numel()
+        elif self.n_in:
+            raise ValueError("this pattern needs an input state")
+        self.ctx.check(_lib.owqs_run_profiled(
+            self._h, ptr, n, 1, _stream_handle(stream), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), by.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return {KINDS[k]: {"launches": int(counts[k]), "ms": float(ms[k]), "bytes": float(by[k])}
+                for k in KINDS if counts[k]}
+
+    def read_state(self, out=None, stream=None, check: bool = True):
+        """Output state as a complex64 CUDA tensor (outputs[k] at bit k)."""
+        import torch
+        n = 1 << self.n_out
+        if out is None:
+            out = torch.empty(n, dtype=torch.complex64, device=f"cuda:{self.ctx.device}")
+        if out.numel() != n or out.dtype != torch.complex64 or not out.is_contiguous():
+            raise TypeError("output must be a contiguous complex64 tensor of 2^n_out entries")
+        self.ctx.check(_lib.owqs_read_state(self._h, out.data_ptr(), n, 1, _stream_handle(stream)))
+        if check:
+            self.check(stream)
+        return out
+
+    def check(self, stream=None):
+        self.ctx.check(_lib.owqs_check(self._h, _stream_handle(stream)))
+
+    def read_probs(self, stream=None) -> np.ndarray:
+        p = np.zeros(max(self.n_meas, 1), np.float64)
+        self.ctx.check(_lib.owqs_read_probs(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            self.n_meas, _stream_handle(stream)))
+        return p[: self.n_meas]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.owqs_pattern_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_pattern(ctx: Context, pattern, outcomes, input_state=None, mode: int = MODE_OWQS,
+                exec_: int = EXEC_FUSED, angles=None):
+    """Load, run and read one pattern; returns (output complex64 CUDA tensor, probs)."""
+    import torch
+    p = Pattern(ctx, pattern)
+    try:
+        p.set_mode(mode)
+        p.set_exec(exec_)
+        if angles is not None:
+            p.set_angles(angles)
+        p.set_outcomes(outcomes)
+        x = None
+        if input_state is not None:
+            x = torch.as_tensor(np.asarray(input_state, np.complex64)).to(f"cuda:{ctx.device}")
+        p.run(x)
+        out = p.read_state()
+        probs = p.read_probs()
+        torch.cuda.synchronize()
+        return out, probs
+    finally:
+        p.close()

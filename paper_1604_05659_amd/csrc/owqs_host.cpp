@@ -1,0 +1,784 @@
+// owqs_host.cpp -- the C ABI of libowqs (include/owqs.h): pattern loading and
+// validation, the host plan compiler and the run / read entry points.
+//
+// The plan compiler walks the command list once per (angles, outcomes, mode,
+// exec) setting and emits one device step per non-trivial command:
+//   - qubit ids map to slots (index bits).  Inputs take slots 0..nin-1; N puts
+//     the new qubit on the top slot; M moves the top qubit into the measured
+//     slot (the kernels' in-place layout), so the vector stays contiguous;
+//   - signals are resolved with the forced outcomes: theta = (-1)^s alpha +
+//     t pi (Eq. 2) and the kernel coefficient c = (-1)^o e^{-i theta}
+//     (Eqs. 11-12) is computed in FP64 and rounded to complex64; X/Z with a
+//     zero signal emit nothing;
+//   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
+//     into its pass (with the device FP64 sigma in OWQS mode).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/owqs.h"
+#include "owqs_internal.h"
+
+using namespace owqs;
+
+struct owqs_ctx {
+  int device = 0;
+  std::string last_error;
+};
+
+namespace {
+
+enum StepKind : int { S_N = 0, S_E = 1, S_M = 2, S_X = 3, S_Z = 4, S_J = 5 };
+
+struct Step {
+  int kind;
+  int n;       // live width before the step
+  int b0, b1;  // slots
+  float2 coef;
+  double host_factor;
+  int m_index;
+  PostPerm pp;
+};
+
+struct Cmd {
+  int op;
+  int q0, q1;  // dense qubit indices
+  double angle;
+  std::vector<int> s, t;  // dense qubit indices
+};
+
+}  // namespace
+
+struct owqs_pattern {
+  owqs_ctx *ctx = nullptr;
+  std::vector<Cmd> cmds;
+  std::vector<int> inputs, outputs;  // dense
+  int nq = 0;
+  int n_meas = 0;
+  int max_live = 0;
+  std::vector<double> angles;     // per M
+  std::vector<uint8_t> outcomes;  // per M
+  owqs_mode mode = OWQS_MODE_OWQS;
+  owqs_exec exec = OWQS_EXEC_FUSED;
+
+  // compiled plan
+  bool dirty = true;
+  std::vector<Step> steps;
+  std::vector<int> final_where;  // slot of outputs[k]
+  double final_factor = 1.0;
+
+  // device memory
+  float2 *psi = nullptr;
+  size_t psi_cap = 0;  // amplitudes
+  void *book_mem = nullptr;
+  float2 *stage = nullptr;  // device staging for reads into host memory (2^nout)
+  DevBook book{};
+  bool ran = false;
+  int ran_mode = 0;
+};
+
+namespace {
+
+owqs_status fail(owqs_ctx *ctx, owqs_status st, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+owqs_status hip_fail(owqs_ctx *ctx, hipError_t e, const char *what) {
+  return fail(ctx, OWQS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Validate D0-D3 (Sec. 2.2) and compute the largest live width.
+owqs_status validate(owqs_pattern *p) {
+  enum { UNPREP = 0, LIVE = 1, MEAS = 2 };
+  std::vector<int> st(p->nq, UNPREP);
+  std::vector<char> is_out(p->nq, 0);
+  for (int q : p->outputs) {
+    if (is_out[q]) return fail(p->ctx, OWQS_E_INVALID_ARG, "duplicate output qubit");
+    is_out[q] = 1;
+  }
+  for (int q : p->inputs) {
+    if (st[q] != UNPREP) return fail(p->ctx, OWQS_E_INVALID_ARG, "duplicate input qubit");
+    st[q] = LIVE;
+  }
+  int n = (int)p->inputs.size(), m = n, meas = 0;
+  for (size_t i = 0; i < p->cmds.size(); ++i) {
+    const Cmd &c = p->cmds[i];
+    auto bad = [&](const char *why) {
+      return fail(p->ctx, OWQS_E_PATTERN, "command " + std::to_string(i) + ": " + why);
+    };
+    switch (c.op) {
+      case OWQS_OP_N:
+        if (st[c.q0] != UNPREP) return bad("N on a qubit that is an input or already prepared (D2)");
+        st[c.q0] = LIVE;
+        ++n;
+        if (n > m) m = n;
+        break;
+      case OWQS_OP_E:
+        if (c.q0 == c.q1) return bad("E on a single qubit");
+        if (st[c.q0] != LIVE || st[c.q1] != LIVE) return bad("E on a qubit not live (D1/D2)");
+        break;
+      case OWQS_OP_M:
+      case OWQS_OP_X:
+      case OWQS_OP_Z:
+        if (st[c.q0] != LIVE) return bad("action on a qubit not live (D1/D2)");
+        for (int j : c.s)
+          if (st[j] != MEAS) return bad("signal depends on an unmeasured qubit (D0)");
+        for (int j : c.t)
+          if (st[j] != MEAS) return bad("signal depends on an unmeasured qubit (D0)");
+        if (c.op == OWQS_OP_M) {
+          if (is_out[c.q0]) return bad("an output qubit is measured (D3)");
+          st[c.q0] = MEAS;
+          --n;
+          ++meas;
+        }
+        break;
+      default:
+        return bad("unknown opcode");
+    }
+    if (m > OWQS_MAX_WIDTH) return fail(p->ctx, OWQS_E_WIDTH, "live width above OWQS_MAX_WIDTH");
+  }
+  for (int q = 0; q < p->nq; ++q) {
+    if (is_out[q] && st[q] != LIVE) return fail(p->ctx, OWQS_E_PATTERN, "an output qubit is not live at the end (D3)");
+    if (!is_out[q] && st[q] == LIVE) return fail(p->ctx, OWQS_E_PATTERN, "a non-output qubit is never measured (D3)");
+  }
+  p->n_meas = meas;
+  p->max_live = m;
+  return OWQS_OK;
+}
+
+int signal(const std::vector<int> &dom, const std::vector<int> &outcome_of) {
+  int s = 0;
+  for (int j : dom) s ^= outcome_of[j];
+  return s;
+}
+
+// Compile the command list into device steps for the current settings.
+void compile(owqs_pattern *p) {
+  const int nq = p->nq;
+  std::vector<int> slot_of(nq, -1), qubit_at(OWQS_MAX_WIDTH + 1, -1), outcome_of(nq, 0);
+  int n = (int)p->inputs.size();
+  for (int k = 0; k < n; ++k) {
+    slot_of[p->inputs[k]] = k;
+    qubit_at[k] = p->inputs[k];
+  }
+  const double r2 = 1.0 / std::sqrt(2.0);
+  double pending = 1.0;
+  int m = 0;
+  const bool fused = p->exec == OWQS_EXEC_FUSED;
+  p->steps.clear();
+  const size_t nc = p->cmds.size();
+
+  auto coef_of = [&](const Cmd &c, int mi, int &o_out) {
+    const int s = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
+    const double theta = (s ? -p->angles[mi] : p->angles[mi]) + (t ? M_PI : 0.0);  // Eq. 2
+    const int o = p->outcomes[mi] & 1;
+    double cr = std::cos(theta), ci = -std::sin(theta);  // e^{-i theta}  (Eqs. 11-12)
+    if (o) { cr = -cr; ci = -ci; }
+    o_out = o;
+    return make_float2((float)cr, (float)ci);
+  };
+
+  for (size_t i = 0; i < nc; ++i) {
+    const Cmd &c = p->cmds[i];
+    // Window N w; E(u, w); M u; then X/Z on w, as one in-place 2x2 pass.
+    if (fused && c.op == OWQS_OP_N && i + 2 < nc) {
+      const int w = c.q0;
+      const Cmd &e = p->cmds[i + 1];
+      const Cmd &mm = p->cmds[i + 2];
+      if (e.op == OWQS_OP_E && (e.q0 == w || e.q1 == w) && mm.op == OWQS_OP_M) {
+        const int u = (e.q0 == w) ? e.q1 : e.q0;
+        if (mm.q0 == u && u != w) {
+          int o = 0;
+          Step st{};
+          st.kind = S_J;
+          st.n = n;
+          st.b0 = slot_of[u];
+          st.coef = coef_of(mm, m, o);
+          st.host_factor = pending * r2;
+          st.m_index = m;
+          outcome_of[u] = o;
+          ++m;
+          // fold the following corrections on w into a signed permutation
+          int idx[2] = {0, 1}, sgn[2] = {1, 1};
+          size_t k = i + 3;
+          while (k < nc && (p->cmds[k].op == OWQS_OP_X || p->cmds[k].op == OWQS_OP_Z) && p->cmds[k].q0 == w) {
+            if (signal(p->cmds[k].s, outcome_of)) {
+              if (p->cmds[k].op == OWQS_OP_X) {
+                std::swap(idx[0], idx[1]);
+                std::swap(sgn[0], sgn[1]);
+              } else {
+                sgn[1] = -sgn[1];
+              }
+            }
+            ++k;
+          }
+          st.pp.swap = idx[0] == 1;
+          st.pp.neg0 = sgn[0] < 0;
+          st.pp.neg1 = sgn[1] < 0;
+          p->steps.push_back(st);
+          slot_of[w] = st.b0;
+          qubit_at[st.b0] = w;
+          slot_of[u] = -1;
+          pending = 1.0;
+          i = k - 1;
+          continue;
+        }
+      }
+    }
+    switch (c.op) {
+      case OWQS_OP_N: {
+        Step st{};
+        st.kind = S_N;
+        st.n = n;
+        p->steps.push_back(st);
+        slot_of[c.q0] = n;
+        qubit_at[n] = c.q0;
+        ++n;
+        pending *= r2;
+        break;
+      }
+      case OWQS_OP_E: {
+        Step st{};
+        st.kind = S_E;
+        st.n = n;
+        st.b0 = slot_of[c.q0];
+        st.b1 = slot_of[c.q1];
+        p->steps.push_back(st);
+        break;
+      }
+      case OWQS_OP_X:
+      case OWQS_OP_Z: {
+        if (signal(c.s, outcome_of)) {
+          Step st{};
+          st.kind = c.op == OWQS_OP_X ? S_X : S_Z;
+          st.n = n;
+          st.b0 = slot_of[c.q0];
+          p->steps.push_back(st);
+        }
+        break;
+      }
+      case OWQS_OP_M: {
+        int o = 0;
+        Step st{};
+        st.kind = S_M;
+        st.n = n;
+        st.b0 = slot_of[c.q0];
+        st.coef = coef_of(c, m, o);
+        st.host_factor = pending;
+        st.m_index = m;
+        p->steps.push_back(st);
+        outcome_of[c.q0] = o;
+        ++m;
+        const int t = n - 1;
+        if (st.b0 != t) {
+          const int top = qubit_at[t];
+          slot_of[top] = st.b0;
+          qubit_at[st.b0] = top;
+        }
+        qubit_at[t] = -1;
+        slot_of[c.q0] = -1;
+        --n;
+        pending = 1.0;
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  p->final_where.assign(p->outputs.size(), 0);
+  for (size_t k = 0; k < p->outputs.size(); ++k) p->final_where[k] = slot_of[p->outputs[k]];
+  p->final_factor = pending;
+  p->dirty = false;
+}
+
+owqs_status ensure_device(owqs_pattern *p) {
+  if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
+  hipError_t e = hipSetDevice(p->ctx->device);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "hipSetDevice");
+  const size_t need = std::max<size_t>(size_t(1) << p->max_live, 4);
+  if (p->psi_cap < need) {
+    if (p->psi) (void)hipFree(p->psi);
+    p->psi = nullptr;
+    p->psi_cap = 0;
+    e = hipMalloc(&p->psi, need * sizeof(float2));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, std::string("state buffer: ") + hipGetErrorString(e));
+    p->psi_cap = need;
+  }
+  if (!p->book_mem) {
+    const size_t nprob = std::max(p->n_meas, 1);
+    const size_t bytes = 64 + nprob * sizeof(double) + kMaxPartials * sizeof(double) + 64;
+    e = hipMalloc(&p->book_mem, bytes);
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, std::string("bookkeeping: ") + hipGetErrorString(e));
+    char *b = static_cast<char *>(p->book_mem);
+    p->book.sigma = reinterpret_cast<double *>(b);
+    p->book.err = reinterpret_cast<int *>(b + 16);
+    p->book.partials = reinterpret_cast<double *>(b + 64);
+    p->book.probs = reinterpret_cast<double *>(b + 64 + kMaxPartials * sizeof(double));
+  }
+  return OWQS_OK;
+}
+
+owqs_status build_pattern(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, const int32_t *dom, size_t ndom,
+                          const int32_t *inputs, int32_t nin, const int32_t *outputs, int32_t nout,
+                          owqs_pattern **out) {
+  if (!ctx || !out || (ncmds && !cmds) || (ndom && !dom) || nin < 0 || nout < 0 || (nin && !inputs) ||
+      (nout && !outputs))
+    return fail(ctx, OWQS_E_INVALID_ARG, "null pointer or negative size");
+  if (nin > OWQS_MAX_WIDTH || nout > OWQS_MAX_WIDTH) return fail(ctx, OWQS_E_WIDTH, "too many inputs/outputs");
+  auto *p = new owqs_pattern();
+  p->ctx = ctx;
+  std::unordered_map<int32_t, int> dense;
+  auto id = [&](int32_t q) -> int {
+    auto it = dense.find(q);
+    if (it != dense.end()) return it->second;
+    const int d = (int)dense.size();
+    dense.emplace(q, d);
+    return d;
+  };
+  for (int k = 0; k < nin; ++k) {
+    if (inputs[k] < 0) { delete p; return fail(ctx, OWQS_E_INVALID_ARG, "negative qubit id"); }
+    p->inputs.push_back(id(inputs[k]));
+  }
+  for (int k = 0; k < nout; ++k) {
+    if (outputs[k] < 0) { delete p; return fail(ctx, OWQS_E_INVALID_ARG, "negative qubit id"); }
+    p->outputs.push_back(id(outputs[k]));
+  }
+  auto domain = [&](int32_t off, int32_t len, std::vector<int> &d) -> bool {
+    if (len == 0) return true;
+    if (off < 0 || len < 0 || size_t(off) + size_t(len) > ndom) return false;
+    for (int32_t k = 0; k < len; ++k) {
+      if (dom[off + k] < 0) return false;
+      d.push_back(id(dom[off + k]));
+    }
+    return true;
+  };
+  for (size_t i = 0; i < ncmds; ++i) {
+    const owqs_cmd &c = cmds[i];
+    Cmd d{};
+    d.op = c.op;
+    if (c.op < OWQS_OP_N || c.op > OWQS_OP_Z || c.q0 < 0 || (c.op == OWQS_OP_E && c.q1 < 0)) {
+      delete p;
+      return fail(ctx, OWQS_E_INVALID_ARG, "command " + std::to_string(i) + ": bad opcode or qubit id");
+    }
+    d.q0 = id(c.q0);
+    d.q1 = c.op == OWQS_OP_E ? id(c.q1) : -1;
+    d.angle = c.angle;
+    const bool has_s = c.op == OWQS_OP_M || c.op == OWQS_OP_X || c.op == OWQS_OP_Z;
+    if (has_s && !domain(c.s_off, c.s_len, d.s)) {
+      delete p;
+      return fail(ctx, OWQS_E_INVALID_ARG, "command " + std::to_string(i) + ": bad s-domain range");
+    }
+    if (c.op == OWQS_OP_M && !domain(c.t_off, c.t_len, d.t)) {
+      delete p;
+      return fail(ctx, OWQS_E_INVALID_ARG, "command " + std::to_string(i) + ": bad t-domain range");
+    }
+    p->cmds.push_back(std::move(d));
+  }
+  p->nq = (int)dense.size();
+  owqs_status st = validate(p);
+  if (st != OWQS_OK) {
+    delete p;
+    return st;
+  }
+  for (const Cmd &c : p->cmds)
+    if (c.op == OWQS_OP_M) p->angles.push_back(c.angle);
+  p->outcomes.assign(p->n_meas, 0);
+  *out = p;
+  return OWQS_OK;
+}
+
+struct Profile {
+  int64_t *counts;
+  double *ms;
+  double *bytes;
+};
+
+// Algorithmic bytes of one step (element level, complex64).
+double step_bytes(const Step &x) {
+  const double a = std::ldexp(8.0, x.n);  // 8 bytes * 2^n
+  switch (x.kind) {
+    case S_N: return 2.0 * a;
+    case S_E: return 0.5 * a;
+    case S_M: return 1.5 * a;
+    case S_X: return 2.0 * a;
+    case S_Z: return 1.0 * a;
+    case S_J: return 2.0 * a;
+  }
+  return 0.0;
+}
+
+owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
+                     Profile *prof) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  const size_t nin = p->inputs.size();
+  const size_t want = size_t(1) << nin;
+  if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
+  if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
+  owqs_status st = ensure_device(p);
+  if (st != OWQS_OK) return st;
+  if (p->dirty) compile(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "init");
+  if (nin > 0 || input != nullptr) {
+    e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
+                       input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "input copy");
+  }
+  const int reduce = p->mode == OWQS_MODE_OWQS ? kReduceRenorm
+                     : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck
+                                                        : kReduceNone;
+  // profiling: ev[2i] before step i's main kernel, ev[2i+1] after it (before
+  // the FP64 finishing kernel, if any), ev[2i+2] after the step
+  std::vector<hipEvent_t> ev;
+  if (prof) {
+    ev.resize(2 * p->steps.size() + 1);
+    for (auto &x : ev) {
+      e = hipEventCreate(&x);
+      if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
+    }
+    e = hipEventRecord(ev[0], s);
+  }
+  for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
+    const Step &x = p->steps[i];
+    MeasureArgs a{};
+    unsigned grid = 0;
+    switch (x.kind) {
+      case S_N: e = launch_prepare(p->psi, x.n, s); break;
+      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
+      case S_X: e = launch_pauli_x(p->psi, x.n, x.b0, s); break;
+      case S_Z: e = launch_pauli_z(p->psi, x.n, x.b0, s); break;
+      case S_M:
+      case S_J:
+        a.coef = x.coef;
+        a.host_factor = x.host_factor;
+        a.reduce = reduce;
+        a.m_index = x.m_index;
+        a.book = p->book;
+        e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
+                          : launch_jwindow(p->psi, x.n, x.b0, a, x.pp, s, &grid);
+        break;
+      default: break;
+    }
+    if (prof && e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s);
+    if ((x.kind == S_M || x.kind == S_J) && e == hipSuccess) e = launch_finish(a, grid, s);
+    if (prof && e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s);
+  }
+  if (e != hipSuccess) {
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return hip_fail(p->ctx, e, "kernel launch");
+  }
+  p->ran = true;
+  p->ran_mode = reduce;
+  if (prof) {
+    e = hipStreamSynchronize(s);
+    for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
+      float t = 0.f, f = 0.f;
+      e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * i + 1], ev[2 * i + 2]);
+      const int k = p->steps[i].kind;
+      prof->counts[k] += 1;
+      prof->ms[k] += t;
+      prof->bytes[k] += step_bytes(p->steps[i]);
+      if ((k == S_M || k == S_J) && reduce != kReduceNone) {
+        prof->counts[OWQS_KIND_FINISH] += 1;
+        prof->ms[OWQS_KIND_FINISH] += f;
+      }
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "profile events");
+  }
+  return OWQS_OK;
+}
+
+// ---- text format v1 ----
+bool parse_text(const char *text, size_t len, std::vector<owqs_cmd> &cmds, std::vector<int32_t> &dom,
+                std::vector<int32_t> &ins, std::vector<int32_t> &outs, std::string &err) {
+  std::string all(text, len);
+  size_t pos = 0;
+  int lineno = 0;
+  while (pos <= all.size()) {
+    size_t eol = all.find('\n', pos);
+    if (eol == std::string::npos) eol = all.size();
+    std::string line = all.substr(pos, eol - pos);
+    pos = eol + 1;
+    ++lineno;
+    const size_t hash = line.find('#');
+    if (hash != std::string::npos) line.resize(hash);
+    std::vector<std::string> tok;
+    {
+      size_t a = 0;
+      while (a < line.size()) {
+        while (a < line.size() && isspace((unsigned char)line[a])) ++a;
+        size_t b = a;
+        while (b < line.size() && !isspace((unsigned char)line[b])) ++b;
+        if (b > a) tok.push_back(line.substr(a, b - a));
+        a = b;
+      }
+    }
+    if (tok.empty()) {
+      if (eol == all.size()) break;
+      continue;
+    }
+    auto to_int = [&](const std::string &s, int32_t &v) {
+      char *end = nullptr;
+      const long x = strtol(s.c_str(), &end, 10);
+      if (!end || *end || x < INT32_MIN || x > INT32_MAX) return false;
+      v = (int32_t)x;
+      return true;
+    };
+    const std::string &h = tok[0];
+    auto bad = [&](const char *why) {
+      err = "line " + std::to_string(lineno) + ": " + why;
+      return false;
+    };
+    if (h == "inputs" || h == "outputs") {
+      auto &dst = (h == "inputs") ? ins : outs;
+      for (size_t k = 1; k < tok.size(); ++k) {
+        int32_t v;
+        if (!to_int(tok[k], v)) return bad("bad qubit id");
+        dst.push_back(v);
+      }
+      continue;
+    }
+    owqs_cmd c{};
+    int32_t v;
+    if (h == "N") {
+      if (tok.size() != 2 || !to_int(tok[1], v)) return bad("N takes one qubit");
+      c.op = OWQS_OP_N;
+      c.q0 = v;
+    } else if (h == "E") {
+      int32_t w;
+      if (tok.size() != 3 || !to_int(tok[1], v) || !to_int(tok[2], w)) return bad("E takes two qubits");
+      c.op = OWQS_OP_E;
+      c.q0 = v;
+      c.q1 = w;
+    } else if (h == "M" || h == "X" || h == "Z") {
+      if (tok.size() < 2 || !to_int(tok[1], v)) return bad("missing qubit");
+      c.op = h == "M" ? OWQS_OP_M : (h == "X" ? OWQS_OP_X : OWQS_OP_Z);
+      c.q0 = v;
+      size_t k = 2;
+      if (c.op == OWQS_OP_M) {
+        if (tok.size() < 3) return bad("M needs an angle");
+        char *end = nullptr;
+        c.angle = strtod(tok[2].c_str(), &end);
+        if (!end || *end) return bad("bad angle");
+        k = 3;
+      }
+      int which = -1;  // 0 = s, 1 = t
+      std::vector<int32_t> sd, td;
+      for (; k < tok.size(); ++k) {
+        if (tok[k] == "s:") { which = 0; continue; }
+        if (tok[k] == "t:") {
+          if (c.op != OWQS_OP_M) return bad("t-domain on a correction");
+          which = 1;
+          continue;
+        }
+        if (which < 0 || !to_int(tok[k], v)) return bad("bad domain");
+        (which == 0 ? sd : td).push_back(v);
+      }
+      c.s_off = (int32_t)dom.size();
+      c.s_len = (int32_t)sd.size();
+      dom.insert(dom.end(), sd.begin(), sd.end());
+      c.t_off = (int32_t)dom.size();
+      c.t_len = (int32_t)td.size();
+      dom.insert(dom.end(), td.begin(), td.end());
+    } else {
+      return bad("unknown command");
+    }
+    cmds.push_back(c);
+    if (eol == all.size()) break;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *owqs_status_str(owqs_status s) {
+  switch (s) {
+    case OWQS_OK: return "OWQS_OK";
+    case OWQS_E_INVALID_ARG: return "OWQS_E_INVALID_ARG";
+    case OWQS_E_PATTERN: return "OWQS_E_PATTERN";
+    case OWQS_E_ZERO_PROB: return "OWQS_E_ZERO_PROB";
+    case OWQS_E_WIDTH: return "OWQS_E_WIDTH";
+    case OWQS_E_NOMEM: return "OWQS_E_NOMEM";
+    case OWQS_E_HIP: return "OWQS_E_HIP";
+    case OWQS_E_NOT_DETERMINISTIC: return "OWQS_E_NOT_DETERMINISTIC";
+    case OWQS_E_STATE: return "OWQS_E_STATE";
+  }
+  return "OWQS_UNKNOWN";
+}
+
+owqs_status owqs_ctx_create(int device, owqs_ctx **out) {
+  if (!out) return OWQS_E_INVALID_ARG;
+  if (device != -1) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device < 0 || device >= count) return OWQS_E_INVALID_ARG;
+  }
+  auto *c = new owqs_ctx();
+  c->device = device;
+  *out = c;
+  return OWQS_OK;
+}
+
+void owqs_ctx_destroy(owqs_ctx *ctx) { delete ctx; }
+
+const char *owqs_last_error(const owqs_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+owqs_status owqs_pattern_create(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, const int32_t *domain_ids,
+                                size_t ndom, const int32_t *inputs, int32_t nin, const int32_t *outputs,
+                                int32_t nout, owqs_pattern **out) {
+  if (cmds)
+    for (size_t i = 0; i < ncmds; ++i)
+      if (cmds[i].reserved != 0) return fail(ctx, OWQS_E_INVALID_ARG, "owqs_cmd.reserved must be 0");
+  return build_pattern(ctx, cmds, ncmds, domain_ids, ndom, inputs, nin, outputs, nout, out);
+}
+
+owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, owqs_pattern **out) {
+  if (!ctx || !text || !out) return fail(ctx, OWQS_E_INVALID_ARG, "null pointer");
+  std::vector<owqs_cmd> cmds;
+  std::vector<int32_t> dom, ins, outs;
+  std::string err;
+  if (!parse_text(text, len, cmds, dom, ins, outs, err)) return fail(ctx, OWQS_E_INVALID_ARG, err);
+  return build_pattern(ctx, cmds.data(), cmds.size(), dom.data(), dom.size(), ins.data(), (int32_t)ins.size(),
+                       outs.data(), (int32_t)outs.size(), out);
+}
+
+void owqs_pattern_destroy(owqs_pattern *p) {
+  if (!p) return;
+  if (p->psi || p->book_mem || p->stage) {
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (p->psi) (void)hipFree(p->psi);
+    if (p->book_mem) (void)hipFree(p->book_mem);
+  }
+  if (p->stage) (void)hipFree(p->stage);
+  delete p;
+}
+
+owqs_status owqs_pattern_info(const owqs_pattern *p, int32_t *n_meas, int32_t *max_live, int32_t *n_in,
+                              int32_t *n_out, size_t *ncmds) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (n_meas) *n_meas = p->n_meas;
+  if (max_live) *max_live = p->max_live;
+  if (n_in) *n_in = (int32_t)p->inputs.size();
+  if (n_out) *n_out = (int32_t)p->outputs.size();
+  if (ncmds) *ncmds = p->cmds.size();
+  return OWQS_OK;
+}
+
+owqs_status owqs_set_mode(owqs_pattern *p, owqs_mode mode) {
+  if (!p || mode < OWQS_MODE_OWQS || mode > OWQS_MODE_EOWQS_CHECK) return OWQS_E_INVALID_ARG;
+  if (p->mode != mode) p->dirty = true;
+  p->mode = mode;
+  return OWQS_OK;
+}
+
+owqs_status owqs_set_exec(owqs_pattern *p, owqs_exec exec) {
+  if (!p || exec < OWQS_EXEC_PLAIN || exec > OWQS_EXEC_FUSED) return OWQS_E_INVALID_ARG;
+  if (p->exec != exec) p->dirty = true;
+  p->exec = exec;
+  return OWQS_OK;
+}
+
+owqs_status owqs_set_angles(owqs_pattern *p, const double *alpha, size_t n_meas) {
+  if (!p || (n_meas && !alpha)) return OWQS_E_INVALID_ARG;
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "angle count != number of M commands");
+  p->angles.assign(alpha, alpha + n_meas);
+  p->dirty = true;
+  return OWQS_OK;
+}
+
+owqs_status owqs_set_outcomes(owqs_pattern *p, const uint8_t *bits, size_t n_meas) {
+  if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
+  for (size_t k = 0; k < n_meas; ++k)
+    if (bits[k] > 1) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcomes must be 0 or 1");
+  p->outcomes.assign(bits, bits + n_meas);
+  p->dirty = true;
+  return OWQS_OK;
+}
+
+owqs_status owqs_run(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream) {
+  return run_impl(p, input, n_amps, input_on_device, stream, nullptr);
+}
+
+owqs_status owqs_run_profiled(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device,
+                              void *stream, int64_t *counts, double *ms, double *bytes) {
+  if (!counts || !ms || !bytes) return OWQS_E_INVALID_ARG;
+  Profile prof{counts, ms, bytes};
+  return run_impl(p, input, n_amps, input_on_device, stream, &prof);
+}
+
+owqs_status owqs_check(owqs_pattern *p, void *stream) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int err[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(err, p->book.err, sizeof(err), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "check");
+  if (err[0] != kErrNone) {
+    const bool zp = err[1] == kErrZeroProb;
+    return fail(p->ctx, zp ? OWQS_E_ZERO_PROB : OWQS_E_NOT_DETERMINISTIC,
+                std::string(zp ? "forced outcome with probability < 1e-10" : "|p - 1/2| > 1e-4") +
+                    " at measurement " + std::to_string(err[0]));
+  }
+  return OWQS_OK;
+}
+
+owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_on_device, void *stream) {
+  if (!p || !out) return OWQS_E_INVALID_ARG;
+  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  const size_t nout = p->outputs.size();
+  if (n_amps != (size_t(1) << nout)) return fail(p->ctx, OWQS_E_INVALID_ARG, "output size must be 2^(outputs)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
+  hipError_t e;
+  if (out_on_device) {
+    e = launch_read(p->psi, static_cast<float2 *>(out), (int)nout, p->final_where.data(), p->final_factor, sigma, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+    return OWQS_OK;
+  }
+  if (!p->stage) {
+    e = hipMalloc(reinterpret_cast<void **>(&p->stage), n_amps * sizeof(float2));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "read staging buffer");
+  }
+  e = launch_read(p->psi, p->stage, (int)nout, p->final_where.data(), p->final_factor, sigma, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, p->stage, n_amps * sizeof(float2), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+  return owqs_check(p, stream);
+}
+
+owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void *stream) {
+  if (!p || (n_meas && !probs)) return OWQS_E_INVALID_ARG;
+  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "probability count != M count");
+  if (p->ran_mode == kReduceNone) {
+    for (size_t k = 0; k < n_meas; ++k) probs[k] = 0.5;
+    return OWQS_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (n_meas) e = hipMemcpyAsync(probs, p->book.probs, n_meas * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "read probs");
+  return OWQS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/owqs.h declares, and validates patterns on a host-only context
+(device -1).  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import owqs_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "owqs.h")
+
+owqs = pytest.importorskip("paper_1604_05659_amd", reason="libowqs.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(owqs_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(owqs.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding wraps each of them
+    assert set(names) == set(owqs.EXPORTED)
+
+
+def test_cmd_struct_layout_matches_header():
+    assert ctypes.sizeof(owqs.OwqsCmd) == 40
+    assert owqs.OwqsCmd.angle.offset == 32
+
+
+@pytest.fixture(scope="module")
+def host_ctx():
+    return owqs.Context(-1)
+
+
+def test_status_strings():
+    assert owqs._lib.owqs_status_str(0) == b"OWQS_OK"
+    assert owqs._lib.owqs_status_str(-3) == b"OWQS_E_ZERO_PROB"
+
+
+def test_info_matches_structure(host_ctx):
+    for wl in (W.plain_small(), W.cluster(rows=4, cols=6), W.recognition(n_logical=5, n_j=30, n_cz=6)):
+        p = owqs.Pattern(host_ctx, wl.pattern)
+        assert p.n_meas == wl.pattern.n_meas()
+        assert p.max_live == wl.pattern.max_live()
+        assert p.n_in == len(wl.pattern.inputs)
+        assert p.n_out == len(wl.pattern.outputs)
+        assert p.ncmds == len(wl.pattern.cmds)
+
+
+def test_text_format_round_trip(host_ctx):
+    wl = W.cluster(rows=3, cols=5)
+    text = wl.pattern.to_text()
+    a = owqs.Pattern(host_ctx, wl.pattern)
+    b = owqs.Pattern(host_ctx, text=text)
+    assert (a.n_meas, a.max_live, a.n_in, a.n_out, a.ncmds) == (b.n_meas, b.max_live, b.n_in, b.n_out, b.ncmds)
+    with pytest.raises(owqs.OwqsError) as e:
+        owqs.Pattern(host_ctx, text="inputs 0\noutputs 1\nQ 3\n")
+    assert e.value.status == owqs.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("cmds,ins,outs", [
+    ([("M", 2, 0.0, (), ())], [1], [2]),                                  # D2
+    ([("M", 1, 0.0, (), ()), ("M", 1, 0.0, (), ())], [1], []),            # D1
+    ([("N", 2), ("M", 1, 0.0, (), ()), ("E", 1, 2)], [1], [2]),           # D1
+    ([("M", 1, 0.0, (), ())], [1], [1]),                                  # D3
+    ([("N", 2), ("M", 1, 0.0, (3,), ())], [1], [2]),                      # D0
+    ([("N", 2), ("N", 2)], [1], [1, 2]),                                  # D2
+    ([("N", 2)], [1], [1]),                                               # D3
+    ([("N", 2), ("X", 2, (5,)), ("M", 1, 0.0, (), ())], [1], [2]),        # D0
+])
+def test_rule_violations_rejected(host_ctx, cmds, ins, outs):
+    with pytest.raises(owqs.OwqsError) as e:
+        owqs.Pattern(host_ctx, W.Pattern(ins, outs, cmds))
+    assert e.value.status == owqs.E_PATTERN
+
+
+def test_width_limit_and_bad_arguments(host_ctx):
+    n = 36
+    cmds = [("N", q) for q in range(n)] + [("M", q, 0.0, (), ()) for q in range(n - 1)]
+    with pytest.raises(owqs.OwqsError) as e:
+        owqs.Pattern(host_ctx, W.Pattern([], [n - 1], cmds))
+    assert e.value.status == owqs.E_WIDTH
+    p = owqs.Pattern(host_ctx, W.plain_small().pattern)
+    with pytest.raises(owqs.OwqsError):
+        p.set_outcomes(np.zeros(3, np.uint8))
+    with pytest.raises(owqs.OwqsError):
+        p.set_outcomes(np.full(p.n_meas, 2, np.uint8))
+    with pytest.raises(owqs.OwqsError):
+        p.set_angles(np.zeros(p.n_meas + 1))
+    with pytest.raises(owqs.OwqsError) as e:
+        p.set_mode(7)
+    # a host-only context cannot run
+    st = owqs._lib.owqs_run(p._h, None, 1, 1, None)
+    assert st == owqs.E_STATE
+
+
+def test_random_patterns_validate(host_ctx):
+    g = np.random.default_rng(99)
+    for _ in range(50):
+        pat = W.random_pattern(g)
+        p = owqs.Pattern(host_ctx, pat)
+        assert p.max_live == pat.max_live()
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads PyTorch's HIP runtime before libowqs, so only one copy
+    of libamdhip64 is mapped (two copies break device-pointer sharing)."""
+    maps = open("/proc/self/maps").read()
+    libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(libs) == 1, libs

@@ -216,57 +216,11 @@ def test_fig5_index_set():
                     np.testing.assert_allclose(out, exp, atol=1e-15)
 
 
-def random_valid_pattern(g, max_qubits=10):
-    """A random pattern obeying D0-D3: random inputs, lazily prepared qubits,
-    E between live qubits, M with random domains over measured qubits, and
-    X/Z corrections with random domains."""
-    nin = int(g.integers(0, 3))
-    ids = list(range(max_qubits))
-    inputs = ids[:nin]
-    live = list(inputs)
-    fresh = ids[nin:]
-    measured = []
-    cmds = []
-    n_out = int(g.integers(1, 3))
-    steps = 0
-    while steps < 60:
-        steps += 1
-        r = g.random()
-        if (r < 0.25 or len(live) < 2) and fresh:
-            q = fresh.pop(0)
-            cmds.append(("N", q))
-            live.append(q)
-        elif r < 0.55 and len(live) >= 2:
-            a, b = g.choice(len(live), size=2, replace=False)
-            cmds.append(("E", live[a], live[b]))
-        elif r < 0.8 and len(live) > n_out:
-            q = live.pop(int(g.integers(len(live))))
-            def dom():
-                if not measured:
-                    return ()
-                k = int(g.integers(0, min(3, len(measured)) + 1))
-                return tuple(int(x) for x in g.choice(measured, size=k, replace=False))
-            cmds.append(("M", q, float(g.uniform(0, 2 * math.pi)), dom(), dom()))
-            measured.append(q)
-        elif live and measured:
-            q = live[int(g.integers(len(live)))]
-            k = int(g.integers(1, min(2, len(measured)) + 1))
-            d = tuple(int(x) for x in g.choice(measured, size=k, replace=False))
-            cmds.append(("X" if g.random() < 0.5 else "Z", q, d))
-        if not fresh and len(live) <= n_out:
-            break
-    while len(live) > n_out:
-        q = live.pop(0)
-        cmds.append(("M", q, float(g.uniform(0, 2 * math.pi)), (), ()))
-        measured.append(q)
-    return W.Pattern(inputs, list(live), cmds)
-
-
 def test_oracle_matches_full_tensor_brute_force():
     g = np.random.default_rng(1604)
     checked = 0
     for trial in range(120):
-        pat = random_valid_pattern(g)
+        pat = W.random_pattern(g)
         nin = len(pat.inputs)
         v = None
         if nin:
