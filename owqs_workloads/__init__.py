@@ -251,6 +251,19 @@ def random_jcz_circuit(n_logical: int, n_j: int, n_cz: int, g: np.random.Generat
     return out
 
 
+def inverse_jcz_gates(gates: Sequence[tuple]) -> List[tuple]:
+    """Gates of the inverse circuit, again using only J and CZ:
+    CZ^-1 = CZ and J(a)^-1 = diag(1, e^{-ia}) H = J(0) J(-a) J(0), listed in
+    application order (J(0) first)."""
+    out: List[tuple] = []
+    for g in reversed(list(gates)):
+        if g[0] == "J":
+            out.extend([("J", g[1], 0.0), ("J", g[1], -g[2]), ("J", g[1], 0.0)])
+        else:
+            out.append(g)
+    return out
+
+
 def circuit_to_pattern(n_logical: int, gates: Sequence[tuple], prepare_zero: bool = False,
                        name: str = "") -> Pattern:
     """Translate a J/CZ circuit into a pattern in execution order.

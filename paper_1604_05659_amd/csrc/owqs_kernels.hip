@@ -101,8 +101,17 @@ __device__ void block_partial(double acc, double *partials) {
 __global__ __launch_bounds__(kBlock) void k_finish_measure(DevBook book, unsigned nparts, int m_index,
                                                             int reduce) {
   __shared__ double wsum[kBlock / 64];
+  // nparts <= kGridCap = 16 * kBlock: issue all loads before summing
+  constexpr int kPer = kGridCap / kBlock;
+  double v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const unsigned i = threadIdx.x + unsigned(k) * kBlock;
+    v[k] = i < nparts ? book.partials[i] : 0.0;
+  }
   double t = 0.0;
-  for (unsigned i = threadIdx.x; i < nparts; i += kBlock) t += book.partials[i];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) t += v[k];
   for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) wsum[wid] = t;
