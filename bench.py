@@ -134,6 +134,110 @@ def cpu_baseline(wl_gates, psi_in, seconds_hint):
     }
 
 
+def bench_batched(owqs, torch, W, ctx, steps):
+    """512 random J/CZ patterns (live widths 8..20, 50..800 commands each):
+    one owqs_run_batch call versus the same patterns run one after another
+    with the plain executor."""
+    wls = [W.batched_random(i) for i in range(512)]
+    pats, ins, outs = [], [], []
+    for wl in wls:
+        p = owqs.Pattern(ctx, wl.pattern)
+        p.set_mode(owqs.MODE_OWQS)
+        p.set_outcomes(wl.outcomes)
+        pats.append(p)
+        ins.append(torch.as_tensor(wl.input_state).cuda())
+        outs.append(torch.empty(1 << len(wl.pattern.outputs), dtype=torch.complex64, device="cuda"))
+    n_cmds = sum(len(wl.pattern.cmds) for wl in wls)
+    widths = [p.plan_info()[0] for p in pats]
+    # batched
+    owqs.run_batch(ctx, pats, ins, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        owqs.run_batch(ctx, pats, ins, outs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    for p in pats:
+        p.check()
+    batched_out = [o.clone() for o in outs]
+    # plain, one pattern after another
+    for p in pats:
+        p.set_exec(owqs.EXEC_PLAIN)
+        p.set_graph(False)
+    for p, x, o in zip(pats[:8], ins, outs):
+        p.run(x)
+        p.read_state(o, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, x, o in zip(pats, ins, outs):
+        p.run(x)
+        p.read_state(o, check=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    diff = max(float((a - b).abs().max().item()) for a, b in zip(batched_out, outs))
+    for p in pats:
+        p.close()
+    return {
+        "workload": "512 random J/CZ patterns, live width 8..20, 50..800 commands, Gaussian inputs, OWQS",
+        "patterns": len(pats),
+        "commands": n_cmds,
+        "lds_resident": int(sum(w <= 14 for w in widths)),
+        "batched_patterns_per_s": round(len(pats) / t_batch, 1),
+        "batched_ms": round(1e3 * t_batch, 3),
+        "plain_patterns_per_s": round(len(pats) / t_plain, 1),
+        "plain_ms": round(1e3 * t_plain, 3),
+        "speedup": round(t_plain / t_batch, 2),
+        "max_abs_diff_batched_vs_plain": diff,
+    }
+
+
+def bench_recognition(owqs, torch, W, ctx, steps):
+    """Recognition problem: a 12-input J/CZ pattern (300 J, 60 CZ) on all 4096
+    basis inputs in one LDS-resident launch, versus the plain executor on a
+    sample of 64 inputs."""
+    wl = W.recognition()
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_EOWQS)
+    p.set_outcomes(wl.outcomes)
+    out = p.run_basis()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.run_basis(out=out)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    p.check()
+    p.set_exec(owqs.EXEC_PLAIN)
+    x = torch.zeros(4096, dtype=torch.complex64, device="cuda")
+    col = torch.empty(1 << 12, dtype=torch.complex64, device="cuda")
+    n_sample = 64
+    x[0] = 1
+    p.run(x)
+    p.read_state(col)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_sample):
+        x.zero_()
+        x[k] = 1
+        p.run(x)
+        p.read_state(col, check=False)
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) / n_sample
+    diff = float((col - out[n_sample - 1]).abs().max().item())
+    w, _ = p.plan_info()
+    p.close()
+    return {
+        "workload": "recognition: 12 inputs, 300 J + 60 CZ (1260 commands), all 4096 basis inputs, EOWQS",
+        "inputs": 4096,
+        "plan_width": w,
+        "batched_inputs_per_s": round(4096 / t_b, 1),
+        "batched_ms": round(1e3 * t_b, 3),
+        "plain_inputs_per_s": round(1 / t_p, 1),
+        "speedup": round(t_p * 4096 / t_b, 1),
+        "max_abs_diff_vs_plain": diff,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +245,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a pattern on a single MI355X "
@@ -231,6 +336,12 @@ def main():
             "max_abs_diff_vs_plain": diff,
             "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
         }
+
+    if not args.no_batch:
+        log("[bench] batched workload")
+        result["batched"] = bench_batched(owqs, torch, W, ctx, args.steps)
+        log("[bench] recognition workload")
+        result["recognition"] = bench_recognition(owqs, torch, W, ctx, args.steps)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -173,6 +173,46 @@ owqs_status owqs_read_state(owqs_pattern *pat, void *out_c64, size_t n_amps,
  * run (zero probability, non-determinism in EOWQS_CHECK mode). */
 owqs_status owqs_check(owqs_pattern *pat, void *stream);
 
+/* Replay the compiled plan as a captured HIP graph (default on).  The graph
+ * is captured on the first run after the plan changes and holds kernels only;
+ * the input copy stays outside it. */
+owqs_status owqs_set_graph(owqs_pattern *pat, int enable);
+
+/* Compile the plan for the current settings (if needed) and report the
+ * largest live width it reaches (plain plans: max_live; fused windows keep
+ * the width of the window's input) and its number of device steps.  Either
+ * pointer may be NULL. */
+owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps);
+
+/* Recognition problem (Sec. 1: which unitary does a pattern implement):
+ * run the pattern on the computational-basis inputs |first>, ...,
+ * |first + count - 1> and write output k (2^nout complex64) to
+ * out_c64 + k * 2^nout, so that with first = 0 and count = 2^nin the device
+ * buffer holds the unitary column by column.  Each input runs in the LDS of
+ * one workgroup: the plan width must be <= 14 (else OWQS_E_WIDTH).
+ * out_c64 (and probs, count * n_meas FP64 values or NULL) are device
+ * pointers.  Asynchronous on `stream`; errors are reported by owqs_check
+ * with the failing input's index.  Does not touch the state read by
+ * owqs_read_state. */
+owqs_status owqs_run_basis(owqs_pattern *pat, uint32_t first, uint32_t count, void *out_c64,
+                           double *probs, void *stream);
+
+/* As owqs_run_basis, for `count` arbitrary input states stored one after the
+ * other at in_c64 (count * 2^nin complex64, device memory). */
+owqs_status owqs_run_states(owqs_pattern *pat, const void *in_c64, uint32_t count, void *out_c64,
+                            double *probs, void *stream);
+
+/* Run `npat` independent patterns of one context as one batch.  inputs[i]
+ * (2^nin_i complex64; may be NULL for a pattern without inputs) and
+ * outputs[i] (2^nout_i complex64) are device pointers.  Patterns whose plan
+ * width is <= 14 run in one launch, one workgroup per pattern with its
+ * vector in LDS (they must share one mode; others of a different mode are
+ * run like the wide ones); wider patterns run their plans (as graphs) on up
+ * to four side streams joined back into `stream`.  Each pattern keeps its own
+ * probabilities and error state (owqs_read_probs, owqs_check). */
+owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat,
+                           const void *const *inputs, void *const *outputs, void *stream);
+
 /* Kernel kinds reported by owqs_run_profiled. */
 enum {
   OWQS_KIND_N = 0,      /* prepare: 16 * 2^n algorithmic bytes at live width n */

@@ -76,6 +76,12 @@ _sig = {
     "owqs_read_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
     "owqs_check": (ctypes.c_int, [_vp, _vp]),
     "owqs_read_probs": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _vp]),
+    "owqs_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t)]),
+    "owqs_run_basis": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp]),
+    "owqs_run_states": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]),
+    "owqs_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
+                                      ctypes.POINTER(_vp), _vp]),
     "owqs_run_profiled": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -181,6 +187,50 @@ class Pattern:
     def set_exec(self, exec_: int):
         self.ctx.check(_lib.owqs_set_exec(self._h, int(exec_)))
 
+    def set_graph(self, enable: bool):
+        self.ctx.check(_lib.owqs_set_graph(self._h, 1 if enable else 0))
+
+    def plan_info(self):
+        """(plan width, number of device steps) for the current settings."""
+        w = ctypes.c_int32()
+        n = ctypes.c_size_t()
+        self.ctx.check(_lib.owqs_plan_info(self._h, ctypes.byref(w), ctypes.byref(n)))
+        return w.value, n.value
+
+    def run_basis(self, first: int = 0, count: Optional[int] = None, out=None, probs=None, stream=None):
+        """Outputs for basis inputs |first> .. |first+count-1> as a
+        (count, 2^n_out) complex64 CUDA tensor (row k = output for |first+k>)."""
+        import torch
+        if count is None:
+            count = (1 << self.n_in) - first
+        if out is None:
+            out = torch.empty((count, 1 << self.n_out), dtype=torch.complex64, device=f"cuda:{self.ctx.device}")
+        self._check_out(out, count << self.n_out)
+        pp = None if probs is None else probs.data_ptr()
+        self.ctx.check(_lib.owqs_run_basis(self._h, int(first), int(count), out.data_ptr(), pp,
+                                           _stream_handle(stream)))
+        return out
+
+    def run_states(self, states, out=None, probs=None, stream=None):
+        """Outputs for a (count, 2^n_in) complex64 CUDA tensor of input states."""
+        import torch
+        if states.dtype != torch.complex64 or not states.is_cuda or not states.is_contiguous():
+            raise TypeError("states must be a contiguous complex64 CUDA tensor")
+        count = states.numel() >> self.n_in
+        if out is None:
+            out = torch.empty((count, 1 << self.n_out), dtype=torch.complex64, device=f"cuda:{self.ctx.device}")
+        self._check_out(out, count << self.n_out)
+        pp = None if probs is None else probs.data_ptr()
+        self.ctx.check(_lib.owqs_run_states(self._h, states.data_ptr(), int(count), out.data_ptr(), pp,
+                                            _stream_handle(stream)))
+        return out
+
+    @staticmethod
+    def _check_out(out, n):
+        import torch
+        if out.dtype != torch.complex64 or not out.is_cuda or not out.is_contiguous() or out.numel() != n:
+            raise TypeError("output must be a contiguous complex64 CUDA tensor of the right size")
+
     def set_angles(self, alphas: Sequence[float]):
         a = np.ascontiguousarray(alphas, np.float64)
         self.ctx.check(_lib.owqs_set_angles(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
@@ -250,6 +300,16 @@ class Pattern:
             self.close()
         except Exception:
             pass
+
+
+def run_batch(ctx: Context, patterns: Sequence["Pattern"], inputs, outputs, stream=None):
+    """Run loaded patterns as one batch (owqs_run_batch).  inputs[i] is a
+    complex64 CUDA tensor or None; outputs[i] a complex64 CUDA tensor."""
+    n = len(patterns)
+    ph = (_vp * max(n, 1))(*[p._h for p in patterns])
+    ih = (_vp * max(n, 1))(*[None if x is None else x.data_ptr() for x in inputs])
+    oh = (_vp * max(n, 1))(*[o.data_ptr() for o in outputs])
+    ctx.check(_lib.owqs_run_batch(ctx._h, ph, n, ih, oh, _stream_handle(stream)))
 
 
 def run_pattern(ctx: Context, pattern, outcomes, input_state=None, mode: int = MODE_OWQS,

@@ -1,0 +1,202 @@
+// owqs_batch.hip -- whole patterns resident in LDS (live width <= 14).
+//
+// One workgroup runs one pattern instance from its first command to the
+// read-out without touching HBM in between: the live vector (2^n complex64,
+// at most 128 KiB) sits in the 160 KiB LDS of a gfx950 CU, every command is a
+// strided pass over it separated by workgroup barriers, and the FP64
+// probability reduction of an M (Eq. 13) is a workgroup reduction, so the
+// renormalisation scale (Eq. 7) never leaves the CU.  HBM traffic is the
+// command table, the input and the output only.
+//
+// Used for batches of many small patterns (each item its own command table)
+// and for the recognition problem (one table, every computational-basis
+// input: column k of the unitary is the output for |k>).
+#include "owqs_internal.h"
+
+namespace owqs {
+namespace {
+
+constexpr int kT = 512;  // 8 wave64 per workgroup
+
+__device__ __forceinline__ uint32_t i0(uint32_t x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1)); }
+
+__device__ __forceinline__ float2 fma_c(float2 a, float2 c, float2 b, float f, float sgn) {
+  const float re = a.x + sgn * (c.x * b.x - c.y * b.y);
+  const float im = a.y + sgn * (c.x * b.y + c.y * b.x);
+  return make_float2(f * re, f * im);
+}
+__device__ __forceinline__ double n2(float2 v) { return double(v.x) * v.x + double(v.y) * v.y; }
+__device__ __forceinline__ float2 neg(float2 v) { return make_float2(-v.x, -v.y); }
+
+// Sum of v over the workgroup, the same value returned to every thread.
+__device__ double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < kT / 64; ++k) s += red[k];
+  return s;
+}
+
+__device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin, int nout, const int *where,
+                         double final_factor, float2 *lds, const float2 *__restrict__ in, int basis,
+                         float2 *__restrict__ out, double *__restrict__ probs, int reduce, int *err, int item,
+                         double *red) {
+  // item < 0: report the failing measurement index instead of the item.
+  // Input: |basis> when basis >= 0, else in[0 .. 2^nin); a pattern without
+  // inputs (nin = 0) and no input pointer starts from the empty product
+  // state (the single amplitude 1).  The host never passes in == nullptr
+  // with nin > 0.
+  const uint32_t din = 1u << nin;
+  for (uint32_t i = threadIdx.x; i < din; i += kT) {
+    float2 v;
+    if (basis >= 0) v = make_float2(i == uint32_t(basis) ? 1.f : 0.f, 0.f);
+    else if (in) v = in[i];
+    else v = make_float2(i == 0 ? 1.f : 0.f, 0.f);
+    lds[i] = v;
+  }
+  double sigma = 1.0;
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    const DevStep st = steps[s];
+    const uint32_t dim = 1u << st.n;
+    const int b = st.b0;
+    if (st.kind == DK_N) {
+      for (uint32_t i = threadIdx.x; i < dim; i += kT) lds[i + dim] = lds[i];
+    } else if (st.kind == DK_E) {
+      const int lo = st.b0 < st.b1 ? st.b0 : st.b1, hi = st.b0 < st.b1 ? st.b1 : st.b0;
+      const uint32_t set = (1u << lo) | (1u << hi);
+      for (uint32_t i = threadIdx.x; i < (dim >> 2); i += kT) {
+        const uint32_t j = i0(i0(i, lo), hi) | set;
+        lds[j] = neg(lds[j]);
+      }
+    } else if (st.kind == DK_X) {
+      for (uint32_t i = threadIdx.x; i < (dim >> 1); i += kT) {
+        const uint32_t j = i0(i, b);
+        const float2 t = lds[j];
+        lds[j] = lds[j + (1u << b)];
+        lds[j + (1u << b)] = t;
+      }
+    } else if (st.kind == DK_Z) {
+      for (uint32_t i = threadIdx.x; i < (dim >> 1); i += kT) {
+        const uint32_t j = i0(i, b) | (1u << b);
+        lds[j] = neg(lds[j]);
+      }
+    } else {  // DK_M or DK_J
+      const float f = float((reduce == kReduceRenorm ? sigma : 1.0) * st.host_factor);
+      const float2 c = st.coef;
+      double acc = 0.0;
+      if (st.kind == DK_M) {
+        const int t = st.n - 1;
+        const uint32_t half = 1u << t;
+        if (b == t) {
+          for (uint32_t j = threadIdx.x; j < half; j += kT) {
+            const float2 o = fma_c(lds[j], c, lds[j + half], f, 1.f);
+            lds[j] = o;
+            acc += n2(o);
+          }
+        } else {
+          for (uint32_t i = threadIdx.x; i < (dim >> 2); i += kT) {
+            const uint32_t j = i0(i, b), st2 = 1u << b;
+            const float2 A = lds[j], B = lds[j + st2], C = lds[j + half], D = lds[j + st2 + half];
+            const float2 o0 = fma_c(A, c, B, f, 1.f), o1 = fma_c(C, c, D, f, 1.f);
+            lds[j] = o0;
+            lds[j + st2] = o1;
+            acc += n2(o0) + n2(o1);
+          }
+        }
+      } else {
+        for (uint32_t i = threadIdx.x; i < (dim >> 1); i += kT) {
+          const uint32_t j = i0(i, b), st2 = 1u << b;
+          const float2 a = lds[j], bb = lds[j + st2];
+          float2 o0 = fma_c(a, c, bb, f, 1.f), o1 = fma_c(a, c, bb, f, -1.f);
+          if (st.pp & 1u) { const float2 t = o0; o0 = o1; o1 = t; }
+          if (st.pp & 2u) o0 = neg(o0);
+          if (st.pp & 4u) o1 = neg(o1);
+          lds[j] = o0;
+          lds[j + st2] = o1;
+          acc += n2(o0) + n2(o1);
+        }
+      }
+      if (reduce != kReduceNone) {
+        const double sum = block_sum(acc, red);
+        const double p = 0.5 * sum;
+        if (probs && threadIdx.x == 0) probs[st.m_index] = p;
+        if (reduce == kReduceRenorm) {
+          if (p < 1e-10) {
+            if (threadIdx.x == 0) { atomicMin(&err[0], item < 0 ? st.m_index : item); err[1] = kErrZeroProb; }
+            sigma = 0.0;
+          } else {
+            sigma = 1.0 / sqrt(sum);
+          }
+        } else if (fabs(p - 0.5) > 1e-4 && threadIdx.x == 0) {
+          atomicMin(&err[0], item < 0 ? st.m_index : item);
+          err[1] = kErrNotDet;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const float scale = float((reduce == kReduceRenorm ? sigma : 1.0) * final_factor);
+  const uint32_t dout = 1u << nout;
+  for (uint32_t x = threadIdx.x; x < dout; x += kT) {
+    uint32_t src = 0;
+    for (int k = 0; k < nout; ++k) src |= ((x >> k) & 1u) << where[k];
+    const float2 v = lds[src];
+    out[x] = make_float2(scale * v.x, scale * v.y);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kT) void k_lds_batch(const LdsItem *__restrict__ items, int count, int reduce) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[kT / 64];
+  for (int it = blockIdx.x; it < count; it += gridDim.x) {
+    const LdsItem *x = items + it;
+    run_item(x->steps, x->nsteps, x->nin, x->nout, x->where, x->final_factor, lds, x->in, x->basis, x->out,
+             x->probs, reduce, x->err, -1, red);
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_lds_shared(LdsItem proto, int count, int reduce, uint32_t first,
+                                                    int basis_mode, size_t probs_stride) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[kT / 64];
+  const size_t din = size_t(1) << proto.nin, dout = size_t(1) << proto.nout;
+  for (int k = blockIdx.x; k < count; k += gridDim.x) {
+    const float2 *in = basis_mode ? nullptr : proto.in + size_t(k) * din;
+    double *pr = proto.probs ? proto.probs + size_t(k) * probs_stride : nullptr;
+    run_item(proto.steps, proto.nsteps, proto.nin, proto.nout, proto.where, proto.final_factor, lds, in,
+             basis_mode ? int(first + k) : -1, proto.out + size_t(k) * dout, pr, reduce, proto.err, k, red);
+  }
+}
+
+unsigned lds_grid(int count) { return unsigned(count < 16384 ? count : 16384); }
+
+}  // namespace
+
+hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int reduce, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t bytes = sizeof(float2) << width;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lds_batch, dim3(lds_grid(count)), dim3(kT), bytes, s, items, count, reduce);
+  return hipGetLastError();
+}
+
+hipError_t launch_lds_shared(const LdsItem &proto, int count, int width, int reduce, uint32_t first,
+                             int basis_mode, size_t probs_stride, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t bytes = sizeof(float2) << width;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_shared),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lds_shared, dim3(lds_grid(count)), dim3(kT), bytes, s, proto, count, reduce, first,
+                     basis_mode, probs_stride);
+  return hipGetLastError();
+}
+
+}  // namespace owqs

@@ -14,6 +14,7 @@
 //     into its pass (with the device FP64 sigma in OWQS mode).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -31,6 +32,13 @@ using namespace owqs;
 struct owqs_ctx {
   int device = 0;
   std::string last_error;
+  // batch runs: side streams (default priority) for patterns too wide for LDS
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  owqs::LdsItem *dev_items = nullptr;  // device copy of an LDS batch's item table
+  size_t dev_items_cap = 0;
+  hipEvent_t items_done = nullptr;     // recorded after the kernel that reads dev_items
 };
 
 namespace {
@@ -73,6 +81,18 @@ struct owqs_pattern {
   std::vector<Step> steps;
   std::vector<int> final_where;  // slot of outputs[k]
   double final_factor = 1.0;
+  int plan_width = 0;            // largest live width the plan reaches
+
+  // the plan as a device command table (LDS-resident runs)
+  DevStep *dev_steps = nullptr;
+  size_t dev_steps_cap = 0;
+  bool dev_steps_valid = false;
+
+  // the plan captured as a HIP graph (kernels only; replayed by owqs_run)
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 
   // device memory
   float2 *psi = nullptr;
@@ -81,7 +101,9 @@ struct owqs_pattern {
   float2 *stage = nullptr;  // device staging for reads into host memory (2^nout)
   DevBook book{};
   bool ran = false;
+  bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)
   int ran_mode = 0;
+  int graph_reduce = -1;
 };
 
 namespace {
@@ -296,21 +318,30 @@ void compile(owqs_pattern *p) {
   p->final_where.assign(p->outputs.size(), 0);
   for (size_t k = 0; k < p->outputs.size(); ++k) p->final_where[k] = slot_of[p->outputs[k]];
   p->final_factor = pending;
+  int w = std::max<int>((int)p->inputs.size(), (int)p->outputs.size());
+  for (const Step &x : p->steps) w = std::max(w, x.n + (x.kind == S_N ? 1 : 0));
+  p->plan_width = std::max(w, 1);
   p->dirty = false;
+  p->dev_steps_valid = false;
+  if (p->graph_exec || p->graph) (void)hipDeviceSynchronize();  // a replay may still be in flight
+  if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
 }
 
-owqs_status ensure_device(owqs_pattern *p) {
+owqs_status ensure_device(owqs_pattern *p, bool need_psi = true) {
   if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
   hipError_t e = hipSetDevice(p->ctx->device);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "hipSetDevice");
   const size_t need = std::max<size_t>(size_t(1) << p->max_live, 4);
-  if (p->psi_cap < need) {
+  if (need_psi && p->psi_cap < need) {
     if (p->psi) (void)hipFree(p->psi);
     p->psi = nullptr;
     p->psi_cap = 0;
     e = hipMalloc(&p->psi, need * sizeof(float2));
     if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, std::string("state buffer: ") + hipGetErrorString(e));
     p->psi_cap = need;
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
   }
   if (!p->book_mem) {
     const size_t nprob = std::max(p->n_meas, 1);
@@ -415,6 +446,85 @@ double step_bytes(const Step &x) {
   return 0.0;
 }
 
+// Enqueue every step of the plan on `s`; with `ev`, record events around the
+// main kernel and the finishing kernel of each step (see run_impl).
+hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev) {
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
+    const Step &x = p->steps[i];
+    MeasureArgs a{};
+    unsigned grid = 0;
+    switch (x.kind) {
+      case S_N: e = launch_prepare(p->psi, x.n, s); break;
+      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
+      case S_X: e = launch_pauli_x(p->psi, x.n, x.b0, s); break;
+      case S_Z: e = launch_pauli_z(p->psi, x.n, x.b0, s); break;
+      case S_M:
+      case S_J:
+        a.coef = x.coef;
+        a.host_factor = x.host_factor;
+        a.reduce = reduce;
+        a.m_index = x.m_index;
+        a.book = p->book;
+        e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
+                          : launch_jwindow(p->psi, x.n, x.b0, a, x.pp, s, &grid);
+        break;
+      default: break;
+    }
+    if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
+    if ((x.kind == S_M || x.kind == S_J) && e == hipSuccess) e = launch_finish(a, grid, s);
+    if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
+  }
+  return e;
+}
+
+// Upload the plan as a DevStep table (for the LDS-resident kernels).
+owqs_status upload_steps(owqs_pattern *p) {
+  if (p->dev_steps_valid) return OWQS_OK;
+  std::vector<DevStep> d(p->steps.size());
+  for (size_t i = 0; i < d.size(); ++i) {
+    const Step &x = p->steps[i];
+    d[i].kind = (uint8_t)x.kind;
+    d[i].n = (uint8_t)x.n;
+    d[i].b0 = (uint8_t)x.b0;
+    d[i].b1 = (uint8_t)x.b1;
+    d[i].m_index = x.m_index;
+    d[i].coef = x.coef;
+    d[i].host_factor = (float)x.host_factor;
+    d[i].pp = (x.pp.swap ? 1u : 0u) | (x.pp.neg0 ? 2u : 0u) | (x.pp.neg1 ? 4u : 0u);
+  }
+  const size_t need = std::max<size_t>(d.size(), 1);
+  hipError_t e = hipSuccess;
+  if (p->dev_steps_cap < need) {
+    if (p->dev_steps) (void)hipFree(p->dev_steps);
+    p->dev_steps = nullptr;
+    p->dev_steps_cap = 0;
+    e = hipMalloc(&p->dev_steps, need * sizeof(DevStep));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "command table");
+    p->dev_steps_cap = need;
+  }
+  if (!d.empty()) e = hipMemcpy(p->dev_steps, d.data(), d.size() * sizeof(DevStep), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "command table upload");
+  p->dev_steps_valid = true;
+  return OWQS_OK;
+}
+
+int reduce_of(const owqs_pattern *p) {
+  return p->mode == OWQS_MODE_OWQS ? kReduceRenorm : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck : kReduceNone;
+}
+
+LdsItem lds_proto(const owqs_pattern *p) {
+  LdsItem it{};
+  it.steps = p->dev_steps;
+  it.nsteps = (int)p->steps.size();
+  it.nin = (int)p->inputs.size();
+  it.nout = (int)p->outputs.size();
+  it.final_factor = p->final_factor;
+  it.basis = -1;
+  for (size_t k = 0; k < p->final_where.size(); ++k) it.where[k] = p->final_where[k];
+  return it;
+}
+
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                      Profile *prof) {
   if (!p) return OWQS_E_INVALID_ARG;
@@ -446,37 +556,36 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
       if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
     }
     e = hipEventRecord(ev[0], s);
-  }
-  for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
-    const Step &x = p->steps[i];
-    MeasureArgs a{};
-    unsigned grid = 0;
-    switch (x.kind) {
-      case S_N: e = launch_prepare(p->psi, x.n, s); break;
-      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
-      case S_X: e = launch_pauli_x(p->psi, x.n, x.b0, s); break;
-      case S_Z: e = launch_pauli_z(p->psi, x.n, x.b0, s); break;
-      case S_M:
-      case S_J:
-        a.coef = x.coef;
-        a.host_factor = x.host_factor;
-        a.reduce = reduce;
-        a.m_index = x.m_index;
-        a.book = p->book;
-        e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
-                          : launch_jwindow(p->psi, x.n, x.b0, a, x.pp, s, &grid);
-        break;
-      default: break;
+    if (e == hipSuccess) e = launch_steps(p, reduce, s, &ev);
+  } else if (p->use_graph && !p->steps.empty()) {
+    if (!p->graph_exec) {
+      if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "capture stream");
+      }
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(p->ctx, e, "begin capture");
+      hipError_t le = launch_steps(p, reduce, p->cap_stream, nullptr);
+      e = hipStreamEndCapture(p->cap_stream, &p->graph);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+        p->graph_exec = nullptr;
+        return hip_fail(p->ctx, e, "graph capture");
+      }
+      p->graph_reduce = reduce;
     }
-    if (prof && e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s);
-    if ((x.kind == S_M || x.kind == S_J) && e == hipSuccess) e = launch_finish(a, grid, s);
-    if (prof && e == hipSuccess) e = hipEventRecord(ev[2 * i + 2], s);
+    e = hipGraphLaunch(p->graph_exec, s);
+  } else {
+    e = launch_steps(p, reduce, s, nullptr);
   }
   if (e != hipSuccess) {
     for (auto &x : ev) (void)hipEventDestroy(x);
     return hip_fail(p->ctx, e, "kernel launch");
   }
   p->ran = true;
+  p->batch_ran = false;
   p->ran_mode = reduce;
   if (prof) {
     e = hipStreamSynchronize(s);
@@ -635,7 +744,19 @@ owqs_status owqs_ctx_create(int device, owqs_ctx **out) {
   return OWQS_OK;
 }
 
-void owqs_ctx_destroy(owqs_ctx *ctx) { delete ctx; }
+void owqs_ctx_destroy(owqs_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->device >= 0 && (ctx->fork || ctx->dev_items || ctx->items_done || !ctx->side.empty())) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto st : ctx->side) (void)hipStreamDestroy(st);
+    for (auto ev : ctx->join) (void)hipEventDestroy(ev);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->items_done) (void)hipEventDestroy(ctx->items_done);
+    if (ctx->dev_items) (void)hipFree(ctx->dev_items);
+  }
+  delete ctx;
+}
 
 const char *owqs_last_error(const owqs_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
 
@@ -660,13 +781,17 @@ owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, 
 
 void owqs_pattern_destroy(owqs_pattern *p) {
   if (!p) return;
-  if (p->psi || p->book_mem || p->stage) {
+  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->psi) (void)hipFree(p->psi);
     if (p->book_mem) (void)hipFree(p->book_mem);
   }
   if (p->stage) (void)hipFree(p->stage);
+  if (p->dev_steps) (void)hipFree(p->dev_steps);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
 }
 
@@ -724,9 +849,194 @@ owqs_status owqs_run_profiled(owqs_pattern *p, const void *input, size_t n_amps,
   return run_impl(p, input, n_amps, input_on_device, stream, &prof);
 }
 
+owqs_status owqs_set_graph(owqs_pattern *p, int enable) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  p->use_graph = enable != 0;
+  return OWQS_OK;
+}
+
+owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (p->dirty) compile(p);
+  if (plan_width) *plan_width = p->plan_width;
+  if (nsteps) *nsteps = p->steps.size();
+  return OWQS_OK;
+}
+
+static owqs_status run_shared(owqs_pattern *p, const void *in, uint32_t first, uint32_t count, void *out,
+                              double *probs, void *stream, int basis_mode) {
+  // every item runs the pattern's one command table in its own workgroup
+  if (!p || !out) return OWQS_E_INVALID_ARG;
+  if (count == 0) return OWQS_OK;
+  if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context");
+  if (basis_mode && (p->inputs.size() > 31 || uint64_t(first) + count > (uint64_t(1) << p->inputs.size())))
+    return fail(p->ctx, OWQS_E_INVALID_ARG, "basis range outside 2^(number of inputs)");
+  if (!basis_mode && !in && !p->inputs.empty()) return fail(p->ctx, OWQS_E_INVALID_ARG, "null inputs");
+  owqs_status st = ensure_device(p, false);
+  if (st != OWQS_OK) return st;
+  if (p->dirty) compile(p);
+  if (p->plan_width > kLdsMaxWidth)
+    return fail(p->ctx, OWQS_E_WIDTH, "plan width " + std::to_string(p->plan_width) + " exceeds the LDS limit 14");
+  st = upload_steps(p);
+  if (st != OWQS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_init(p->psi, p->book, s, 0);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "init");
+  LdsItem proto = lds_proto(p);
+  proto.in = static_cast<const float2 *>(in);
+  if (!basis_mode && !in) {
+    // only reachable with nin = 0 (checked above): every item starts from the
+    // empty product state
+    basis_mode = 1;
+    first = 0;
+    if (count != 1) return fail(p->ctx, OWQS_E_INVALID_ARG, "without inputs a pattern has a single input state");
+  }
+  proto.out = static_cast<float2 *>(out);
+  proto.probs = probs;
+  const int reduce = reduce_of(p);
+  proto.err = p->book.err;
+  e = launch_lds_shared(proto, (int)count, p->plan_width, reduce, first, basis_mode, (size_t)p->n_meas, s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "LDS kernel");
+  p->ran = false;  // the pattern's own state buffer was not written
+  p->batch_ran = true;
+  return OWQS_OK;
+}
+
+owqs_status owqs_run_basis(owqs_pattern *p, uint32_t first, uint32_t count, void *out_c64, double *probs,
+                           void *stream) {
+  return run_shared(p, nullptr, first, count, out_c64, probs, stream, 1);
+}
+
+owqs_status owqs_run_states(owqs_pattern *p, const void *in_c64, uint32_t count, void *out_c64, double *probs,
+                            void *stream) {
+  return run_shared(p, in_c64, 0, count, out_c64, probs, stream, 0);
+}
+
+owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat, const void *const *inputs,
+                           void *const *outputs, void *stream) {
+  if (!ctx || (npat && (!pats || !outputs))) return fail(ctx, OWQS_E_INVALID_ARG, "null argument");
+  if (ctx->device < 0) return fail(ctx, OWQS_E_STATE, "host-only context");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // split: LDS-resident items (one workgroup each) and wide patterns
+  std::vector<LdsItem> items;
+  std::vector<size_t> wide;
+  int width = 1, reduce = -1;
+  {
+    std::vector<const owqs_pattern *> seen(pats, pats + npat);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+      return fail(ctx, OWQS_E_INVALID_ARG, "a pattern appears twice in one batch");
+  }
+  for (size_t i = 0; i < npat; ++i) {
+    owqs_pattern *p = pats[i];
+    if (!p || p->ctx != ctx || !outputs[i]) return fail(ctx, OWQS_E_INVALID_ARG, "pattern " + std::to_string(i));
+    if (!p->inputs.empty() && (!inputs || !inputs[i])) return fail(ctx, OWQS_E_INVALID_ARG, "null input");
+    if (p->dirty) compile(p);
+    owqs_status st = ensure_device(p, p->plan_width > kLdsMaxWidth);
+    if (st != OWQS_OK) return st;
+    if (p->plan_width <= kLdsMaxWidth && (reduce < 0 || reduce == reduce_of(p))) {
+      reduce = reduce_of(p);
+      st = upload_steps(p);
+      if (st != OWQS_OK) return st;
+      e = launch_init(p->psi, p->book, s, 0);  // clears the pattern's error slot
+      if (e != hipSuccess) return hip_fail(ctx, e, "init");
+      LdsItem it = lds_proto(p);
+      it.in = inputs ? static_cast<const float2 *>(inputs[i]) : nullptr;
+      if (p->inputs.empty() && !it.in) it.basis = 0;  // empty product state
+      it.out = static_cast<float2 *>(outputs[i]);
+      it.probs = p->book.probs;
+      it.err = p->book.err;
+      items.push_back(it);
+      width = std::max(width, p->plan_width);
+      p->ran = false;
+      p->batch_ran = true;
+    } else {
+      wide.push_back(i);
+    }
+  }
+  // wide patterns go to the side streams, longest plan first
+  std::sort(wide.begin(), wide.end(), [&](size_t a, size_t b) {
+    return (pats[a]->steps.size() << pats[a]->plan_width) > (pats[b]->steps.size() << pats[b]->plan_width);
+  });
+  const size_t nside = std::min<size_t>(wide.size(), 4);
+  if (nside) {
+    if (!ctx->fork) {
+      e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(ctx, e, "event");
+    }
+    while (ctx->side.size() < 4) {
+      hipStream_t st;
+      hipEvent_t ev;
+      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(ctx, e, "side stream");
+      ctx->side.push_back(st);
+      ctx->join.push_back(ev);
+    }
+    e = hipEventRecord(ctx->fork, s);
+    for (size_t k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamWaitEvent(ctx->side[k], ctx->fork, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fork");
+    for (size_t j = 0; j < wide.size(); ++j) {
+      owqs_pattern *p = pats[wide[j]];
+      hipStream_t st = ctx->side[j % nside];
+      owqs_status r = run_impl(p, inputs ? inputs[wide[j]] : nullptr, size_t(1) << p->inputs.size(), 1, st,
+                               nullptr);
+      if (r != OWQS_OK) return r;
+      r = owqs_read_state(p, outputs[wide[j]], size_t(1) << p->outputs.size(), 1, st);
+      if (r != OWQS_OK) return r;
+    }
+  }
+  if (!items.empty()) {
+    const size_t bytes = items.size() * sizeof(LdsItem);
+    // the previous batch kernel may still read the item table
+    if (ctx->items_done) {
+      e = hipEventSynchronize(ctx->items_done);
+      if (e != hipSuccess) return hip_fail(ctx, e, "previous batch");
+    }
+    if (ctx->dev_items_cap < items.size()) {
+      if (ctx->dev_items) (void)hipFree(ctx->dev_items);
+      ctx->dev_items = nullptr;
+      ctx->dev_items_cap = 0;
+      e = hipMalloc(&ctx->dev_items, bytes);
+      if (e != hipSuccess) return fail(ctx, OWQS_E_NOMEM, "batch item table");
+      ctx->dev_items_cap = items.size();
+    }
+    // longest first, so the biggest items start early
+    std::vector<size_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      return ((size_t)items[a].nsteps << std::max(items[a].nin, items[a].nout)) >
+             ((size_t)items[b].nsteps << std::max(items[b].nin, items[b].nout));
+    });
+    std::vector<LdsItem> sorted(items.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+    e = hipMemcpyAsync(ctx->dev_items, sorted.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table is released on return
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch item upload");
+    e = launch_lds_batch(ctx->dev_items, (int)sorted.size(), width, reduce, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "LDS batch kernel");
+    if (!ctx->items_done) {
+      e = hipEventCreateWithFlags(&ctx->items_done, hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(ctx, e, "event");
+    }
+    e = hipEventRecord(ctx->items_done, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "event");
+  }
+  if (nside) {
+    for (size_t k = 0; k < nside && e == hipSuccess; ++k) {
+      e = hipEventRecord(ctx->join[k], ctx->side[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->join[k], 0);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "join");
+  }
+  return OWQS_OK;
+}
+
 owqs_status owqs_check(owqs_pattern *p, void *stream) {
   if (!p) return OWQS_E_INVALID_ARG;
-  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (!p->ran && !p->batch_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int err[2] = {0, 0};
   hipError_t e = hipMemcpyAsync(err, p->book.err, sizeof(err), hipMemcpyDeviceToHost, s);
@@ -736,7 +1046,7 @@ owqs_status owqs_check(owqs_pattern *p, void *stream) {
     const bool zp = err[1] == kErrZeroProb;
     return fail(p->ctx, zp ? OWQS_E_ZERO_PROB : OWQS_E_NOT_DETERMINISTIC,
                 std::string(zp ? "forced outcome with probability < 1e-10" : "|p - 1/2| > 1e-4") +
-                    " at measurement " + std::to_string(err[0]));
+                    " at measurement (or batch item) " + std::to_string(err[0]));
   }
   return OWQS_OK;
 }
@@ -767,9 +1077,9 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
 
 owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void *stream) {
   if (!p || (n_meas && !probs)) return OWQS_E_INVALID_ARG;
-  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (!p->ran && !p->batch_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
   if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "probability count != M count");
-  if (p->ran_mode == kReduceNone) {
+  if (reduce_of(p) == kReduceNone) {
     for (size_t k = 0; k < n_meas; ++k) probs[k] = 0.5;
     return OWQS_OK;
   }

@@ -44,6 +44,32 @@ struct PostPerm {
   int swap, neg0, neg1;
 };
 
+// One compiled step in device memory, for the kernels that walk a command
+// table themselves (whole pattern resident in LDS).  24 bytes.
+struct DevStep {
+  uint8_t kind, n, b0, b1;  // step kind, live width before it, slots
+  int32_t m_index;          // M / window: index of the measurement
+  float2 coef;              // M / window: (-1)^o e^{-i theta}
+  float host_factor;        // M / window: (1/sqrt 2)^(pending N)
+  uint32_t pp;              // window: bit 0 swap, bit 1 negate 0, bit 2 negate 1
+};
+
+enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5 };
+
+// One pattern of an LDS-resident batch.
+struct LdsItem {
+  const DevStep *steps;
+  const float2 *in;     // 2^nin amplitudes (ignored for basis inputs)
+  float2 *out;          // 2^nout amplitudes
+  double *probs;        // n_meas entries, or null
+  int *err;             // {first failing M (or item), kind}: this item's error slot
+  double final_factor;
+  int nsteps, nin, nout, basis;  // basis >= 0: input is |basis>
+  int where[kWhereMax];
+};
+
+constexpr int kLdsMaxWidth = 14;  // 2^14 complex64 = 128 KiB of the 160 KiB LDS
+
 // ---- launchers (owqs_kernels.hip); all enqueue on `s` and return the launch status
 // Reset the book (sigma = 1, no error); with set_one also psi[0] = 1
 // (the empty product state when the pattern has no inputs).
@@ -61,5 +87,18 @@ hipError_t launch_jwindow(float2 *psi, int n, int b, const MeasureArgs &a, PostP
 hipError_t launch_finish(const MeasureArgs &a, unsigned nparts, hipStream_t s);
 hipError_t launch_read(const float2 *psi, float2 *out, int nout, const int *where, double host_factor,
                        const double *sigma, hipStream_t s);
+
+
+// ---- owqs_batch.hip
+// Run `count` items, each a whole pattern resident in the LDS of one
+// workgroup (live width <= kLdsMaxWidth).  `width` is the largest live width
+// of any item (sets the dynamic LDS size).  Errors (zero probability, failed
+// determinism check) go to each item's err slot: err[0] = first failing M.
+hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int reduce, hipStream_t s);
+// Items share one command table and differ only by input: item k runs on
+// basis state |first + k> (basis_mode = 1) or on in + k * 2^nin, and writes
+// out + k * 2^nout.  Errors go to proto.err with err[0] = first failing item.
+hipError_t launch_lds_shared(const LdsItem &proto, int count, int width, int reduce, uint32_t first,
+                             int basis_mode, size_t probs_stride, hipStream_t s);
 
 }  // namespace owqs
