@@ -213,6 +213,28 @@ owqs_status owqs_run_states(owqs_pattern *pat, const void *in_c64, uint32_t coun
 owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat,
                            const void *const *inputs, void *const *outputs, void *stream);
 
+/* Gradient of an output observable with respect to the M angles, for
+ * `batch` angle sets at once (adjoint method).  The loss of set b is
+ * L_b = sum_i <Z_{obs[i]}> on the output state (obs[i] indexes the outputs
+ * list), evaluated with fixed probabilities 1/2 (EOWQS, Sec. 4.5): the
+ * pattern must have a flow for this to be the OWQS loss too.  Every pattern
+ * whose N-E-M-X windows (the translation of J gates) come after a prefix
+ * without measurements is supported; the plan is switched to FUSED.
+ *   input_c64: device, 2^nin complex64 shared by all sets (NULL if nin = 0)
+ *   alpha:     host, batch * n_meas radians (row b = set b, M order)
+ *   loss:      device, batch FP64
+ *   grad:      device, batch * n_meas FP64, dL_b/dalpha_m (0 for M commands
+ *              outside windows)
+ *   ckpt_stride: windows per checkpoint segment (0 = 16); the forward pass
+ *              stores the live vectors at segment starts, and the backward
+ *              pass recomputes each segment from its checkpoint.
+ * Asynchronous on `stream`; device memory of about
+ * (2 + segments + ckpt_stride) * batch * 2^width * 8 bytes stays allocated
+ * with the pattern. */
+owqs_status owqs_adjoint(owqs_pattern *pat, const void *input_c64, const double *alpha, size_t batch,
+                         const int32_t *obs, int32_t nobs, double *loss, double *grad,
+                         int32_t ckpt_stride, void *stream);
+
 /* Kernel kinds reported by owqs_run_profiled. */
 enum {
   OWQS_KIND_N = 0,      /* prepare: 16 * 2^n algorithmic bytes at live width n */

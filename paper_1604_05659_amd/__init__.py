@@ -82,6 +82,8 @@ _sig = {
     "owqs_run_states": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
                                       ctypes.POINTER(_vp), _vp]),
+    "owqs_adjoint": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _i32p,
+                                    ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp]),
     "owqs_run_profiled": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -231,6 +233,29 @@ class Pattern:
         if out.dtype != torch.complex64 or not out.is_cuda or not out.is_contiguous() or out.numel() != n:
             raise TypeError("output must be a contiguous complex64 CUDA tensor of the right size")
 
+    def adjoint(self, alphas, obs: Optional[Sequence[int]] = None, psi_in=None, ckpt_stride: int = 0,
+                stream=None):
+        """Loss sum_i <Z_obs[i]> (EOWQS) and its gradient for a (B, n_meas)
+        array of M angles: returns (loss (B,), grad (B, n_meas)) as float64
+        CUDA tensors."""
+        import torch
+        a = np.ascontiguousarray(np.asarray(alphas, np.float64).reshape(-1, self.n_meas))
+        batch = a.shape[0]
+        obs_l = list(range(self.n_out)) if obs is None else [int(o) for o in obs]
+        ob = np.array(obs_l or [0], np.int32)
+        dev = f"cuda:{self.ctx.device}"
+        loss = torch.empty(batch, dtype=torch.float64, device=dev)
+        grad = torch.empty((batch, self.n_meas), dtype=torch.float64, device=dev)
+        ptr = None
+        if psi_in is not None:
+            if psi_in.dtype != torch.complex64 or not psi_in.is_cuda or not psi_in.is_contiguous():
+                raise TypeError("input must be a contiguous complex64 CUDA tensor")
+            ptr = psi_in.data_ptr()
+        self.ctx.check(_lib.owqs_adjoint(
+            self._h, ptr, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), batch, ob.ctypes.data_as(_i32p),
+            len(obs_l), loss.data_ptr(), grad.data_ptr(), int(ckpt_stride), _stream_handle(stream)))
+        return loss, grad
+
     def set_angles(self, alphas: Sequence[float]):
         a = np.ascontiguousarray(alphas, np.float64)
         self.ctx.check(_lib.owqs_set_angles(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
@@ -310,6 +335,41 @@ def run_batch(ctx: Context, patterns: Sequence["Pattern"], inputs, outputs, stre
     ih = (_vp * max(n, 1))(*[None if x is None else x.data_ptr() for x in inputs])
     oh = (_vp * max(n, 1))(*[o.data_ptr() for o in outputs])
     ctx.check(_lib.owqs_run_batch(ctx._h, ph, n, ih, oh, _stream_handle(stream)))
+
+
+def _make_loss_function():
+    import torch
+
+    class PatternLoss(torch.autograd.Function):
+        """L_b = sum_i <Z_obs[i]> of the pattern's output for each row b of
+        the (B, n_meas) angle tensor; the gradient comes from owqs_adjoint
+        (computed together with the loss in the forward call)."""
+
+        @staticmethod
+        def forward(ctx, alphas, pattern, obs, psi_in, ckpt_stride):
+            a = alphas.detach().to("cpu", torch.float64).numpy()
+            loss, grad = pattern.adjoint(a, obs, psi_in, ckpt_stride)
+            ctx.save_for_backward(grad)
+            ctx.in_dtype = alphas.dtype
+            ctx.in_device = alphas.device
+            return loss.to(device=alphas.device, dtype=alphas.dtype)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            g = gout.to(grad.device, grad.dtype)[:, None] * grad
+            return g.to(device=ctx.in_device, dtype=ctx.in_dtype), None, None, None, None
+
+    return PatternLoss
+
+
+PatternLoss = _make_loss_function()
+
+
+def pattern_loss(pattern: "Pattern", alphas, obs=None, psi_in=None, ckpt_stride: int = 0):
+    """Differentiable loss: ``pattern_loss(p, alphas).sum().backward()`` fills
+    ``alphas.grad`` with the adjoint gradient."""
+    return PatternLoss.apply(alphas, pattern, obs, psi_in, ckpt_stride)
 
 
 def run_pattern(ctx: Context, pattern, outcomes, input_state=None, mode: int = MODE_OWQS,

@@ -1,0 +1,256 @@
+// owqs_adjoint.hip -- batched forward and adjoint sweeps for the gradient of
+// an output observable with respect to the measurement angles.
+//
+// B angle sets of one pattern run side by side: the state buffer holds B
+// vectors of `stride` amplitudes each, and every kernel takes the set as
+// blockIdx.y.  The plan is the fused one: after a prefix without parameters
+// (preparations), every step is a window (N w; E u w; M u; X/Z on w) or a
+// Pauli / controlled-Z step.  With fixed probability 1/2 (Sec. 4.5) a window
+// is the unitary P f [[1, c], [1, -c]] on one slot (f = 1/sqrt 2, c =
+// (-1)^o e^{-i theta}, Eqs. 11-12, P the folded corrections) and E, X, Z are
+// self-adjoint, so the reverse sweep carries the adjoint state
+// lambda = U_{>k}^dagger (W psi_final) back through the windows:
+//   dL/dtheta_k = 2 Re <lambda_k | dW_k/dtheta psi_{k-1}>,
+//   dW/dtheta (a, b) = P f (-i c b, i c b),
+//   lambda_{k-1} = W_k^dagger lambda_k = f (mu0 + mu1, conj(c) (mu0 - mu1)),
+//   mu = P^T lambda_k,
+// and dtheta/dalpha = (-1)^s (Eq. 2).  Gradient partials are FP64 per block;
+// one reduction kernel sums them in block order at the end.
+#include "owqs_internal.h"
+
+namespace owqs {
+namespace {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ uint64_t j0(uint64_t x, int b) {
+  return ((x >> b) << (b + 1)) | (x & ((uint64_t(1) << b) - 1));
+}
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+#define SET_LOOP(count)                                                                          \
+  float2 *const v = psi + size_t(blockIdx.y) * stride;                                            \
+  for (uint64_t i = uint64_t(blockIdx.x) * kB + threadIdx.x; i < (count); i += uint64_t(gridDim.x) * kB)
+
+// Every set starts from the same input: in[0 .. din), or the empty product
+// state (the single amplitude 1) when in is null (then din = 1).
+__global__ __launch_bounds__(kB) void k_b_init(float2 *psi, size_t stride, uint64_t din, const float2 *in) {
+  SET_LOOP(din) v[i] = in ? in[i] : make_float2(i == 0 ? 1.f : 0.f, 0.f);
+}
+
+__global__ __launch_bounds__(kB) void k_b_prepare(float2 *psi, size_t stride, uint64_t dim) {
+  SET_LOOP(dim) v[i + dim] = v[i];
+}
+
+__global__ __launch_bounds__(kB) void k_b_cz(float2 *psi, size_t stride, uint64_t quarter, int lo, int hi) {
+  SET_LOOP(quarter) {
+    const uint64_t j = j0(j0(i, lo), hi) | (uint64_t(1) << lo) | (uint64_t(1) << hi);
+    v[j] = make_float2(-v[j].x, -v[j].y);
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_b_x(float2 *psi, size_t stride, uint64_t half, int b) {
+  SET_LOOP(half) {
+    const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
+    const float2 t = v[j];
+    v[j] = v[k];
+    v[k] = t;
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_b_z(float2 *psi, size_t stride, uint64_t half, int b) {
+  SET_LOOP(half) {
+    const uint64_t j = j0(i, b) | (uint64_t(1) << b);
+    v[j] = make_float2(-v[j].x, -v[j].y);
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_b_window(float2 *psi, size_t stride, uint64_t half, int b,
+                                                  const float2 *coefs, float f, PostPerm pp) {
+  const float2 c = coefs[blockIdx.y];
+  SET_LOOP(half) {
+    const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
+    const float2 a = v[j], cb = cmulf(c, v[k]);
+    float2 o0 = make_float2(f * (a.x + cb.x), f * (a.y + cb.y));
+    float2 o1 = make_float2(f * (a.x - cb.x), f * (a.y - cb.y));
+    if (pp.swap) { const float2 t = o0; o0 = o1; o1 = t; }
+    if (pp.neg0) o0 = make_float2(-o0.x, -o0.y);
+    if (pp.neg1) o1 = make_float2(-o1.x, -o1.y);
+    v[j] = o0;
+    v[k] = o1;
+  }
+}
+
+// Adjoint of one window: psi_in = the window's input (read only), lam = the
+// adjoint state after the window (updated in place to the state before it).
+// partials[set * gridDim.x + block] = this block's sum of
+// 2 Re <lam | dW/dtheta psi_in>.
+__global__ __launch_bounds__(kB) void k_b_window_adj(const float2 *__restrict__ psi_in, float2 *__restrict__ lam,
+                                                      size_t stride, uint64_t half, int b, const float2 *coefs,
+                                                      float f, PostPerm pp, double *partials) {
+  __shared__ double red[kB / 64];
+  const float2 c = coefs[blockIdx.y];
+  const float2 *x = psi_in + size_t(blockIdx.y) * stride;
+  float2 *l = lam + size_t(blockIdx.y) * stride;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kB + threadIdx.x; i < half; i += uint64_t(gridDim.x) * kB) {
+    const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
+    const float2 cb = cmulf(c, x[k]);                       // c b
+    // dW/dtheta (a, b) before the corrections: (-i c b, +i c b)
+    float2 d0 = make_float2(f * cb.y, -f * cb.x), d1 = make_float2(-f * cb.y, f * cb.x);
+    if (pp.swap) { const float2 t = d0; d0 = d1; d1 = t; }
+    if (pp.neg0) d0 = make_float2(-d0.x, -d0.y);
+    if (pp.neg1) d1 = make_float2(-d1.x, -d1.y);
+    const float2 l0 = l[j], l1 = l[k];
+    acc += 2.0 * (double(l0.x) * d0.x + double(l0.y) * d0.y + double(l1.x) * d1.x + double(l1.y) * d1.y);
+    // mu = P^T lam: undo the negations, then the swap
+    float2 m0 = pp.neg0 ? make_float2(-l0.x, -l0.y) : l0;
+    float2 m1 = pp.neg1 ? make_float2(-l1.x, -l1.y) : l1;
+    if (pp.swap) { const float2 t = m0; m0 = m1; m1 = t; }
+    const float2 s = make_float2(m0.x + m1.x, m0.y + m1.y), dlt = make_float2(m0.x - m1.x, m0.y - m1.y);
+    const float2 cc = make_float2(c.x, -c.y);
+    const float2 cd = cmulf(cc, dlt);
+    l[j] = make_float2(f * s.x, f * s.y);
+    l[k] = make_float2(f * cd.x, f * cd.y);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kB / 64; ++q) t += red[q];
+    partials[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+struct ObsBits {
+  int n;
+  int bit[kWhereMax];
+};
+
+// Loss L = ff2 * sum_x W(x) |psi(x)|^2, W(x) = sum_k (1 - 2 bit_{obs_k}(x));
+// lam = ff2 * W * psi.  partials[set * gridDim.x + block].
+__global__ __launch_bounds__(kB) void k_b_loss(const float2 *__restrict__ psi, float2 *__restrict__ lam,
+                                                size_t stride, uint64_t dim, ObsBits ob, double ff2,
+                                                double *partials) {
+  __shared__ double red[kB / 64];
+  const float2 *x = psi + size_t(blockIdx.y) * stride;
+  float2 *l = lam + size_t(blockIdx.y) * stride;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kB + threadIdx.x; i < dim; i += uint64_t(gridDim.x) * kB) {
+    int wsum = 0;
+    for (int k = 0; k < ob.n; ++k) wsum += 1 - 2 * int((i >> ob.bit[k]) & 1);
+    const float2 a = x[i];
+    acc += ff2 * wsum * (double(a.x) * a.x + double(a.y) * a.y);
+    const float w = float(ff2 * wsum);
+    l[i] = make_float2(w * a.x, w * a.y);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kB / 64; ++q) t += red[q];
+    partials[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// out[r * out_stride + out_col[q]] = scale[q] * sum of partials[r][q][0..nblk)
+// for rows r (sets) and columns q (windows); one thread per (r, q).
+__global__ __launch_bounds__(kB) void k_b_reduce(const double *__restrict__ partials, int nq, int nsets, int nblk,
+                                                  const int *out_col, const double *scale, double *out,
+                                                  size_t out_stride) {
+  const int id = blockIdx.x * kB + threadIdx.x;
+  if (id >= nq * nsets) return;
+  const int q = id / nsets, r = id % nsets;
+  const double *p = partials + (size_t(q) * nsets + r) * nblk;
+  double t = 0.0;
+  for (int k = 0; k < nblk; ++k) t += p[k];
+  out[size_t(r) * out_stride + out_col[q]] = scale[q] * t;
+}
+
+unsigned blocks_for(uint64_t count) {
+  uint64_t g = (count + kB - 1) / kB;
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  return unsigned(g);
+}
+
+}  // namespace
+
+hipError_t launch_b_step(const DevStep &st, float2 *psi, size_t stride, int nsets, const float2 *coefs,
+                         hipStream_t s) {
+  const uint64_t dim = uint64_t(1) << st.n;
+  switch (st.kind) {
+    case DK_N:
+      hipLaunchKernelGGL(k_b_prepare, dim3(blocks_for(dim), nsets), dim3(kB), 0, s, psi, stride, dim);
+      break;
+    case DK_E: {
+      const int lo = st.b0 < st.b1 ? st.b0 : st.b1, hi = st.b0 < st.b1 ? st.b1 : st.b0;
+      hipLaunchKernelGGL(k_b_cz, dim3(blocks_for(dim >> 2), nsets), dim3(kB), 0, s, psi, stride, dim >> 2, lo, hi);
+      break;
+    }
+    case DK_X:
+      hipLaunchKernelGGL(k_b_x, dim3(blocks_for(dim >> 1), nsets), dim3(kB), 0, s, psi, stride, dim >> 1,
+                         int(st.b0));
+      break;
+    case DK_Z:
+      hipLaunchKernelGGL(k_b_z, dim3(blocks_for(dim >> 1), nsets), dim3(kB), 0, s, psi, stride, dim >> 1,
+                         int(st.b0));
+      break;
+    case DK_J: {
+      PostPerm pp{int(st.pp & 1u), int((st.pp >> 1) & 1u), int((st.pp >> 2) & 1u)};
+      hipLaunchKernelGGL(k_b_window, dim3(blocks_for(dim >> 1), nsets), dim3(kB), 0, s, psi, stride, dim >> 1,
+                         int(st.b0), coefs, st.host_factor, pp);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_b_init(float2 *psi, size_t stride, int nsets, int nin, const float2 *in, hipStream_t s) {
+  const uint64_t din = uint64_t(1) << nin;
+  hipLaunchKernelGGL(k_b_init, dim3(blocks_for(din), nsets), dim3(kB), 0, s, psi, stride, din, in);
+  return hipGetLastError();
+}
+
+unsigned adj_blocks(int n) { return blocks_for((uint64_t(1) << n) >> 1); }
+
+hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *lam, size_t stride, int nsets,
+                               const float2 *coefs, double *partials, hipStream_t s) {
+  const uint64_t half = (uint64_t(1) << st.n) >> 1;
+  PostPerm pp{int(st.pp & 1u), int((st.pp >> 1) & 1u), int((st.pp >> 2) & 1u)};
+  hipLaunchKernelGGL(k_b_window_adj, dim3(blocks_for(half), nsets), dim3(kB), 0, s, psi_in, lam, stride, half,
+                     int(st.b0), coefs, st.host_factor, pp, partials);
+  return hipGetLastError();
+}
+
+unsigned loss_blocks(int n) { return blocks_for(uint64_t(1) << n); }
+
+hipError_t launch_b_loss(const float2 *psi, float2 *lam, size_t stride, int nsets, int n, const int *obs_bits,
+                         int nobs, double ff2, double *partials, hipStream_t s) {
+  ObsBits ob{};
+  ob.n = nobs;
+  for (int k = 0; k < nobs; ++k) ob.bit[k] = obs_bits[k];
+  const uint64_t dim = uint64_t(1) << n;
+  hipLaunchKernelGGL(k_b_loss, dim3(blocks_for(dim), nsets), dim3(kB), 0, s, psi, lam, stride, dim, ob, ff2,
+                     partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_reduce(const double *partials, int nq, int nsets, int nblk, const int *out_col,
+                           const double *scale, double *out, size_t out_stride, hipStream_t s) {
+  const int n = nq * nsets;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_reduce, dim3((n + kB - 1) / kB), dim3(kB), 0, s, partials, nq, nsets, nblk, out_col, scale,
+                     out, out_stride);
+  return hipGetLastError();
+}
+
+}  // namespace owqs

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -53,6 +54,7 @@ struct Step {
   double host_factor;
   int m_index;
   PostPerm pp;
+  int sig_s, sig_t, outcome;  // M / window: resolved signals and forced outcome
 };
 
 struct Cmd {
@@ -100,6 +102,13 @@ struct owqs_pattern {
   void *book_mem = nullptr;
   float2 *stage = nullptr;  // device staging for reads into host memory (2^nout)
   DevBook book{};
+  // adjoint buffers (owqs_adjoint), grown on demand
+  void *adj_mem = nullptr;
+  size_t adj_cap = 0;
+  std::vector<float2> adj_coefs;   // host copies kept alive for the async uploads
+  std::vector<int> adj_cols;
+  std::vector<double> adj_scale;
+
   bool ran = false;
   bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)
   int ran_mode = 0;
@@ -198,8 +207,11 @@ void compile(owqs_pattern *p) {
   p->steps.clear();
   const size_t nc = p->cmds.size();
 
+  int last_s = 0, last_t = 0;
   auto coef_of = [&](const Cmd &c, int mi, int &o_out) {
     const int s = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
+    last_s = s;
+    last_t = t;
     const double theta = (s ? -p->angles[mi] : p->angles[mi]) + (t ? M_PI : 0.0);  // Eq. 2
     const int o = p->outcomes[mi] & 1;
     double cr = std::cos(theta), ci = -std::sin(theta);  // e^{-i theta}  (Eqs. 11-12)
@@ -224,6 +236,9 @@ void compile(owqs_pattern *p) {
           st.n = n;
           st.b0 = slot_of[u];
           st.coef = coef_of(mm, m, o);
+          st.sig_s = last_s;
+          st.sig_t = last_t;
+          st.outcome = o;
           st.host_factor = pending * r2;
           st.m_index = m;
           outcome_of[u] = o;
@@ -294,6 +309,9 @@ void compile(owqs_pattern *p) {
         st.n = n;
         st.b0 = slot_of[c.q0];
         st.coef = coef_of(c, m, o);
+        st.sig_s = last_s;
+        st.sig_t = last_t;
+        st.outcome = o;
         st.host_factor = pending;
         st.m_index = m;
         p->steps.push_back(st);
@@ -781,7 +799,7 @@ owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, 
 
 void owqs_pattern_destroy(owqs_pattern *p) {
   if (!p) return;
-  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec) {
+  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->psi) (void)hipFree(p->psi);
@@ -789,6 +807,7 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   }
   if (p->stage) (void)hipFree(p->stage);
   if (p->dev_steps) (void)hipFree(p->dev_steps);
+  if (p->adj_mem) (void)hipFree(p->adj_mem);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -1031,6 +1050,162 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "join");
   }
+  return OWQS_OK;
+}
+
+owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *alpha, size_t batch,
+                         const int32_t *obs, int32_t nobs, double *loss, double *grad, int32_t ckpt_stride,
+                         void *stream) {
+  if (!p || !alpha || !loss || !grad || batch == 0 || (nobs && !obs) || nobs < 0 || ckpt_stride < 0)
+    return fail(p ? p->ctx : nullptr, OWQS_E_INVALID_ARG, "null pointer or bad size");
+  if (batch > 65535) return fail(p->ctx, OWQS_E_INVALID_ARG, "batch above 65535");
+  if (!p->inputs.empty() && !input_c64) return fail(p->ctx, OWQS_E_INVALID_ARG, "the pattern needs an input state");
+  for (int32_t k = 0; k < nobs; ++k)
+    if (obs[k] < 0 || obs[k] >= (int32_t)p->outputs.size())
+      return fail(p->ctx, OWQS_E_INVALID_ARG, "observable index outside the outputs");
+  owqs_status st = ensure_device(p, false);
+  if (st != OWQS_OK) return st;
+  if (p->exec != OWQS_EXEC_FUSED) {
+    p->exec = OWQS_EXEC_FUSED;
+    p->dirty = true;
+  }
+  if (p->dirty) compile(p);
+  // structure: a prefix without measurements, then windows and E/X/Z steps
+  const size_t ns = p->steps.size();
+  size_t fw = ns;
+  for (size_t i = 0; i < ns; ++i) {
+    if (p->steps[i].kind == S_J) { fw = i; break; }
+    if (p->steps[i].kind == S_M)
+      return fail(p->ctx, OWQS_E_STATE, "adjoint: a measurement outside an N-E-M window comes before the first window");
+  }
+  std::vector<size_t> wins;
+  for (size_t i = fw; i < ns; ++i) {
+    const int k = p->steps[i].kind;
+    if (k == S_J) wins.push_back(i);
+    else if (k == S_N || k == S_M)
+      return fail(p->ctx, OWQS_E_STATE, "adjoint: only windows and E/X/Z steps may follow the first window");
+  }
+  const int nw = fw < ns ? p->steps[fw].n : p->plan_width;
+  const int W = p->plan_width;
+  const size_t stride = size_t(1) << W;
+  const size_t nwin = wins.size();
+  const int cs = ckpt_stride > 0 ? ckpt_stride : 16;
+  const size_t nseg = nwin ? (nwin + cs - 1) / cs : 0;
+  const unsigned nblk = adj_blocks(nw);
+  const unsigned lblk = loss_blocks((int)p->outputs.size());
+  // device memory: psi, lam, checkpoints, stash, partials, coefs, cols, scales
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };  // keep every region 256-byte aligned
+  const size_t vec = up(batch * stride * sizeof(float2));
+  const size_t off_lam = vec, off_ckpt = 2 * vec, off_stash = off_ckpt + nseg * vec;
+  const size_t off_part = off_stash + size_t(cs) * vec;
+  const size_t npart = std::max<size_t>(nwin * batch * nblk, batch * lblk);
+  const size_t off_coef = off_part + up(npart * sizeof(double));
+  const size_t off_cols = off_coef + up(std::max<size_t>(nwin, 1) * batch * sizeof(float2));
+  const size_t off_scale = off_cols + up((std::max<size_t>(nwin, 1) + 1) * sizeof(int));
+  const size_t total = off_scale + up((std::max<size_t>(nwin, 1) + 1) * sizeof(double));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (p->adj_cap < total) {
+    if (p->adj_mem) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p->adj_mem);
+    }
+    p->adj_mem = nullptr;
+    p->adj_cap = 0;
+    e = hipMalloc(&p->adj_mem, total);
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "adjoint buffers");
+    p->adj_cap = total;
+  } else {
+    e = hipStreamSynchronize(s);  // the host tables below are reused
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint");
+  }
+  char *base = static_cast<char *>(p->adj_mem);
+  float2 *psi = reinterpret_cast<float2 *>(base);
+  float2 *lam = reinterpret_cast<float2 *>(base + off_lam);
+  auto ckpt = [&](size_t j) { return reinterpret_cast<float2 *>(base + off_ckpt + j * vec); };
+  auto stash = [&](size_t j) { return reinterpret_cast<float2 *>(base + off_stash + j * vec); };
+  double *part = reinterpret_cast<double *>(base + off_part);
+  float2 *coefs = reinterpret_cast<float2 *>(base + off_coef);
+  int *cols = reinterpret_cast<int *>(base + off_cols);
+  double *scales = reinterpret_cast<double *>(base + off_scale);
+  // per-set window coefficients c = (-1)^o e^{-i theta}, theta = (-1)^s alpha + t pi (Eq. 2)
+  p->adj_coefs.assign(std::max<size_t>(nwin, 1) * batch, make_float2(0.f, 0.f));
+  p->adj_cols.assign(std::max<size_t>(nwin, 1) + 1, 0);
+  p->adj_scale.assign(std::max<size_t>(nwin, 1) + 1, 1.0);
+  for (size_t q = 0; q < nwin; ++q) {
+    const Step &x = p->steps[wins[q]];
+    for (size_t b = 0; b < batch; ++b) {
+      const double a = alpha[b * p->n_meas + x.m_index];
+      const double th = (x.sig_s ? -a : a) + (x.sig_t ? M_PI : 0.0);
+      double cr = std::cos(th), ci = -std::sin(th);
+      if (x.outcome) { cr = -cr; ci = -ci; }
+      p->adj_coefs[q * batch + b] = make_float2((float)cr, (float)ci);
+    }
+    p->adj_cols[q] = x.m_index;
+    p->adj_scale[q] = x.sig_s ? -1.0 : 1.0;  // dtheta/dalpha
+  }
+  e = hipMemcpyAsync(coefs, p->adj_coefs.data(), p->adj_coefs.size() * sizeof(float2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cols, p->adj_cols.data(), p->adj_cols.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(scales, p->adj_scale.data(), p->adj_scale.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(grad, 0, batch * std::max(p->n_meas, 1) * sizeof(double), s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint tables");
+  // device step rows (same encoding as the LDS kernels)
+  std::vector<DevStep> d(ns);
+  for (size_t i = 0; i < ns; ++i) {
+    const Step &x = p->steps[i];
+    d[i].kind = (uint8_t)x.kind;
+    d[i].n = (uint8_t)x.n;
+    d[i].b0 = (uint8_t)x.b0;
+    d[i].b1 = (uint8_t)x.b1;
+    d[i].m_index = x.m_index;
+    d[i].host_factor = (float)x.host_factor;
+    d[i].pp = (x.pp.swap ? 1u : 0u) | (x.pp.neg0 ? 2u : 0u) | (x.pp.neg1 ? 4u : 0u);
+  }
+  std::vector<size_t> win_of(ns, SIZE_MAX);
+  for (size_t q = 0; q < nwin; ++q) win_of[wins[q]] = q;
+  const int nsets = (int)batch;
+  const size_t seg_bytes = vec;
+  // forward: prefix, then the windowed part with a checkpoint at each segment start
+  e = launch_b_init(psi, stride, nsets, (int)p->inputs.size(), static_cast<const float2 *>(input_c64), s);
+  for (size_t i = 0; i < ns && e == hipSuccess; ++i) {
+    const size_t q = win_of[i];
+    if (q != SIZE_MAX && q % cs == 0) e = hipMemcpyAsync(ckpt(q / cs), psi, seg_bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_b_step(d[i], psi, stride, nsets, q != SIZE_MAX ? coefs + q * batch : nullptr, s);
+  }
+  // loss and the adjoint seed lambda = ff^2 W psi
+  std::vector<int> obs_bits(nobs);
+  for (int32_t k = 0; k < nobs; ++k) obs_bits[k] = p->final_where[obs[k]];
+  if (e == hipSuccess)
+    e = launch_b_loss(psi, lam, stride, nsets, (int)p->outputs.size(), obs_bits.data(), nobs,
+                      p->final_factor * p->final_factor, part, s);
+  if (e == hipSuccess) e = launch_b_reduce(part, 1, nsets, (int)lblk, cols + nwin, scales + nwin, loss, 1, s);
+  // the loss reduction reads `part` before the window partials overwrite it
+  // (same stream).  cols[nwin] = 0 and scales[nwin] = 1 were uploaded above.
+  // backward, one segment at a time: restore, recompute with a stash of the
+  // window inputs, then sweep lambda back through the segment
+  for (size_t j = nseg; j-- > 0 && e == hipSuccess;) {
+    const size_t first = wins[j * cs];
+    const size_t last = (j + 1) * cs < nwin ? wins[(j + 1) * cs] : ns;
+    e = hipMemcpyAsync(psi, ckpt(j), seg_bytes, hipMemcpyDeviceToDevice, s);
+    for (size_t i = first; i < last && e == hipSuccess; ++i) {
+      const size_t q = win_of[i];
+      if (q != SIZE_MAX) e = hipMemcpyAsync(stash(q - j * cs), psi, seg_bytes, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess) e = launch_b_step(d[i], psi, stride, nsets, q != SIZE_MAX ? coefs + q * batch : nullptr, s);
+    }
+    for (size_t i = last; i-- > first && e == hipSuccess;) {
+      const size_t q = win_of[i];
+      if (q != SIZE_MAX)
+        e = launch_b_window_adj(d[i], stash(q - j * cs), lam, stride, nsets, coefs + q * batch,
+                                part + q * batch * nblk, s);
+      else
+        e = launch_b_step(d[i], lam, stride, nsets, nullptr, s);  // E, X, Z are self-adjoint
+    }
+  }
+  if (e == hipSuccess && nwin)
+    e = launch_b_reduce(part, (int)nwin, nsets, (int)nblk, cols, scales, grad, (size_t)p->n_meas, s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint");
   return OWQS_OK;
 }
 

@@ -101,4 +101,20 @@ hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int redu
 hipError_t launch_lds_shared(const LdsItem &proto, int count, int width, int reduce, uint32_t first,
                              int basis_mode, size_t probs_stride, hipStream_t s);
 
+
+// ---- owqs_adjoint.hip: B sets side by side, set = blockIdx.y, set stride
+// `stride` amplitudes.  Steps are DevStep rows (N, E, X, Z, J); J reads its
+// per-set coefficient from coefs[set].
+hipError_t launch_b_init(float2 *psi, size_t stride, int nsets, int nin, const float2 *in, hipStream_t s);
+hipError_t launch_b_step(const DevStep &st, float2 *psi, size_t stride, int nsets, const float2 *coefs,
+                         hipStream_t s);
+unsigned adj_blocks(int n);   // blocks per set of launch_b_window_adj at width n
+hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *lam, size_t stride, int nsets,
+                               const float2 *coefs, double *partials, hipStream_t s);
+unsigned loss_blocks(int n);  // blocks per set of launch_b_loss at width n
+hipError_t launch_b_loss(const float2 *psi, float2 *lam, size_t stride, int nsets, int n, const int *obs_bits,
+                         int nobs, double ff2, double *partials, hipStream_t s);
+hipError_t launch_b_reduce(const double *partials, int nq, int nsets, int nblk, const int *out_col,
+                           const double *scale, double *out, size_t out_stride, hipStream_t s);
+
 }  // namespace owqs

@@ -1,0 +1,153 @@
+"""GPU parity of the adjoint gradient d(sum_i <Z_i>)/d(alpha) against the FP64
+oracle's exact parameter-shift gradient (and central differences), plus
+properties that hold at full size: checkpoint strides agree, the GPU's own
+shift rule agrees with its adjoint, and the torch.autograd wrapper returns
+the same gradient.
+
+Tolerance for gradients: |dg| <= 1e-4 * max(1, |g|); losses within 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import owqs_workloads as W
+from oracle import core as oc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+owqs = pytest.importorskip("paper_1604_05659_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return owqs.Context(0)
+
+
+def _gtol(g):
+    return 1e-4 * np.maximum(1.0, np.abs(g))
+
+
+def _load(ctx, wl):
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_EOWQS)
+    p.set_outcomes(wl.outcomes)
+    return p
+
+
+def test_adjoint_small_against_oracle(ctx, parity_report):
+    wl, sets = W.ansatz(n_logical=4, layers=3, batch=4)
+    p = _load(ctx, wl)
+    loss, grad = p.adjoint(sets)
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    worst = 0.0
+    for b in range(4):
+        want_l = oc.loss_at(wl.pattern, wl.outcomes, sets[b])
+        assert abs(loss[b] - want_l) <= 1e-5
+        g_shift = oc.param_shift_grad(wl.pattern, wl.outcomes, sets[b])
+        g_fd = oc.central_fd_grad(wl.pattern, wl.outcomes, sets[b], h=1e-4)
+        assert np.all(np.abs(grad[b] - g_shift) <= _gtol(g_shift)), np.max(np.abs(grad[b] - g_shift))
+        assert np.all(np.abs(grad[b] - g_fd) <= _gtol(g_fd))
+        worst = max(worst, float(np.max(np.abs(grad[b] - g_shift))))
+    parity_report("adjoint_ansatz4x3", max_abs_grad_err=worst)
+    p.close()
+
+
+def test_adjoint_with_inputs_and_observable_subset(ctx):
+    wl = W.plain_large(n_logical=6, n_j=40, n_cz=8)
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_EOWQS)
+    p.set_outcomes(wl.outcomes)
+    g = np.random.default_rng(11)
+    base = wl.pattern.angles()
+    sets = np.stack([base, base + g.normal(0, 0.3, base.size)])
+    x = torch.as_tensor(wl.input_state).cuda()
+    obs = [0, 2, 5]
+    loss, grad = p.adjoint(sets, obs, x)
+    inp = wl.input_state.astype(np.complex128)
+    for b in range(2):
+        want_l = oc.loss_at(wl.pattern, wl.outcomes, sets[b], inp, obs=obs)
+        assert abs(loss[b].item() - want_l) <= 1e-5
+        g_shift = oc.param_shift_grad(wl.pattern, wl.outcomes, sets[b], inp, obs=obs)
+        gg = grad[b].cpu().numpy()
+        assert np.all(np.abs(gg - g_shift) <= _gtol(g_shift)), np.max(np.abs(gg - g_shift))
+    p.close()
+
+
+def test_checkpoint_strides_agree(ctx):
+    wl, sets = W.ansatz(n_logical=6, layers=5, batch=3)
+    p = _load(ctx, wl)
+    ref = None
+    for stride in (1, 3, 6, 16, 1000):
+        loss, grad = p.adjoint(sets, ckpt_stride=stride)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = (loss.clone(), grad.clone())
+        else:
+            assert torch.equal(loss, ref[0]) and torch.equal(grad, ref[1]), stride
+    p.close()
+
+
+def test_full_size_gradient(ctx, parity_report):
+    """16 qubits, 25 layers, 400 angles, 64 angle sets."""
+    wl, sets = W.ansatz()
+    p = _load(ctx, wl)
+    loss, grad = p.adjoint(sets)
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    assert grad.shape == (64, 400)
+    rng = np.random.default_rng(400)
+    # oracle: losses of two sets, exact shift-rule gradient at sampled entries
+    worst_l, worst_g = 0.0, 0.0
+    for b in (0, 37):
+        want = oc.loss_at(wl.pattern, wl.outcomes, sets[b])
+        worst_l = max(worst_l, abs(loss[b] - want))
+        idx = sorted(rng.choice(400, 5, replace=False).tolist() + [0, 399])
+        g_shift = oc.param_shift_grad(wl.pattern, wl.outcomes, sets[b], indices=idx)
+        d = np.abs(grad[b, idx] - g_shift[idx])
+        assert np.all(d <= _gtol(g_shift[idx])), d
+        worst_g = max(worst_g, float(d.max()))
+    assert worst_l <= 1e-5
+    # the GPU's own shift rule at sampled (set, angle) pairs, all in one batch
+    picks = [(int(rng.integers(64)), int(rng.integers(400))) for _ in range(16)]
+    shifted = []
+    for b, k in picks:
+        for sgn in (1, -1):
+            a = sets[b].copy()
+            a[k] += sgn * math.pi / 2
+            shifted.append(a)
+    sl, _ = p.adjoint(np.stack(shifted))
+    sl = sl.cpu().numpy()
+    worst_s = 0.0
+    for i, (b, k) in enumerate(picks):
+        gs = 0.5 * (sl[2 * i] - sl[2 * i + 1])
+        worst_s = max(worst_s, abs(gs - grad[b, k]))
+        assert abs(gs - grad[b, k]) <= 1e-4 * max(1.0, abs(gs))
+    parity_report("adjoint_ansatz16x25_batch64", max_abs_loss_err=worst_l, max_abs_grad_err_vs_oracle=worst_g,
+                  max_abs_grad_err_vs_gpu_shift=worst_s)
+    p.close()
+
+
+def test_autograd_function(ctx):
+    wl, sets = W.ansatz(n_logical=5, layers=4, batch=3)
+    p = _load(ctx, wl)
+    alphas = torch.tensor(sets, dtype=torch.float64, requires_grad=True)
+    loss = owqs.pattern_loss(p, alphas)
+    w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)
+    (loss * w).sum().backward()
+    ref_l, ref_g = p.adjoint(sets)
+    np.testing.assert_allclose(loss.detach().numpy(), ref_l.cpu().numpy(), atol=0)
+    np.testing.assert_allclose(alphas.grad.numpy(), (w[:, None] * ref_g.cpu()).numpy(), rtol=1e-12, atol=1e-15)
+    p.close()
+
+
+def test_adjoint_rejects_measurements_outside_windows(ctx):
+    wl = W.cluster(rows=3, cols=4)
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_outcomes(wl.outcomes)
+    with pytest.raises(owqs.OwqsError) as e:
+        p.adjoint(np.zeros((1, p.n_meas)))
+    assert e.value.status == owqs.E_STATE
+    p.close()
