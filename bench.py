@@ -42,7 +42,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("owqs_kernels.hip", "owqs_internal.h"):
+    for f in ("owqs_kernels.hip",):
         with open(os.path.join(ROOT, "paper_1604_05659_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -62,13 +62,19 @@ def measured_traffic(kernel: str):
     return e.get("bytes_per_launch")
 
 
-def time_exec(owqs, torch, pat, inp, out, exec_, steps, warmup):
+def kernel_table(prof):
+    return {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
+                "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in prof.items()}
+
+
+def time_exec(owqs, torch, pat, inp, out, exec_, steps, warmup, profile=True):
     pat.set_exec(exec_)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         pat.run(inp)
         pat.read_state(out, check=False)
-    pat.check()
+    if warmup:
+        pat.check()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -82,7 +88,7 @@ def time_exec(owqs, torch, pat, inp, out, exec_, steps, warmup):
     wall = time.perf_counter() - t0
     pat.check()
     ev_ms = ev0.elapsed_time(ev1)
-    prof = pat.run_profiled(inp)
+    prof = pat.run_profiled(inp) if profile else None
     return wall, ev_ms, prof
 
 
@@ -238,6 +244,114 @@ def bench_recognition(owqs, torch, W, ctx, steps):
     }
 
 
+def bench_adjoint(owqs, torch, W, ctx, steps):
+    """Differentiated workload: 16-qubit layered ansatz, 25 layers, 400 M
+    angles, 64 angle sets; one owqs_adjoint call = forward + checkpointed
+    backward for all sets."""
+    wl, sets = W.ansatz()
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_EOWQS)
+    p.set_outcomes(wl.outcomes)
+    p.adjoint(sets)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss, grad = p.adjoint(sets)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    w, nsteps = p.plan_info()
+    p.close()
+    return {
+        "workload": "layered ansatz, 16 qubits, 25 layers (400 angles), 64 angle sets, loss sum_i <Z_i>, EOWQS",
+        "sets": int(sets.shape[0]),
+        "angles": int(sets.shape[1]),
+        "plan_width": w,
+        "ms_forward_backward": round(1e3 * t, 3),
+        "sets_per_s": round(sets.shape[0] / t, 1),
+        "gradient_entries_per_s": round(sets.size / t, 1),
+    }
+
+
+def bench_cluster(owqs, torch, W, ctx, steps):
+    """20 x 200 cluster measured column by column (width 21), OWQS."""
+    wl = W.cluster()
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_outcomes(wl.outcomes)
+    out = torch.empty(1 << 20, dtype=torch.complex64, device="cuda")
+    nt = wl.pattern.nontrivial_count(wl.outcomes)
+    res = {"workload": "2D cluster 20 x 200, angles k pi/4, live width 21, OWQS",
+           "commands_listed": len(wl.pattern.cmds), "commands_nontrivial": nt}
+    for name, ex in (("plain", owqs.EXEC_PLAIN), ("fused", owqs.EXEC_FUSED)):
+        p.set_exec(ex)
+        p.run(None)
+        p.read_state(out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p.run(None)
+            p.read_state(out, check=False)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        p.check()
+        res[name] = {"ms_per_run": round(1e3 * t, 3), "commands_per_s": round(nt / t, 1),
+                     "plan_steps": p.plan_info()[1]}
+    p.close()
+    return res
+
+
+def bench_small(owqs, torch, W, ctx, steps):
+    """The small plain pattern (4 logical qubits, 106 commands): latency of
+    one run plus read-out through the C ABI (fused plan replayed as a graph)."""
+    wl = W.plain_small()
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_outcomes(wl.outcomes)
+    out = torch.empty(16, dtype=torch.complex64, device="cuda")
+    p.run(None)
+    p.read_state(out)
+    reps = 200 * steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.run(None)
+        p.read_state(out, check=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    p.close()
+    return {"workload": "plain_small: 4 logical qubits, 20 J + 6 CZ, 106 commands, OWQS, fused + graph",
+            "us_per_pattern": round(1e6 * t, 2)}
+
+
+def pmc_probe():
+    """The first 8 gates of the large circuit at its full width (24 <-> 25),
+    run once with the plain executor and once fused, each command its own
+    dispatch (no graph): a few dozen dispatches of exactly the kernels and
+    launch shapes of the timed workload, for hardware-counter passes."""
+    import torch
+    import owqs_workloads as W
+    import paper_1604_05659_amd as owqs
+
+    wl = W.plain_large(**WORKLOAD)
+    gates = wl.meta["gates"][:8]
+    pat_def = W.circuit_to_pattern(WORKLOAD["n_logical"], gates)
+    outc = W.outcome_bits(pat_def.n_meas(), np.random.default_rng(1))
+    ctx = owqs.Context(0)
+    p = owqs.Pattern(ctx, pat_def)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_outcomes(outc)
+    p.set_graph(False)
+    inp = torch.as_tensor(wl.input_state).cuda()
+    out = torch.empty(1 << 24, dtype=torch.complex64, device="cuda")
+    for ex in (owqs.EXEC_PLAIN, owqs.EXEC_FUSED):
+        p.set_exec(ex)
+        p.run(inp)
+        p.read_state(out)
+    torch.cuda.synchronize()
+    p.close()
+    print(json.dumps({"pmc_probe": "done", "commands": len(pat_def.cmds), "counts": pat_def.counts()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,11 +360,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the extra event-timed step (for counter collection runs)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="one short run at full width, few dispatches: for rocprofv3 --pmc passes")
+    ap.add_argument("--only-plain", action="store_true",
+                    help="run only the plain executor on the large workload (for counter collection runs)")
     args = ap.parse_args()
+    if args.pmc_probe:
+        pmc_probe()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a pattern on a single MI355X "
               "(no multi-GPU path); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.only_plain:
+        args.no_fused = args.no_batch = args.no_adjoint = args.no_cpu_baseline = True
 
     import torch
     import owqs_workloads as W
@@ -273,17 +399,14 @@ def main():
     pat.set_outcomes(wl.outcomes)
     inp = torch.as_tensor(wl.input_state).cuda()
     out = torch.empty(1 << len(pat_def.outputs), dtype=torch.complex64, device="cuda")
-
-    log("[bench] plain executor")
-    wall, ev_ms, prof = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_PLAIN, args.steps, args.warmup)
-    probs = pat.read_probs()
-    ms_step = 1e3 * wall / args.steps
     names = {"measure(M)": "k_measure", "prepare(N)": "k_prepare", "cz(E)": "k_cz", "pauli_x(X)": "k_x",
              "jwindow(NEMX)": "k_jwindow"}
-    dom, roof = roofline_of(prof, names)
-    step_bytes = sum(v["bytes"] for v in prof.values())
-    kernels = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
-                   "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in prof.items()}
+
+    log("[bench] plain executor")
+    wall, ev_ms, prof = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_PLAIN, args.steps, args.warmup,
+                                  not args.no_profile)
+    probs = pat.read_probs()
+    ms_step = 1e3 * wall / args.steps
     result = {
         "metric": "pattern commands/s & HBM GB/s at 2^25 amps; batched vs plain at err<=1e-5",
         "value": round(n_nontriv / (ms_step / 1e3), 1),
@@ -301,22 +424,26 @@ def main():
             "workload": ("plain_large: random J/CZ circuit on 24 logical qubits, 2000 J(alpha) + 300 CZ, "
                          "pattern of 8300 commands, live width 24<->25 (2^25 complex64 amplitudes), "
                          "complex Gaussian input, seeded forced outcomes, OWQS mode (FP64 probabilities)"),
-            "exec": "plain (one kernel per non-trivial command)",
+            "exec": "plain (one kernel per non-trivial command, replayed as a HIP graph)",
             "commands_listed": n_all,
             "commands_nontrivial": n_nontriv,
             "counts": counts,
         },
         "commands_all_per_s": round(n_all / (ms_step / 1e3), 1),
-        "hbm_gbs_step": round(step_bytes / (ms_step / 1e3) / 1e9, 1),
         "event_ms_per_step": round(ev_ms / args.steps, 3),
-        "roofline": roof,
-        "kernels": kernels,
         "checks": {"max_abs_p_minus_half": float(np.max(np.abs(probs - 0.5)))},
     }
+    if prof:
+        _, roof = roofline_of(prof, names)
+        step_bytes = sum(v["bytes"] for v in prof.values())
+        result["hbm_gbs_step"] = round(step_bytes / (ms_step / 1e3) / 1e9, 1)
+        result["roofline"] = roof
+        result["kernels"] = kernel_table(prof)
 
     if not args.no_fused:
         log("[bench] fused executor")
-        wall_f, ev_f, prof_f = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_FUSED, args.steps, args.warmup)
+        wall_f, ev_f, prof_f = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_FUSED, args.steps, args.warmup,
+                                         not args.no_profile)
         probs_f = pat.read_probs()
         fused_out = out.clone()
         pat.set_exec(owqs.EXEC_PLAIN)
@@ -324,31 +451,38 @@ def main():
         pat.read_state(out)
         diff = float((fused_out - out).abs().max().item())
         ms_f = 1e3 * wall_f / args.steps
-        _, roof_f = roofline_of(prof_f, names)
         result["fused"] = {
             "value": round(n_nontriv / (ms_f / 1e3), 1),
             "unit": "commands/s",
             "ms_per_step": round(ms_f, 3),
             "live_width": 24,
-            "roofline": roof_f,
-            "kernels": {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / v["launches"], 2),
-                            "GB/s": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in prof_f.items()},
             "max_abs_diff_vs_plain": diff,
             "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
         }
+        if prof_f:
+            _, roof_f = roofline_of(prof_f, names)
+            result["fused"]["roofline"] = roof_f
+            result["fused"]["kernels"] = kernel_table(prof_f)
+    pat.close()
 
     if not args.no_batch:
         log("[bench] batched workload")
         result["batched"] = bench_batched(owqs, torch, W, ctx, args.steps)
         log("[bench] recognition workload")
         result["recognition"] = bench_recognition(owqs, torch, W, ctx, args.steps)
+        log("[bench] cluster workload")
+        result["cluster"] = bench_cluster(owqs, torch, W, ctx, args.steps)
+        log("[bench] small workload")
+        result["small"] = bench_small(owqs, torch, W, ctx, args.steps)
+    if not args.no_adjoint:
+        log("[bench] differentiated workload")
+        result["adjoint"] = bench_adjoint(owqs, torch, W, ctx, args.steps)
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(wl.meta["gates"], wl.input_state, 20)
     else:
         result["cpu_baseline"] = None
-    pat.close()
     print(json.dumps(result), flush=True)
 
 
