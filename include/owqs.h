@@ -94,11 +94,12 @@ typedef struct {
 typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 2 } owqs_mode;
 
 /* Execution plan.  PLAIN: one kernel per non-trivial command, the live width
- * growing on N and shrinking on M.  FUSED (default): windows of commands are
- * merged into single passes over the state (N w; E u w; M u; corrections on
- * w becomes one 2x2 update in place; runs of E/Z become one diagonal pass).
- * Both give the same result to FP32 rounding. */
-typedef enum { OWQS_EXEC_PLAIN = 0, OWQS_EXEC_FUSED = 1 } owqs_exec;
+ * growing on N and shrinking on M.  FUSED: windows of commands are merged
+ * into single passes over the state (N w; E u w; ...; M u; corrections on w
+ * becomes one 2x2 update in place).  AUTO (default): the fused plan, run as
+ * one workgroup with the whole vector in LDS when its width is <= 14, else
+ * as FUSED.  All give the same result to FP32 rounding. */
+typedef enum { OWQS_EXEC_PLAIN = 0, OWQS_EXEC_FUSED = 1, OWQS_EXEC_AUTO = 2 } owqs_exec;
 
 typedef struct owqs_ctx owqs_ctx;
 typedef struct owqs_pattern owqs_pattern;

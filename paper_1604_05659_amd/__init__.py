@@ -40,7 +40,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK = 0
 E_INVALID_ARG, E_PATTERN, E_ZERO_PROB, E_WIDTH, E_NOMEM, E_HIP, E_NOT_DETERMINISTIC, E_STATE = range(-1, -9, -1)
 MODE_OWQS, MODE_EOWQS, MODE_EOWQS_CHECK = 0, 1, 2
-EXEC_PLAIN, EXEC_FUSED = 0, 1
+EXEC_PLAIN, EXEC_FUSED, EXEC_AUTO = 0, 1, 2
 OPS = {"N": 0, "E": 1, "M": 2, "X": 3, "Z": 4}
 KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)"}
 NUM_KINDS = 8
@@ -373,7 +373,7 @@ def pattern_loss(pattern: "Pattern", alphas, obs=None, psi_in=None, ckpt_stride:
 
 
 def run_pattern(ctx: Context, pattern, outcomes, input_state=None, mode: int = MODE_OWQS,
-                exec_: int = EXEC_FUSED, angles=None):
+                exec_: int = EXEC_AUTO, angles=None):
     """Load, run and read one pattern; returns (output complex64 CUDA tensor, probs)."""
     import torch
     p = Pattern(ctx, pattern)

@@ -6,14 +6,13 @@
 // blockIdx.y.  The plan is the fused one: after a prefix without parameters
 // (preparations), every step is a window (N w; E u w; M u; X/Z on w) or a
 // Pauli / controlled-Z step.  With fixed probability 1/2 (Sec. 4.5) a window
-// is the unitary P f [[1, c], [1, -c]] on one slot (f = 1/sqrt 2, c =
-// (-1)^o e^{-i theta}, Eqs. 11-12, P the folded corrections) and E, X, Z are
-// self-adjoint, so the reverse sweep carries the adjoint state
+// is, at every index j of the other slots, the unitary (up to the factor f)
+// P diag(1, so1) f [[1, c sb], [1, s c sb]] on one slot (f = 1/sqrt 2, c =
+// (-1)^o e^{-i theta}, Eqs. 11-12; sb, so1, s the signs of the E commands
+// inside the window; P the folded corrections), and E, X, Z are self-adjoint,
+// so the reverse sweep carries the adjoint state
 // lambda = U_{>k}^dagger (W psi_final) back through the windows:
 //   dL/dtheta_k = 2 Re <lambda_k | dW_k/dtheta psi_{k-1}>,
-//   dW/dtheta (a, b) = P f (-i c b, i c b),
-//   lambda_{k-1} = W_k^dagger lambda_k = f (mu0 + mu1, conj(c) (mu0 - mu1)),
-//   mu = P^T lambda_k,
 // and dtheta/dalpha = (-1)^s (Eq. 2).  Gradient partials are FP64 per block;
 // one reduction kernel sums them in block order at the end.
 #include "owqs_internal.h"
@@ -67,17 +66,24 @@ __global__ __launch_bounds__(kB) void k_b_z(float2 *psi, size_t stride, uint64_t
   }
 }
 
+__device__ __forceinline__ float sgnb(uint64_t j, uint64_t mask) { return (__popcll(j & mask) & 1) ? -1.f : 1.f; }
+
+// Forward window on every set (see Window): o0 = f (a + c sb b),
+// o1 = so1 f (a + s c sb b), then the folded corrections.
 __global__ __launch_bounds__(kB) void k_b_window(float2 *psi, size_t stride, uint64_t half, int b,
-                                                  const float2 *coefs, float f, PostPerm pp) {
+                                                  const float2 *coefs, float f, Window w) {
   const float2 c = coefs[blockIdx.y];
+  const float s1 = w.vw_even ? 1.f : -1.f;
   SET_LOOP(half) {
     const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
-    const float2 a = v[j], cb = cmulf(c, v[k]);
+    const float sb = sgnb(j, w.mask_b), so1 = sgnb(j, w.mask_o1);
+    const float2 a = v[j], cb0 = cmulf(c, v[k]);
+    const float2 cb = make_float2(sb * cb0.x, sb * cb0.y);
     float2 o0 = make_float2(f * (a.x + cb.x), f * (a.y + cb.y));
-    float2 o1 = make_float2(f * (a.x - cb.x), f * (a.y - cb.y));
-    if (pp.swap) { const float2 t = o0; o0 = o1; o1 = t; }
-    if (pp.neg0) o0 = make_float2(-o0.x, -o0.y);
-    if (pp.neg1) o1 = make_float2(-o1.x, -o1.y);
+    float2 o1 = make_float2(so1 * f * (a.x + s1 * cb.x), so1 * f * (a.y + s1 * cb.y));
+    if (w.swap) { const float2 t = o0; o0 = o1; o1 = t; }
+    if (w.neg0) o0 = make_float2(-o0.x, -o0.y);
+    if (w.neg1) o1 = make_float2(-o1.x, -o1.y);
     v[j] = o0;
     v[k] = o1;
   }
@@ -85,39 +91,45 @@ __global__ __launch_bounds__(kB) void k_b_window(float2 *psi, size_t stride, uin
 
 // Adjoint of one window: psi_in = the window's input (read only), lam = the
 // adjoint state after the window (updated in place to the state before it).
+// With mu = P^T lam (P the folded corrections):
+//   d(o0, o1)/dtheta = P (f sb (-i c b), so1 s f sb (-i c b)),
+//   lam_a = f (mu0 + so1 mu1),  lam_b = f sb conj(c) (mu0 + so1 s mu1).
 // partials[set * gridDim.x + block] = this block's sum of
 // 2 Re <lam | dW/dtheta psi_in>.
 __global__ __launch_bounds__(kB) void k_b_window_adj(const float2 *__restrict__ psi_in, float2 *__restrict__ lam,
                                                       size_t stride, uint64_t half, int b, const float2 *coefs,
-                                                      float f, PostPerm pp, double *partials) {
+                                                      float f, Window w, double *partials) {
   __shared__ double red[kB / 64];
   const float2 c = coefs[blockIdx.y];
+  const float s1 = w.vw_even ? 1.f : -1.f;
   const float2 *x = psi_in + size_t(blockIdx.y) * stride;
   float2 *l = lam + size_t(blockIdx.y) * stride;
   double acc = 0.0;
   for (uint64_t i = uint64_t(blockIdx.x) * kB + threadIdx.x; i < half; i += uint64_t(gridDim.x) * kB) {
     const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
-    const float2 cb = cmulf(c, x[k]);                       // c b
-    // dW/dtheta (a, b) before the corrections: (-i c b, +i c b)
-    float2 d0 = make_float2(f * cb.y, -f * cb.x), d1 = make_float2(-f * cb.y, f * cb.x);
-    if (pp.swap) { const float2 t = d0; d0 = d1; d1 = t; }
-    if (pp.neg0) d0 = make_float2(-d0.x, -d0.y);
-    if (pp.neg1) d1 = make_float2(-d1.x, -d1.y);
+    const float sb = sgnb(j, w.mask_b), so1 = sgnb(j, w.mask_o1);
+    const float2 cb = cmulf(c, x[k]);                                   // c b
+    // -i c b = (cb.y, -cb.x)
+    const float g0 = f * sb, g1 = so1 * s1 * f * sb;
+    float2 d0 = make_float2(g0 * cb.y, -g0 * cb.x), d1 = make_float2(g1 * cb.y, -g1 * cb.x);
+    if (w.swap) { const float2 t = d0; d0 = d1; d1 = t; }
+    if (w.neg0) d0 = make_float2(-d0.x, -d0.y);
+    if (w.neg1) d1 = make_float2(-d1.x, -d1.y);
     const float2 l0 = l[j], l1 = l[k];
     acc += 2.0 * (double(l0.x) * d0.x + double(l0.y) * d0.y + double(l1.x) * d1.x + double(l1.y) * d1.y);
     // mu = P^T lam: undo the negations, then the swap
-    float2 m0 = pp.neg0 ? make_float2(-l0.x, -l0.y) : l0;
-    float2 m1 = pp.neg1 ? make_float2(-l1.x, -l1.y) : l1;
-    if (pp.swap) { const float2 t = m0; m0 = m1; m1 = t; }
-    const float2 s = make_float2(m0.x + m1.x, m0.y + m1.y), dlt = make_float2(m0.x - m1.x, m0.y - m1.y);
-    const float2 cc = make_float2(c.x, -c.y);
-    const float2 cd = cmulf(cc, dlt);
-    l[j] = make_float2(f * s.x, f * s.y);
-    l[k] = make_float2(f * cd.x, f * cd.y);
+    float2 m0 = w.neg0 ? make_float2(-l0.x, -l0.y) : l0;
+    float2 m1 = w.neg1 ? make_float2(-l1.x, -l1.y) : l1;
+    if (w.swap) { const float2 t = m0; m0 = m1; m1 = t; }
+    const float2 sm = make_float2(m0.x + so1 * m1.x, m0.y + so1 * m1.y);
+    const float2 dm = make_float2(m0.x + so1 * s1 * m1.x, m0.y + so1 * s1 * m1.y);
+    const float2 cd = cmulf(make_float2(c.x, -c.y), dm);
+    l[j] = make_float2(f * sm.x, f * sm.y);
+    l[k] = make_float2(f * sb * cd.x, f * sb * cd.y);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) red[w] = acc;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
@@ -202,12 +214,10 @@ hipError_t launch_b_step(const DevStep &st, float2 *psi, size_t stride, int nset
       hipLaunchKernelGGL(k_b_z, dim3(blocks_for(dim >> 1), nsets), dim3(kB), 0, s, psi, stride, dim >> 1,
                          int(st.b0));
       break;
-    case DK_J: {
-      PostPerm pp{int(st.pp & 1u), int((st.pp >> 1) & 1u), int((st.pp >> 2) & 1u)};
+    case DK_J:
       hipLaunchKernelGGL(k_b_window, dim3(blocks_for(dim >> 1), nsets), dim3(kB), 0, s, psi, stride, dim >> 1,
-                         int(st.b0), coefs, st.host_factor, pp);
+                         int(st.b0), coefs, st.host_factor, window_of(st));
       break;
-    }
     default:
       return hipErrorInvalidValue;
   }
@@ -225,9 +235,8 @@ unsigned adj_blocks(int n) { return blocks_for((uint64_t(1) << n) >> 1); }
 hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *lam, size_t stride, int nsets,
                                const float2 *coefs, double *partials, hipStream_t s) {
   const uint64_t half = (uint64_t(1) << st.n) >> 1;
-  PostPerm pp{int(st.pp & 1u), int((st.pp >> 1) & 1u), int((st.pp >> 2) & 1u)};
   hipLaunchKernelGGL(k_b_window_adj, dim3(blocks_for(half), nsets), dim3(kB), 0, s, psi_in, lam, stride, half,
-                     int(st.b0), coefs, st.host_factor, pp, partials);
+                     int(st.b0), coefs, st.host_factor, window_of(st), partials);
   return hipGetLastError();
 }
 

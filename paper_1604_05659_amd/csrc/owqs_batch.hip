@@ -16,7 +16,9 @@
 namespace owqs {
 namespace {
 
-constexpr int kT = 512;  // 8 wave64 per workgroup
+// Workgroup size by live width: one wave64 up to width 8 (its barriers are
+// nearly free), 4 waves up to width 11, 8 waves above.
+constexpr int threads_for(int width) { return width <= 8 ? 64 : width <= 11 ? 256 : 512; }
 
 __device__ __forceinline__ uint32_t i0(uint32_t x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1)); }
 
@@ -29,6 +31,7 @@ __device__ __forceinline__ double n2(float2 v) { return double(v.x) * v.x + doub
 __device__ __forceinline__ float2 neg(float2 v) { return make_float2(-v.x, -v.y); }
 
 // Sum of v over the workgroup, the same value returned to every thread.
+template <int kT>
 __device__ double block_sum(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -40,6 +43,7 @@ __device__ double block_sum(double v, double *red) {
   return s;
 }
 
+template <int kT>
 __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin, int nout, const int *where,
                          double final_factor, float2 *lds, const float2 *__restrict__ in, int basis,
                          float2 *__restrict__ out, double *__restrict__ probs, int reduce, int *err, int item,
@@ -108,20 +112,25 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
           }
         }
       } else {
+        const Window w = window_of(st);
+        const float s1 = w.vw_even ? 1.f : -1.f;
         for (uint32_t i = threadIdx.x; i < (dim >> 1); i += kT) {
           const uint32_t j = i0(i, b), st2 = 1u << b;
+          const float sb = (__popcll(j & w.mask_b) & 1) ? -1.f : 1.f;
+          const float so1 = (__popcll(j & w.mask_o1) & 1) ? -1.f : 1.f;
           const float2 a = lds[j], bb = lds[j + st2];
-          float2 o0 = fma_c(a, c, bb, f, 1.f), o1 = fma_c(a, c, bb, f, -1.f);
-          if (st.pp & 1u) { const float2 t = o0; o0 = o1; o1 = t; }
-          if (st.pp & 2u) o0 = neg(o0);
-          if (st.pp & 4u) o1 = neg(o1);
+          float2 o0 = fma_c(a, c, bb, f, sb), o1 = fma_c(a, c, bb, f, s1 * sb);
+          if (so1 < 0.f) o1 = neg(o1);
+          if (w.swap) { const float2 t = o0; o0 = o1; o1 = t; }
+          if (w.neg0) o0 = neg(o0);
+          if (w.neg1) o1 = neg(o1);
           lds[j] = o0;
           lds[j + st2] = o1;
           acc += n2(o0) + n2(o1);
         }
       }
       if (reduce != kReduceNone) {
-        const double sum = block_sum(acc, red);
+        const double sum = block_sum<kT>(acc, red);
         const double p = 0.5 * sum;
         if (probs && threadIdx.x == 0) probs[st.m_index] = p;
         if (reduce == kReduceRenorm) {
@@ -150,16 +159,18 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
   __syncthreads();
 }
 
+template <int kT>
 __global__ __launch_bounds__(kT) void k_lds_batch(const LdsItem *__restrict__ items, int count, int reduce) {
   extern __shared__ float2 lds[];
   __shared__ double red[kT / 64];
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
     const LdsItem *x = items + it;
-    run_item(x->steps, x->nsteps, x->nin, x->nout, x->where, x->final_factor, lds, x->in, x->basis, x->out,
+    run_item<kT>(x->steps, x->nsteps, x->nin, x->nout, x->where, x->final_factor, lds, x->in, x->basis, x->out,
              x->probs, reduce, x->err, -1, red);
   }
 }
 
+template <int kT>
 __global__ __launch_bounds__(kT) void k_lds_shared(LdsItem proto, int count, int reduce, uint32_t first,
                                                     int basis_mode, size_t probs_stride) {
   extern __shared__ float2 lds[];
@@ -168,35 +179,54 @@ __global__ __launch_bounds__(kT) void k_lds_shared(LdsItem proto, int count, int
   for (int k = blockIdx.x; k < count; k += gridDim.x) {
     const float2 *in = basis_mode ? nullptr : proto.in + size_t(k) * din;
     double *pr = proto.probs ? proto.probs + size_t(k) * probs_stride : nullptr;
-    run_item(proto.steps, proto.nsteps, proto.nin, proto.nout, proto.where, proto.final_factor, lds, in,
+    run_item<kT>(proto.steps, proto.nsteps, proto.nin, proto.nout, proto.where, proto.final_factor, lds, in,
              basis_mode ? int(first + k) : -1, proto.out + size_t(k) * dout, pr, reduce, proto.err, k, red);
   }
 }
 
 unsigned lds_grid(int count) { return unsigned(count < 16384 ? count : 16384); }
 
+template <int kT>
+hipError_t lds_batch_t(const LdsItem *items, int count, size_t bytes, int reduce, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch<kT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lds_batch<kT>, dim3(lds_grid(count)), dim3(kT), bytes, s, items, count, reduce);
+  return hipGetLastError();
+}
+
+template <int kT>
+hipError_t lds_shared_t(const LdsItem &proto, int count, size_t bytes, int reduce, uint32_t first, int basis_mode,
+                        size_t probs_stride, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_shared<kT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lds_shared<kT>, dim3(lds_grid(count)), dim3(kT), bytes, s, proto, count, reduce, first,
+                     basis_mode, probs_stride);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int reduce, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const size_t bytes = sizeof(float2) << width;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lds_batch, dim3(lds_grid(count)), dim3(kT), bytes, s, items, count, reduce);
-  return hipGetLastError();
+  switch (threads_for(width)) {
+    case 64: return lds_batch_t<64>(items, count, bytes, reduce, s);
+    case 256: return lds_batch_t<256>(items, count, bytes, reduce, s);
+    default: return lds_batch_t<512>(items, count, bytes, reduce, s);
+  }
 }
 
 hipError_t launch_lds_shared(const LdsItem &proto, int count, int width, int reduce, uint32_t first,
                              int basis_mode, size_t probs_stride, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const size_t bytes = sizeof(float2) << width;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_shared),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lds_shared, dim3(lds_grid(count)), dim3(kT), bytes, s, proto, count, reduce, first,
-                     basis_mode, probs_stride);
-  return hipGetLastError();
+  switch (threads_for(width)) {
+    case 64: return lds_shared_t<64>(proto, count, bytes, reduce, first, basis_mode, probs_stride, s);
+    case 256: return lds_shared_t<256>(proto, count, bytes, reduce, first, basis_mode, probs_stride, s);
+    default: return lds_shared_t<512>(proto, count, bytes, reduce, first, basis_mode, probs_stride, s);
+  }
 }
 
 }  // namespace owqs

@@ -53,7 +53,7 @@ struct Step {
   float2 coef;
   double host_factor;
   int m_index;
-  PostPerm pp;
+  Window win;
   int sig_s, sig_t, outcome;  // M / window: resolved signals and forced outcome
 };
 
@@ -76,7 +76,7 @@ struct owqs_pattern {
   std::vector<double> angles;     // per M
   std::vector<uint8_t> outcomes;  // per M
   owqs_mode mode = OWQS_MODE_OWQS;
-  owqs_exec exec = OWQS_EXEC_FUSED;
+  owqs_exec exec = OWQS_EXEC_AUTO;
 
   // compiled plan
   bool dirty = true;
@@ -110,6 +110,7 @@ struct owqs_pattern {
   std::vector<double> adj_scale;
 
   bool ran = false;
+  bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
   bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)
   int ran_mode = 0;
   int graph_reduce = -1;
@@ -203,7 +204,7 @@ void compile(owqs_pattern *p) {
   const double r2 = 1.0 / std::sqrt(2.0);
   double pending = 1.0;
   int m = 0;
-  const bool fused = p->exec == OWQS_EXEC_FUSED;
+  const bool fused = p->exec != OWQS_EXEC_PLAIN;
   p->steps.clear();
   const size_t nc = p->cmds.size();
 
@@ -222,30 +223,54 @@ void compile(owqs_pattern *p) {
 
   for (size_t i = 0; i < nc; ++i) {
     const Cmd &c = p->cmds[i];
-    // Window N w; E(u, w); M u; then X/Z on w, as one in-place 2x2 pass.
+    // Window N w; E ... (each on v or w); M v; then X/Z on w, as one
+    // in-place 2x2 pass over v's slot (E's to other qubits become signs).
     if (fused && c.op == OWQS_OP_N && i + 2 < nc) {
       const int w = c.q0;
-      const Cmd &e = p->cmds[i + 1];
-      const Cmd &mm = p->cmds[i + 2];
-      if (e.op == OWQS_OP_E && (e.q0 == w || e.q1 == w) && mm.op == OWQS_OP_M) {
-        const int u = (e.q0 == w) ? e.q1 : e.q0;
-        if (mm.q0 == u && u != w) {
+      size_t j = i + 1;
+      while (j < nc && p->cmds[j].op == OWQS_OP_E) ++j;
+      if (j > i + 1 && j < nc && p->cmds[j].op == OWQS_OP_M && p->cmds[j].q0 != w) {
+        const Cmd &mm = p->cmds[j];
+        const int v = mm.q0;
+        bool ok = slot_of[v] >= 0;
+        int vw = 0;
+        uint64_t mask_b = 0, mask_o1 = 0;
+        for (size_t k = i + 1; k < j && ok; ++k) {
+          const int a = p->cmds[k].q0, b = p->cmds[k].q1;
+          if ((a == v && b == w) || (a == w && b == v)) {
+            ++vw;
+          } else if (a == v || b == v) {
+            const int x = a == v ? b : a;
+            ok = slot_of[x] >= 0;
+            if (ok) mask_b ^= uint64_t(1) << slot_of[x];
+          } else if (a == w || b == w) {
+            const int y = a == w ? b : a;
+            ok = slot_of[y] >= 0;
+            if (ok) mask_o1 ^= uint64_t(1) << slot_of[y];
+          } else {
+            ok = false;  // an E on two other qubits ends the window
+          }
+        }
+        if (ok && vw > 0) {
           int o = 0;
           Step st{};
           st.kind = S_J;
           st.n = n;
-          st.b0 = slot_of[u];
+          st.b0 = slot_of[v];
           st.coef = coef_of(mm, m, o);
           st.sig_s = last_s;
           st.sig_t = last_t;
           st.outcome = o;
           st.host_factor = pending * r2;
           st.m_index = m;
-          outcome_of[u] = o;
+          outcome_of[v] = o;
           ++m;
+          st.win.mask_b = mask_b;
+          st.win.mask_o1 = mask_o1;
+          st.win.vw_even = (vw % 2 == 0) ? 1 : 0;
           // fold the following corrections on w into a signed permutation
           int idx[2] = {0, 1}, sgn[2] = {1, 1};
-          size_t k = i + 3;
+          size_t k = j + 1;
           while (k < nc && (p->cmds[k].op == OWQS_OP_X || p->cmds[k].op == OWQS_OP_Z) && p->cmds[k].q0 == w) {
             if (signal(p->cmds[k].s, outcome_of)) {
               if (p->cmds[k].op == OWQS_OP_X) {
@@ -257,13 +282,13 @@ void compile(owqs_pattern *p) {
             }
             ++k;
           }
-          st.pp.swap = idx[0] == 1;
-          st.pp.neg0 = sgn[0] < 0;
-          st.pp.neg1 = sgn[1] < 0;
+          st.win.swap = idx[0] == 1;
+          st.win.neg0 = sgn[0] < 0;
+          st.win.neg1 = sgn[1] < 0;
           p->steps.push_back(st);
           slot_of[w] = st.b0;
           qubit_at[st.b0] = w;
-          slot_of[u] = -1;
+          slot_of[v] = -1;
           pending = 1.0;
           i = k - 1;
           continue;
@@ -485,7 +510,7 @@ hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<
         a.m_index = x.m_index;
         a.book = p->book;
         e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
-                          : launch_jwindow(p->psi, x.n, x.b0, a, x.pp, s, &grid);
+                          : launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &grid);
         break;
       default: break;
     }
@@ -509,7 +534,9 @@ owqs_status upload_steps(owqs_pattern *p) {
     d[i].m_index = x.m_index;
     d[i].coef = x.coef;
     d[i].host_factor = (float)x.host_factor;
-    d[i].pp = (x.pp.swap ? 1u : 0u) | (x.pp.neg0 ? 2u : 0u) | (x.pp.neg1 ? 4u : 0u);
+    d[i].pp = (x.win.swap ? 1u : 0u) | (x.win.neg0 ? 2u : 0u) | (x.win.neg1 ? 4u : 0u) | (x.win.vw_even ? 8u : 0u);
+    d[i].mask_b = x.win.mask_b;
+    d[i].mask_o1 = x.win.mask_o1;
   }
   const size_t need = std::max<size_t>(d.size(), 1);
   hipError_t e = hipSuccess;
@@ -564,6 +591,26 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
   const int reduce = p->mode == OWQS_MODE_OWQS ? kReduceRenorm
                      : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck
                                                         : kReduceNone;
+  if (!prof && p->exec == OWQS_EXEC_AUTO && p->plan_width <= kLdsMaxWidth) {
+    // whole pattern in one workgroup's LDS; the ordered, scaled read-out is
+    // written to psi[0 .. 2^nout) (the input was read into LDS first)
+    st = upload_steps(p);
+    if (st != OWQS_OK) return st;
+    // (the input, or the empty product state set by the init kernel, is in psi)
+    LdsItem proto = lds_proto(p);
+    proto.in = p->psi;
+    proto.out = p->psi;
+    proto.probs = p->book.probs;
+    proto.err = p->book.err;
+    e = launch_lds_shared(proto, 1, p->plan_width, reduce, 0, 0, (size_t)p->n_meas, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "LDS run");
+    p->ran = true;
+    p->out_in_order = true;
+    p->batch_ran = false;
+    p->ran_mode = reduce;
+    return OWQS_OK;
+  }
+  p->out_in_order = false;
   // profiling: ev[2i] before step i's main kernel, ev[2i+1] after it (before
   // the FP64 finishing kernel, if any), ev[2i+2] after the step
   std::vector<hipEvent_t> ev;
@@ -833,8 +880,8 @@ owqs_status owqs_set_mode(owqs_pattern *p, owqs_mode mode) {
 }
 
 owqs_status owqs_set_exec(owqs_pattern *p, owqs_exec exec) {
-  if (!p || exec < OWQS_EXEC_PLAIN || exec > OWQS_EXEC_FUSED) return OWQS_E_INVALID_ARG;
-  if (p->exec != exec) p->dirty = true;
+  if (!p || exec < OWQS_EXEC_PLAIN || exec > OWQS_EXEC_AUTO) return OWQS_E_INVALID_ARG;
+  if ((p->exec == OWQS_EXEC_PLAIN) != (exec == OWQS_EXEC_PLAIN)) p->dirty = true;
   p->exec = exec;
   return OWQS_OK;
 }
@@ -1065,8 +1112,8 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
       return fail(p->ctx, OWQS_E_INVALID_ARG, "observable index outside the outputs");
   owqs_status st = ensure_device(p, false);
   if (st != OWQS_OK) return st;
-  if (p->exec != OWQS_EXEC_FUSED) {
-    p->exec = OWQS_EXEC_FUSED;
+  if (p->exec == OWQS_EXEC_PLAIN) {
+    p->exec = OWQS_EXEC_AUTO;
     p->dirty = true;
   }
   if (p->dirty) compile(p);
@@ -1161,7 +1208,9 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
     d[i].b1 = (uint8_t)x.b1;
     d[i].m_index = x.m_index;
     d[i].host_factor = (float)x.host_factor;
-    d[i].pp = (x.pp.swap ? 1u : 0u) | (x.pp.neg0 ? 2u : 0u) | (x.pp.neg1 ? 4u : 0u);
+    d[i].pp = (x.win.swap ? 1u : 0u) | (x.win.neg0 ? 2u : 0u) | (x.win.neg1 ? 4u : 0u) | (x.win.vw_even ? 8u : 0u);
+    d[i].mask_b = x.win.mask_b;
+    d[i].mask_o1 = x.win.mask_o1;
   }
   std::vector<size_t> win_of(ns, SIZE_MAX);
   for (size_t q = 0; q < nwin; ++q) win_of[wins[q]] = q;
@@ -1234,6 +1283,15 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
   hipError_t e;
+  if (p->out_in_order) {
+    e = hipMemcpyAsync(out, p->psi, n_amps * sizeof(float2),
+                       out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+    if (out_on_device) return OWQS_OK;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+    return owqs_check(p, stream);
+  }
   if (out_on_device) {
     e = launch_read(p->psi, static_cast<float2 *>(out), (int)nout, p->final_where.data(), p->final_factor, sigma, s);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "read");

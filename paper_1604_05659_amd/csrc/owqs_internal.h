@@ -38,10 +38,19 @@ struct MeasureArgs {
   DevBook book;
 };
 
-// Signed 2x2 permutation applied to a window's two outputs (X/Z on the new
-// qubit folded in): first swap if `swap`, then negate entry 0 / entry 1.
-struct PostPerm {
+// Shape of a window  N w; E...; M v; (X|Z on w)*  executed as one 2x2 update
+// of v's slot (w takes that slot).  With a = psi[v = 0], b = psi[v = 1] at the
+// index j of the other slots:
+//   o0 = f (a + c sb b),  o1 = so1 f (a + s c sb b),
+// sb = (-1)^parity(j & mask_b) (the E(v, x) with x != w), so1 =
+// (-1)^parity(j & mask_o1) (the E(w, y) with y != v), s = -1 when E(v, w)
+// occurs an odd number of times; then the folded corrections: swap (o0, o1)
+// if `swap`, negate o0 / o1 if neg0 / neg1.
+struct Window {
+  uint64_t mask_b;
+  uint64_t mask_o1;
   int swap, neg0, neg1;
+  int vw_even;  // 1: E(v, w) occurs an even number of times (s = +1)
 };
 
 // One compiled step in device memory, for the kernels that walk a command
@@ -51,8 +60,21 @@ struct DevStep {
   int32_t m_index;          // M / window: index of the measurement
   float2 coef;              // M / window: (-1)^o e^{-i theta}
   float host_factor;        // M / window: (1/sqrt 2)^(pending N)
-  uint32_t pp;              // window: bit 0 swap, bit 1 negate 0, bit 2 negate 1
-};
+  uint32_t pp;              // window: bit 0 swap, bit 1 negate 0, bit 2 negate 1, bit 3 vw_even
+  uint64_t mask_b;          // window: see Window
+  uint64_t mask_o1;
+};  // 40 bytes
+
+__host__ __device__ inline Window window_of(const DevStep &st) {
+  Window w{};
+  w.mask_b = st.mask_b;
+  w.mask_o1 = st.mask_o1;
+  w.swap = int(st.pp & 1u);
+  w.neg0 = int((st.pp >> 1) & 1u);
+  w.neg1 = int((st.pp >> 2) & 1u);
+  w.vw_even = int((st.pp >> 3) & 1u);
+  return w;
+}
 
 enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5 };
 
@@ -82,7 +104,7 @@ hipError_t launch_pauli_z(float2 *psi, int n, int b, hipStream_t s);
 // unless the mode skips probabilities); *grid receives its block count.
 // launch_finish then reduces the partials (no-op when the mode skips them).
 hipError_t launch_measure(float2 *psi, int n, int b, const MeasureArgs &a, hipStream_t s, unsigned *grid);
-hipError_t launch_jwindow(float2 *psi, int n, int b, const MeasureArgs &a, PostPerm pp, hipStream_t s,
+hipError_t launch_jwindow(float2 *psi, int n, int b, const MeasureArgs &a, const Window &win, hipStream_t s,
                           unsigned *grid);
 hipError_t launch_finish(const MeasureArgs &a, unsigned nparts, hipStream_t s);
 hipError_t launch_read(const float2 *psi, float2 *out, int nout, const int *where, double host_factor,

@@ -17,8 +17,9 @@
 //            probability reduced in the same pass.  In place: the vector
 //            halves by moving the top qubit into the measured slot, so the
 //            pass reads every amplitude once and writes half of them.
-//   jwindow  (N w; E u w; M u; X/Z on w): the same window done as one 2x2
-//            update of slot(u) in place (the new qubit w takes u's slot).
+//   jwindow  (N w; E's on v or w; M v; X/Z on w): the same window done as
+//            one 2x2 update of slot(v) in place (the new qubit w takes v's
+//            slot); E's touching other qubits become index-parity signs.
 //   read     : gather the outputs into the caller's bit order, scaled by the
 //            FP64 factor.
 #include <climits>
@@ -412,13 +413,29 @@ __global__ void k_measure_small(float2 *psi, int n, int b, MeasureArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Window N w; E u w; M u; (X|Z on w)*: with a = psi[bit b = 0], b' = psi[b = 1]
-//   o0 = f (a + c b'),  o1 = f (a - c b')   (the E negates the w = 1 branch)
-// then the folded corrections permute/negate (o0, o1); w takes slot b.
+// Window N w; E...; M v; (X|Z on w)*: one in-place 2x2 pass over v's slot b
+// (see Window): o0 = f (a + c sb b), o1 = so1 f (a + s c sb b), then the
+// folded corrections; w takes slot b.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float sgn_of(uint64_t j, uint64_t mask) {
+  return (__popcll(j & mask) & 1) ? -1.f : 1.f;
+}
+
+__device__ __forceinline__ void window_pair(float2 a, float2 bb, uint64_t j, float2 c, float f, const Window &w,
+                                            float2 &o0, float2 &o1) {
+  const float sb = sgn_of(j, w.mask_b), so1 = sgn_of(j, w.mask_o1);
+  float2 cb = make_float2(sb * (c.x * bb.x - c.y * bb.y), sb * (c.x * bb.y + c.y * bb.x));
+  o0 = make_float2(f * (a.x + cb.x), f * (a.y + cb.y));
+  const float s = w.vw_even ? 1.f : -1.f;
+  o1 = make_float2(so1 * f * (a.x + s * cb.x), so1 * f * (a.y + s * cb.y));
+  if (w.swap) { const float2 t = o0; o0 = o1; o1 = t; }
+  if (w.neg0) o0 = make_float2(-o0.x, -o0.y);
+  if (w.neg1) o1 = make_float2(-o1.x, -o1.y);
+}
+
 template <bool kB0>
 __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, uint64_t units, int b,
-                                                     MeasureArgs a, PostPerm pp) {
+                                                     MeasureArgs a, Window win) {
   const float f = scale_of(a);
   const float2 c = a.coef;
   const uint64_t step = uint64_t(1) << b;
@@ -440,14 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, ui
       for (int k = 0; k < kUnroll; ++k) {
         const uint64_t u = base_ + uint64_t(k) * kBlock;
         if (u < units) {
-          float2 p0 = axpc(lo2(A[k]), c, lo2(B[k]), f), q0 = axmc(lo2(A[k]), c, lo2(B[k]), f);
-          float2 p1 = axpc(hi2(A[k]), c, hi2(B[k]), f), q1 = axmc(hi2(A[k]), c, hi2(B[k]), f);
-          if (pp.swap) {
-            float2 t = p0; p0 = q0; q0 = t;
-            t = p1; p1 = q1; q1 = t;
-          }
-          if (pp.neg0) { p0 = make_float2(-p0.x, -p0.y); p1 = make_float2(-p1.x, -p1.y); }
-          if (pp.neg1) { q0 = make_float2(-q0.x, -q0.y); q1 = make_float2(-q1.x, -q1.y); }
+          float2 p0, q0, p1, q1;
+          window_pair(lo2(A[k]), lo2(B[k]), j[k], c, f, win, p0, q0);
+          window_pair(hi2(A[k]), hi2(B[k]), j[k] + 1, c, f, win, p1, q1);
           st4(psi, j[k], pack(p0, p1));
           st4(psi, j[k] + step, pack(q0, q1));
           acc += nrm2(p0) + nrm2(p1) + nrm2(q0) + nrm2(q1);
@@ -464,10 +476,8 @@ __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, ui
       for (int k = 0; k < kUnroll; ++k) {
         const uint64_t u = base_ + uint64_t(k) * kBlock;
         if (u < units) {
-          float2 p = axpc(lo2(X[k]), c, hi2(X[k]), f), q = axmc(lo2(X[k]), c, hi2(X[k]), f);
-          if (pp.swap) { const float2 t = p; p = q; q = t; }
-          if (pp.neg0) p = make_float2(-p.x, -p.y);
-          if (pp.neg1) q = make_float2(-q.x, -q.y);
+          float2 p, q;
+          window_pair(lo2(X[k]), hi2(X[k]), 2 * u, c, f, win, p, q);
           st4(psi, 2 * u, pack(p, q));
           acc += nrm2(p) + nrm2(q);
         }
@@ -585,17 +595,17 @@ hipError_t launch_measure(float2 *psi, int n, int b, const MeasureArgs &a, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_jwindow(float2 *psi, int n, int b, const MeasureArgs &a, PostPerm pp, hipStream_t s,
+hipError_t launch_jwindow(float2 *psi, int n, int b, const MeasureArgs &a, const Window &win, hipStream_t s,
                           unsigned *grid) {
   unsigned g;
   if (b >= 1) {
     const uint64_t units = uint64_t(1) << (n - 2);
     g = grid_for(units);
-    hipLaunchKernelGGL(k_jwindow<false>, dim3(g), dim3(kBlock), 0, s, psi, units, b, a, pp);
+    hipLaunchKernelGGL(k_jwindow<false>, dim3(g), dim3(kBlock), 0, s, psi, units, b, a, win);
   } else {
     const uint64_t units = uint64_t(1) << (n - 1);
     g = grid_for(units);
-    hipLaunchKernelGGL(k_jwindow<true>, dim3(g), dim3(kBlock), 0, s, psi, units, b, a, pp);
+    hipLaunchKernelGGL(k_jwindow<true>, dim3(g), dim3(kBlock), 0, s, psi, units, b, a, win);
   }
   *grid = g;
   return hipGetLastError();

@@ -22,7 +22,7 @@ torch = pytest.importorskip("torch")
 owqs = pytest.importorskip("paper_1604_05659_amd")
 
 MODES = {"owqs": owqs.MODE_OWQS, "eowqs": owqs.MODE_EOWQS}
-EXECS = {"plain": owqs.EXEC_PLAIN, "fused": owqs.EXEC_FUSED}
+EXECS = {"plain": owqs.EXEC_PLAIN, "fused": owqs.EXEC_FUSED, "auto": owqs.EXEC_AUTO}
 
 
 @pytest.fixture(scope="module")
@@ -153,6 +153,39 @@ def test_j_window_every_bit(ctx, n):
                     got, p = gpu(ctx, pat, [o], inp, mode, ex)
                     want, pw = oracle(pat, [o], inp, mode)
                     assert_close(got, want, what=f"J n={n} b={b} o={o} mode={mode} ex={ex}")
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 13, 17])
+def test_generalized_windows(ctx, n):
+    """N w; E's on v or w (to other qubits too, E(v, w) an odd or even number
+    of times); M v; X/Z on w: fused windows with index-parity signs."""
+    g = np.random.default_rng(8000 + n)
+    inp = gaussian(n, 9000 + n)
+    qs = list(range(n))
+    for trial in range(6):
+        v = int(g.integers(n))
+        others = [q for q in qs if q != v]
+        cmds = [("N", n)]
+        es = [("E", v, n)]
+        if trial % 3 == 1:
+            es.append(("E", n, v))          # E(v, w) twice: they cancel
+        elif trial % 3 == 2:
+            es += [("E", n, v), ("E", v, n)]  # three times: one CZ
+        for x in g.choice(others, size=min(len(others), int(g.integers(0, 3))), replace=False) if others else []:
+            es.append(("E", v, int(x)))
+        for y in g.choice(others, size=min(len(others), int(g.integers(0, 3))), replace=False) if others else []:
+            es.append(("E", n, int(y)))
+        g.shuffle(es)
+        cmds += [tuple(e) for e in es]
+        cmds.append(("M", v, float(g.uniform(0, 2 * math.pi)), (), ()))
+        cmds += [("Z", n, (v,)), ("X", n, (v,))] if trial % 2 else [("X", n, (v,))]
+        pat = W.Pattern(qs, [q for q in qs if q != v] + [n], cmds)
+        for o in (0, 1):
+            want, pw = oracle(pat, [o], inp)
+            for ex in EXECS.values():
+                got, p = gpu(ctx, pat, [o], inp, owqs.MODE_OWQS, ex)
+                assert_close(got, want, what=f"window n={n} trial={trial} o={o} ex={ex}")
+                np.testing.assert_allclose(p, pw, atol=P_TOL)
 
 
 def test_random_patterns(ctx):
