@@ -230,7 +230,7 @@ def bench_recognition(owqs, torch, W, ctx, steps):
     torch.cuda.synchronize()
     t_p = (time.perf_counter() - t0) / n_sample
     diff = float((col - out[n_sample - 1]).abs().max().item())
-    w, _ = p.plan_info()
+    w = p.plan_info()[0]
     p.close()
     return {
         "workload": "recognition: 12 inputs, 300 J + 60 CZ (1260 commands), all 4096 basis inputs, EOWQS",
@@ -259,7 +259,7 @@ def bench_adjoint(owqs, torch, W, ctx, steps):
         loss, grad = p.adjoint(sets)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    w, nsteps = p.plan_info()
+    w = p.plan_info()[0]
     p.close()
     return {
         "workload": "layered ansatz, 16 qubits, 25 layers (400 angles), 64 angle sets, loss sum_i <Z_i>, EOWQS",
@@ -295,7 +295,7 @@ def bench_cluster(owqs, torch, W, ctx, steps):
         t = (time.perf_counter() - t0) / steps
         p.check()
         res[name] = {"ms_per_run": round(1e3 * t, 3), "commands_per_s": round(nt / t, 1),
-                     "plan_steps": p.plan_info()[1]}
+                     "plan_steps": p.plan_info()[1], "passes": p.plan_info()[2]}
     p.close()
     return res
 
@@ -441,10 +441,13 @@ def main():
         result["kernels"] = kernel_table(prof)
 
     if not args.no_fused:
-        log("[bench] fused executor")
+        log("[bench] fused executor (tile size picked by the autotuner)")
+        pat.set_exec(owqs.EXEC_FUSED)
+        tile_bits, _ = pat.tune(inp)
         wall_f, ev_f, prof_f = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_FUSED, args.steps, args.warmup,
                                          not args.no_profile)
         probs_f = pat.read_probs()
+        fused_passes = pat.plan_info()[2]
         fused_out = out.clone()
         pat.set_exec(owqs.EXEC_PLAIN)
         pat.run(inp)
@@ -456,6 +459,8 @@ def main():
             "unit": "commands/s",
             "ms_per_step": round(ms_f, 3),
             "live_width": 24,
+            "tile_bits": tile_bits,
+            "passes": fused_passes,
             "max_abs_diff_vs_plain": diff,
             "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
         }

@@ -96,9 +96,11 @@ typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 
 /* Execution plan.  PLAIN: one kernel per non-trivial command, the live width
  * growing on N and shrinking on M.  FUSED: windows of commands are merged
  * into single passes over the state (N w; E u w; ...; M u; corrections on w
- * becomes one 2x2 update in place).  AUTO (default): the fused plan, run as
- * one workgroup with the whole vector in LDS when its width is <= 14, else
- * as FUSED.  All give the same result to FP32 rounding. */
+ * becomes one 2x2 update in place), and at live widths >= 18 runs of
+ * windows/E/X/Z whose paired slots fit an LDS tile run as one
+ * pass per run (2^12-amplitude tiles by default).  AUTO (default): the fused plan, run as one workgroup with
+ * the whole vector in LDS when its width is <= 14, else as FUSED.  All give
+ * the same result to FP32 rounding. */
 typedef enum { OWQS_EXEC_PLAIN = 0, OWQS_EXEC_FUSED = 1, OWQS_EXEC_AUTO = 2 } owqs_exec;
 
 typedef struct owqs_ctx owqs_ctx;
@@ -179,11 +181,26 @@ owqs_status owqs_check(owqs_pattern *pat, void *stream);
  * the input copy stays outside it. */
 owqs_status owqs_set_graph(owqs_pattern *pat, int enable);
 
+/* Tile size of the fused passes: 2^bits amplitudes per LDS tile, bits in
+ * 10..13, or 0 for the default min(12, width - 8).  Larger tiles chain more
+ * commands per pass; smaller ones fit more workgroups per CU. */
+owqs_status owqs_set_tile_bits(owqs_pattern *pat, int32_t bits);
+
+/* Autotuner: time the pattern (3 runs after a warm-up, HIP events on
+ * `stream`) with every tile size 10..13 of the fused passes and keep the
+ * fastest (owqs_set_tile_bits).  Plans without tile passes return at once
+ * with *best_ms = 0.  The runs overwrite the pattern's state.  Either output
+ * pointer may be NULL. */
+owqs_status owqs_tune(owqs_pattern *pat, const void *input_c64, size_t n_amps, int input_on_device,
+                      void *stream, int32_t *best_bits, float *best_ms);
+
 /* Compile the plan for the current settings (if needed) and report the
  * largest live width it reaches (plain plans: max_live; fused windows keep
- * the width of the window's input) and its number of device steps.  Either
+ * the width of the window's input), its number of steps (one per
+ * non-trivial command or fused window) and the number of passes over the
+ * state in global memory (steps after grouping runs into tile passes).  Any
  * pointer may be NULL. */
-owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps);
+owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps, size_t *npasses);
 
 /* Recognition problem (Sec. 1: which unitary does a pattern implement):
  * run the pattern on the computational-basis inputs |first>, ...,
@@ -245,6 +262,7 @@ enum {
   OWQS_KIND_Z = 4,      /* 8 * 2^n */
   OWQS_KIND_J = 5,      /* fused window N w; E u w; M u; X/Z w: 16 * 2^n */
   OWQS_KIND_FINISH = 6, /* one-block FP64 finish of an M/window probability (bytes not counted) */
+  OWQS_KIND_TILE = 7,   /* a group of windows/E/X/Z steps in one pass: 16 * 2^n */
   OWQS_NUM_KINDS = 8
 };
 

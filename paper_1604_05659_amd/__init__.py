@@ -42,7 +42,7 @@ E_INVALID_ARG, E_PATTERN, E_ZERO_PROB, E_WIDTH, E_NOMEM, E_HIP, E_NOT_DETERMINIS
 MODE_OWQS, MODE_EOWQS, MODE_EOWQS_CHECK = 0, 1, 2
 EXEC_PLAIN, EXEC_FUSED, EXEC_AUTO = 0, 1, 2
 OPS = {"N": 0, "E": 1, "M": 2, "X": 3, "Z": 4}
-KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)"}
+KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)", 7: "tile(group)"}
 NUM_KINDS = 8
 
 
@@ -77,7 +77,10 @@ _sig = {
     "owqs_check": (ctypes.c_int, [_vp, _vp]),
     "owqs_read_probs": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _vp]),
     "owqs_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
-    "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t)]),
+    "owqs_set_tile_bits": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "owqs_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _i32p,
+                                 ctypes.POINTER(ctypes.c_float)]),
+    "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "owqs_run_basis": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_states": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
@@ -192,12 +195,24 @@ class Pattern:
     def set_graph(self, enable: bool):
         self.ctx.check(_lib.owqs_set_graph(self._h, 1 if enable else 0))
 
+    def set_tile_bits(self, bits: int):
+        self.ctx.check(_lib.owqs_set_tile_bits(self._h, int(bits)))
+
+    def tune(self, psi_in=None, stream=None):
+        """Pick the fastest tile size for this pattern; returns (bits, ms per run)."""
+        b = ctypes.c_int32()
+        t = ctypes.c_float()
+        ptr, n = (None, 1) if psi_in is None else (psi_in.data_ptr(), psi_in.numel())
+        self.ctx.check(_lib.owqs_tune(self._h, ptr, n, 1, _stream_handle(stream), ctypes.byref(b), ctypes.byref(t)))
+        return b.value, t.value
+
     def plan_info(self):
-        """(plan width, number of device steps) for the current settings."""
+        """(plan width, steps, passes over global memory) for the current settings."""
         w = ctypes.c_int32()
         n = ctypes.c_size_t()
-        self.ctx.check(_lib.owqs_plan_info(self._h, ctypes.byref(w), ctypes.byref(n)))
-        return w.value, n.value
+        x = ctypes.c_size_t()
+        self.ctx.check(_lib.owqs_plan_info(self._h, ctypes.byref(w), ctypes.byref(n), ctypes.byref(x)))
+        return w.value, n.value, x.value
 
     def run_basis(self, first: int = 0, count: Optional[int] = None, out=None, probs=None, stream=None):
         """Outputs for basis inputs |first> .. |first+count-1> as a

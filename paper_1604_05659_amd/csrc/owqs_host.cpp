@@ -44,7 +44,7 @@ struct owqs_ctx {
 
 namespace {
 
-enum StepKind : int { S_N = 0, S_E = 1, S_M = 2, S_X = 3, S_Z = 4, S_J = 5 };
+enum StepKind : int { S_N = 0, S_E = 1, S_M = 2, S_X = 3, S_Z = 4, S_J = 5, S_F = 7 };
 
 struct Step {
   int kind;
@@ -55,6 +55,13 @@ struct Step {
   int m_index;
   Window win;
   int sig_s, sig_t, outcome;  // M / window: resolved signals and forced outcome
+  int group;                  // S_F: index into the pattern's tile groups
+};
+
+struct TileGroup {
+  TileArgs ta;
+  size_t op_off;  // first FuseOp of the group in the pattern's table
+  size_t m_off;   // first window's measurement index in the pattern's m table
 };
 
 struct Cmd {
@@ -84,6 +91,17 @@ struct owqs_pattern {
   std::vector<int> final_where;  // slot of outputs[k]
   double final_factor = 1.0;
   int plan_width = 0;            // largest live width the plan reaches
+
+  int tile_bits = 0;  // 0: automatic (min(12, n - 8)); else 10..13
+  // execution steps of the global-memory path: the plan with runs of
+  // window/E/X/Z steps grouped into tile passes (S_F)
+  std::vector<Step> xsteps;
+  std::vector<TileGroup> groups;
+  std::vector<FuseOp> fuse_ops;
+  std::vector<int> fuse_m;        // measurement index of every window of every group
+  FuseOp *dev_fuse = nullptr;     // fuse_ops, then fuse_m (as int) in one allocation
+  size_t dev_fuse_cap = 0;
+  bool dev_fuse_valid = false;
 
   // the plan as a device command table (LDS-resident runs)
   DevStep *dev_steps = nullptr;
@@ -190,6 +208,122 @@ int signal(const std::vector<int> &dom, const std::vector<int> &outcome_of) {
   int s = 0;
   for (int j : dom) s ^= outcome_of[j];
   return s;
+}
+
+// Group runs of window/E/X/Z steps at one width >= kTileMinWidth into tile
+// passes (see owqs_tile.hip).  A run ends at N or M steps, at a width change,
+// when a new mixing slot would not fit the tile, or when it holds the largest
+// number of windows that one pass may chain (16 when probabilities are
+// computed: the windows of a pass are not renormalised one by one, and 16
+// windows keep the FP32 norm in range down to p ~ 1e-4 per window).
+void group_tiles(owqs_pattern *p) {
+  p->xsteps.clear();
+  p->groups.clear();
+  p->fuse_ops.clear();
+  p->fuse_m.clear();
+  const size_t ns = p->steps.size();
+  const bool fused = p->exec != OWQS_EXEC_PLAIN;
+  const int win_cap = p->mode == OWQS_MODE_EOWQS ? kMaxGroupWindows : 16;
+  auto groupable = [](int k) { return k == S_J || k == S_E || k == S_X || k == S_Z; };
+  size_t i = 0;
+  while (i < ns) {
+    const Step &x0 = p->steps[i];
+    if (!fused || !groupable(x0.kind) || x0.n < kTileMinWidth) {
+      p->xsteps.push_back(x0);
+      ++i;
+      continue;
+    }
+    const int n = x0.n;
+    int k = std::min(kDefaultTileBits, n - 8);
+    if (p->tile_bits) k = std::min(p->tile_bits, n - 2);
+    uint64_t tmask = (uint64_t(1) << kLowBits) - 1;
+    int used = kLowBits, nwin = 0;
+    size_t j = i;
+    for (; j < ns; ++j) {
+      const Step &x = p->steps[j];
+      if (!groupable(x.kind) || x.n != n) break;
+      if (x.kind == S_J && nwin == win_cap) break;
+      if (j - i == 128) break;
+      if (x.kind == S_J || x.kind == S_X) {
+        const uint64_t bit = uint64_t(1) << x.b0;
+        if (!(tmask & bit)) {
+          if (used == k) break;
+          tmask |= bit;
+          ++used;
+        }
+      }
+      nwin += x.kind == S_J;
+    }
+    if (j - i < 2) {
+      p->xsteps.push_back(x0);
+      ++i;
+      continue;
+    }
+    // fill the tile up to k bits with the lowest unused slots (more work per pass)
+    for (int b = 0; used < k && b < n; ++b)
+      if (!(tmask & (uint64_t(1) << b))) {
+        tmask |= uint64_t(1) << b;
+        ++used;
+      }
+    TileGroup tg{};
+    tg.ta.n = n;
+    tg.ta.k = k;
+    int local_of[64];
+    for (int b = 0, li = 0, oi = 0; b < n; ++b) {
+      if (tmask & (uint64_t(1) << b)) {
+        tg.ta.tpos[li] = (uint8_t)b;
+        local_of[b] = li++;
+      } else {
+        tg.ta.opos[oi++] = (uint8_t)b;
+        local_of[b] = -1;
+      }
+    }
+    auto split = [&](uint64_t gmask, uint32_t &lm, uint64_t &om) {
+      lm = 0;
+      om = 0;
+      for (int b = 0; b < n; ++b)
+        if (gmask & (uint64_t(1) << b)) {
+          if (local_of[b] >= 0) lm |= 1u << local_of[b];
+          else om |= uint64_t(1) << b;
+        }
+    };
+    tg.op_off = p->fuse_ops.size();
+    tg.m_off = p->fuse_m.size();
+    int widx = 0;
+    for (size_t q = i; q < j; ++q) {
+      const Step &x = p->steps[q];
+      FuseOp op{};
+      op.kind = (uint8_t)x.kind;
+      if (x.kind == S_J) {
+        op.lb = (uint8_t)local_of[x.b0];
+        op.flags = (x.win.swap ? 1 : 0) | (x.win.neg0 ? 2 : 0) | (x.win.neg1 ? 4 : 0) | (x.win.vw_even ? 8 : 0) |
+                   (widx == 0 ? 16 : 0);
+        op.widx = (uint8_t)widx++;
+        op.m_index = x.m_index;
+        p->fuse_m.push_back(x.m_index);
+        op.coef = x.coef;
+        op.f = (float)x.host_factor;
+        split(x.win.mask_b, op.lmask_b, op.omask_b);
+        split(x.win.mask_o1, op.lmask_o1, op.omask_o1);
+      } else if (x.kind == S_X) {
+        op.lb = (uint8_t)local_of[x.b0];
+      } else if (x.kind == S_E) {
+        split((uint64_t(1) << x.b0) | (uint64_t(1) << x.b1), op.lmask_b, op.omask_b);
+      } else {  // S_Z
+        split(uint64_t(1) << x.b0, op.lmask_b, op.omask_b);
+      }
+      p->fuse_ops.push_back(op);
+    }
+    tg.ta.nops = (int)(j - i);
+    tg.ta.nwin = widx;
+    Step gs{};
+    gs.kind = S_F;
+    gs.n = n;
+    gs.group = (int)p->groups.size();
+    p->groups.push_back(tg);
+    p->xsteps.push_back(gs);
+    i = j;
+  }
 }
 
 // Compile the command list into device steps for the current settings.
@@ -364,8 +498,10 @@ void compile(owqs_pattern *p) {
   int w = std::max<int>((int)p->inputs.size(), (int)p->outputs.size());
   for (const Step &x : p->steps) w = std::max(w, x.n + (x.kind == S_N ? 1 : 0));
   p->plan_width = std::max(w, 1);
+  group_tiles(p);
   p->dirty = false;
   p->dev_steps_valid = false;
+  p->dev_fuse_valid = false;
   if (p->graph_exec || p->graph) (void)hipDeviceSynchronize();  // a replay may still be in flight
   if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
@@ -485,18 +621,24 @@ double step_bytes(const Step &x) {
     case S_X: return 2.0 * a;
     case S_Z: return 1.0 * a;
     case S_J: return 2.0 * a;
+    case S_F: return 2.0 * a;  // one read and one write of the vector
   }
   return 0.0;
 }
 
 // Enqueue every step of the plan on `s`; with `ev`, record events around the
 // main kernel and the finishing kernel of each step (see run_impl).
+int *fuse_m_dev(owqs_pattern *p) { return reinterpret_cast<int *>(p->dev_fuse + p->fuse_ops.size()); }
+
 hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev) {
   hipError_t e = hipSuccess;
-  for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
-    const Step &x = p->steps[i];
+  for (size_t i = 0; i < p->xsteps.size() && e == hipSuccess; ++i) {
+    const Step &x = p->xsteps[i];
     MeasureArgs a{};
+    a.reduce = reduce;
+    a.book = p->book;
     unsigned grid = 0;
+    const FuseOp *ops = nullptr;
     switch (x.kind) {
       case S_N: e = launch_prepare(p->psi, x.n, s); break;
       case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
@@ -506,19 +648,56 @@ hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<
       case S_J:
         a.coef = x.coef;
         a.host_factor = x.host_factor;
-        a.reduce = reduce;
         a.m_index = x.m_index;
-        a.book = p->book;
         e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
                           : launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &grid);
         break;
+      case S_F: {
+        const TileGroup &tg = p->groups[x.group];
+        ops = p->dev_fuse + tg.op_off;
+        e = launch_tile(p->psi, tg.ta, ops, a, s, &grid);
+        break;
+      }
       default: break;
     }
     if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
     if ((x.kind == S_M || x.kind == S_J) && e == hipSuccess) e = launch_finish(a, grid, s);
+    if (x.kind == S_F && e == hipSuccess) {
+      const TileGroup &tg = p->groups[x.group];
+      e = launch_finish_group(a, fuse_m_dev(p) + tg.m_off, tg.ta.nwin, grid, s);
+    }
     if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
   }
   return e;
+}
+
+// Upload the tile groups' command table: FuseOps, then the windows'
+// measurement indices.
+owqs_status upload_fuse(owqs_pattern *p) {
+  if (p->dev_fuse_valid) return OWQS_OK;
+  static const hipError_t prep = tile_prepare();  // once per process, outside any capture
+  if (prep != hipSuccess) return hip_fail(p->ctx, prep, "tile kernel attribute");
+  const size_t mints = (p->fuse_m.size() * sizeof(int) + sizeof(FuseOp) - 1) / sizeof(FuseOp);
+  const size_t need = std::max<size_t>(p->fuse_ops.size() + mints, 1);
+  hipError_t e = hipSuccess;
+  if (p->dev_fuse_cap < need) {
+    if (p->dev_fuse) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p->dev_fuse);
+    }
+    p->dev_fuse = nullptr;
+    p->dev_fuse_cap = 0;
+    e = hipMalloc(&p->dev_fuse, need * sizeof(FuseOp));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "fused command table");
+    p->dev_fuse_cap = need;
+  }
+  if (!p->fuse_ops.empty())
+    e = hipMemcpy(p->dev_fuse, p->fuse_ops.data(), p->fuse_ops.size() * sizeof(FuseOp), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->fuse_m.empty())
+    e = hipMemcpy(fuse_m_dev(p), p->fuse_m.data(), p->fuse_m.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "fused command table upload");
+  p->dev_fuse_valid = true;
+  return OWQS_OK;
 }
 
 // Upload the plan as a DevStep table (for the LDS-resident kernels).
@@ -611,18 +790,20 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
     return OWQS_OK;
   }
   p->out_in_order = false;
+  st = upload_fuse(p);
+  if (st != OWQS_OK) return st;
   // profiling: ev[2i] before step i's main kernel, ev[2i+1] after it (before
   // the FP64 finishing kernel, if any), ev[2i+2] after the step
   std::vector<hipEvent_t> ev;
   if (prof) {
-    ev.resize(2 * p->steps.size() + 1);
+    ev.resize(2 * p->xsteps.size() + 1);
     for (auto &x : ev) {
       e = hipEventCreate(&x);
       if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
     }
     e = hipEventRecord(ev[0], s);
     if (e == hipSuccess) e = launch_steps(p, reduce, s, &ev);
-  } else if (p->use_graph && !p->steps.empty()) {
+  } else if (p->use_graph && !p->xsteps.empty()) {
     if (!p->graph_exec) {
       if (!p->cap_stream) {
         e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -654,15 +835,15 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
   p->ran_mode = reduce;
   if (prof) {
     e = hipStreamSynchronize(s);
-    for (size_t i = 0; i < p->steps.size() && e == hipSuccess; ++i) {
+    for (size_t i = 0; i < p->xsteps.size() && e == hipSuccess; ++i) {
       float t = 0.f, f = 0.f;
       e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
       if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * i + 1], ev[2 * i + 2]);
-      const int k = p->steps[i].kind;
+      const int k = p->xsteps[i].kind;
       prof->counts[k] += 1;
       prof->ms[k] += t;
-      prof->bytes[k] += step_bytes(p->steps[i]);
-      if ((k == S_M || k == S_J) && reduce != kReduceNone) {
+      prof->bytes[k] += step_bytes(p->xsteps[i]);
+      if ((k == S_M || k == S_J || k == S_F) && reduce != kReduceNone) {
         prof->counts[OWQS_KIND_FINISH] += 1;
         prof->ms[OWQS_KIND_FINISH] += f;
       }
@@ -854,6 +1035,7 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   }
   if (p->stage) (void)hipFree(p->stage);
   if (p->dev_steps) (void)hipFree(p->dev_steps);
+  if (p->dev_fuse) (void)hipFree(p->dev_fuse);
   if (p->adj_mem) (void)hipFree(p->adj_mem);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -921,11 +1103,76 @@ owqs_status owqs_set_graph(owqs_pattern *p, int enable) {
   return OWQS_OK;
 }
 
-owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps) {
+owqs_status owqs_set_tile_bits(owqs_pattern *p, int32_t bits) {
+  if (!p || (bits != 0 && (bits < 10 || bits > kMaxTileBits))) return OWQS_E_INVALID_ARG;
+  if (p->tile_bits != bits) p->dirty = true;
+  p->tile_bits = bits;
+  return OWQS_OK;
+}
+
+owqs_status owqs_tune(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
+                      int32_t *best_bits, float *best_ms) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (p->dirty) compile(p);
+  // only plans with tile passes have a schedule to choose
+  bool tiled = p->exec != OWQS_EXEC_PLAIN && !(p->exec == OWQS_EXEC_AUTO && p->plan_width <= kLdsMaxWidth);
+  if (tiled) {
+    tiled = false;
+    for (const Step &x : p->steps) tiled |= x.n >= kTileMinWidth && (x.kind == S_J || x.kind == S_E);
+  }
+  if (!tiled) {
+    if (best_bits) *best_bits = p->tile_bits;
+    if (best_ms) *best_ms = 0.f;
+    return OWQS_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "tune events");
+  const int keep = p->tile_bits;
+  int best = keep;
+  float best_t = 0.f;
+  owqs_status st = OWQS_OK;
+  for (int bits = 10; bits <= kMaxTileBits && st == OWQS_OK; ++bits) {
+    owqs_set_tile_bits(p, bits);
+    st = owqs_run(p, input, n_amps, input_on_device, stream);  // capture / warm-up
+    if (st != OWQS_OK) break;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && st == OWQS_OK && e == hipSuccess; ++r)
+      st = owqs_run(p, input, n_amps, input_on_device, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) break;
+    if (best_t == 0.f || t < best_t) {
+      best_t = t;
+      best = bits;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != OWQS_OK) {
+    owqs_set_tile_bits(p, keep);
+    return st;
+  }
+  if (e != hipSuccess) {
+    owqs_set_tile_bits(p, keep);
+    return hip_fail(p->ctx, e, "tune");
+  }
+  owqs_set_tile_bits(p, best);
+  if (best_bits) *best_bits = best;
+  if (best_ms) *best_ms = best_t / 3.f;
+  return OWQS_OK;
+}
+
+owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps, size_t *npasses) {
   if (!p) return OWQS_E_INVALID_ARG;
   if (p->dirty) compile(p);
   if (plan_width) *plan_width = p->plan_width;
   if (nsteps) *nsteps = p->steps.size();
+  if (npasses) *npasses = p->xsteps.size();
   return OWQS_OK;
 }
 

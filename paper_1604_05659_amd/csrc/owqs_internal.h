@@ -78,6 +78,36 @@ __host__ __device__ inline Window window_of(const DevStep &st) {
 
 enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5 };
 
+// ---- tile fusion (owqs_tile.hip)
+constexpr int kLowBits = 5;            // slots 0..4 are always in a tile (256-byte runs)
+constexpr int kMaxTileBits = 13;       // 2^13 complex64 = 64 KiB of LDS
+constexpr int kDefaultTileBits = 12;   // 32 KiB tiles: four workgroups per CU
+constexpr int kTileMinWidth = 18;      // narrower vectors have too few tiles to fill the chip
+constexpr int kMaxGroupWindows = 32;
+constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
+
+// One command of a fused group, with its slots mapped into the tile.
+struct FuseOp {
+  uint8_t kind;      // DK_J, DK_X, DK_E, DK_Z
+  uint8_t lb;        // J, X: local (tile) bit of the mixing slot
+  uint8_t flags;     // J: bit 0 swap, 1 negate o0, 2 negate o1, 3 vw_even, 4 apply sigma
+  uint8_t widx;      // J: index of the window inside its group
+  int32_t m_index;   // J: measurement index
+  float2 coef;       // J
+  float f;           // J: host factor
+  uint32_t lmask_b;  // J: local bits of mask_b;  E/Z: local bits that must all be 1
+  uint32_t lmask_o1; // J: local bits of mask_o1
+  uint32_t pad;
+  uint64_t omask_b;  // J: outer bits of mask_b;  E/Z: outer bits that must all be 1
+  uint64_t omask_o1; // J: outer bits of mask_o1
+};  // 48 bytes
+
+struct TileArgs {
+  int n, k, nops, nwin;
+  uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
+  uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
+};
+
 // One pattern of an LDS-resident batch.
 struct LdsItem {
   const DevStep *steps;
@@ -138,5 +168,15 @@ hipError_t launch_b_loss(const float2 *psi, float2 *lam, size_t stride, int nset
                          int nobs, double ff2, double *partials, hipStream_t s);
 hipError_t launch_b_reduce(const double *partials, int nq, int nsets, int nblk, const int *out_col,
                            const double *scale, double *out, size_t out_stride, hipStream_t s);
+
+
+// ---- owqs_tile.hip: one group of commands in one pass; *grid receives the
+// block count, which launch_finish_group needs to reduce the partials.
+hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const MeasureArgs &a, hipStream_t s,
+                       unsigned *grid);
+hipError_t launch_finish_group(const MeasureArgs &a, const int *m_of_window, int nwin, unsigned nblk,
+                               hipStream_t s);
+// Raise k_tile's dynamic LDS limit to 64 KiB; call outside stream capture.
+hipError_t tile_prepare();
 
 }  // namespace owqs

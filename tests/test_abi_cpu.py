@@ -128,14 +128,15 @@ def test_fused_plan_forms_windows(host_ctx):
     wl = W.plain_large(n_logical=10, n_j=100, n_cz=20)
     p = owqs.Pattern(host_ctx, wl.pattern)
     p.set_exec(owqs.EXEC_FUSED)
-    w, n = p.plan_info()
+    w, n, _ = p.plan_info()
     assert n == 100 + 20 and w == 10
     p.set_exec(owqs.EXEC_PLAIN)
-    w2, n2 = p.plan_info()
+    w2, n2, _ = p.plan_info()
     assert w2 == 11 and n2 == 100 * 3 + 20  # N, E, M per J (X only when its signal is 1) + CZ
     wl = W.cluster(rows=20, cols=200)
     q = owqs.Pattern(host_ctx, wl.pattern)
     q.set_outcomes(wl.outcomes)
     q.set_exec(owqs.EXEC_FUSED)
-    w3, n3 = q.plan_info()
+    w3, n3, x3 = q.plan_info()
     assert w3 <= 21 and n3 < 4400, n3
+    assert x3 < n3  # runs of windows group into tile passes at width >= 18

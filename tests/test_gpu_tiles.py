@@ -1,0 +1,161 @@
+"""GPU parity of the tile-fused passes (runs of windows / E / X / Z at live
+widths >= 18 executed as one LDS-tiled pass each) against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import owqs_workloads as W
+from oracle import core as oc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+owqs = pytest.importorskip("paper_1604_05659_amd")
+
+AMP_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return owqs.Context(0)
+
+
+def _run(ctx, pattern, outcomes, inp, mode, exec_=owqs.EXEC_FUSED):
+    p = owqs.Pattern(ctx, pattern)
+    p.set_mode(mode)
+    p.set_exec(exec_)
+    p.set_outcomes(outcomes)
+    x = None if inp is None else torch.as_tensor(inp).cuda()
+    p.run(x)
+    out = p.read_state().cpu().numpy().astype(np.complex128)
+    probs = p.read_probs()
+    info = p.plan_info()
+    p.close()
+    return out, probs, info
+
+
+def random_windowed_pattern(g, n, n_ops):
+    """n input qubits; a random mix of generalized windows (with E's to other
+    live qubits and X/Z corrections on the new qubit), standalone E, X and Z
+    steps with signals, and an occasional plain N ... M pair that breaks the
+    tile groups."""
+    live = list(range(n))
+    nxt = n
+    measured = []
+    cmds = []
+    for _ in range(n_ops):
+        r = g.random()
+        if r < 0.6:
+            v = live[int(g.integers(len(live)))]
+            w = nxt
+            nxt += 1
+            es = [("E", v, w)]
+            others = [q for q in live if q != v]
+            for x in g.choice(others, size=int(g.integers(0, 3)), replace=False):
+                es.append(("E", v, int(x)))
+            for y in g.choice(others, size=int(g.integers(0, 2)), replace=False):
+                es.append(("E", w, int(y)))
+            g.shuffle(es)
+            s_dom = tuple(int(q) for q in g.choice(measured, size=min(len(measured), 1), replace=False)) \
+                if measured and g.random() < 0.3 else ()
+            cmds += [("N", w)] + [tuple(e) for e in es] + [("M", v, float(g.uniform(0, 2 * math.pi)), s_dom, ())]
+            cmds.append(("X", w, (v,)))
+            if g.random() < 0.5:
+                cmds.append(("Z", w, (v,)))
+            live[live.index(v)] = w
+            measured.append(v)
+        elif r < 0.8:
+            a, b = g.choice(len(live), size=2, replace=False)
+            cmds.append(("E", live[a], live[b]))
+        elif r < 0.95 and measured:
+            q = live[int(g.integers(len(live)))]
+            cmds.append(("X" if g.random() < 0.5 else "Z", q, (measured[int(g.integers(len(measured)))],)))
+        else:
+            # an E between two other qubits inside the run keeps this from
+            # being a window: plain N, E, E, M steps that end the tile group
+            v = live[int(g.integers(len(live)))]
+            u = nxt
+            nxt += 1
+            a, b = [q for q in live if q != v][:2]
+            cmds += [("N", u), ("E", u, v), ("E", a, b), ("M", v, float(g.uniform(0, 2 * math.pi)), (), ())]
+            live[live.index(v)] = u
+            measured.append(v)
+    return W.Pattern(list(range(n)), list(live), cmds)
+
+
+@pytest.mark.parametrize("n", [18, 19, 21])
+@pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS_CHECK, owqs.MODE_EOWQS])
+def test_random_windowed_patterns(ctx, n, mode, parity_report):
+    g = np.random.default_rng(1800 + n)
+    pat = random_windowed_pattern(g, n, 120)
+    inp = W.gaussian_state(n, g)
+    outc = g.integers(0, 2, size=pat.n_meas()).astype(np.uint8)
+    want, pw = oc.run(pat, outc, inp.astype(np.complex128), oc.MODE_OWQS)
+    if mode == owqs.MODE_OWQS:
+        got, probs, info = _run(ctx, pat, outc, inp, mode)
+        assert info[2] < info[1], info      # some runs were grouped
+        err = float(np.max(np.abs(got - want)))
+        parity_report(f"tiles_random_n{n}_owqs", max_amp_err=err, passes=info[2], steps=info[1])
+        assert err <= AMP_TOL, err
+        np.testing.assert_allclose(probs, pw, atol=1e-5)
+    else:
+        # random patterns have no flow: EOWQS keeps the fixed scale, so compare
+        # directions (1 - F) and, in check mode, expect the determinism error
+        p = owqs.Pattern(ctx, pat)
+        p.set_mode(mode)
+        p.set_exec(owqs.EXEC_FUSED)
+        p.set_outcomes(outc)
+        p.run(torch.as_tensor(inp).cuda())
+        out = p.read_state(check=False).cpu().numpy().astype(np.complex128)
+        f = abs(np.vdot(out, want)) ** 2 / (np.vdot(out, out).real * np.vdot(want, want).real)
+        assert 1 - f <= 1e-8, 1 - f
+        if mode == owqs.MODE_EOWQS_CHECK and np.max(np.abs(pw - 0.5)) > 1e-3:
+            with pytest.raises(owqs.OwqsError) as e:
+                p.check()
+            assert e.value.status == owqs.E_NOT_DETERMINISTIC
+        p.close()
+
+
+@pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS])
+def test_flow_circuit_width_19(ctx, mode):
+    wl = W.plain_large(n_logical=19, n_j=300, n_cz=60)
+    want, pw = oc.run(wl.pattern, wl.outcomes, wl.input_state.astype(np.complex128),
+                      oc.MODE_OWQS if mode == owqs.MODE_OWQS else oc.MODE_EOWQS)
+    for ex in (owqs.EXEC_FUSED, owqs.EXEC_AUTO):
+        got, probs, info = _run(ctx, wl.pattern, wl.outcomes, wl.input_state, mode, ex)
+        assert info[2] * 4 < info[1]
+        assert float(np.max(np.abs(got - want))) <= AMP_TOL
+        if mode == owqs.MODE_OWQS:
+            np.testing.assert_allclose(probs, pw, atol=1e-5)
+
+
+def test_cluster_20_rows(ctx, parity_report):
+    wl = W.cluster(rows=20, cols=10)
+    want, pw = oc.run(wl.pattern, wl.outcomes)
+    got, probs, info = _run(ctx, wl.pattern, wl.outcomes, None, owqs.MODE_OWQS)
+    err = float(np.max(np.abs(got - want)))
+    parity_report("cluster20x10_fused_tiles", max_amp_err=err, passes=info[2], steps=info[1])
+    assert info[2] < info[1]
+    assert err <= AMP_TOL
+    np.testing.assert_allclose(probs, pw, atol=1e-5)
+
+
+def test_autotuner_keeps_results(ctx):
+    wl = W.plain_large(n_logical=20, n_j=200, n_cz=40)
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_outcomes(wl.outcomes)
+    x = torch.as_tensor(wl.input_state).cuda()
+    bits, ms = p.tune(x)
+    assert 10 <= bits <= 13 and ms > 0
+    p.run(x)
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    want, _ = oc.run(wl.pattern, wl.outcomes, wl.input_state.astype(np.complex128))
+    assert float(np.max(np.abs(got - want))) <= AMP_TOL
+    # a plan without tile passes has nothing to tune
+    q = owqs.Pattern(ctx, W.plain_small().pattern)
+    assert q.tune() == (0, 0.0)
+    p.close()
+    q.close()
