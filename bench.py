@@ -40,24 +40,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def source_hash(name: str) -> str:
     h = hashlib.sha256()
-    for f in ("owqs_kernels.hip",):
-        with open(os.path.join(ROOT, "paper_1604_05659_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1604_05659_amd", "csrc", name), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on a different kernel source."""
+    """HBM-side bytes per launch from the committed rocprofv3 counter summary
+    (profiles/traffic.json), or None when it is missing or was taken on a
+    different version of the kernel's source file."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     e = d.get(kernel)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != source_hash(e.get("source", "owqs_kernels.hip")):
         return None
     return e.get("bytes_per_launch")
 
@@ -400,7 +400,7 @@ def main():
     inp = torch.as_tensor(wl.input_state).cuda()
     out = torch.empty(1 << len(pat_def.outputs), dtype=torch.complex64, device="cuda")
     names = {"measure(M)": "k_measure", "prepare(N)": "k_prepare", "cz(E)": "k_cz", "pauli_x(X)": "k_x",
-             "jwindow(NEMX)": "k_jwindow"}
+             "jwindow(NEMX)": "k_jwindow", "tile(group)": "k_tile"}
 
     log("[bench] plain executor")
     wall, ev_ms, prof = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_PLAIN, args.steps, args.warmup,
