@@ -280,6 +280,42 @@ owqs_status owqs_run_profiled(owqs_pattern *pat, const void *input_c64, size_t n
  * modes; 0.5 in EOWQS mode).  Waits for `stream`. */
 owqs_status owqs_read_probs(owqs_pattern *pat, double *p, size_t n_meas, void *stream);
 
+/* Forced outcomes from a documented bit stream (outcomes are forced so that
+ * runs are comparable; the paper samples them, Fig. 6).  The m-th M gets the
+ * top bit of output m of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+ * started at `seed`: with gamma = 0x9E3779B97F4A7C15 and
+ * mix(z) = z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27,
+ * z *= 0x94D049BB133111EB, z ^= z >> 31, output m is
+ * mix(seed + (m + 1) * gamma) (arithmetic mod 2^64).  Replaces any outcomes
+ * set before; host only. */
+owqs_status owqs_set_outcome_seed(owqs_pattern *pat, uint64_t seed);
+
+/* Copy the forced outcomes (bits[m] for the m-th M) to host memory. */
+owqs_status owqs_get_outcomes(const owqs_pattern *pat, uint8_t *bits, size_t n_meas);
+
+/* Lockstep execution for debugging against a reference: run commands
+ * [cmd_begin, cmd_end) of the pattern (execution order, Sec. 2.2) with the
+ * plain plan, one kernel per non-trivial command, on `stream`.
+ * cmd_begin = 0 starts from the input (same rules as owqs_run); any other
+ * cmd_begin must equal the cmd_end of the previous ranged run of this
+ * pattern, with no other run in between (else OWQS_E_STATE).  Probabilities
+ * of the M's run so far are read with owqs_read_probs and the live state with
+ * owqs_read_live; owqs_read_state refuses to read a ranged run. */
+owqs_status owqs_run_range(owqs_pattern *pat, const void *input_c64, size_t n_amps,
+                           int input_on_device, size_t cmd_begin, size_t cmd_end, void *stream);
+
+/* After owqs_run_range: the live vector as it stands (2^n complex64, scaled
+ * to the true state: normalised in OWQS mode, Eqs. 3-4), its width n in
+ * *n_live and the caller's id of the qubit held by each index bit in
+ * qubits[0 .. n) (bit 0 first; N puts its qubit on the new top bit, M moves
+ * the top qubit into the measured bit, Sec. 4.2).  out_c64 is host memory
+ * of n_amps = 2^n entries, or NULL to query n_live and qubits only (either
+ * may be NULL; qubits needs OWQS_MAX_WIDTH entries).  Waits for `stream`;
+ * reports a pending device error like owqs_check.  Allocates a temporary
+ * device buffer of 2^n entries. */
+owqs_status owqs_read_live(owqs_pattern *pat, void *out_c64, size_t n_amps, int32_t *qubits,
+                           int32_t *n_live, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,30 @@ class OracleError(RuntimeError):
         self.cmd = cmd
 
 
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, count: int) -> list:
+    """The first `count` outputs of SplitMix64 (Steele, Lea and Flood, "Fast
+    splittable pseudorandom number generators", OOPSLA 2014) started at
+    `seed`: the state advances by the golden-ratio increment and each new
+    state goes through the variant-13 64-bit finaliser."""
+    out = []
+    x = seed & _M64
+    for _ in range(count):
+        x = (x + 0x9E3779B97F4A7C15) & _M64
+        z = x
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def outcomes_from_seed(seed: int, n_meas: int) -> np.ndarray:
+    """Forced outcome bits of a seeded run: the top bit of each output."""
+    return np.array([v >> 63 for v in splitmix64(seed, n_meas)], np.uint8)
+
+
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (OpenMP for the amplitude loops)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):

@@ -57,6 +57,7 @@ assert ctypes.sizeof(OwqsCmd) == 40
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
+MAX_WIDTH = 34  # OWQS_MAX_WIDTH
 _sig = {
     "owqs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "owqs_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -76,6 +77,11 @@ _sig = {
     "owqs_read_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp]),
     "owqs_check": (ctypes.c_int, [_vp, _vp]),
     "owqs_read_probs": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _vp]),
+    "owqs_set_outcome_seed": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "owqs_get_outcomes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
+    "owqs_run_range": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_size_t, ctypes.c_size_t,
+                                      _vp]),
+    "owqs_read_live": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _i32p, _vp]),
     "owqs_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "owqs_set_tile_bits": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "owqs_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _i32p,
@@ -278,6 +284,41 @@ class Pattern:
     def set_outcomes(self, bits: Sequence[int]):
         b = np.ascontiguousarray(bits, np.uint8)
         self.ctx.check(_lib.owqs_set_outcomes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), b.size))
+
+    def set_outcome_seed(self, seed: int):
+        """Outcomes from the SplitMix64 bit stream of `seed` (owqs_set_outcome_seed)."""
+        self.ctx.check(_lib.owqs_set_outcome_seed(self._h, int(seed) & (2**64 - 1)))
+
+    def outcomes(self) -> np.ndarray:
+        b = np.zeros(max(self.n_meas, 1), np.uint8)
+        self.ctx.check(_lib.owqs_get_outcomes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), self.n_meas))
+        return b[: self.n_meas]
+
+    def run_range(self, begin: int, end: int, psi_in=None, stream=None):
+        """Run commands [begin, end) with the plain plan (owqs_run_range); begin = 0
+        starts from psi_in (complex64 CUDA tensor, None when n_in = 0)."""
+        ptr, n = None, 1
+        if psi_in is not None:
+            import torch
+            if psi_in.dtype != torch.complex64 or not psi_in.is_cuda or not psi_in.is_contiguous():
+                raise TypeError("input must be a contiguous complex64 CUDA tensor")
+            ptr, n = psi_in.data_ptr(), psi_in.numel()
+        elif begin == 0 and self.n_in:
+            raise ValueError("this pattern needs an input state")
+        self.ctx.check(_lib.owqs_run_range(self._h, ptr, n, 1, int(begin), int(end), _stream_handle(stream)))
+
+    def read_live(self, stream=None):
+        """After run_range: (live vector as complex64 numpy array, caller qubit id of each bit)."""
+        q = np.zeros(MAX_WIDTH, np.int32)
+        nl = np.zeros(1, np.int32)
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        self.ctx.check(_lib.owqs_read_live(self._h, None, 0, q.ctypes.data_as(i32), nl.ctypes.data_as(i32),
+                                           _stream_handle(stream)))
+        n = int(nl[0])
+        out = np.zeros(1 << n, np.complex64)
+        self.ctx.check(_lib.owqs_read_live(self._h, out.ctypes.data, out.size, q.ctypes.data_as(i32),
+                                           nl.ctypes.data_as(i32), _stream_handle(stream)))
+        return out, [int(x) for x in q[:n]]
 
     def run(self, psi_in=None, stream=None):
         """psi_in: complex64 CUDA tensor of 2^n_in amplitudes (None when n_in = 0)."""

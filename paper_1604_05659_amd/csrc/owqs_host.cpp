@@ -73,6 +73,8 @@ struct Cmd {
 
 }  // namespace
 
+constexpr size_t kTraceStride = OWQS_MAX_WIDTH + 1;
+
 struct owqs_pattern {
   owqs_ctx *ctx = nullptr;
   std::vector<Cmd> cmds;
@@ -126,6 +128,19 @@ struct owqs_pattern {
   std::vector<float2> adj_coefs;   // host copies kept alive for the async uploads
   std::vector<int> adj_cols;
   std::vector<double> adj_scale;
+
+  // lockstep runs (owqs_run_range): the plain plan, one step per non-trivial
+  // command, with the state after every command
+  bool lk_valid = false;
+  std::vector<Step> lk_steps;
+  std::vector<size_t> lk_step_end;   // steps emitted by commands 0..i
+  std::vector<int> lk_width;         // live width after command i
+  std::vector<double> lk_pending;    // host factor of the live vector after command i
+  std::vector<int> lk_qubits;        // dense qubit at each bit after command i (stride kTraceStride)
+  size_t lk_next = SIZE_MAX;         // first command not yet run by the ranged run in progress
+  bool lk_ran = false;
+
+  std::vector<int32_t> user_id;  // dense qubit index -> caller's id
 
   bool ran = false;
   bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
@@ -326,8 +341,19 @@ void group_tiles(owqs_pattern *p) {
   }
 }
 
-// Compile the command list into device steps for the current settings.
-void compile(owqs_pattern *p) {
+// State after each command of a plain plan (for ranged runs).
+struct PlanTrace {
+  std::vector<size_t> &step_end;
+  std::vector<int> &width;
+  std::vector<double> &pending;
+  std::vector<int> &qubits;
+};
+
+// Translate the command list into steps (Sec. 4.4: N appends the top slot,
+// M moves the top qubit into the measured slot); with `fused`, runs of the
+// form N w; E's; M v; X/Z on w become one window step.
+void compile_plan(owqs_pattern *p, bool fused, std::vector<Step> &steps, std::vector<int> &final_where,
+                  double &final_factor, PlanTrace *tr) {
   const int nq = p->nq;
   std::vector<int> slot_of(nq, -1), qubit_at(OWQS_MAX_WIDTH + 1, -1), outcome_of(nq, 0);
   int n = (int)p->inputs.size();
@@ -338,9 +364,14 @@ void compile(owqs_pattern *p) {
   const double r2 = 1.0 / std::sqrt(2.0);
   double pending = 1.0;
   int m = 0;
-  const bool fused = p->exec != OWQS_EXEC_PLAIN;
-  p->steps.clear();
+  steps.clear();
   const size_t nc = p->cmds.size();
+  if (tr) {
+    tr->step_end.assign(nc, 0);
+    tr->width.assign(nc, 0);
+    tr->pending.assign(nc, 1.0);
+    tr->qubits.assign(nc * kTraceStride, -1);
+  }
 
   int last_s = 0, last_t = 0;
   auto coef_of = [&](const Cmd &c, int mi, int &o_out) {
@@ -419,7 +450,7 @@ void compile(owqs_pattern *p) {
           st.win.swap = idx[0] == 1;
           st.win.neg0 = sgn[0] < 0;
           st.win.neg1 = sgn[1] < 0;
-          p->steps.push_back(st);
+          steps.push_back(st);
           slot_of[w] = st.b0;
           qubit_at[st.b0] = w;
           slot_of[v] = -1;
@@ -434,7 +465,7 @@ void compile(owqs_pattern *p) {
         Step st{};
         st.kind = S_N;
         st.n = n;
-        p->steps.push_back(st);
+        steps.push_back(st);
         slot_of[c.q0] = n;
         qubit_at[n] = c.q0;
         ++n;
@@ -447,7 +478,7 @@ void compile(owqs_pattern *p) {
         st.n = n;
         st.b0 = slot_of[c.q0];
         st.b1 = slot_of[c.q1];
-        p->steps.push_back(st);
+        steps.push_back(st);
         break;
       }
       case OWQS_OP_X:
@@ -457,7 +488,7 @@ void compile(owqs_pattern *p) {
           st.kind = c.op == OWQS_OP_X ? S_X : S_Z;
           st.n = n;
           st.b0 = slot_of[c.q0];
-          p->steps.push_back(st);
+          steps.push_back(st);
         }
         break;
       }
@@ -473,7 +504,7 @@ void compile(owqs_pattern *p) {
         st.outcome = o;
         st.host_factor = pending;
         st.m_index = m;
-        p->steps.push_back(st);
+        steps.push_back(st);
         outcome_of[c.q0] = o;
         ++m;
         const int t = n - 1;
@@ -491,10 +522,23 @@ void compile(owqs_pattern *p) {
       default:
         break;
     }
+    if (tr) {
+      tr->step_end[i] = steps.size();
+      tr->width[i] = n;
+      tr->pending[i] = pending;
+      for (int b = 0; b < n; ++b) tr->qubits[i * kTraceStride + b] = qubit_at[b];
+    }
   }
-  p->final_where.assign(p->outputs.size(), 0);
-  for (size_t k = 0; k < p->outputs.size(); ++k) p->final_where[k] = slot_of[p->outputs[k]];
-  p->final_factor = pending;
+  final_where.assign(p->outputs.size(), 0);
+  for (size_t k = 0; k < p->outputs.size(); ++k) final_where[k] = slot_of[p->outputs[k]];
+  final_factor = pending;
+}
+
+// Compile the command list into device steps for the current settings.
+void compile(owqs_pattern *p) {
+  compile_plan(p, p->exec != OWQS_EXEC_PLAIN, p->steps, p->final_where, p->final_factor, nullptr);
+  p->lk_valid = false;
+  p->lk_next = SIZE_MAX;
   int w = std::max<int>((int)p->inputs.size(), (int)p->outputs.size());
   for (const Step &x : p->steps) w = std::max(w, x.n + (x.kind == S_N ? 1 : 0));
   p->plan_width = std::max(w, 1);
@@ -593,6 +637,8 @@ owqs_status build_pattern(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, con
     p->cmds.push_back(std::move(d));
   }
   p->nq = (int)dense.size();
+  p->user_id.assign(p->nq, -1);
+  for (const auto &kv : dense) p->user_id[kv.second] = kv.first;
   owqs_status st = validate(p);
   if (st != OWQS_OK) {
     delete p;
@@ -630,10 +676,11 @@ double step_bytes(const Step &x) {
 // main kernel and the finishing kernel of each step (see run_impl).
 int *fuse_m_dev(owqs_pattern *p) { return reinterpret_cast<int *>(p->dev_fuse + p->fuse_ops.size()); }
 
-hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev) {
+hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
+                        hipStream_t s, std::vector<hipEvent_t> *ev) {
   hipError_t e = hipSuccess;
-  for (size_t i = 0; i < p->xsteps.size() && e == hipSuccess; ++i) {
-    const Step &x = p->xsteps[i];
+  for (size_t i = i0; i < i1 && e == hipSuccess; ++i) {
+    const Step &x = xs[i];
     MeasureArgs a{};
     a.reduce = reduce;
     a.book = p->book;
@@ -669,6 +716,10 @@ hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<
     if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
   }
   return e;
+}
+
+hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev) {
+  return launch_range(p, p->xsteps, 0, p->xsteps.size(), reduce, s, ev);
 }
 
 // Upload the tile groups' command table: FuseOps, then the windows'
@@ -749,6 +800,12 @@ LdsItem lds_proto(const owqs_pattern *p) {
   return it;
 }
 
+// Any other run overwrites the state (or its scale) that a ranged run left.
+void end_ranged(owqs_pattern *p) {
+  p->lk_next = SIZE_MAX;
+  p->lk_ran = false;
+}
+
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                      Profile *prof) {
   if (!p) return OWQS_E_INVALID_ARG;
@@ -760,6 +817,7 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
   if (st != OWQS_OK) return st;
   if (p->dirty) compile(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  end_ranged(p);
   hipError_t e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "init");
   if (nin > 0 || input != nullptr) {
@@ -1193,6 +1251,7 @@ static owqs_status run_shared(owqs_pattern *p, const void *in, uint32_t first, u
   st = upload_steps(p);
   if (st != OWQS_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  end_ranged(p);
   hipError_t e = launch_init(p->psi, p->book, s, 0);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "init");
   LdsItem proto = lds_proto(p);
@@ -1253,6 +1312,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
       reduce = reduce_of(p);
       st = upload_steps(p);
       if (st != OWQS_OK) return st;
+      end_ranged(p);
       e = launch_init(p->psi, p->book, s, 0);  // clears the pattern's error slot
       if (e != hipSuccess) return hip_fail(ctx, e, "init");
       LdsItem it = lds_proto(p);
@@ -1359,6 +1419,7 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
       return fail(p->ctx, OWQS_E_INVALID_ARG, "observable index outside the outputs");
   owqs_status st = ensure_device(p, false);
   if (st != OWQS_OK) return st;
+  end_ranged(p);
   if (p->exec == OWQS_EXEC_PLAIN) {
     p->exec = OWQS_EXEC_AUTO;
     p->dirty = true;
@@ -1507,7 +1568,7 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
 
 owqs_status owqs_check(owqs_pattern *p, void *stream) {
   if (!p) return OWQS_E_INVALID_ARG;
-  if (!p->ran && !p->batch_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (!p->ran && !p->batch_ran && !p->lk_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
   hipStream_t s = static_cast<hipStream_t>(stream);
   int err[2] = {0, 0};
   hipError_t e = hipMemcpyAsync(err, p->book.err, sizeof(err), hipMemcpyDeviceToHost, s);
@@ -1524,7 +1585,9 @@ owqs_status owqs_check(owqs_pattern *p, void *stream) {
 
 owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_on_device, void *stream) {
   if (!p || !out) return OWQS_E_INVALID_ARG;
-  if (!p->ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (!p->ran)
+    return fail(p->ctx, OWQS_E_STATE, p->lk_ran ? "the last run was a ranged run: read it with owqs_read_live"
+                                                : "no run yet");
   const size_t nout = p->outputs.size();
   if (n_amps != (size_t(1) << nout)) return fail(p->ctx, OWQS_E_INVALID_ARG, "output size must be 2^(outputs)");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1557,7 +1620,7 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
 
 owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void *stream) {
   if (!p || (n_meas && !probs)) return OWQS_E_INVALID_ARG;
-  if (!p->ran && !p->batch_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
+  if (!p->ran && !p->batch_ran && !p->lk_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
   if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "probability count != M count");
   if (reduce_of(p) == kReduceNone) {
     for (size_t k = 0; k < n_meas; ++k) probs[k] = 0.5;
@@ -1569,6 +1632,104 @@ owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void 
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "read probs");
   return OWQS_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k (k = 0, 1, ...)
+// of the generator started at `seed` is mix(seed + (k + 1) * gamma); the
+// outcome of the m-th M is the top bit of output m.
+owqs_status owqs_set_outcome_seed(owqs_pattern *p, uint64_t seed) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  uint64_t x = seed;
+  for (int m = 0; m < p->n_meas; ++m) {
+    x += 0x9E3779B97F4A7C15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    p->outcomes[m] = uint8_t(z >> 63);
+  }
+  p->dirty = true;
+  return OWQS_OK;
+}
+
+owqs_status owqs_get_outcomes(const owqs_pattern *p, uint8_t *bits, size_t n_meas) {
+  if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
+  std::copy(p->outcomes.begin(), p->outcomes.end(), bits);
+  return OWQS_OK;
+}
+
+owqs_status owqs_run_range(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device,
+                           size_t cmd_begin, size_t cmd_end, void *stream) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  const size_t nc = p->cmds.size();
+  if (cmd_begin > cmd_end || cmd_end > nc) return fail(p->ctx, OWQS_E_INVALID_ARG, "command range outside the pattern");
+  owqs_status st = ensure_device(p);
+  if (st != OWQS_OK) return st;
+  if (p->dirty) compile(p);
+  if (!p->lk_valid) {
+    double ff = 1.0;
+    std::vector<int> fw;
+    PlanTrace tr{p->lk_step_end, p->lk_width, p->lk_pending, p->lk_qubits};
+    compile_plan(p, false, p->lk_steps, fw, ff, &tr);
+    p->lk_valid = true;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (cmd_begin == 0) {
+    const size_t nin = p->inputs.size();
+    const size_t want = size_t(1) << nin;
+    if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
+    if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
+    end_ranged(p);
+    p->ran = false;
+    p->batch_ran = false;
+    p->out_in_order = false;
+    e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
+    if (e == hipSuccess && (nin > 0 || input != nullptr))
+      e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
+                         input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "input");
+  } else if (p->lk_next != cmd_begin) {
+    return fail(p->ctx, OWQS_E_STATE, "a ranged run must start at 0 or where the previous ranged run ended");
+  }
+  const size_t i0 = cmd_begin ? p->lk_step_end[cmd_begin - 1] : 0;
+  const size_t i1 = cmd_end ? p->lk_step_end[cmd_end - 1] : 0;
+  p->lk_next = SIZE_MAX;  // set again only once the range is enqueued
+  e = launch_range(p, p->lk_steps, i0, i1, reduce_of(p), s, nullptr);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
+  p->lk_next = cmd_end;
+  p->lk_ran = true;
+  p->ran_mode = reduce_of(p);
+  return OWQS_OK;
+}
+
+owqs_status owqs_read_live(owqs_pattern *p, void *out_c64, size_t n_amps, int32_t *qubits, int32_t *n_live,
+                           void *stream) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (!p->lk_ran || p->lk_next == SIZE_MAX) return fail(p->ctx, OWQS_E_STATE, "no ranged run to read");
+  const size_t e_cmd = p->lk_next;
+  const int n = e_cmd ? p->lk_width[e_cmd - 1] : (int)p->inputs.size();
+  if (n_live) *n_live = n;
+  if (qubits)
+    for (int b = 0; b < n; ++b)
+      qubits[b] = p->user_id[e_cmd ? p->lk_qubits[(e_cmd - 1) * kTraceStride + b] : p->inputs[b]];
+  if (!out_c64) return OWQS_OK;
+  if (n_amps != (size_t(1) << n)) return fail(p->ctx, OWQS_E_INVALID_ARG, "output size must be 2^(live width)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int where[OWQS_MAX_WIDTH + 1];
+  for (int b = 0; b < n; ++b) where[b] = b;
+  const double factor = e_cmd ? p->lk_pending[e_cmd - 1] : 1.0;
+  const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
+  float2 *tmp = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&tmp), n_amps * sizeof(float2));
+  if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "live read buffer");
+  e = launch_read(p->psi, tmp, n, where, factor, sigma, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out_c64, tmp, n_amps * sizeof(float2), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "live read");
+  return owqs_check(p, stream);
 }
 
 }  // extern "C"

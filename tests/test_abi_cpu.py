@@ -140,3 +140,28 @@ def test_fused_plan_forms_windows(host_ctx):
     w3, n3, x3 = q.plan_info()
     assert w3 <= 21 and n3 < 4400, n3
     assert x3 < n3  # runs of windows group into tile passes at width >= 18
+
+
+def test_outcome_seed_follows_the_oracle_stream(host_ctx):
+    from oracle import core as oc
+    for wl in (W.plain_small(), W.cluster(rows=4, cols=6)):
+        p = owqs.Pattern(host_ctx, wl.pattern)
+        for seed in (0, 1, 1234567, 2**64 - 1, 160405659):
+            p.set_outcome_seed(seed)
+            np.testing.assert_array_equal(p.outcomes(), oc.outcomes_from_seed(seed, p.n_meas))
+        p.set_outcomes(wl.outcomes)
+        np.testing.assert_array_equal(p.outcomes(), wl.outcomes)
+        p.close()
+
+
+def test_ranged_run_argument_checks(host_ctx):
+    p = owqs.Pattern(host_ctx, W.plain_small().pattern)
+    # no ranged run to read yet
+    st = owqs._lib.owqs_read_live(p._h, None, 0, None, None, None)
+    assert st == owqs.E_STATE
+    # a range outside the pattern is rejected before anything else
+    assert owqs._lib.owqs_run_range(p._h, None, 1, 1, 3, 2, None) == owqs.E_INVALID_ARG
+    assert owqs._lib.owqs_run_range(p._h, None, 1, 1, 0, p.ncmds + 1, None) == owqs.E_INVALID_ARG
+    # a host-only context cannot run
+    assert owqs._lib.owqs_run_range(p._h, None, 1, 1, 0, 4, None) == owqs.E_STATE
+    p.close()
