@@ -283,6 +283,8 @@ void group_tiles(owqs_pattern *p) {
     TileGroup tg{};
     tg.ta.n = n;
     tg.ta.k = k;
+    tg.ta.tmask = tmask;
+    tg.ta.omask = ((n >= 64 ? ~uint64_t(0) : (uint64_t(1) << n) - 1)) & ~tmask;
     int local_of[64];
     for (int b = 0, li = 0, oi = 0; b < n; ++b) {
       if (tmask & (uint64_t(1) << b)) {

@@ -103,6 +103,8 @@ struct FuseOp {
 };  // 48 bytes
 
 struct TileArgs {
+  uint64_t tmask;    // global slots in the tile (tile bit i = the i-th lowest)
+  uint64_t omask;    // the other live slots (outer bit i = the i-th lowest)
   int n, k, nops, nwin;
   uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)

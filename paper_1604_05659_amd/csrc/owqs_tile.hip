@@ -21,131 +21,300 @@
 namespace owqs {
 namespace {
 
-constexpr int kTT = 256;  // threads per workgroup
+constexpr int kTT = 256;  // threads per workgroup of the finishing kernel
+
+// Threads per workgroup of a tile pass: 512 (8 waves) for 2^13-amplitude
+// tiles, so that a CU holding two such tiles still runs 16 waves.
+constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : 256; }
 
 __device__ __forceinline__ uint32_t ins0u(uint32_t x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1)); }
-__device__ __forceinline__ int par64(uint64_t x) { return __popcll(x) & 1; }
-__device__ __forceinline__ int par32(uint32_t x) { return __popc(x) & 1; }
+__device__ __forceinline__ uint32_t par64(uint64_t x) { return uint32_t(__popcll(x) & 1); }
+__device__ __forceinline__ uint32_t par32(uint32_t x) { return uint32_t(__popc(x) & 1); }
+__device__ __forceinline__ float xsign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
+__device__ __forceinline__ float2 xsign2(float2 v, uint32_t s) { return make_float2(xsign(v.x, s), xsign(v.y, s)); }
+__device__ __forceinline__ float2 &at(char *lds, uint32_t byte_off) { return *reinterpret_cast<float2 *>(lds + byte_off); }
 
-// Global index of local element e of the tile whose outer bits are `base`.
-__device__ __forceinline__ uint64_t gidx(uint32_t e, uint64_t base, const TileArgs &ta) {
-  uint64_t g = base | (e & ((1u << kLowBits) - 1));
-  for (int i = kLowBits; i < ta.k; ++i) g |= uint64_t((e >> i) & 1u) << ta.tpos[i];
-  return g;
+// One command of the group, read as whole dwords from a uniform address so
+// that it comes through scalar loads (its byte fields are unpacked after).
+__device__ __forceinline__ FuseOp load_op(const FuseOp *ops, int o) {
+  static_assert(sizeof(FuseOp) == 48, "FuseOp is 12 dwords");
+  const uint32_t *src = reinterpret_cast<const uint32_t *>(ops) + 12 * __builtin_amdgcn_readfirstlane(o);
+  uint32_t w[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) w[i] = src[i];
+  FuseOp op;
+  __builtin_memcpy(&op, w, sizeof(op));
+  return op;
 }
 
-// kTB = tile bits (ta.k).  Each thread moves kPer = 2^kTB / kTT amplitudes
-// per tile; all its loads are issued before the first LDS store (and all LDS
-// reads before the first global store), so the memory system sees kPer
-// requests in flight per thread.
+// x plus the FP64 value of another lane chosen by a DPP control (two 32-bit
+// DPP moves); lanes whose source is outside the row mask or the row add 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double add_dpp(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(u), kCtrl, kRowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(u >> 32), kCtrl, kRowMask, 0xf, false);
+  return x + __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Sum of x over the 64 lanes of the wave, valid in lane 63: shifts by 1, 2,
+// 4 and 8 inside each 16-lane row leave the row sums in lanes 15, 31, 47 and
+// 63; the row broadcasts 15 and 31 then add them up into lane 63.
+__device__ __forceinline__ double wave_sum_to_last(double x) {
+  x = add_dpp<0x111, 0xf>(x);  // row_shr:1
+  x = add_dpp<0x112, 0xf>(x);  // row_shr:2
+  x = add_dpp<0x114, 0xf>(x);  // row_shr:4
+  x = add_dpp<0x118, 0xf>(x);  // row_shr:8
+  x = add_dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = add_dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// Deposit the low bits of x, lowest first, into the set bits of mask.
+__device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  for (uint64_t bb = 1; mask; bb <<= 1) {
+    const uint64_t low = mask & (~mask + 1);
+    if (x & bb) r |= low;
+    mask ^= low;
+  }
+  return r;
+}
+
+// Negate the tile elements whose local bits m are all set (E: two bits,
+// Z: one; no bit when the factor depends on outer bits only).  Only the
+// affected quarter / half / whole tile is visited: element
+// ins0(ins0(q, lo), hi) | m for q < 2^(k-2), and so on.  Insertion of zero
+// bits acts on each bit separately, so the part from the thread index and the
+// part from the loop counter r (uniform) are combined with an OR.
+template <int kTB, int kT>
+__device__ __forceinline__ void diag_flip(char *lds, uint32_t tid, uint32_t m) {
+  constexpr int kPer = (1 << kTB) / kT;
+  constexpr uint32_t kNeg = 0x80000000u;
+  const int nb = __popc(m);
+  if (nb == 2) {
+    const int lo = __ffs(m) - 1, hi = 31 - __clz(m);
+    const uint32_t et = (ins0u(ins0u(tid, lo), hi) | m) << 3;
+#pragma unroll
+    for (int r = 0; r < kPer / 4; ++r) {
+      const uint32_t a = et | (ins0u(ins0u(uint32_t(r) * kT, lo), hi) << 3);
+      at(lds, a) = xsign2(at(lds, a), kNeg);
+    }
+  } else if (nb == 1) {
+    const int lo = __ffs(m) - 1;
+    const uint32_t et = (ins0u(tid, lo) | m) << 3;
+#pragma unroll
+    for (int r = 0; r < kPer / 2; ++r) {
+      const uint32_t a = et | (ins0u(uint32_t(r) * kT, lo) << 3);
+      at(lds, a) = xsign2(at(lds, a), kNeg);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const uint32_t a = (tid + uint32_t(r) * kT) << 3;
+      at(lds, a) = xsign2(at(lds, a), kNeg);
+    }
+  }
+}
+
+// X: swap the element pairs that differ in local bit lb.
+template <int kTB, int kT>
+__device__ __forceinline__ void pair_swap(char *lds, uint32_t tid, int lb) {
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  const uint32_t et = ins0u(tid, lb) << 3, bit8 = 8u << lb;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const uint32_t a0 = et | (ins0u(uint32_t(r) * kT, lb) << 3), a1 = a0 | bit8;
+    const float2 x = at(lds, a0);
+    at(lds, a0) = at(lds, a1);
+    at(lds, a1) = x;
+  }
+}
+
+// A window on the element pairs (a, b) that differ in local bit lb:
+//   t = fc0 b,  o0 = fa a + t,  o1 = fb a + r t   (r = +-1, sign bit rsign),
+// with b negated where the local bits lmb have odd parity and o1 negated
+// where the local bits lmo have odd parity (kMasked), and the outputs
+// exchanged by the folded X correction (kSw).  Returns this thread's FP32
+// sum of |o0|^2 + |o1|^2 (kAcc).
+template <bool kMasked, bool kSw, bool kAcc, int kTB, int kT>
+__device__ __forceinline__ float window_pass(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0,
+                                             uint32_t rsign, uint32_t lmb, uint32_t lmo) {
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  const uint32_t et = ins0u(tid, lb), bit8 = 8u << lb;
+  const uint32_t sbt = kMasked ? par32(et & lmb) << 31 : 0u;
+  const uint32_t sot = kMasked ? par32(et & lmo) << 31 : 0u;
+  float acc = 0.f;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const uint32_t ur = ins0u(uint32_t(r) * kT, lb);
+    const uint32_t a0 = (et << 3) | (ur << 3), a1 = a0 | bit8;
+    const float2 a = at(lds, a0);
+    float2 b = at(lds, a1);
+    float fbe = fb;
+    uint32_t ts = rsign;
+    if (kMasked) {
+      b = xsign2(b, sbt ^ (par32(ur & lmb) << 31));
+      const uint32_t so = sot ^ (par32(ur & lmo) << 31);
+      fbe = xsign(fb, so);
+      ts ^= so;
+    }
+    const float2 t = make_float2(fc0.x * b.x - fc0.y * b.y, fc0.x * b.y + fc0.y * b.x);
+    const float2 p0 = make_float2(fmaf(fa, a.x, t.x), fmaf(fa, a.y, t.y));
+    const float2 te = xsign2(t, ts);
+    const float2 p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
+    at(lds, a0) = kSw ? p1 : p0;
+    at(lds, a1) = kSw ? p0 : p1;
+    if (kAcc) acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
+  }
+  return acc;
+}
+
+// The unmasked window with compile-time r and a mixing bit below the thread
+// index bits: element pair r of the thread is then at a fixed offset from
+// the thread's first pair, and the sign of t in o1 is an instruction
+// modifier.
+template <bool kSw, bool kAcc, bool kRneg, int kTB, int kT>
+__device__ __forceinline__ float window_low(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0) {
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  constexpr int kLogT = kT == 512 ? 9 : 8;
+  const uint32_t a0t = ins0u(tid, lb) << 3, a1t = a0t | (8u << lb);
+  float acc = 0.f;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    // pair index tid + r kT with lb < log2 kT: insertion shifts r kT up by one
+    const uint32_t off = uint32_t(r) << (kLogT + 4);
+    const float2 a = at(lds, a0t + off), b = at(lds, a1t + off);
+    const float2 t = make_float2(fc0.x * b.x - fc0.y * b.y, fc0.x * b.y + fc0.y * b.x);
+    const float2 p0 = make_float2(fmaf(fa, a.x, t.x), fmaf(fa, a.y, t.y));
+    const float2 p1 = kRneg ? make_float2(fmaf(fb, a.x, -t.x), fmaf(fb, a.y, -t.y))
+                            : make_float2(fmaf(fb, a.x, t.x), fmaf(fb, a.y, t.y));
+    at(lds, a0t + off) = kSw ? p1 : p0;
+    at(lds, a1t + off) = kSw ? p0 : p1;
+    if (kAcc) acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
+  }
+  return acc;
+}
+
+template <bool kAcc, int kTB, int kT>
+__device__ __forceinline__ float window_any(bool masked, bool sw, char *lds, uint32_t tid, int lb, float fa, float fb,
+                                            float2 fc0, uint32_t rsign, uint32_t lmb, uint32_t lmo) {
+  constexpr int kLogT = kT == 512 ? 9 : 8;
+  if (masked)
+    return sw ? window_pass<true, true, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo)
+              : window_pass<true, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo);
+  if (lb < kLogT) {
+    if (rsign)
+      return sw ? window_low<true, kAcc, true, kTB, kT>(lds, tid, lb, fa, fb, fc0)
+                : window_low<false, kAcc, true, kTB, kT>(lds, tid, lb, fa, fb, fc0);
+    return sw ? window_low<true, kAcc, false, kTB, kT>(lds, tid, lb, fa, fb, fc0)
+              : window_low<false, kAcc, false, kTB, kT>(lds, tid, lb, fa, fb, fc0);
+  }
+  return sw ? window_pass<false, true, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, 0u, 0u)
+            : window_pass<false, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, 0u, 0u);
+}
+
+// kTB = tile bits (ta.k).  Global memory <-> LDS: each thread moves
+// kPer = 2^kTB / kT amplitudes per tile, all loads issued before the first
+// LDS store (and all LDS reads before the first global store), so the memory
+// system sees kPer requests in flight per thread.  Element e of the tile
+// whose outer bits are `ob` sits at global index ob | pdep(e, tmask); with
+// e = tid + r kT that is ob | pdep(tid, tmask) | (a uniform part from r).
+// Every command of the group is then one pass over the tile in LDS.
 template <int kTB>
-__global__ __launch_bounds__(kTT) void k_tile(float2 *__restrict__ psi, TileArgs ta, const FuseOp *__restrict__ ops,
-                                               MeasureArgs ma, double *__restrict__ partials) {
-  constexpr uint32_t kSize = 1u << kTB, kHalf = kSize >> 1;
-  constexpr int kPer = kSize / kTT;
+__global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__ psi, TileArgs ta,
+                                                            const FuseOp *__restrict__ ops, MeasureArgs ma,
+                                                            double *__restrict__ partials) {
+  constexpr int kT = tile_threads(kTB);
+  constexpr int kLogT = kT == 512 ? 9 : 8;
+  constexpr int kPer = (1 << kTB) / kT;
+  constexpr int kHi = kTB - kLogT;  // tile bits above the thread index
   extern __shared__ float2 tile[];
-  __shared__ double wacc[kMaxGroupWindows][kTT / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double wacc[kMaxGroupWindows][kT / 64];
+  char *const lds = reinterpret_cast<char *>(tile);
+  const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const bool reduce = ma.reduce != kReduceNone;
   if (reduce)
-    for (int i = threadIdx.x; i < ta.nwin * (kTT / 64); i += kTT) wacc[i / (kTT / 64)][i % (kTT / 64)] = 0.0;
+    for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
   const double sg = (ma.reduce == kReduceRenorm) ? *ma.book.sigma : 1.0;
-  // the part of each element's global index that comes from threadIdx.x
-  const uint64_t g_tid = gidx(threadIdx.x, 0, ta);
-  uint64_t g_r[kPer];
+  const uint64_t g_tid = pdep64(tid, ta.tmask);
+  uint64_t hp[kHi];  // global bit of tile bits 8 .. kTB-1
+  {
+    uint64_t m = ta.tmask;
+    for (int i = 0; i < kLogT; ++i) m &= m - 1;
 #pragma unroll
-  for (int r = 0; r < kPer; ++r) g_r[r] = gidx(uint32_t(r) * kTT, 0, ta);
+    for (int j = 0; j < kHi; ++j) {
+      hp[j] = m & (~m + 1);
+      m &= m - 1;
+    }
+  }
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    uint64_t base = 0;
-    for (int i = 0; i < ta.n - kTB; ++i) base |= ((t >> i) & 1) << ta.opos[i];
-    float2 v[kPer];
+    const uint64_t ob = pdep64(t, ta.omask);
+    const uint64_t gb = ob | g_tid;
+    {
+      float2 v[kPer];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) v[r] = psi[base | g_tid | g_r[r]];
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) tile[threadIdx.x + r * kTT] = v[r];
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        v[r] = psi[g];
+      }
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) tile[tid + r * kT] = v[r];
+    }
     __syncthreads();
     for (int o = 0; o < ta.nops; ++o) {
-      const FuseOp op = ops[o];
+      const FuseOp op = load_op(ops, o);
       if (op.kind == DK_E || op.kind == DK_Z) {
-        if ((base & op.omask_b) == op.omask_b) {
-#pragma unroll
-          for (int r = 0; r < kPer; ++r) {
-            const uint32_t e = threadIdx.x + r * kTT;
-            if ((e & op.lmask_b) == op.lmask_b) tile[e] = make_float2(-tile[e].x, -tile[e].y);
-          }
-        }
+        if ((ob & op.omask_b) == op.omask_b) diag_flip<kTB, kT>(lds, tid, op.lmask_b);
       } else if (op.kind == DK_X) {
-        const int lb = op.lb;
-#pragma unroll
-        for (int r = 0; r < kPer / 2; ++r) {
-          const uint32_t q = threadIdx.x + r * kTT;
-          const uint32_t e0 = ins0u(q, lb), e1 = e0 | (1u << lb);
-          const float2 a = tile[e0];
-          tile[e0] = tile[e1];
-          tile[e1] = a;
-        }
-      } else {  // window
-        const int lb = op.lb;
+        pair_swap<kTB, kT>(lds, tid, op.lb);
+      } else {  // window: fold the tile-constant signs and the corrections
         const float f = float((op.flags & 16u) ? sg * op.f : double(op.f));
-        const float s1 = (op.flags & 8u) ? 1.f : -1.f;
-        const int ob = par64(base & op.omask_b), oo = par64(base & op.omask_o1);
-        // fold the corrections and the tile-constant signs into the two
-        // output coefficients: o0 = f0 (a + c0 b), o1 = f1 (a + c1 b)
-        const float2 c = op.coef;
         const bool sw = op.flags & 1u;
-        float f0 = f, f1 = (oo ? -f : f);
-        float2 c0 = ob ? make_float2(-c.x, -c.y) : c, c1 = make_float2(s1 * c0.x, s1 * c0.y);
-        if (op.flags & 2u) { if (sw) f1 = -f1; else f0 = -f0; }
-        if (op.flags & 4u) { if (sw) f0 = -f0; else f1 = -f1; }
-        float acc = 0.f;  // per-thread partial of at most kPer/2 pairs; FP64 from the wave sum on
-        if (op.lmask_b == 0 && op.lmask_o1 == 0) {
-#pragma unroll
-          for (int r = 0; r < kPer / 2; ++r) {
-            const uint32_t q = threadIdx.x + r * kTT;
-            const uint32_t e0 = ins0u(q, lb), e1 = e0 | (1u << lb);
-            const float2 a = tile[e0], b = tile[e1];
-            const float2 p0 = make_float2(f0 * (a.x + (c0.x * b.x - c0.y * b.y)), f0 * (a.y + (c0.x * b.y + c0.y * b.x)));
-            const float2 p1 = make_float2(f1 * (a.x + (c1.x * b.x - c1.y * b.y)), f1 * (a.y + (c1.x * b.y + c1.y * b.x)));
-            tile[e0] = sw ? p1 : p0;
-            tile[e1] = sw ? p0 : p1;
-            acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < kPer / 2; ++r) {
-            const uint32_t q = threadIdx.x + r * kTT;
-            const uint32_t e0 = ins0u(q, lb), e1 = e0 | (1u << lb);
-            const float sb = par32(e0 & op.lmask_b) ? -1.f : 1.f;
-            const float so1 = par32(e0 & op.lmask_o1) ? -1.f : 1.f;
-            const float2 a = tile[e0], b0 = tile[e1];
-            const float2 b = make_float2(sb * b0.x, sb * b0.y);
-            const float g1 = so1 * f1;
-            const float2 p0 = make_float2(f0 * (a.x + (c0.x * b.x - c0.y * b.y)), f0 * (a.y + (c0.x * b.y + c0.y * b.x)));
-            const float2 p1 = make_float2(g1 * (a.x + (c1.x * b.x - c1.y * b.y)), g1 * (a.y + (c1.x * b.y + c1.y * b.x)));
-            tile[e0] = sw ? p1 : p0;
-            tile[e1] = sw ? p0 : p1;
-            acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
-          }
-        }
+        float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
+        if (op.flags & 2u) { if (sw) fb = -fb; else fa = -fa; }
+        if (op.flags & 4u) { if (sw) fa = -fa; else fb = -fb; }
+        const float2 c0 = par64(ob & op.omask_b) ? make_float2(-op.coef.x, -op.coef.y) : op.coef;
+        const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
+        // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
+        const bool s1neg = !(op.flags & 8u);
+        const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
+        const bool masked = (op.lmask_b | op.lmask_o1) != 0;
         if (reduce) {
-          double d = acc;
-          for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
-          if (lane == 0) wacc[op.widx][wave] += d;
+          const float acc =
+              window_any<true, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
+          const double d = wave_sum_to_last(acc);  // FP64 from the wave sum on
+          if (lane == 63) wacc[op.widx][wave] += d;
+        } else {
+          window_any<false, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
         }
       }
       __syncthreads();
     }
+    {
+      float2 v[kPer];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) v[r] = tile[threadIdx.x + r * kTT];
+      for (int r = 0; r < kPer; ++r) v[r] = tile[tid + r * kT];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) psi[base | g_tid | g_r[r]] = v[r];
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
+#pragma unroll
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        psi[g] = v[r];
+      }
+    }
     __syncthreads();
   }
   if (reduce) {
-    for (int w = threadIdx.x; w < ta.nwin; w += kTT) {
+    for (int w = tid; w < ta.nwin; w += kT) {
       double s = 0.0;
-      for (int k = 0; k < kTT / 64; ++k) s += wacc[w][k];
+      for (int k = 0; k < kT / 64; ++k) s += wacc[w][k];
       partials[size_t(w) * gridDim.x + blockIdx.x] = s;
     }
   }
@@ -217,10 +386,10 @@ hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const
   const size_t bytes = sizeof(float2) << ta.k;
   const unsigned g = tile_grid(ta);
   switch (ta.k) {
-    case 10: hipLaunchKernelGGL(k_tile<10>, dim3(g), dim3(kTT), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 11: hipLaunchKernelGGL(k_tile<11>, dim3(g), dim3(kTT), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 12: hipLaunchKernelGGL(k_tile<12>, dim3(g), dim3(kTT), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 13: hipLaunchKernelGGL(k_tile<13>, dim3(g), dim3(kTT), bytes, s, psi, ta, ops, a, a.book.partials); break;
+    case 10: hipLaunchKernelGGL(k_tile<10>, dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials); break;
+    case 11: hipLaunchKernelGGL(k_tile<11>, dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials); break;
+    case 12: hipLaunchKernelGGL(k_tile<12>, dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials); break;
+    case 13: hipLaunchKernelGGL(k_tile<13>, dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials); break;
     default: return hipErrorInvalidValue;
   }
   *grid = g;
