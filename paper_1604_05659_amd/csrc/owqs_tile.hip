@@ -24,8 +24,11 @@ namespace {
 constexpr int kTT = 256;  // threads per workgroup of the finishing kernel
 
 // Threads per workgroup of a tile pass: 512 (8 waves) for 2^13-amplitude
-// tiles, so that a CU holding two such tiles still runs 16 waves.
-constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : 256; }
+// tiles, so that a CU holding two such tiles still runs 16 waves; 128 for
+// 2^10 and 2^11 tiles, so that every thread has 8 or 16 amplitudes to work
+// on per command (the per-command decoding is paid once per wave).
+constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : tile_bits <= 11 ? 128 : 256; }
+constexpr int log2_threads(int t) { return t == 512 ? 9 : t == 256 ? 8 : 7; }
 
 __device__ __forceinline__ uint32_t ins0u(uint32_t x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1)); }
 __device__ __forceinline__ uint32_t par64(uint64_t x) { return uint32_t(__popcll(x) & 1); }
@@ -177,7 +180,7 @@ __device__ __forceinline__ float window_pass(char *lds, uint32_t tid, int lb, fl
 template <bool kSw, bool kAcc, bool kRneg, int kTB, int kT>
 __device__ __forceinline__ float window_low(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0) {
   constexpr int kPairs = (1 << kTB) / kT / 2;
-  constexpr int kLogT = kT == 512 ? 9 : 8;
+  constexpr int kLogT = log2_threads(kT);
   const uint32_t a0t = ins0u(tid, lb) << 3, a1t = a0t | (8u << lb);
   float acc = 0.f;
 #pragma unroll
@@ -199,7 +202,7 @@ __device__ __forceinline__ float window_low(char *lds, uint32_t tid, int lb, flo
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ float window_any(bool masked, bool sw, char *lds, uint32_t tid, int lb, float fa, float fb,
                                             float2 fc0, uint32_t rsign, uint32_t lmb, uint32_t lmo) {
-  constexpr int kLogT = kT == 512 ? 9 : 8;
+  constexpr int kLogT = log2_threads(kT);
   if (masked)
     return sw ? window_pass<true, true, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo)
               : window_pass<true, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo);
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
                                                             const FuseOp *__restrict__ ops, MeasureArgs ma,
                                                             double *__restrict__ partials) {
   constexpr int kT = tile_threads(kTB);
-  constexpr int kLogT = kT == 512 ? 9 : 8;
+  constexpr int kLogT = log2_threads(kT);
   constexpr int kPer = (1 << kTB) / kT;
   constexpr int kHi = kTB - kLogT;  // tile bits above the thread index
   extern __shared__ float2 tile[];
