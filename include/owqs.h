@@ -96,7 +96,7 @@ typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 
 /* Execution plan.  PLAIN: one kernel per non-trivial command, the live width
  * growing on N and shrinking on M.  FUSED: windows of commands are merged
  * into single passes over the state (N w; E u w; ...; M u; corrections on w
- * becomes one 2x2 update in place), and at live widths >= 18 runs of
+ * becomes one 2x2 update in place), and at live widths >= 15 runs of
  * windows/E/X/Z whose paired slots fit an LDS tile run as one
  * pass per run (2^12-amplitude tiles by default).  AUTO (default): the fused plan, run as one workgroup with
  * the whole vector in LDS when its width is <= 14, else as FUSED.  All give

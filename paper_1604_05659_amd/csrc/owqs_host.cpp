@@ -94,7 +94,7 @@ struct owqs_pattern {
   double final_factor = 1.0;
   int plan_width = 0;            // largest live width the plan reaches
 
-  int tile_bits = 0;  // 0: automatic (min(12, n - 8)); else 10..13
+  int tile_bits = 0;  // 0: automatic (max(10, min(12, n - 8))); else 10..13
   // execution steps of the global-memory path: the plan with runs of
   // window/E/X/Z steps grouped into tile passes (S_F)
   std::vector<Step> xsteps;
@@ -249,7 +249,7 @@ void group_tiles(owqs_pattern *p) {
       continue;
     }
     const int n = x0.n;
-    int k = std::min(kDefaultTileBits, n - 8);
+    int k = std::max(kMinTileBits, std::min(kDefaultTileBits, n - 8));
     if (p->tile_bits) k = std::min(p->tile_bits, n - 2);
     uint64_t tmask = (uint64_t(1) << kLowBits) - 1;
     int used = kLowBits, nwin = 0;

@@ -82,7 +82,8 @@ enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J 
 constexpr int kLowBits = 5;            // slots 0..4 are always in a tile (256-byte runs)
 constexpr int kMaxTileBits = 13;       // 2^13 complex64 = 64 KiB of LDS
 constexpr int kDefaultTileBits = 12;   // 32 KiB tiles: four workgroups per CU
-constexpr int kTileMinWidth = 18;      // narrower vectors have too few tiles to fill the chip
+constexpr int kMinTileBits = 10;       // smallest tile the kernels take
+constexpr int kTileMinWidth = 15;      // at least 2^5 tiles of 2^10; narrower runs stay one kernel per step
 constexpr int kMaxGroupWindows = 32;
 constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
 

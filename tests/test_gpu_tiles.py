@@ -1,5 +1,5 @@
 """GPU parity of the tile-fused passes (runs of windows / E / X / Z at live
-widths >= 18 executed as one LDS-tiled pass each) against the FP64 oracle."""
+widths >= 15 executed as one LDS-tiled pass each) against the FP64 oracle."""
 import math
 
 import numpy as np
@@ -86,7 +86,7 @@ def random_windowed_pattern(g, n, n_ops):
     return W.Pattern(list(range(n)), list(live), cmds)
 
 
-@pytest.mark.parametrize("n", [18, 19, 21])
+@pytest.mark.parametrize("n", [15, 16, 18, 19, 21])
 @pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS_CHECK, owqs.MODE_EOWQS])
 def test_random_windowed_patterns(ctx, n, mode, parity_report):
     g = np.random.default_rng(1800 + n)
