@@ -244,11 +244,19 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
  *   grad:      device, batch * n_meas FP64, dL_b/dalpha_m (0 for M commands
  *              outside windows)
  *   ckpt_stride: windows per checkpoint segment (0 = 16); the forward pass
- *              stores the live vectors at segment starts, and the backward
- *              pass recomputes each segment from its checkpoint.
+ *              stores the live vectors at segment starts.  When every window
+ *              has an odd number of E between its two qubits (so its 2x2
+ *              part is invertible; J gates are), the backward pass starts
+ *              each segment from the next checkpoint and recovers every
+ *              window's input from its output (Eqs. 11-12 with p = 1/2 make
+ *              the window unitary up to its scale); otherwise it recomputes
+ *              the segment forward from its checkpoint and keeps the window
+ *              inputs.  A negative stride -s selects the recomputing sweep
+ *              with segments of s windows for any pattern (the two sweeps
+ *              agree to FP32 rounding).
  * Asynchronous on `stream`; device memory of about
- * (2 + segments + ckpt_stride) * batch * 2^width * 8 bytes stays allocated
- * with the pattern. */
+ * (2 + segments) * batch * 2^width * 8 bytes (plus ckpt_stride such vectors
+ * for the recomputing sweep) stays allocated with the pattern. */
 owqs_status owqs_adjoint(owqs_pattern *pat, const void *input_c64, const double *alpha, size_t batch,
                          const int32_t *obs, int32_t nobs, double *loss, double *grad,
                          int32_t ckpt_stride, void *stream);

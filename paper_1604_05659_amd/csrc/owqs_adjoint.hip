@@ -138,6 +138,64 @@ __global__ __launch_bounds__(kB) void k_b_window_adj(const float2 *__restrict__ 
   }
 }
 
+// Reverse sweep through one window whose 2x2 part is invertible (an odd
+// number of E between its two qubits, s = -1): with K = [[1, sb c], [1, -sb c]]
+// and |c| = 1, K^dagger K = 2, so the window's input is recovered from its
+// output as psi_in = (1 / (2 f^2)) W^dagger psi_out, the same map the adjoint
+// state takes (up to the scale).  One pass reads psi_out and lam_out, writes
+// psi_in and lam_in, and adds this block's 2 Re <lam | dW/dtheta psi_in> to
+// partials[set * gridDim.x + block] (see k_b_window_adj).
+__global__ __launch_bounds__(kB) void k_b_window_rev(float2 *__restrict__ psi, float2 *__restrict__ lam,
+                                                      size_t stride, uint64_t half, int b, const float2 *coefs,
+                                                      float f, Window w, double *partials) {
+  __shared__ double red[kB / 64];
+  const float2 c = coefs[blockIdx.y];
+  const float2 cc = make_float2(c.x, -c.y);
+  const float g = 0.5f / f;
+  float2 *x = psi + size_t(blockIdx.y) * stride;
+  float2 *l = lam + size_t(blockIdx.y) * stride;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kB + threadIdx.x; i < half; i += uint64_t(gridDim.x) * kB) {
+    const uint64_t j = j0(i, b), k = j | (uint64_t(1) << b);
+    const float sb = sgnb(j, w.mask_b), so1 = sgnb(j, w.mask_o1);
+    // undo the folded corrections on the output, then invert K
+    float2 o0 = x[j], o1 = x[k];
+    if (w.neg0) o0 = make_float2(-o0.x, -o0.y);
+    if (w.neg1) o1 = make_float2(-o1.x, -o1.y);
+    if (w.swap) { const float2 t = o0; o0 = o1; o1 = t; }
+    const float2 pa = make_float2(g * (o0.x + so1 * o1.x), g * (o0.y + so1 * o1.y));
+    const float2 pd = cmulf(cc, make_float2(o0.x - so1 * o1.x, o0.y - so1 * o1.y));
+    const float2 pb = make_float2(g * sb * pd.x, g * sb * pd.y);
+    // gradient term with the recovered input (s = -1)
+    const float2 cb = cmulf(c, pb);
+    const float g0 = f * sb, g1 = -so1 * f * sb;
+    float2 d0 = make_float2(g0 * cb.y, -g0 * cb.x), d1 = make_float2(g1 * cb.y, -g1 * cb.x);
+    if (w.swap) { const float2 t = d0; d0 = d1; d1 = t; }
+    if (w.neg0) d0 = make_float2(-d0.x, -d0.y);
+    if (w.neg1) d1 = make_float2(-d1.x, -d1.y);
+    const float2 l0 = l[j], l1 = l[k];
+    acc += 2.0 * (double(l0.x) * d0.x + double(l0.y) * d0.y + double(l1.x) * d1.x + double(l1.y) * d1.y);
+    float2 m0 = w.neg0 ? make_float2(-l0.x, -l0.y) : l0;
+    float2 m1 = w.neg1 ? make_float2(-l1.x, -l1.y) : l1;
+    if (w.swap) { const float2 t = m0; m0 = m1; m1 = t; }
+    const float2 sm = make_float2(m0.x + so1 * m1.x, m0.y + so1 * m1.y);
+    const float2 cd = cmulf(cc, make_float2(m0.x - so1 * m1.x, m0.y - so1 * m1.y));
+    x[j] = pa;
+    x[k] = pb;
+    l[j] = make_float2(f * sm.x, f * sm.y);
+    l[k] = make_float2(f * sb * cd.x, f * sb * cd.y);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kB / 64; ++q) t += red[q];
+    partials[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
 struct ObsBits {
   int n;
   int bit[kWhereMax];
@@ -236,6 +294,14 @@ hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *
                                const float2 *coefs, double *partials, hipStream_t s) {
   const uint64_t half = (uint64_t(1) << st.n) >> 1;
   hipLaunchKernelGGL(k_b_window_adj, dim3(blocks_for(half), nsets), dim3(kB), 0, s, psi_in, lam, stride, half,
+                     int(st.b0), coefs, st.host_factor, window_of(st), partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_window_rev(const DevStep &st, float2 *psi, float2 *lam, size_t stride, int nsets,
+                               const float2 *coefs, double *partials, hipStream_t s) {
+  const uint64_t half = (uint64_t(1) << st.n) >> 1;
+  hipLaunchKernelGGL(k_b_window_rev, dim3(blocks_for(half), nsets), dim3(kB), 0, s, psi, lam, stride, half,
                      int(st.b0), coefs, st.host_factor, window_of(st), partials);
   return hipGetLastError();
 }

@@ -1412,7 +1412,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
 owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *alpha, size_t batch,
                          const int32_t *obs, int32_t nobs, double *loss, double *grad, int32_t ckpt_stride,
                          void *stream) {
-  if (!p || !alpha || !loss || !grad || batch == 0 || (nobs && !obs) || nobs < 0 || ckpt_stride < 0)
+  if (!p || !alpha || !loss || !grad || batch == 0 || (nobs && !obs) || nobs < 0)
     return fail(p ? p->ctx : nullptr, OWQS_E_INVALID_ARG, "null pointer or bad size");
   if (batch > 65535) return fail(p->ctx, OWQS_E_INVALID_ARG, "batch above 65535");
   if (!p->inputs.empty() && !input_c64) return fail(p->ctx, OWQS_E_INVALID_ARG, "the pattern needs an input state");
@@ -1446,15 +1446,21 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
   const int W = p->plan_width;
   const size_t stride = size_t(1) << W;
   const size_t nwin = wins.size();
-  const int cs = ckpt_stride > 0 ? ckpt_stride : 16;
+  const int cs = ckpt_stride != 0 ? (ckpt_stride > 0 ? ckpt_stride : -ckpt_stride) : 16;
   const size_t nseg = nwin ? (nwin + cs - 1) / cs : 0;
   const unsigned nblk = adj_blocks(nw);
   const unsigned lblk = loss_blocks((int)p->outputs.size());
+  // windows with an odd number of E between their two qubits are invertible:
+  // the reverse sweep then recovers each window's input from its output
+  // (no forward recompute, no stash), restarting from the forward checkpoint
+  // at every segment so that rounding cannot build up over more than one
+  bool reversible = ckpt_stride >= 0;  // a negative stride asks for the recompute sweep
+  for (size_t q : wins) reversible = reversible && !p->steps[q].win.vw_even;
   // device memory: psi, lam, checkpoints, stash, partials, coefs, cols, scales
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };  // keep every region 256-byte aligned
   const size_t vec = up(batch * stride * sizeof(float2));
   const size_t off_lam = vec, off_ckpt = 2 * vec, off_stash = off_ckpt + nseg * vec;
-  const size_t off_part = off_stash + size_t(cs) * vec;
+  const size_t off_part = off_stash + (reversible ? 0 : size_t(cs)) * vec;
   const size_t npart = std::max<size_t>(nwin * batch * nblk, batch * lblk);
   const size_t off_coef = off_part + up(npart * sizeof(double));
   const size_t off_cols = off_coef + up(std::max<size_t>(nwin, 1) * batch * sizeof(float2));
@@ -1542,9 +1548,34 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
   if (e == hipSuccess) e = launch_b_reduce(part, 1, nsets, (int)lblk, cols + nwin, scales + nwin, loss, 1, s);
   // the loss reduction reads `part` before the window partials overwrite it
   // (same stream).  cols[nwin] = 0 and scales[nwin] = 1 were uploaded above.
+  if (reversible) {
+    // backward, one segment at a time from its end state (the next segment's
+    // checkpoint, or the final state): each window step recovers its input and
+    // moves lambda back in one pass; E, X and Z are their own inverses and
+    // adjoints, applied to psi and lambda together (lam is the buffer after
+    // psi, so the two are 2 * batch sets of one array when vec holds exactly
+    // batch vectors)
+    const bool joint = vec == batch * stride * sizeof(float2) && 2 * batch <= 65535;
+    for (size_t j = nseg; j-- > 0 && e == hipSuccess;) {
+      const size_t first = wins[j * cs];
+      const size_t last = (j + 1) * cs < nwin ? wins[(j + 1) * cs] : ns;
+      if (j + 1 < nseg) e = hipMemcpyAsync(psi, ckpt(j + 1), seg_bytes, hipMemcpyDeviceToDevice, s);
+      for (size_t i = last; i-- > first && e == hipSuccess;) {
+        const size_t q = win_of[i];
+        if (q != SIZE_MAX) {
+          e = launch_b_window_rev(d[i], psi, lam, stride, nsets, coefs + q * batch, part + q * batch * nblk, s);
+        } else if (joint) {
+          e = launch_b_step(d[i], psi, stride, 2 * nsets, nullptr, s);
+        } else {
+          e = launch_b_step(d[i], psi, stride, nsets, nullptr, s);
+          if (e == hipSuccess) e = launch_b_step(d[i], lam, stride, nsets, nullptr, s);
+        }
+      }
+    }
+  }
   // backward, one segment at a time: restore, recompute with a stash of the
   // window inputs, then sweep lambda back through the segment
-  for (size_t j = nseg; j-- > 0 && e == hipSuccess;) {
+  for (size_t j = reversible ? 0 : nseg; j-- > 0 && e == hipSuccess;) {
     const size_t first = wins[j * cs];
     const size_t last = (j + 1) * cs < nwin ? wins[(j + 1) * cs] : ns;
     e = hipMemcpyAsync(psi, ckpt(j), seg_bytes, hipMemcpyDeviceToDevice, s);

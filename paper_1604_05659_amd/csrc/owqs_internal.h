@@ -166,6 +166,8 @@ hipError_t launch_b_step(const DevStep &st, float2 *psi, size_t stride, int nset
 unsigned adj_blocks(int n);   // blocks per set of launch_b_window_adj at width n
 hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *lam, size_t stride, int nsets,
                                const float2 *coefs, double *partials, hipStream_t s);
+hipError_t launch_b_window_rev(const DevStep &st, float2 *psi, float2 *lam, size_t stride, int nsets,
+                               const float2 *coefs, double *partials, hipStream_t s);
 unsigned loss_blocks(int n);  // blocks per set of launch_b_loss at width n
 hipError_t launch_b_loss(const float2 *psi, float2 *lam, size_t stride, int nsets, int n, const int *obs_bits,
                          int nobs, double ff2, double *partials, hipStream_t s);

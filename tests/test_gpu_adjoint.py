@@ -78,16 +78,39 @@ def test_adjoint_with_inputs_and_observable_subset(ctx):
 
 
 def test_checkpoint_strides_agree(ctx):
+    """The recomputing sweep (negative strides) gives bit-identical results for
+    every segment length; the reversing sweep restarts each segment from its
+    checkpoint, so its rounding depends on the segment length, within 1e-5."""
     wl, sets = W.ansatz(n_logical=6, layers=5, batch=3)
     p = _load(ctx, wl)
     ref = None
-    for stride in (1, 3, 6, 16, 1000):
+    for stride in (-1, -3, -6, -16, -1000):
         loss, grad = p.adjoint(sets, ckpt_stride=stride)
         torch.cuda.synchronize()
         if ref is None:
             ref = (loss.clone(), grad.clone())
         else:
             assert torch.equal(loss, ref[0]) and torch.equal(grad, ref[1]), stride
+    for stride in (1, 3, 6, 16, 1000):
+        loss, grad = p.adjoint(sets, ckpt_stride=stride)
+        torch.cuda.synchronize()
+        assert torch.equal(loss, ref[0]), stride  # the forward sweep is the same
+        d = (grad - ref[1]).abs()
+        assert bool((d <= 1e-5 * torch.clamp(ref[1].abs(), min=1.0)).all()), (stride, float(d.max()))
+    p.close()
+
+
+def test_reversing_sweep_matches_recompute_at_full_size(ctx, parity_report):
+    """16 qubits, 25 layers, 64 sets: the two backward sweeps agree."""
+    wl, sets = W.ansatz()
+    p = _load(ctx, wl)
+    l_rev, g_rev = p.adjoint(sets)
+    l_rev, g_rev = l_rev.clone(), g_rev.clone()
+    l_rec, g_rec = p.adjoint(sets, ckpt_stride=-16)
+    assert torch.equal(l_rev, l_rec)
+    d = float((g_rev - g_rec).abs().max())
+    parity_report("adjoint_reverse_vs_recompute_16x25", max_abs_grad_diff=d)
+    assert d <= 1e-5, d
     p.close()
 
 
