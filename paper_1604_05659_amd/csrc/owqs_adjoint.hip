@@ -144,10 +144,10 @@ __global__ __launch_bounds__(kB) void k_b_window_adj(const float2 *__restrict__ 
 // output as psi_in = (1 / (2 f^2)) W^dagger psi_out, the same map the adjoint
 // state takes (up to the scale).  One pass reads psi_out and lam_out, writes
 // psi_in and lam_in, and adds this block's 2 Re <lam | dW/dtheta psi_in> to
-// partials[set * gridDim.x + block] (see k_b_window_adj).
+// partials[set * prow + block] (see k_b_window_adj; prow >= gridDim.x).
 __global__ __launch_bounds__(kB) void k_b_window_rev(float2 *__restrict__ psi, float2 *__restrict__ lam,
                                                       size_t stride, uint64_t half, int b, const float2 *coefs,
-                                                      float f, Window w, double *partials) {
+                                                      float f, Window w, double *partials, unsigned prow) {
   __shared__ double red[kB / 64];
   const float2 c = coefs[blockIdx.y];
   const float2 cc = make_float2(c.x, -c.y);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kB) void k_b_window_rev(float2 *__restrict__ psi, f
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int q = 0; q < kB / 64; ++q) t += red[q];
-    partials[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+    partials[size_t(blockIdx.y) * prow + blockIdx.x] = t;
   }
 }
 
@@ -299,10 +299,12 @@ hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *
 }
 
 hipError_t launch_b_window_rev(const DevStep &st, float2 *psi, float2 *lam, size_t stride, int nsets,
-                               const float2 *coefs, double *partials, hipStream_t s) {
+                               const float2 *coefs, double *partials, unsigned prow, hipStream_t s) {
   const uint64_t half = (uint64_t(1) << st.n) >> 1;
-  hipLaunchKernelGGL(k_b_window_rev, dim3(blocks_for(half), nsets), dim3(kB), 0, s, psi, lam, stride, half,
-                     int(st.b0), coefs, st.host_factor, window_of(st), partials);
+  const unsigned g = blocks_for(half);
+  if (g > prow) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_b_window_rev, dim3(g, nsets), dim3(kB), 0, s, psi, lam, stride, half, int(st.b0), coefs,
+                     st.host_factor, window_of(st), partials, prow);
   return hipGetLastError();
 }
 

@@ -106,6 +106,12 @@ struct FuseOp {
 struct TileArgs {
   uint64_t tmask;    // global slots in the tile (tile bit i = the i-th lowest)
   uint64_t omask;    // the other live slots (outer bit i = the i-th lowest)
+  // several vectors (sets) at once: set y at psi + y * set_stride, window
+  // coefficients coefs[m_index * nsets + y] (coefs null: one vector, the
+  // coefficients of the command table)
+  uint64_t set_stride;
+  const float2 *coefs;
+  int nsets;
   int n, k, nops, nwin;
   uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
@@ -167,7 +173,7 @@ unsigned adj_blocks(int n);   // blocks per set of launch_b_window_adj at width 
 hipError_t launch_b_window_adj(const DevStep &st, const float2 *psi_in, float2 *lam, size_t stride, int nsets,
                                const float2 *coefs, double *partials, hipStream_t s);
 hipError_t launch_b_window_rev(const DevStep &st, float2 *psi, float2 *lam, size_t stride, int nsets,
-                               const float2 *coefs, double *partials, hipStream_t s);
+                               const float2 *coefs, double *partials, unsigned prow, hipStream_t s);
 unsigned loss_blocks(int n);  // blocks per set of launch_b_loss at width n
 hipError_t launch_b_loss(const float2 *psi, float2 *lam, size_t stride, int nsets, int n, const int *obs_bits,
                          int nobs, double ff2, double *partials, hipStream_t s);
@@ -183,5 +189,16 @@ hipError_t launch_finish_group(const MeasureArgs &a, const int *m_of_window, int
                                hipStream_t s);
 // Raise k_tile's dynamic LDS limit to 64 KiB; call outside stream capture.
 hipError_t tile_prepare();
+// The group on `nsets` vectors at once (EOWQS scale, no probabilities).
+hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta, const FuseOp *ops, int nsets, size_t set_stride,
+                            const float2 *coefs, hipStream_t s);
+// Reverse sweep of the group on nsets (psi, lam) pairs: psi goes from the
+// group's output back to its input, lam (the adjoint state) from after the
+// group to before it, and partials[((q_first + g) * nsets + y) * nblk + block]
+// receives this block's gradient sum of window g (windows must be invertible).
+hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta, const FuseOp *ops, int nsets,
+                           size_t set_stride, const float2 *coefs, double *partials, int q_first, unsigned nblk,
+                           hipStream_t s);
+unsigned tile_grid(const TileArgs &ta);
 
 }  // namespace owqs

@@ -252,6 +252,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
       m &= m - 1;
     }
   }
+  psi += size_t(blockIdx.y) * ta.set_stride;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t ob = pdep64(t, ta.omask);
@@ -282,7 +283,9 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
         float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
         if (op.flags & 2u) { if (sw) fb = -fb; else fa = -fa; }
         if (op.flags & 4u) { if (sw) fa = -fa; else fb = -fb; }
-        const float2 c0 = par64(ob & op.omask_b) ? make_float2(-op.coef.x, -op.coef.y) : op.coef;
+        float2 cw = make_float2(op.coef.x, op.coef.y);
+        if (ta.coefs) cw = ta.coefs[size_t(op.m_index) * ta.nsets + blockIdx.y];
+        const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
         const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
         // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
         const bool s1neg = !(op.flags & 8u);
@@ -320,6 +323,157 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
       for (int k = 0; k < kT / 64; ++k) s += wacc[w][k];
       partials[size_t(w) * gridDim.x + blockIdx.x] = s;
     }
+  }
+}
+
+// Reverse sweep of a window on the element pairs that differ in local bit
+// lb, for the psi tile (output -> input) and the lambda tile (after -> before)
+// at once; windows must have an odd number of E between their qubits.  In
+// the window's own terms (see k_b_window_rev): o0 = f (a + sb c b),
+// o1 = so1 f (a - sb c b), then the folded corrections P; the pair's signs
+// sb, so1 are the parities of its local bits under lmb / lmo times the
+// tile-constant parities osb / oso of the outer bits.  Returns this thread's
+// sum of 2 Re <lambda | dW/dtheta psi_in>.
+template <int kTB, int kT>
+__device__ __forceinline__ double window_rev(char *lp, char *ll, uint32_t tid, int lb, float f, float2 c, uint32_t lmb,
+                                             uint32_t lmo, float osb, float oso, bool swap, bool neg0, bool neg1) {
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  const uint32_t et = ins0u(tid, lb), bit8 = 8u << lb;
+  const float2 cc = make_float2(c.x, -c.y);
+  const float g = 0.5f / f;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const uint32_t ur = ins0u(uint32_t(r) * kT, lb);
+    const uint32_t e0 = et | ur, a0 = e0 << 3, a1 = a0 | bit8;
+    const float sb = par32(e0 & lmb) ? -osb : osb, so1 = par32(e0 & lmo) ? -oso : oso;
+    float2 o0 = *reinterpret_cast<const float2 *>(lp + a0), o1 = *reinterpret_cast<const float2 *>(lp + a1);
+    if (neg0) o0 = make_float2(-o0.x, -o0.y);
+    if (neg1) o1 = make_float2(-o1.x, -o1.y);
+    if (swap) { const float2 t = o0; o0 = o1; o1 = t; }
+    const float2 pa = make_float2(g * (o0.x + so1 * o1.x), g * (o0.y + so1 * o1.y));
+    const float2 dd = make_float2(o0.x - so1 * o1.x, o0.y - so1 * o1.y);
+    const float2 pd = make_float2(cc.x * dd.x - cc.y * dd.y, cc.x * dd.y + cc.y * dd.x);
+    const float2 pb = make_float2(g * sb * pd.x, g * sb * pd.y);
+    const float2 cb = make_float2(c.x * pb.x - c.y * pb.y, c.x * pb.y + c.y * pb.x);
+    const float g0 = f * sb, g1 = -so1 * f * sb;
+    float2 d0 = make_float2(g0 * cb.y, -g0 * cb.x), d1 = make_float2(g1 * cb.y, -g1 * cb.x);
+    if (swap) { const float2 t = d0; d0 = d1; d1 = t; }
+    if (neg0) d0 = make_float2(-d0.x, -d0.y);
+    if (neg1) d1 = make_float2(-d1.x, -d1.y);
+    const float2 l0 = *reinterpret_cast<const float2 *>(ll + a0), l1 = *reinterpret_cast<const float2 *>(ll + a1);
+    acc += 2.0 * (double(l0.x) * d0.x + double(l0.y) * d0.y + double(l1.x) * d1.x + double(l1.y) * d1.y);
+    float2 m0 = neg0 ? make_float2(-l0.x, -l0.y) : l0;
+    float2 m1 = neg1 ? make_float2(-l1.x, -l1.y) : l1;
+    if (swap) { const float2 t = m0; m0 = m1; m1 = t; }
+    const float2 sm = make_float2(m0.x + so1 * m1.x, m0.y + so1 * m1.y);
+    const float2 dm = make_float2(m0.x - so1 * m1.x, m0.y - so1 * m1.y);
+    const float2 cd = make_float2(cc.x * dm.x - cc.y * dm.y, cc.x * dm.y + cc.y * dm.x);
+    *reinterpret_cast<float2 *>(lp + a0) = pa;
+    *reinterpret_cast<float2 *>(lp + a1) = pb;
+    *reinterpret_cast<float2 *>(ll + a0) = make_float2(f * sm.x, f * sm.y);
+    *reinterpret_cast<float2 *>(ll + a1) = make_float2(f * sb * cd.x, f * sb * cd.y);
+  }
+  return acc;
+}
+
+// The reverse of a tile group on set blockIdx.y: the psi and lambda tiles sit
+// side by side in LDS and the commands run last to first (E, X, Z are their
+// own inverses and adjoints).
+template <int kTB>
+__global__ __launch_bounds__(tile_threads(kTB)) void k_tile_rev(float2 *__restrict__ psi, float2 *__restrict__ lam,
+                                                                TileArgs ta, const FuseOp *__restrict__ ops,
+                                                                double *__restrict__ partials, int q_first,
+                                                                unsigned nblk) {
+  constexpr int kT = tile_threads(kTB);
+  constexpr int kLogT = log2_threads(kT);
+  constexpr int kPer = (1 << kTB) / kT;
+  constexpr int kHi = kTB - kLogT;
+  extern __shared__ float2 tile[];
+  __shared__ double wacc[kMaxGroupWindows][kT / 64];
+  char *const lp = reinterpret_cast<char *>(tile);
+  char *const ll = reinterpret_cast<char *>(tile + (1 << kTB));
+  const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
+  psi += size_t(blockIdx.y) * ta.set_stride;
+  lam += size_t(blockIdx.y) * ta.set_stride;
+  const uint64_t g_tid = pdep64(tid, ta.tmask);
+  uint64_t hp[kHi];
+  {
+    uint64_t m = ta.tmask;
+    for (int i = 0; i < kLogT; ++i) m &= m - 1;
+#pragma unroll
+    for (int j = 0; j < kHi; ++j) {
+      hp[j] = m & (~m + 1);
+      m &= m - 1;
+    }
+  }
+  const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t ob = pdep64(t, ta.omask);
+    const uint64_t gb = ob | g_tid;
+    {
+      float2 v[kPer], w[kPer];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
+#pragma unroll
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        v[r] = psi[g];
+        w[r] = lam[g];
+      }
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        tile[tid + r * kT] = v[r];
+        tile[(1 << kTB) + tid + r * kT] = w[r];
+      }
+    }
+    __syncthreads();
+    for (int o = ta.nops - 1; o >= 0; --o) {
+      const FuseOp op = load_op(ops, o);
+      if (op.kind == DK_E || op.kind == DK_Z) {
+        if ((ob & op.omask_b) == op.omask_b) {
+          diag_flip<kTB, kT>(lp, tid, op.lmask_b);
+          diag_flip<kTB, kT>(ll, tid, op.lmask_b);
+        }
+      } else if (op.kind == DK_X) {
+        pair_swap<kTB, kT>(lp, tid, op.lb);
+        pair_swap<kTB, kT>(ll, tid, op.lb);
+      } else {
+        const float2 cw = ta.coefs[size_t(op.m_index) * ta.nsets + blockIdx.y];
+        const float osb = par64(ob & op.omask_b) ? -1.f : 1.f, oso = par64(ob & op.omask_o1) ? -1.f : 1.f;
+        const double acc = window_rev<kTB, kT>(lp, ll, tid, op.lb, op.f, cw, op.lmask_b, op.lmask_o1, osb, oso,
+                                               op.flags & 1u, op.flags & 2u, op.flags & 4u);
+        const double d = wave_sum_to_last(acc);
+        if (lane == 63) wacc[op.widx][wave] += d;
+      }
+      __syncthreads();
+    }
+    {
+      float2 v[kPer], w[kPer];
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        v[r] = tile[tid + r * kT];
+        w[r] = tile[(1 << kTB) + tid + r * kT];
+      }
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
+#pragma unroll
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        psi[g] = v[r];
+        lam[g] = w[r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int w = tid; w < ta.nwin; w += kT) {
+    double s = 0.0;
+    for (int k = 0; k < kT / 64; ++k) s += wacc[w][k];
+    partials[((size_t(q_first) + w) * ta.nsets + blockIdx.y) * nblk + blockIdx.x] = s;
   }
 }
 
@@ -379,8 +533,13 @@ hipError_t tile_prepare() {
   hipError_t e = hipSuccess;
   const void *fns[] = {reinterpret_cast<const void *>(k_tile<10>), reinterpret_cast<const void *>(k_tile<11>),
                        reinterpret_cast<const void *>(k_tile<12>), reinterpret_cast<const void *>(k_tile<13>)};
-  for (int i = 0; i < 4 && e == hipSuccess; ++i)
+  const void *rev[] = {reinterpret_cast<const void *>(k_tile_rev<10>), reinterpret_cast<const void *>(k_tile_rev<11>),
+                       reinterpret_cast<const void *>(k_tile_rev<12>), reinterpret_cast<const void *>(k_tile_rev<13>)};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
     e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(rev[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(2 * sizeof(float2) << (10 + i)));
+  }
   return e;
 }
 
@@ -396,6 +555,46 @@ hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const
     default: return hipErrorInvalidValue;
   }
   *grid = g;
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta0, const FuseOp *ops, int nsets, size_t set_stride,
+                            const float2 *coefs, hipStream_t s) {
+  TileArgs ta = ta0;
+  ta.set_stride = set_stride;
+  ta.coefs = coefs;
+  ta.nsets = nsets;
+  MeasureArgs a{};
+  a.reduce = kReduceNone;
+  const size_t bytes = sizeof(float2) << ta.k;
+  const dim3 grid(tile_grid(ta), unsigned(nsets));
+  switch (ta.k) {
+    case 10: hipLaunchKernelGGL(k_tile<10>, grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr); break;
+    case 11: hipLaunchKernelGGL(k_tile<11>, grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr); break;
+    case 12: hipLaunchKernelGGL(k_tile<12>, grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr); break;
+    case 13: hipLaunchKernelGGL(k_tile<13>, grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta0, const FuseOp *ops, int nsets,
+                           size_t set_stride, const float2 *coefs, double *partials, int q_first, unsigned nblk,
+                           hipStream_t s) {
+  TileArgs ta = ta0;
+  ta.set_stride = set_stride;
+  ta.coefs = coefs;
+  ta.nsets = nsets;
+  const size_t bytes = 2 * sizeof(float2) << ta.k;
+  const dim3 grid(tile_grid(ta), unsigned(nsets));
+  if (grid.x > nblk) return hipErrorInvalidValue;  // the partials rows hold nblk blocks
+  switch (ta.k) {
+    case 10: hipLaunchKernelGGL(k_tile_rev<10>, grid, dim3(tile_threads(10)), bytes, s, psi, lam, ta, ops, partials, q_first, nblk); break;
+    case 11: hipLaunchKernelGGL(k_tile_rev<11>, grid, dim3(tile_threads(11)), bytes, s, psi, lam, ta, ops, partials, q_first, nblk); break;
+    case 12: hipLaunchKernelGGL(k_tile_rev<12>, grid, dim3(tile_threads(12)), bytes, s, psi, lam, ta, ops, partials, q_first, nblk); break;
+    case 13: hipLaunchKernelGGL(k_tile_rev<13>, grid, dim3(tile_threads(13)), bytes, s, psi, lam, ta, ops, partials, q_first, nblk); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

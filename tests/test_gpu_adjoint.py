@@ -79,8 +79,9 @@ def test_adjoint_with_inputs_and_observable_subset(ctx):
 
 def test_checkpoint_strides_agree(ctx):
     """The recomputing sweep (negative strides) gives bit-identical results for
-    every segment length; the reversing sweep restarts each segment from its
-    checkpoint, so its rounding depends on the segment length, within 1e-5."""
+    every segment length; the reversing sweep (grouped forward, windows
+    inverted backward, each segment restarted from its checkpoint) agrees
+    with it to FP32 rounding: losses within 1e-6, gradients within 1e-5."""
     wl, sets = W.ansatz(n_logical=6, layers=5, batch=3)
     p = _load(ctx, wl)
     ref = None
@@ -94,7 +95,8 @@ def test_checkpoint_strides_agree(ctx):
     for stride in (1, 3, 6, 16, 1000):
         loss, grad = p.adjoint(sets, ckpt_stride=stride)
         torch.cuda.synchronize()
-        assert torch.equal(loss, ref[0]), stride  # the forward sweep is the same
+        # the forward sweep runs grouped (tile passes) here, per step there
+        assert float((loss - ref[0]).abs().max()) <= 1e-6, stride
         d = (grad - ref[1]).abs()
         assert bool((d <= 1e-5 * torch.clamp(ref[1].abs(), min=1.0)).all()), (stride, float(d.max()))
     p.close()
@@ -107,7 +109,7 @@ def test_reversing_sweep_matches_recompute_at_full_size(ctx, parity_report):
     l_rev, g_rev = p.adjoint(sets)
     l_rev, g_rev = l_rev.clone(), g_rev.clone()
     l_rec, g_rec = p.adjoint(sets, ckpt_stride=-16)
-    assert torch.equal(l_rev, l_rec)
+    assert float((l_rev - l_rec).abs().max()) <= 1e-6
     d = float((g_rev - g_rec).abs().max())
     parity_report("adjoint_reverse_vs_recompute_16x25", max_abs_grad_diff=d)
     assert d <= 1e-5, d
