@@ -176,3 +176,74 @@ def test_adjoint_rejects_measurements_outside_windows(ctx):
         p.adjoint(np.zeros((1, p.n_meas)))
     assert e.value.status == owqs.E_STATE
     p.close()
+
+
+def _masked_window_pattern(g, n, n_ops):
+    """n inputs; windows whose runs also hold E's from v or w to other live
+    qubits (sign masks), standalone E and signalled X/Z steps: no measurement
+    outside a window, as the adjoint requires.  No flow, but every window is
+    invertible (one E between v and w)."""
+    live = list(range(n))
+    nxt, measured, cmds = n, [], []
+    for _ in range(n_ops):
+        r = g.random()
+        if r < 0.7:
+            v = live[int(g.integers(len(live)))]
+            w = nxt
+            nxt += 1
+            others = [q for q in live if q != v]
+            es = [("E", v, w)]
+            es += [("E", v, int(x)) for x in g.choice(others, size=int(g.integers(0, 3)), replace=False)]
+            es += [("E", w, int(y)) for y in g.choice(others, size=int(g.integers(0, 2)), replace=False)]
+            g.shuffle(es)
+            cmds += [("N", w)] + [tuple(e) for e in es] + [("M", v, float(g.uniform(0, 2 * math.pi)), (), ())]
+            cmds.append(("X", w, (v,)))
+            live[live.index(v)] = w
+            measured.append(v)
+        elif r < 0.85:
+            a, b = g.choice(len(live), size=2, replace=False)
+            cmds.append(("E", live[a], live[b]))
+        elif measured:
+            q = live[int(g.integers(len(live)))]
+            cmds.append(("X" if g.random() < 0.5 else "Z", q, (measured[int(g.integers(len(measured)))],)))
+    return W.Pattern(list(range(n)), list(live), cmds)
+
+
+def test_masked_windows_reversing_tiled_sweep(ctx, parity_report):
+    """Width 16 (tile passes), windows with sign masks: the reversing sweep
+    agrees with the recomputing per-step sweep, and with the shift rule
+    evaluated on GPU forward losses."""
+    g = np.random.default_rng(1616)
+    pat = _masked_window_pattern(g, 16, 160)
+    p = owqs.Pattern(ctx, pat)
+    p.set_mode(owqs.MODE_EOWQS)
+    p.set_outcomes(g.integers(0, 2, size=pat.n_meas()).astype(np.uint8))
+    x = torch.as_tensor(W.gaussian_state(16, g)).cuda()
+    base = pat.angles()
+    sets = np.stack([base + g.normal(0, 0.4, base.size) for _ in range(4)])
+    l_rev, g_rev = p.adjoint(sets, psi_in=x)
+    l_rev, g_rev = l_rev.cpu().numpy(), g_rev.cpu().numpy()
+    assert p.plan_info()[2] < p.plan_info()[1]  # tile passes were formed
+    l_rec, g_rec = p.adjoint(sets, psi_in=x, ckpt_stride=-8)
+    l_rec, g_rec = l_rec.cpu().numpy(), g_rec.cpu().numpy()
+    assert np.max(np.abs(l_rev - l_rec)) <= 1e-5
+    d = np.abs(g_rev - g_rec)
+    assert np.all(d <= 1e-4 * np.maximum(1.0, np.abs(g_rec))), d.max()
+    # shift rule on the GPU's own forward losses at sampled (set, angle)
+    picks = [(int(g.integers(4)), int(g.integers(base.size))) for _ in range(12)]
+    shifted = []
+    for b, k in picks:
+        for sgn in (1, -1):
+            a = sets[b].copy()
+            a[k] += sgn * math.pi / 2
+            shifted.append(a)
+    sl, _ = p.adjoint(np.stack(shifted), psi_in=x)
+    sl = sl.cpu().numpy()
+    worst = 0.0
+    for i, (b, k) in enumerate(picks):
+        gs = 0.5 * (sl[2 * i] - sl[2 * i + 1])
+        worst = max(worst, abs(gs - g_rev[b, k]))
+        assert abs(gs - g_rev[b, k]) <= 1e-4 * max(1.0, abs(gs)), (b, k, gs, g_rev[b, k])
+    parity_report("adjoint_masked_windows_width16", max_grad_diff_vs_recompute=float(d.max()),
+                  max_grad_diff_vs_gpu_shift=worst)
+    p.close()
