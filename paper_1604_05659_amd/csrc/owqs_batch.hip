@@ -43,6 +43,22 @@ __device__ double block_sum(double v, double *red) {
   return s;
 }
 
+// One command row, read as whole dwords through the constant address space
+// (the table is never written by the kernels), so the scalar unit loads it:
+// every thread of the workgroup walks the same command list.
+__device__ __forceinline__ DevStep load_step(const DevStep *steps, int s) {
+  static_assert(sizeof(DevStep) % 4 == 0, "DevStep is whole dwords");
+  constexpr int kWords = sizeof(DevStep) / 4;
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(steps)) + kWords * __builtin_amdgcn_readfirstlane(s);
+  uint32_t w[kWords];
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) w[i] = src[i];
+  DevStep st;
+  __builtin_memcpy(&st, w, sizeof(st));
+  return st;
+}
+
 template <int kT>
 __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin, int nout, const int *where,
                          double final_factor, float2 *lds, const float2 *__restrict__ in, int basis,
@@ -64,7 +80,7 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
   double sigma = 1.0;
   __syncthreads();
   for (int s = 0; s < nsteps; ++s) {
-    const DevStep st = steps[s];
+    const DevStep st = load_step(steps, s);
     const uint32_t dim = 1u << st.n;
     const int b = st.b0;
     if (st.kind == DK_N) {

@@ -39,9 +39,12 @@ __device__ __forceinline__ float2 &at(char *lds, uint32_t byte_off) { return *re
 
 // One command of the group, read as whole dwords from a uniform address so
 // that it comes through scalar loads (its byte fields are unpacked after).
-__device__ __forceinline__ FuseOp load_op(const FuseOp *ops, int o) {
+__device__ __forceinline__ FuseOp load_op(const FuseOp *__restrict__ ops, int o) {
   static_assert(sizeof(FuseOp) == 48, "FuseOp is 12 dwords");
-  const uint32_t *src = reinterpret_cast<const uint32_t *>(ops) + 12 * __builtin_amdgcn_readfirstlane(o);
+  // the command table is never written by the kernels: read it through the
+  // constant address space, which the scalar unit may always load
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(ops)) + 12 * __builtin_amdgcn_readfirstlane(o);
   uint32_t w[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) w[i] = src[i];
@@ -71,6 +74,14 @@ __device__ __forceinline__ double wave_sum_to_last(double x) {
   x = add_dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
   x = add_dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
+}
+
+// Window coefficient of measurement m for set blockIdx.y (read-only table,
+// uniform over the workgroup: scalar loads through the constant space).
+__device__ __forceinline__ float2 set_coef(const TileArgs &ta, int m) {
+  typedef const __attribute__((address_space(4))) float cf;
+  cf *tab = reinterpret_cast<cf *>(reinterpret_cast<uintptr_t>(ta.coefs)) + 2 * (size_t(m) * ta.nsets + blockIdx.y);
+  return make_float2(tab[0], tab[1]);
 }
 
 // Deposit the low bits of x, lowest first, into the set bits of mask.
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
         if (op.flags & 2u) { if (sw) fb = -fb; else fa = -fa; }
         if (op.flags & 4u) { if (sw) fa = -fa; else fb = -fb; }
         float2 cw = make_float2(op.coef.x, op.coef.y);
-        if (ta.coefs) cw = ta.coefs[size_t(op.m_index) * ta.nsets + blockIdx.y];
+        if (ta.coefs) cw = set_coef(ta, op.m_index);
         const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
         const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
         // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
@@ -442,7 +453,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_rev(float2 *__restri
         pair_swap<kTB, kT>(lp, tid, op.lb);
         pair_swap<kTB, kT>(ll, tid, op.lb);
       } else {
-        const float2 cw = ta.coefs[size_t(op.m_index) * ta.nsets + blockIdx.y];
+        const float2 cw = set_coef(ta, op.m_index);
         const float osb = par64(ob & op.omask_b) ? -1.f : 1.f, oso = par64(ob & op.omask_o1) ? -1.f : 1.f;
         const double acc = window_rev<kTB, kT>(lp, ll, tid, op.lb, op.f, cw, op.lmask_b, op.lmask_o1, osb, oso,
                                                op.flags & 1u, op.flags & 2u, op.flags & 4u);
