@@ -92,7 +92,7 @@ def _load():
         lib.owqs_oracle_run.argtypes = [
             ctypes.c_int, ip, ip, ip, dp, ip, ip, ip, ip, ip,
             ctypes.c_int, ip, ctypes.c_int, ip, dp, dp,
-            ctypes.POINTER(ctypes.c_ubyte), ctypes.c_int, ctypes.c_int,
+            ctypes.POINTER(ctypes.c_ubyte), dp, ctypes.c_int, ctypes.c_int,
             dp, dp, dp, ip, ip, ip]
         lib.owqs_oracle_set_threads.restype = ctypes.c_int
         lib.owqs_oracle_set_threads.argtypes = [ctypes.c_int]
@@ -138,8 +138,22 @@ def _arrays(pattern):
     return op, q0, q1, al, so, sl, to, tl, dom_a
 
 
+def run_sampled(pattern, uniforms: Sequence[float], input_state: Optional[np.ndarray] = None,
+                stop: Optional[int] = None):
+    """OWQS run whose outcomes are drawn (Fig. 6): the m-th M gives 0 when
+    uniforms[m] <= p_0 (Eq. 13 of the outcome-0 branch, Eq. 11).  Returns
+    (psi, probs, outcomes) on a full run, (live vector, slots, probs,
+    outcomes) on a partial one; probs[m] is the probability of the drawn
+    outcome."""
+    u = np.ascontiguousarray(uniforms, np.float64)
+    if u.size != pattern.n_meas():
+        raise ValueError("one uniform per M command")
+    res = run(pattern, np.zeros(pattern.n_meas(), np.uint8), input_state, MODE_OWQS, stop, _uniforms=u)
+    return res
+
+
 def run(pattern, outcomes: Sequence[int], input_state: Optional[np.ndarray] = None,
-        mode: int = MODE_OWQS, stop: Optional[int] = None):
+        mode: int = MODE_OWQS, stop: Optional[int] = None, _uniforms: Optional[np.ndarray] = None):
     """Execute the pattern.
 
     Full run (stop is None): returns (psi_out complex128 over the outputs in
@@ -180,16 +194,18 @@ def run(pattern, outcomes: Sequence[int], input_state: Optional[np.ndarray] = No
         _ptr(to, ctypes.c_int), _ptr(tl, ctypes.c_int), _ptr(dom, ctypes.c_int),
         nin, _ptr(inputs, ctypes.c_int), len(pattern.outputs), _ptr(outputs, ctypes.c_int),
         _ptr(in_re, ctypes.c_double), _ptr(in_im, ctypes.c_double),
-        _ptr(oc, ctypes.c_ubyte), int(mode), -1 if stop is None else int(stop),
+        _ptr(oc, ctypes.c_ubyte), None if _uniforms is None else _ptr(_uniforms, ctypes.c_double),
+        int(mode), -1 if stop is None else int(stop),
         _ptr(out_re, ctypes.c_double), _ptr(out_im, ctypes.c_double), _ptr(probs, ctypes.c_double),
         _ptr(slots, ctypes.c_int), _ptr(n_live, ctypes.c_int), _ptr(err, ctypes.c_int))
     if rc != 0:
         raise OracleError(rc, int(err[0]))
     nm_done = nmeas if stop is None else sum(1 for c in pattern.cmds[:stop] if c[0] == "M")
+    drawn = () if _uniforms is None else (oc[:nm_done].copy(),)
     if stop is None:
-        return out_re + 1j * out_im, probs[:nmeas].copy()
+        return (out_re + 1j * out_im, probs[:nmeas].copy()) + drawn
     nl = int(n_live[0])
-    return (out_re[: 1 << nl] + 1j * out_im[: 1 << nl]), list(slots[:nl]), probs[:nm_done].copy()
+    return ((out_re[: 1 << nl] + 1j * out_im[: 1 << nl]), list(slots[:nl]), probs[:nm_done].copy()) + drawn
 
 
 # ---------------------------------------------------------------------------

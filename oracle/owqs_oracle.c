@@ -88,7 +88,10 @@ int owqs_oracle_set_threads(int nthreads) {
  * Commands are parallel arrays: op, q0, q1 (E's second qubit), alpha (M),
  * s_off/s_len, t_off/t_len index into dom[] (t used by M only).
  * inputs[k] is bit k of the input vector (in_re/in_im, 2^nin entries).
- * outcomes[m] is the forced outcome of the m-th M command.
+ * outcomes[m] is the forced outcome of the m-th M command; with uniforms
+ * non-NULL the outcomes are drawn instead (Fig. 6: outcome 0 when
+ * uniforms[m] <= p_0, the probability of the outcome-0 branch, Eq. 13 with
+ * the operator of Eq. 11) and written to outcomes[m].
  * On a full run out_re/out_im receive 2^nout amplitudes with outputs[k] at
  * bit k; on a partial run they receive the live vector (2^n_live entries) and
  * live_slots[k] the qubit held by bit k.  probs[m] receives p of the m-th M.
@@ -98,7 +101,7 @@ int owqs_oracle_run(int ncmd, const int *op, const int *q0, const int *q1,
                     const int *t_off, const int *t_len, const int *dom,
                     int nin, const int *inputs, int nout, const int *outputs,
                     const double *in_re, const double *in_im,
-                    const unsigned char *outcomes, int mode, int stop,
+                    unsigned char *outcomes, const double *uniforms, int mode, int stop,
                     double *out_re, double *out_im, double *probs,
                     int *live_slots, int *n_live_out, int *err_cmd) {
   if (ncmd < 0 || nin < 0 || nout < 0 || nin > ORACLE_MAX_WIDTH) return -1;
@@ -188,14 +191,32 @@ int owqs_oracle_run(int ncmd, const int *op, const int *q0, const int *q1,
       int s = signal_of(dom, s_off[c], s_len[c], qstate, qout, nq);
       int t = signal_of(dom, t_off[c], t_len[c], qstate, qout, nq);
       if (s < 0 || t < 0) { rc = -2; goto fail; }
-      int o = outcomes[m_index] & 1;
       double theta = (s ? -alpha[c] : alpha[c]) + (t ? M_PI : 0.0);   /* Eq. 2 */
       cplx coef = cexp(-I * theta);                                   /* Eqs. 11, 12 */
-      if (o) coef = -coef;
       int b = -1;
       for (int k = 0; k < n; ++k) if (slot[k] == v) b = k;
       size_t half = (size_t)1 << (n - 1);
       size_t low = ((size_t)1 << b) - 1;
+      int o;
+      if (uniforms) {
+        /* probability of outcome 0 relative to the current norm */
+        double p0 = 0.0, nrm = 0.0;
+        const double r0 = 1.0 / sqrt(2.0);
+#pragma omp parallel for schedule(static) reduction(+ : p0, nrm)
+        for (size_t k = 0; k < half; ++k) {
+          size_t k0 = ((k >> b) << (b + 1)) | (k & low);
+          size_t k1 = k0 | ((size_t)1 << b);
+          cplx val = (psi[k0] + coef * psi[k1]) * r0;
+          p0 += creal(val) * creal(val) + cimag(val) * cimag(val);
+          nrm += creal(psi[k0]) * creal(psi[k0]) + cimag(psi[k0]) * cimag(psi[k0]) +
+                 creal(psi[k1]) * creal(psi[k1]) + cimag(psi[k1]) * cimag(psi[k1]);
+        }
+        o = (nrm > 0.0 && uniforms[m_index] <= p0 / nrm) ? 0 : 1;
+        outcomes[m_index] = (unsigned char)o;
+      } else {
+        o = outcomes[m_index] & 1;
+      }
+      if (o) coef = -coef;
       cplx *next = malloc(sizeof(cplx) * (half ? half : 1));
       if (!next) { rc = -5; goto fail; }
       const double r = 1.0 / sqrt(2.0);

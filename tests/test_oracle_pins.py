@@ -381,3 +381,47 @@ def test_seeded_outcome_stream_is_splitmix64():
     a, b = oc.outcomes_from_seed(7, 4096), oc.outcomes_from_seed(8, 4096)
     assert abs(a.mean() - 0.5) < 0.04 and abs(b.mean() - 0.5) < 0.04
     assert 0.4 < (a != b).mean() < 0.6
+
+
+def test_sampled_outcomes_follow_the_bloch_sphere_probability():
+    """Sampling (Fig. 6): outcome 0 exactly when u <= p_0.  For the qubit
+    cos a |0> + e^{ib} sin a |1> measured in the XY plane at alpha, p_0 is
+    (1 + sin 2a cos(b - alpha)) / 2 (Bloch vector (sin 2a cos b, sin 2a sin b,
+    cos 2a) projected on (cos alpha, sin alpha, 0))."""
+    g = np.random.default_rng(404)
+    for a, b, alpha in [(0.3, 1.1, 0.4), (1.2, -0.7, 2.5), (0.785, 0.0, 0.0), (0.1, 2.0, 5.0)]:
+        psi = np.array([math.cos(a), complex(math.cos(b), math.sin(b)) * math.sin(a)], np.complex128)
+        p0 = 0.5 * (1.0 + math.sin(2 * a) * math.cos(b - alpha))
+        pat = W.Pattern([0], [], [("M", 0, alpha, (), ())])
+        for u in np.concatenate([np.linspace(0.0, 0.999, 37), [p0 - 1e-9, p0 + 1e-9]]):
+            u = float(min(max(u, 0.0), 0.999999))
+            _, probs, outc = oc.run_sampled(pat, [u], psi)
+            assert outc[0] == (0 if u <= p0 else 1), (a, b, alpha, u, p0)
+            assert probs[0] == pytest.approx(p0 if outc[0] == 0 else 1 - p0, abs=1e-12)
+        # frequencies over many draws
+        us = g.random(4000)
+        zeros = sum(int(oc.run_sampled(pat, [float(u)], psi)[2][0] == 0) for u in us)
+        sd = math.sqrt(4000 * p0 * (1 - p0)) + 1e-9
+        assert abs(zeros - 4000 * p0) <= 5 * sd + 1
+
+
+def test_sampled_runs_of_flow_patterns_are_deterministic():
+    """Patterns with flow give the same output whatever is drawn (Sec. 4.5),
+    and a drawn outcome string replayed as forced outcomes reproduces the run."""
+    g = np.random.default_rng(405)
+    wl = W.plain_small()
+    want, _ = oc.run(wl.pattern, np.zeros(wl.pattern.n_meas(), np.uint8))
+    for _ in range(5):
+        u = g.random(wl.pattern.n_meas())
+        got, probs, outc = oc.run_sampled(wl.pattern, u)
+        np.testing.assert_allclose(got, want, atol=1e-12)
+        np.testing.assert_allclose(probs, 0.5, atol=1e-12)
+        replay, pr = oc.run(wl.pattern, outc)
+        np.testing.assert_allclose(replay, got, atol=1e-12)
+        np.testing.assert_allclose(pr, probs, atol=1e-12)
+    # cluster patterns agree up to the global phase of signal-adapted angles
+    cl = W.cluster(rows=4, cols=6)
+    ref, _ = oc.run(cl.pattern, np.zeros(cl.pattern.n_meas(), np.uint8))
+    got, _, outc = oc.run_sampled(cl.pattern, g.random(cl.pattern.n_meas()))
+    assert abs(abs(np.vdot(ref, got)) - 1.0) < 1e-10
+    assert outc.any() and not outc.all()
