@@ -300,6 +300,33 @@ def bench_cluster(owqs, torch, W, ctx, steps):
     return res
 
 
+def bench_sampled(owqs, torch, pat, inp, out, n_nontriv, steps, warmup):
+    """The same large pattern with its outcomes drawn on the device from seeded
+    uniforms (plain plan, signals resolved on the GPU, replayed as a graph).
+    The pattern is deterministic, so the output must equal the forced run's."""
+    pat.set_exec(owqs.EXEC_PLAIN)
+    pat.run(inp)
+    pat.read_state(out)
+    forced = out.clone()
+    u = np.random.default_rng([160405659, 2, 4, 0]).random(pat.n_meas)
+    pat.set_uniforms(u)
+    for _ in range(warmup):
+        pat.run(inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pat.run(inp)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pat.read_state(out)
+    drawn = pat.read_outcomes()
+    res = {"workload": "plain_large with outcomes drawn on the device (u <= p_0 gives 0; seeded uniforms)",
+           "ms_per_run": round(1e3 * dt, 3), "commands_per_s": round(n_nontriv / dt, 1),
+           "ones_drawn": int(drawn.sum()), "max_abs_diff_vs_forced": float((out - forced).abs().max().item())}
+    pat.set_uniforms(None)
+    return res
+
+
 def bench_small(owqs, torch, W, ctx, steps):
     """The small plain pattern (4 logical qubits, 106 commands): latency of
     one run plus read-out through the C ABI (fused plan replayed as a graph)."""
@@ -361,6 +388,7 @@ def main():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-sampled", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the extra event-timed step (for counter collection runs)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -376,7 +404,7 @@ def main():
               "(no multi-GPU path); use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.only_plain:
-        args.no_fused = args.no_batch = args.no_adjoint = args.no_cpu_baseline = True
+        args.no_fused = args.no_batch = args.no_adjoint = args.no_sampled = args.no_cpu_baseline = True
 
     import torch
     import owqs_workloads as W
@@ -468,6 +496,9 @@ def main():
             _, roof_f = roofline_of(prof_f, names)
             result["fused"]["roofline"] = roof_f
             result["fused"]["kernels"] = kernel_table(prof_f)
+    if not args.no_sampled:
+        log("[bench] drawn outcomes")
+        result["sampled"] = bench_sampled(owqs, torch, pat, inp, out, n_nontriv, args.steps, args.warmup)
     pat.close()
 
     if not args.no_batch:

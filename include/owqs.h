@@ -301,6 +301,24 @@ owqs_status owqs_set_outcome_seed(owqs_pattern *pat, uint64_t seed);
 /* Copy the forced outcomes (bits[m] for the m-th M) to host memory. */
 owqs_status owqs_get_outcomes(const owqs_pattern *pat, uint8_t *bits, size_t n_meas);
 
+/* Drawn outcomes (Fig. 6): owqs_run draws the outcome of the m-th M on the
+ * device, 0 when u[m] <= p_0 and 1 otherwise, where p_0 is the probability
+ * of outcome 0 (Eq. 13 with the operator of Eq. 11) of the state at that
+ * point; signals and angles of later commands (Eq. 2) use the drawn
+ * outcomes, so no host round trip happens during a run (the run is replayed
+ * as a HIP graph like a forced one).  u: host, n_meas values in [0, 1),
+ * copied (the call waits for earlier device work).  u = NULL (n_meas = 0)
+ * returns to forced outcomes, as do owqs_set_outcomes and
+ * owqs_set_outcome_seed.  Needs OWQS mode (else owqs_run returns
+ * OWQS_E_STATE).  Only owqs_run draws: owqs_run_range, owqs_run_basis,
+ * owqs_run_states and owqs_adjoint take the forced outcomes, and
+ * owqs_run_batch refuses a pattern that draws (OWQS_E_STATE). */
+owqs_status owqs_set_uniforms(owqs_pattern *pat, const double *u, size_t n_meas);
+
+/* The outcomes of the last run: drawn ones after a run with uniforms (waits
+ * for `stream`), else the forced ones. */
+owqs_status owqs_read_outcomes(owqs_pattern *pat, uint8_t *bits, size_t n_meas, void *stream);
+
 /* Lockstep execution for debugging against a reference: run commands
  * [cmd_begin, cmd_end) of the pattern (execution order, Sec. 2.2) with the
  * plain plan, one kernel per non-trivial command, on `stream`.

@@ -79,6 +79,8 @@ _sig = {
     "owqs_read_probs": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _vp]),
     "owqs_set_outcome_seed": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "owqs_get_outcomes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t]),
+    "owqs_set_uniforms": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "owqs_read_outcomes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t, _vp]),
     "owqs_run_range": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_size_t, ctypes.c_size_t,
                                       _vp]),
     "owqs_read_live": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _i32p, _vp]),
@@ -292,6 +294,23 @@ class Pattern:
     def outcomes(self) -> np.ndarray:
         b = np.zeros(max(self.n_meas, 1), np.uint8)
         self.ctx.check(_lib.owqs_get_outcomes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), self.n_meas))
+        return b[: self.n_meas]
+
+    def set_uniforms(self, u):
+        """Draw outcomes on the device from these uniforms (owqs_set_uniforms);
+        None returns to forced outcomes."""
+        if u is None:
+            self.ctx.check(_lib.owqs_set_uniforms(self._h, None, 0))
+            return
+        a = np.ascontiguousarray(u, np.float64)
+        self.ctx.check(_lib.owqs_set_uniforms(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.size))
+
+    def read_outcomes(self, stream=None) -> np.ndarray:
+        """Outcomes of the last run (drawn or forced)."""
+        b = np.zeros(max(self.n_meas, 1), np.uint8)
+        h = None if self.ctx.device < 0 else _stream_handle(stream)  # a host-only context has no stream
+        self.ctx.check(_lib.owqs_read_outcomes(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                               self.n_meas, h))
         return b[: self.n_meas]
 
     def run_range(self, begin: int, end: int, psi_in=None, stream=None):

@@ -142,6 +142,27 @@ struct owqs_pattern {
 
   std::vector<int32_t> user_id;  // dense qubit index -> caller's id
 
+  // drawn outcomes (owqs_set_uniforms): the plain plan with every signal and
+  // measurement coefficient resolved on the device
+  struct SStep {
+    int kind, n, b0, b1, m;
+    double alpha, host_factor;
+    SigRef s, t;
+  };
+  bool sampling = false;
+  std::vector<double> uniforms;
+  bool s_valid = false;
+  std::vector<SStep> s_steps;
+  std::vector<int> s_dom;           // measurement indices of the signal domains
+  std::vector<int> s_final_where;
+  double s_final_factor = 1.0;
+  void *s_mem = nullptr;            // uniforms, outcomes, coefficient, domains
+  size_t s_cap = 0;
+  bool s_uploaded = false;          // uniforms and domains are on the device
+  hipGraph_t s_graph = nullptr;
+  hipGraphExec_t s_exec = nullptr;
+  bool sampled_ran = false;
+
   bool ran = false;
   bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
   bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)
@@ -808,8 +829,214 @@ void end_ranged(owqs_pattern *p) {
   p->lk_ran = false;
 }
 
+// The plan for drawn outcomes: one step per command in execution order (N
+// appends the top slot, M moves the top qubit into the measured slot, as in
+// compile_plan); every X/Z is kept (its signal is known only on the device)
+// and the signal domains become lists of measurement indices.
+void compile_sampled(owqs_pattern *p) {
+  std::vector<int> slot_of(p->nq, -1), qubit_at(OWQS_MAX_WIDTH + 1, -1), m_of(p->nq, -1);
+  int n = (int)p->inputs.size();
+  for (int k = 0; k < n; ++k) {
+    slot_of[p->inputs[k]] = k;
+    qubit_at[k] = p->inputs[k];
+  }
+  const double r2 = 1.0 / std::sqrt(2.0);
+  double pending = 1.0;
+  int m = 0;
+  p->s_steps.clear();
+  p->s_dom.clear();
+  auto dom = [&](const std::vector<int> &qs) {
+    SigRef r{(int)p->s_dom.size(), (int)qs.size()};
+    for (int q : qs) p->s_dom.push_back(m_of[q]);  // D0: measured before
+    return r;
+  };
+  for (const Cmd &c : p->cmds) {
+    owqs_pattern::SStep st{};
+    st.n = n;
+    switch (c.op) {
+      case OWQS_OP_N:
+        st.kind = S_N;
+        slot_of[c.q0] = n;
+        qubit_at[n] = c.q0;
+        ++n;
+        pending *= r2;
+        break;
+      case OWQS_OP_E:
+        st.kind = S_E;
+        st.b0 = slot_of[c.q0];
+        st.b1 = slot_of[c.q1];
+        break;
+      case OWQS_OP_X:
+      case OWQS_OP_Z:
+        st.kind = c.op == OWQS_OP_X ? S_X : S_Z;
+        st.b0 = slot_of[c.q0];
+        st.s = dom(c.s);
+        break;
+      case OWQS_OP_M: {
+        st.kind = S_M;
+        st.b0 = slot_of[c.q0];
+        st.m = m;
+        st.alpha = p->angles[m];
+        st.host_factor = pending;
+        st.s = dom(c.s);
+        st.t = dom(c.t);
+        m_of[c.q0] = m++;
+        const int t = n - 1;
+        if (st.b0 != t) {
+          const int top = qubit_at[t];
+          slot_of[top] = st.b0;
+          qubit_at[st.b0] = top;
+        }
+        qubit_at[t] = -1;
+        slot_of[c.q0] = -1;
+        --n;
+        pending = 1.0;
+        break;
+      }
+      default:
+        continue;
+    }
+    p->s_steps.push_back(st);
+  }
+  p->s_final_where.assign(p->outputs.size(), 0);
+  for (size_t k = 0; k < p->outputs.size(); ++k) p->s_final_where[k] = slot_of[p->outputs[k]];
+  p->s_final_factor = pending;
+  p->s_valid = true;
+  p->s_uploaded = false;
+  if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
+  if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
+}
+
+// Device layout of s_mem: uniforms (double), outcomes (int), coefficient
+// (float2), domains (int), each 256-byte aligned.
+struct SampleMem {
+  double *u;
+  int *outc;
+  float2 *coef;
+  int *dom;
+};
+SampleMem sample_mem(owqs_pattern *p) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  char *b = static_cast<char *>(p->s_mem);
+  const size_t nm = std::max<size_t>(p->n_meas, 1);
+  SampleMem sm{};
+  sm.u = reinterpret_cast<double *>(b);
+  sm.outc = reinterpret_cast<int *>(b + up(nm * sizeof(double)));
+  sm.coef = reinterpret_cast<float2 *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)));
+  sm.dom = reinterpret_cast<int *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256);
+  return sm;
+}
+
+hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
+  const SampleMem sm = sample_mem(p);
+  hipError_t e = hipSuccess;
+  for (const owqs_pattern::SStep &x : p->s_steps) {
+    if (e != hipSuccess) break;
+    switch (x.kind) {
+      case S_N: e = launch_prepare(p->psi, x.n, s); break;
+      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
+      case S_X:
+      case S_Z: e = launch_s_pauli(p->psi, x.n, x.b0, x.kind == S_X, x.s, sm.dom, sm.outc, s); break;
+      case S_M: {
+        unsigned g = 0, g2 = 0;
+        e = launch_s_prob(p->psi, x.n, x.b0, x.alpha, x.s, x.t, sm.dom, sm.outc, p->book.partials, &g, s);
+        if (e == hipSuccess)
+          e = launch_s_decide(p->book.partials, g, sm.u, x.m, x.alpha, x.s, x.t, sm.dom, sm.outc, sm.coef, s);
+        MeasureArgs a{};
+        a.coef_dev = sm.coef;
+        a.host_factor = x.host_factor;
+        a.reduce = kReduceRenorm;
+        a.m_index = x.m;
+        a.book = p->book;
+        if (e == hipSuccess) e = launch_measure(p->psi, x.n, x.b0, a, s, &g2);
+        if (e == hipSuccess) e = launch_finish(a, g2, s);
+        break;
+      }
+      default: break;
+    }
+  }
+  return e;
+}
+
+owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream) {
+  const size_t nin = p->inputs.size();
+  const size_t want = size_t(1) << nin;
+  if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
+  if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
+  if (p->mode != OWQS_MODE_OWQS) return fail(p->ctx, OWQS_E_STATE, "drawn outcomes need OWQS mode (probabilities)");
+  owqs_status st = ensure_device(p);
+  if (st != OWQS_OK) return st;
+  if (!p->s_valid) compile_sampled(p);
+  const size_t nm = std::max<size_t>(p->n_meas, 1);
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t need = up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 + up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int));
+  hipError_t e = hipSuccess;
+  if (p->s_cap < need) {
+    if (p->s_mem) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p->s_mem);
+    }
+    p->s_mem = nullptr;
+    p->s_cap = 0;
+    e = hipMalloc(&p->s_mem, need);
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sampling tables");
+    p->s_cap = need;
+    p->s_uploaded = false;
+    if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
+    if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
+  }
+  const SampleMem sm = sample_mem(p);
+  if (!p->s_uploaded) {  // synchronous: the host tables may change after this call
+    if (p->n_meas) e = hipMemcpy(sm.u, p->uniforms.data(), p->n_meas * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->s_dom.empty())
+      e = hipMemcpy(sm.dom, p->s_dom.data(), p->s_dom.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "sampling tables upload");
+    p->s_uploaded = true;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  end_ranged(p);
+  e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
+  if (e == hipSuccess && (nin > 0 || input != nullptr))
+    e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
+                       input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "input");
+  if (p->use_graph && !p->s_steps.empty()) {
+    if (!p->s_exec) {
+      if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "capture stream");
+      }
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(p->ctx, e, "begin capture");
+      hipError_t le = launch_sampled(p, p->cap_stream);
+      e = hipStreamEndCapture(p->cap_stream, &p->s_graph);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->s_exec, p->s_graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
+        p->s_exec = nullptr;
+        return hip_fail(p->ctx, e, "graph capture");
+      }
+    }
+    e = hipGraphLaunch(p->s_exec, s);
+  } else {
+    e = launch_sampled(p, s);
+  }
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
+  p->ran = true;
+  p->batch_ran = false;
+  p->out_in_order = false;
+  p->sampled_ran = true;
+  p->ran_mode = kReduceRenorm;
+  return OWQS_OK;
+}
+
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                      Profile *prof) {
+  if (p && p->sampling) {
+    if (prof) return fail(p->ctx, OWQS_E_STATE, "profiled runs take forced outcomes");
+    return run_sampled(p, input, n_amps, input_on_device, stream);
+  }
   if (!p) return OWQS_E_INVALID_ARG;
   const size_t nin = p->inputs.size();
   const size_t want = size_t(1) << nin;
@@ -820,6 +1047,7 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
   if (p->dirty) compile(p);
   hipStream_t s = static_cast<hipStream_t>(stream);
   end_ranged(p);
+  p->sampled_ran = false;
   hipError_t e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "init");
   if (nin > 0 || input != nullptr) {
@@ -1087,7 +1315,7 @@ owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, 
 
 void owqs_pattern_destroy(owqs_pattern *p) {
   if (!p) return;
-  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem) {
+  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem || p->s_mem) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->psi) (void)hipFree(p->psi);
@@ -1097,6 +1325,9 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   if (p->dev_steps) (void)hipFree(p->dev_steps);
   if (p->dev_fuse) (void)hipFree(p->dev_fuse);
   if (p->adj_mem) (void)hipFree(p->adj_mem);
+  if (p->s_mem) (void)hipFree(p->s_mem);
+  if (p->s_exec) (void)hipGraphExecDestroy(p->s_exec);
+  if (p->s_graph) (void)hipGraphDestroy(p->s_graph);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -1133,6 +1364,7 @@ owqs_status owqs_set_angles(owqs_pattern *p, const double *alpha, size_t n_meas)
   if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "angle count != number of M commands");
   p->angles.assign(alpha, alpha + n_meas);
   p->dirty = true;
+  p->s_valid = false;
   return OWQS_OK;
 }
 
@@ -1143,6 +1375,7 @@ owqs_status owqs_set_outcomes(owqs_pattern *p, const uint8_t *bits, size_t n_mea
     if (bits[k] > 1) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcomes must be 0 or 1");
   p->outcomes.assign(bits, bits + n_meas);
   p->dirty = true;
+  p->sampling = false;
   return OWQS_OK;
 }
 
@@ -1289,6 +1522,9 @@ owqs_status owqs_run_states(owqs_pattern *p, const void *in_c64, uint32_t count,
 owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat, const void *const *inputs,
                            void *const *outputs, void *stream) {
   if (!ctx || (npat && (!pats || !outputs))) return fail(ctx, OWQS_E_INVALID_ARG, "null argument");
+  for (size_t i = 0; i < npat; ++i)
+    if (pats[i] && pats[i]->sampling)
+      return fail(ctx, OWQS_E_STATE, "batched runs take forced outcomes (pattern " + std::to_string(i) + " draws them)");
   if (ctx->device < 0) return fail(ctx, OWQS_E_STATE, "host-only context");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
@@ -1684,6 +1920,8 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
   if (n_amps != (size_t(1) << nout)) return fail(p->ctx, OWQS_E_INVALID_ARG, "output size must be 2^(outputs)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
+  const int *where = p->sampled_ran ? p->s_final_where.data() : p->final_where.data();
+  const double factor = p->sampled_ran ? p->s_final_factor : p->final_factor;
   hipError_t e;
   if (p->out_in_order) {
     e = hipMemcpyAsync(out, p->psi, n_amps * sizeof(float2),
@@ -1695,7 +1933,7 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
     return owqs_check(p, stream);
   }
   if (out_on_device) {
-    e = launch_read(p->psi, static_cast<float2 *>(out), (int)nout, p->final_where.data(), p->final_factor, sigma, s);
+    e = launch_read(p->psi, static_cast<float2 *>(out), (int)nout, where, factor, sigma, s);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
     return OWQS_OK;
   }
@@ -1703,7 +1941,7 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
     e = hipMalloc(reinterpret_cast<void **>(&p->stage), n_amps * sizeof(float2));
     if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "read staging buffer");
   }
-  e = launch_read(p->psi, p->stage, (int)nout, p->final_where.data(), p->final_factor, sigma, s);
+  e = launch_read(p->psi, p->stage, (int)nout, where, factor, sigma, s);
   if (e == hipSuccess) e = hipMemcpyAsync(out, p->stage, n_amps * sizeof(float2), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
@@ -1741,6 +1979,7 @@ owqs_status owqs_set_outcome_seed(owqs_pattern *p, uint64_t seed) {
     p->outcomes[m] = uint8_t(z >> 63);
   }
   p->dirty = true;
+  p->sampling = false;
   return OWQS_OK;
 }
 
@@ -1748,6 +1987,38 @@ owqs_status owqs_get_outcomes(const owqs_pattern *p, uint8_t *bits, size_t n_mea
   if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
   if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
   std::copy(p->outcomes.begin(), p->outcomes.end(), bits);
+  return OWQS_OK;
+}
+
+owqs_status owqs_set_uniforms(owqs_pattern *p, const double *u, size_t n_meas) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (!u) {
+    if (n_meas) return OWQS_E_INVALID_ARG;
+    p->sampling = false;
+    return OWQS_OK;
+  }
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "uniform count != number of M commands");
+  for (size_t k = 0; k < n_meas; ++k)
+    if (!(u[k] >= 0.0 && u[k] < 1.0)) return fail(p->ctx, OWQS_E_INVALID_ARG, "uniforms must lie in [0, 1)");
+  // a run in flight may still read the device copy: let it finish first
+  if (p->s_mem && p->ctx->device >= 0) (void)hipDeviceSynchronize();
+  p->uniforms.assign(u, u + n_meas);
+  p->sampling = true;
+  p->s_uploaded = false;
+  return OWQS_OK;
+}
+
+owqs_status owqs_read_outcomes(owqs_pattern *p, uint8_t *bits, size_t n_meas, void *stream) {
+  if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
+  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
+  if (!p->sampled_ran) return owqs_get_outcomes(p, bits, n_meas);
+  std::vector<int> o(std::max<size_t>(n_meas, 1));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (n_meas) e = hipMemcpyAsync(o.data(), sample_mem(p).outc, n_meas * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "read outcomes");
+  for (size_t k = 0; k < n_meas; ++k) bits[k] = uint8_t(o[k] & 1);
   return OWQS_OK;
 }
 

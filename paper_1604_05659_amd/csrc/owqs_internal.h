@@ -32,6 +32,7 @@ enum ReduceMode : int {
 
 struct MeasureArgs {
   float2 coef;          // (-1)^o e^{-i theta} rounded to complex64
+  const float2 *coef_dev;  // non-null: read the coefficient from device memory instead (drawn outcomes)
   double host_factor;   // (1/sqrt 2)^(N commands since the previous M)
   int reduce;           // ReduceMode
   int m_index;          // index of this M (probs slot)
@@ -189,6 +190,7 @@ hipError_t launch_finish_group(const MeasureArgs &a, const int *m_of_window, int
                                hipStream_t s);
 // Raise k_tile's dynamic LDS limit to 64 KiB; call outside stream capture.
 hipError_t tile_prepare();
+
 // The group on `nsets` vectors at once (EOWQS scale, no probabilities).
 hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta, const FuseOp *ops, int nsets, size_t set_stride,
                             const float2 *coefs, hipStream_t s);
@@ -200,5 +202,26 @@ hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta, const F
                            size_t set_stride, const float2 *coefs, double *partials, int q_first, unsigned nblk,
                            hipStream_t s);
 unsigned tile_grid(const TileArgs &ta);
+
+// ---- drawn outcomes (owqs_sample.hip)
+constexpr unsigned kSampleGrid = 4096;  // 2 * kSampleGrid <= kMaxPartials
+// Signals of a command: XOR of the drawn outcomes outc[dom[off .. off+len)].
+struct SigRef {
+  int off, len;
+};
+// X (x = 1) or Z (x = 0) on slot b at live width n when its signal is 1.
+hipError_t launch_s_pauli(float2 *psi, int n, int b, int x, SigRef sig, const int *dom, const int *outc,
+                          hipStream_t s);
+// Probability pass of M at slot b: per-block FP64 sums of |psi_0 + c0 psi_1|^2
+// (c0 = e^{-i theta}, theta from alpha and the s, t signals, Eq. 2) into
+// partials[0 .. grid) and of |psi_0|^2 + |psi_1|^2 into partials[kSampleGrid ..)
+// (grid <= kSampleGrid).
+hipError_t launch_s_prob(const float2 *psi, int n, int b, double alpha, SigRef sg, SigRef tg, const int *dom,
+                         const int *outc, double *partials, unsigned *grid, hipStream_t s);
+// One block: p_0 from the partials, outcome o = (u[m] <= p_0 ? 0 : 1) into
+// outc[m] and the collapse coefficient (-1)^o e^{-i theta} into *coef.
+hipError_t launch_s_decide(const double *partials, unsigned nparts, const double *u, int m, double alpha,
+                           SigRef sg, SigRef tg, const int *dom, int *outc, float2 *coef, hipStream_t s);
+
 
 }  // namespace owqs

@@ -323,7 +323,7 @@ template <int kCase>  // 0: b == t, 1: b == 0 < t, 2: 1 <= b < t
 __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, uint64_t units, int b,
                                                      uint64_t half, MeasureArgs a) {
   const float f = scale_of(a);
-  const float2 c = a.coef;
+  const float2 c = a.coef_dev ? *a.coef_dev : a.coef;
   const uint64_t step = uint64_t(1) << b;
   double acc = 0.0;
   GRID_STRIDE_UNITS(units) {
@@ -402,7 +402,7 @@ __global__ void k_measure_small(float2 *psi, int n, int b, MeasureArgs a) {
       } else {
         k0 = (j & ~(uint64_t(1) << b)) + half;
       }
-      out[j] = axpc(in[k0], a.coef, in[k0 | (uint64_t(1) << b)], f);
+      out[j] = axpc(in[k0], a.coef_dev ? *a.coef_dev : a.coef, in[k0 | (uint64_t(1) << b)], f);
     }
     for (uint64_t j = 0; j < half; ++j) {
       psi[j] = out[j];
@@ -437,7 +437,7 @@ template <bool kB0>
 __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, uint64_t units, int b,
                                                      MeasureArgs a, Window win) {
   const float f = scale_of(a);
-  const float2 c = a.coef;
+  const float2 c = a.coef_dev ? *a.coef_dev : a.coef;
   const uint64_t step = uint64_t(1) << b;
   double acc = 0.0;
   GRID_STRIDE_UNITS(units) {

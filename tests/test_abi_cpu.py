@@ -165,3 +165,21 @@ def test_ranged_run_argument_checks(host_ctx):
     # a host-only context cannot run
     assert owqs._lib.owqs_run_range(p._h, None, 1, 1, 0, 4, None) == owqs.E_STATE
     p.close()
+
+
+def test_uniforms_argument_checks(host_ctx):
+    wl = W.plain_small()
+    p = owqs.Pattern(host_ctx, wl.pattern)
+    with pytest.raises(owqs.OwqsError):
+        p.set_uniforms(np.full(p.n_meas - 1, 0.5))
+    for bad in (1.0, -0.1, float("nan")):
+        u = np.full(p.n_meas, 0.5)
+        u[3] = bad
+        with pytest.raises(owqs.OwqsError):
+            p.set_uniforms(u)
+    p.set_uniforms(np.full(p.n_meas, 0.25))
+    p.set_uniforms(None)
+    # before any run, the outcomes read back are the forced ones
+    p.set_outcomes(wl.outcomes)
+    np.testing.assert_array_equal(p.read_outcomes(), wl.outcomes)
+    p.close()
