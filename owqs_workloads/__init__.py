@@ -541,3 +541,58 @@ def basis_state(n_qubits: int, k: int) -> np.ndarray:
     v = np.zeros(1 << n_qubits, dtype=np.complex64)
     v[k] = 1.0
     return v
+
+
+# ---------------------------------------------------------------------------
+# Standard-form patterns (input to the reordering of Sec. 4.3)
+# ---------------------------------------------------------------------------
+def standard_form(pattern: Pattern) -> Pattern:
+    """The same pattern with every N first, then every E, then the M commands
+    in their order, then the corrections.  Valid when the corrections all come
+    after the last M (each E involves qubits prepared before it and measured
+    after it, so E and N commute to the front, Eqs. 15-16)."""
+    cmds = pattern.cmds
+    last_m = max((i for i, c in enumerate(cmds) if c[0] == "M"), default=-1)
+    if any(c[0] in ("X", "Z") and i < last_m for i, c in enumerate(cmds)):
+        raise ValueError("corrections before a measurement: not standardisable by commuting")
+    ns = [c for c in cmds if c[0] == "N"]
+    es = [c for c in cmds if c[0] == "E"]
+    ms = [c for c in cmds if c[0] == "M"]
+    cs = [c for c in cmds if c[0] in ("X", "Z")]
+    return Pattern(list(pattern.inputs), list(pattern.outputs), ns + es + ms + cs, pattern.name + "/standard")
+
+
+def random_standard_pattern(g: np.random.Generator, n_qubits: int = 9, n_in: int = 2, n_out: int = 2,
+                            extra_edges: int = 4, max_dom: int = 2) -> Pattern:
+    """A random pattern in standard form: a connected random graph on
+    n_qubits (a random spanning tree plus extra edges), inputs the first
+    n_in qubits, outputs the last n_out, measurements in a random order with
+    s- and t-domains drawn from the qubits measured before, and X/Z
+    corrections on the outputs with domains over measured qubits."""
+    qs = list(range(n_qubits))
+    perm = list(g.permutation(n_qubits))
+    edges = set()
+    for i in range(1, n_qubits):
+        a, b = perm[i], perm[int(g.integers(i))]
+        edges.add((min(a, b), max(a, b)))
+    while len(edges) < n_qubits - 1 + extra_edges and len(edges) < n_qubits * (n_qubits - 1) // 2:
+        a, b = (int(x) for x in g.choice(n_qubits, size=2, replace=False))
+        edges.add((min(a, b), max(a, b)))
+    inputs, outputs = qs[:n_in], qs[n_qubits - n_out:]
+    meas = [q for q in g.permutation(n_qubits).tolist() if q not in outputs]
+    cmds = [("N", q) for q in qs if q not in inputs]
+    cmds += [("E", a, b) for a, b in sorted(edges)]
+    done: List[int] = []
+    for q in meas:
+        ks = int(g.integers(0, min(max_dom, len(done)) + 1))
+        kt = int(g.integers(0, min(max_dom, len(done)) + 1))
+        s = tuple(int(x) for x in g.choice(done, size=ks, replace=False)) if ks else ()
+        t = tuple(int(x) for x in g.choice(done, size=kt, replace=False)) if kt else ()
+        cmds.append(("M", q, float(g.uniform(0, 2 * math.pi)), s, t))
+        done.append(q)
+    for q in outputs:
+        for op in ("X", "Z"):
+            k = int(g.integers(0, min(max_dom, len(done)) + 1))
+            if k:
+                cmds.append((op, q, tuple(int(x) for x in g.choice(done, size=k, replace=False))))
+    return Pattern(inputs, outputs, cmds, "random_standard")
