@@ -297,6 +297,47 @@ def bench_cluster(owqs, torch, W, ctx, steps):
         res[name] = {"ms_per_run": round(1e3 * t, 3), "commands_per_s": round(nt / t, 1),
                      "plan_steps": p.plan_info()[1], "passes": p.plan_info()[2]}
     p.close()
+    res["proa"] = bench_proa(owqs, torch, W, ctx, wl, steps)
+    return res
+
+
+def bench_proa(owqs, torch, W, ctx, wl, steps):
+    """The same cluster as a standard-form pattern (all N, all E, then the
+    M's: 4000 qubits live at once), reordered on the host by the library
+    (PROA, Sec. 4.3) and run fused; compared with the column-by-column order."""
+    std = W.standard_form(wl.pattern)
+    src = owqs.Pattern(ctx, std)
+    t0 = time.perf_counter()
+    re, stats = src.reorder()
+    host_ms = 1e3 * (time.perf_counter() - t0)
+    spec = re.commands()
+    per_q = dict(zip([c[1] for c in wl.pattern.cmds if c[0] == "M"], (int(b) for b in wl.outcomes)))
+    re.set_mode(owqs.MODE_OWQS)
+    re.set_exec(owqs.EXEC_FUSED)
+    re.set_outcomes(np.array([per_q[c[1]] for c in spec.cmds if c[0] == "M"], np.uint8))
+    out = torch.empty(1 << 20, dtype=torch.complex64, device="cuda")
+    re.run(None)
+    re.read_state(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        re.run(None)
+        re.read_state(out, check=False)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    re.check()
+    col = owqs.Pattern(ctx, wl.pattern)
+    col.set_outcomes(wl.outcomes)
+    col.set_exec(owqs.EXEC_FUSED)
+    col.run(None)
+    ref = col.read_state()
+    diff = float((ref - out).abs().max().item())
+    col.close()
+    res = {"source_live_width": src.max_live, "host_reorder_ms": round(host_ms, 1),
+           "max_state_space": stats["max_state_space"], "live_width": stats["max_live"], "alpha": stats["alpha"],
+           "fused_ms_per_run": round(1e3 * t, 3), "max_abs_diff_vs_column_order": diff}
+    re.close()
+    src.close()
     return res
 
 

@@ -51,7 +51,7 @@ typedef enum {
   OWQS_E_INVALID_ARG = -1,       /* null pointer, size mismatch, bad enum */
   OWQS_E_PATTERN = -2,           /* pattern breaks rule D0, D1, D2 or D3 (Sec. 2.2) */
   OWQS_E_ZERO_PROB = -3,         /* a forced outcome has probability < 1e-10 */
-  OWQS_E_WIDTH = -4,             /* live width above OWQS_MAX_WIDTH */
+  OWQS_E_WIDTH = -4,             /* live width above OWQS_MAX_WIDTH (plan or run) */
   OWQS_E_NOMEM = -5,             /* device or host allocation failed */
   OWQS_E_HIP = -6,               /* a HIP runtime call failed */
   OWQS_E_NOT_DETERMINISTIC = -7, /* EOWQS check mode saw |p - 1/2| > 1e-4 */
@@ -124,7 +124,10 @@ const char *owqs_last_error(const owqs_ctx *ctx);
  * outcome; no action on a measured qubit; no action on an unprepared
  * non-input; exactly the non-outputs are measured) and its largest live width
  * is computed; no device memory is allocated yet.  Every M starts with its
- * outcome forced to 0. */
+ * outcome forced to 0.  A pattern wider than OWQS_MAX_WIDTH loads (it can be
+ * read back and reordered, owqs_pattern_reorder), but every call that plans
+ * or runs it returns OWQS_E_WIDTH.  More than OWQS_MAX_WIDTH inputs or
+ * outputs is OWQS_E_WIDTH here. */
 owqs_status owqs_pattern_create(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds,
                                 const int32_t *domain_ids, size_t ndom,
                                 const int32_t *inputs, int32_t nin,
@@ -341,6 +344,58 @@ owqs_status owqs_run_range(owqs_pattern *pat, const void *input_c64, size_t n_am
  * device buffer of 2^n entries. */
 owqs_status owqs_read_live(owqs_pattern *pat, void *out_c64, size_t n_amps, int32_t *qubits,
                            int32_t *n_live, void *stream);
+
+/* The pattern's commands in execution order, in the form owqs_pattern_create
+ * takes: the caller's qubit ids, the current angles (owqs_set_angles), the
+ * domains packed in order into `domain_ids`, q1 = 0 for non-E commands.
+ * *ncmds and *ndom receive the sizes; cmds / domain_ids may be NULL to query
+ * them, else they must hold cmd_cap >= *ncmds and dom_cap >= *ndom entries
+ * (else OWQS_E_INVALID_ARG, sizes still written).  inputs / outputs (NULL to
+ * skip) receive the n_in / n_out ids of owqs_pattern_info. */
+owqs_status owqs_pattern_commands(const owqs_pattern *pat, owqs_cmd *cmds, size_t cmd_cap,
+                                  int32_t *domain_ids, size_t dom_cap, int32_t *inputs,
+                                  int32_t *outputs, size_t *ncmds, size_t *ndom);
+
+/* Pattern reordering (PROA, Sec. 4.3, Eq. 18) weights.  alpha <= 0 selects
+ * the default: beta = delta = |O|, gamma = 1/2, alpha swept from |O| down
+ * to 1, keeping the order with the smallest largest state-space (the first
+ * alpha that reaches it).  ignore_dependencies = 1 takes the positive branch
+ * of EOWQS (Sec. 4.5, every outcome 0): measurements may go in any order, and
+ * the reordered pattern has no signal domains and no corrections, so it is
+ * only meaningful run with the outcomes forced to 0. */
+typedef struct {
+  double alpha, beta, gamma, delta;
+  int32_t ignore_dependencies;
+  int32_t reserved; /* must be 0 */
+} owqs_proa_opts;
+
+typedef struct {
+  int32_t max_state_space; /* m: the largest measurement state-space MS(v) */
+  int32_t max_live;        /* live width of the reordered pattern run as one vector */
+  double alpha;            /* alpha of the chosen order */
+} owqs_proa_stats;
+
+/* Reorder a pattern whose corrections all follow its M and E commands
+ * (standard form, Sec. 2.2; else OWQS_E_PATTERN) with PROA (Sec. 4.3).  The
+ * E commands give the entanglement graph (an edge per odd count of E's on a
+ * pair).  Every qubit starts in its own sub-state; measuring v merges the
+ * sub-states of v and of the neighbours it is not yet entangled with into
+ * its measurement state-space MS(v).  Each step measures, among the qubits
+ * whose domains are all measured, the one of least cost
+ *   alpha |MS(v)| + beta OS(v) - gamma SS(v)          if v was in an earlier MS,
+ *   alpha (|MS(v)| + 1) delta + beta OS(v) - gamma SS(v)  otherwise,
+ * OS(v) = v's edges to outputs, SS(v) = unmeasured qubits whose domains hold
+ * v; ties go to the smallest qubit id.  *out receives a new pattern (same
+ * context, inputs, outputs, angles and domains; mode and forced outcomes at
+ * their defaults; owned by the caller) that before each M v prepares v and
+ * its not-yet-entangled neighbours not prepared yet (v first, then by id),
+ * applies those E's (v, u) by id of u, then measures v; after the last M it
+ * prepares the remaining outputs by id, applies the remaining E's (lower id
+ * first) and the corrections in their original order.  It computes the same
+ * output state and outcome probabilities as the source.  opts may be NULL
+ * (defaults); stats may be NULL.  Host only: no device work. */
+owqs_status owqs_pattern_reorder(const owqs_pattern *pat, const owqs_proa_opts *opts,
+                                 owqs_pattern **out, owqs_proa_stats *stats);
 
 #ifdef __cplusplus
 }

@@ -30,10 +30,10 @@ def _graph(pattern):
     qubits = set(pattern.inputs) | set(pattern.outputs)
     for c in pattern.cmds:
         qubits.add(c[1])
-        if c[0] == "E":
+        if c[0] == "E":  # E twice is the identity: an edge is an odd number of E's
             qubits.add(c[2])
-            nbr.setdefault(c[1], set()).add(c[2])
-            nbr.setdefault(c[2], set()).add(c[1])
+            nbr.setdefault(c[1], set()).symmetric_difference_update({c[2]})
+            nbr.setdefault(c[2], set()).symmetric_difference_update({c[1]})
     for q in qubits:
         nbr.setdefault(q, set())
     return qubits, nbr

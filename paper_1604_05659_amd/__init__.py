@@ -16,6 +16,7 @@ Typical use::
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 from typing import Optional, Sequence
@@ -95,6 +96,10 @@ _sig = {
                                       ctypes.POINTER(_vp), _vp]),
     "owqs_adjoint": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _i32p,
                                     ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp]),
+    "owqs_pattern_commands": (ctypes.c_int, [_vp, ctypes.POINTER(OwqsCmd), ctypes.c_size_t, _i32p, ctypes.c_size_t,
+                                             _i32p, _i32p, ctypes.POINTER(ctypes.c_size_t),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+    "owqs_pattern_reorder": (ctypes.c_int, [_vp, ctypes.c_void_p, ctypes.POINTER(_vp), ctypes.c_void_p]),
     "owqs_run_profiled": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -105,6 +110,19 @@ for _name, (_res, _args) in _sig.items():
     _f.argtypes = _args
 
 EXPORTED = tuple(_sig)
+
+
+class ProaOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("delta", ctypes.c_double), ("ignore_dependencies", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ProaStats(ctypes.Structure):
+    _fields_ = [("max_state_space", ctypes.c_int32), ("max_live", ctypes.c_int32), ("alpha", ctypes.c_double)]
+
+
+PatternSpec = collections.namedtuple("PatternSpec", "inputs outputs cmds")
+_OP_NAMES = {v: k for k, v in OPS.items()}
 
 
 class OwqsError(RuntimeError):
@@ -187,12 +205,68 @@ class Pattern:
                 ctx._h, cmds, len(pattern.cmds), dom.ctypes.data_as(_i32p), ndom,
                 ins.ctypes.data_as(_i32p), len(pattern.inputs), outs.ctypes.data_as(_i32p),
                 len(pattern.outputs), ctypes.byref(h)))
+        self._adopt(h)
+
+    @classmethod
+    def _from_handle(cls, ctx: Context, h) -> "Pattern":
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self._adopt(h)
+        return self
+
+    def _adopt(self, h):
+        ctx = self.ctx
         self._h = h
         nm, ml, ni, no = (ctypes.c_int32() for _ in range(4))
         nc = ctypes.c_size_t()
         ctx.check(_lib.owqs_pattern_info(h, ctypes.byref(nm), ctypes.byref(ml), ctypes.byref(ni),
                                          ctypes.byref(no), ctypes.byref(nc)))
         self.n_meas, self.max_live, self.n_in, self.n_out, self.ncmds = nm.value, ml.value, ni.value, no.value, nc.value
+
+    def commands(self) -> PatternSpec:
+        """The pattern as loaded (owqs_pattern_commands): inputs, outputs and
+        command tuples ("N", q), ("E", u, v), ("M", q, alpha, s, t),
+        ("X", q, s), ("Z", q, s) with domains as tuples of qubit ids."""
+        nc, nd = ctypes.c_size_t(), ctypes.c_size_t()
+        self.ctx.check(_lib.owqs_pattern_commands(self._h, None, 0, None, 0, None, None, ctypes.byref(nc),
+                                                  ctypes.byref(nd)))
+        cmds = (OwqsCmd * max(nc.value, 1))()
+        dom = np.zeros(max(nd.value, 1), np.int32)
+        ins = np.zeros(max(self.n_in, 1), np.int32)
+        outs = np.zeros(max(self.n_out, 1), np.int32)
+        self.ctx.check(_lib.owqs_pattern_commands(self._h, cmds, nc.value, dom.ctypes.data_as(_i32p), dom.size,
+                                                  ins.ctypes.data_as(_i32p), outs.ctypes.data_as(_i32p),
+                                                  ctypes.byref(nc), ctypes.byref(nd)))
+
+        def rng(off, n):
+            return tuple(int(q) for q in dom[off:off + n])
+
+        out = []
+        for c in cmds[: nc.value]:
+            op = _OP_NAMES[c.op]
+            if op == "N":
+                out.append(("N", c.q0))
+            elif op == "E":
+                out.append(("E", c.q0, c.q1))
+            elif op == "M":
+                out.append(("M", c.q0, c.angle, rng(c.s_off, c.s_len), rng(c.t_off, c.t_len)))
+            else:
+                out.append((op, c.q0, rng(c.s_off, c.s_len)))
+        return PatternSpec([int(q) for q in ins[: self.n_in]], [int(q) for q in outs[: self.n_out]], out)
+
+    def reorder(self, weights: Optional[Sequence[float]] = None, ignore_dependencies: bool = False):
+        """PROA (owqs_pattern_reorder): returns (reordered Pattern, stats dict
+        with max_state_space, max_live, alpha).  weights = (alpha, beta,
+        gamma, delta), or None for the default alpha sweep."""
+        opts = ProaOpts()
+        if weights is not None:
+            opts.alpha, opts.beta, opts.gamma, opts.delta = (float(w) for w in weights)
+        opts.ignore_dependencies = 1 if ignore_dependencies else 0
+        st = ProaStats()
+        h = _vp()
+        self.ctx.check(_lib.owqs_pattern_reorder(self._h, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(st)))
+        return Pattern._from_handle(self.ctx, h), {"max_state_space": st.max_state_space,
+                                                   "max_live": st.max_live, "alpha": st.alpha}
 
     def set_mode(self, mode: int):
         self.ctx.check(_lib.owqs_set_mode(self._h, int(mode)))

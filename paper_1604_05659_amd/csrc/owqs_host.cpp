@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/owqs.h"
+#include "owqs_pattern_access.h"
 #include "owqs_internal.h"
 
 using namespace owqs;
@@ -229,7 +230,6 @@ owqs_status validate(owqs_pattern *p) {
       default:
         return bad("unknown opcode");
     }
-    if (m > OWQS_MAX_WIDTH) return fail(p->ctx, OWQS_E_WIDTH, "live width above OWQS_MAX_WIDTH");
   }
   for (int q = 0; q < p->nq; ++q) {
     if (is_out[q] && st[q] != LIVE) return fail(p->ctx, OWQS_E_PATTERN, "an output qubit is not live at the end (D3)");
@@ -574,7 +574,17 @@ void compile(owqs_pattern *p) {
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
 }
 
+// Patterns of any width load (so they can be reordered and read back); only
+// those within OWQS_MAX_WIDTH compile and run.
+owqs_status width_guard(owqs_pattern *p) {
+  if (p->max_live > OWQS_MAX_WIDTH)
+    return fail(p->ctx, OWQS_E_WIDTH, "live width " + std::to_string(p->max_live) +
+                                          " above OWQS_MAX_WIDTH (owqs_pattern_reorder can narrow it)");
+  return OWQS_OK;
+}
+
 owqs_status ensure_device(owqs_pattern *p, bool need_psi = true) {
+  if (owqs_status w = width_guard(p)) return w;
   if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
   hipError_t e = hipSetDevice(p->ctx->device);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "hipSetDevice");
@@ -1248,6 +1258,41 @@ bool parse_text(const char *text, size_t len, std::vector<owqs_cmd> &cmds, std::
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace owqs {
+
+void pattern_export(const owqs_pattern *p, std::vector<owqs_cmd> &cmds, std::vector<int32_t> &dom,
+                    std::vector<int32_t> &inputs, std::vector<int32_t> &outputs) {
+  cmds.clear();
+  dom.clear();
+  inputs.clear();
+  outputs.clear();
+  for (int q : p->inputs) inputs.push_back(p->user_id[q]);
+  for (int q : p->outputs) outputs.push_back(p->user_id[q]);
+  size_t m = 0;
+  for (const Cmd &c : p->cmds) {
+    owqs_cmd o{};
+    o.op = c.op;
+    o.q0 = p->user_id[c.q0];
+    o.q1 = c.op == OWQS_OP_E ? p->user_id[c.q1] : 0;
+    o.s_off = (int32_t)dom.size();
+    for (int q : c.s) dom.push_back(p->user_id[q]);
+    o.s_len = (int32_t)c.s.size();
+    o.t_off = (int32_t)dom.size();
+    for (int q : c.t) dom.push_back(p->user_id[q]);
+    o.t_len = (int32_t)c.t.size();
+    if (c.op == OWQS_OP_M) o.angle = p->angles[m++];
+    cmds.push_back(o);
+  }
+}
+
+owqs_ctx *pattern_ctx(const owqs_pattern *p) { return p->ctx; }
+
+owqs_status pattern_fail(const owqs_pattern *p, owqs_status st, const std::string &msg) {
+  return fail(p->ctx, st, msg);
+}
+
+}  // namespace owqs
+
 extern "C" {
 
 const char *owqs_status_str(owqs_status s) {
@@ -1345,6 +1390,23 @@ owqs_status owqs_pattern_info(const owqs_pattern *p, int32_t *n_meas, int32_t *m
   return OWQS_OK;
 }
 
+owqs_status owqs_pattern_commands(const owqs_pattern *p, owqs_cmd *cmds, size_t cmd_cap, int32_t *domain_ids,
+                                  size_t dom_cap, int32_t *inputs, int32_t *outputs, size_t *ncmds, size_t *ndom) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  std::vector<owqs_cmd> c;
+  std::vector<int32_t> d, in, out;
+  pattern_export(p, c, d, in, out);
+  if (ncmds) *ncmds = c.size();
+  if (ndom) *ndom = d.size();
+  if ((cmds && cmd_cap < c.size()) || (domain_ids && dom_cap < d.size()))
+    return fail(p->ctx, OWQS_E_INVALID_ARG, "command or domain buffer too small");
+  if (cmds && !c.empty()) std::memcpy(cmds, c.data(), c.size() * sizeof(owqs_cmd));
+  if (domain_ids && !d.empty()) std::memcpy(domain_ids, d.data(), d.size() * sizeof(int32_t));
+  if (inputs && !in.empty()) std::memcpy(inputs, in.data(), in.size() * sizeof(int32_t));
+  if (outputs && !out.empty()) std::memcpy(outputs, out.data(), out.size() * sizeof(int32_t));
+  return OWQS_OK;
+}
+
 owqs_status owqs_set_mode(owqs_pattern *p, owqs_mode mode) {
   if (!p || mode < OWQS_MODE_OWQS || mode > OWQS_MODE_EOWQS_CHECK) return OWQS_E_INVALID_ARG;
   if (p->mode != mode) p->dirty = true;
@@ -1406,6 +1468,7 @@ owqs_status owqs_set_tile_bits(owqs_pattern *p, int32_t bits) {
 owqs_status owqs_tune(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                       int32_t *best_bits, float *best_ms) {
   if (!p) return OWQS_E_INVALID_ARG;
+  if (owqs_status w = width_guard(p)) return w;
   if (p->dirty) compile(p);
   // only plans with tile passes have a schedule to choose
   bool tiled = p->exec != OWQS_EXEC_PLAIN && !(p->exec == OWQS_EXEC_AUTO && p->plan_width <= kLdsMaxWidth);
@@ -1462,6 +1525,7 @@ owqs_status owqs_tune(owqs_pattern *p, const void *input, size_t n_amps, int inp
 
 owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps, size_t *npasses) {
   if (!p) return OWQS_E_INVALID_ARG;
+  if (owqs_status w = width_guard(p)) return w;
   if (p->dirty) compile(p);
   if (plan_width) *plan_width = p->plan_width;
   if (nsteps) *nsteps = p->steps.size();
@@ -1543,6 +1607,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     owqs_pattern *p = pats[i];
     if (!p || p->ctx != ctx || !outputs[i]) return fail(ctx, OWQS_E_INVALID_ARG, "pattern " + std::to_string(i));
     if (!p->inputs.empty() && (!inputs || !inputs[i])) return fail(ctx, OWQS_E_INVALID_ARG, "null input");
+    if (owqs_status w = width_guard(p)) return w;
     if (p->dirty) compile(p);
     owqs_status st = ensure_device(p, p->plan_width > kLdsMaxWidth);
     if (st != OWQS_OK) return st;

@@ -88,9 +88,15 @@ def test_rule_violations_rejected(host_ctx, cmds, ins, outs):
 def test_width_limit_and_bad_arguments(host_ctx):
     n = 36
     cmds = [("N", q) for q in range(n)] + [("M", q, 0.0, (), ()) for q in range(n - 1)]
+    wide = owqs.Pattern(host_ctx, W.Pattern([], [n - 1], cmds))  # loads: it can still be reordered
+    assert wide.max_live == n
     with pytest.raises(owqs.OwqsError) as e:
-        owqs.Pattern(host_ctx, W.Pattern([], [n - 1], cmds))
+        wide.plan_info()
     assert e.value.status == owqs.E_WIDTH
+    narrow, stats = wide.reorder()
+    assert stats["max_live"] == narrow.max_live == 1  # no E: one qubit at a time
+    narrow.close()
+    wide.close()
     p = owqs.Pattern(host_ctx, W.plain_small().pattern)
     with pytest.raises(owqs.OwqsError):
         p.set_outcomes(np.zeros(3, np.uint8))
