@@ -162,3 +162,13 @@ def test_no_measurements(ctx):
     pat = W.Pattern([0, 1], [0, 1], [("E", 0, 1)])
     got, stats = check_against_oracle(ctx, pat)
     assert canon(got.cmds) == [("E", 0, 1)] and stats["max_state_space"] == 0
+
+
+def test_table3_cnot(ctx):
+    """Table III, CNOT row: m = 3 in both modes, through the library."""
+    pat = W.Pattern([1, 2], [1, 4], [("N", 3), ("N", 4), ("E", 1, 3), ("E", 2, 3), ("E", 3, 4),
+                                     ("M", 2, 0.0, (), ()), ("M", 3, 0.0, (), ()),
+                                     ("X", 4, (3,)), ("Z", 4, (2,)), ("Z", 1, (2,))])
+    for free in (False, True):
+        _, stats = check_against_oracle(ctx, pat, free=free)
+        assert stats["max_state_space"] == 3

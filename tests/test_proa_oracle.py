@@ -91,3 +91,33 @@ def test_positive_branch_ignores_dependencies():
         want, _ = oc.run(pat, zeros, inp)
         got, _ = oc.run(re, zeros, inp)
         np.testing.assert_allclose(got, want, atol=1e-10)
+
+
+def cnot_pattern():
+    """CNOT in the measurement calculus (the standard four-qubit pattern):
+    inputs 1 (control), 2 (target); outputs 1, 4.  Commands in standard form:
+    N3 N4, E13 E23 E34, M2 at 0, M3 at 0, then X4^{s3} Z4^{s2} Z1^{s2}."""
+    cmds = [("N", 3), ("N", 4), ("E", 1, 3), ("E", 2, 3), ("E", 3, 4),
+            ("M", 2, 0.0, (), ()), ("M", 3, 0.0, (), ()),
+            ("X", 4, (3,)), ("Z", 4, (2,)), ("Z", 1, (2,))]
+    return W.Pattern([1, 2], [1, 4], cmds)
+
+
+def test_table3_cnot_state_space():
+    """Table III, CNOT row: 4 qubits, m = 3 = |O| + 1 (OWQS and EOWQS)."""
+    pat = cnot_pattern()
+    for free in (False, True):
+        order, spaces, m, _ = proa.proa(pat, ignore_dependencies=free)
+        assert m == 3
+    # and the pattern is a CNOT for every outcome string: |c t> -> |c, t xor c>
+    order, _, _, _ = proa.proa(pat)
+    re = proa.reordered_pattern(pat, order)
+    for k in range(4):
+        inp = np.zeros(4, np.complex128)
+        inp[k] = 1.0
+        c, t = k & 1, (k >> 1) & 1
+        for bits in range(4):
+            per_q = {2: bits & 1, 3: bits >> 1}
+            out, _ = oc.run(re, _outcomes_for(re, per_q), inp)
+            j = c | ((t ^ c) << 1)
+            assert abs(abs(out[j]) - 1.0) < 1e-12
