@@ -17,6 +17,7 @@
 // weights are |O|, |O|, 1/2, |O| with alpha swept from |O| down to 1 (Sec. 5),
 // keeping the order whose largest state-space is smallest.
 #include <algorithm>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,12 @@ struct Sweep {
   int m = 0;
 };
 
+// One pass with fixed weights.  The ready qubits sit in a set ordered by
+// (cost, id), so the first entry is the least cost with ties to the smallest
+// id.  Measuring v changes only the costs of the qubits of its merged
+// state-space, of their not-yet-entangled neighbours (whose MS holds that
+// state-space) and of the qubits v depended on (their SS drops); those are
+// re-keyed, and qubits whose last domain qubit was v join the set.
 Sweep order_once(const Graph &g, double alpha, double beta, double gamma, double delta, bool free_order) {
   const int nq = g.nq;
   std::vector<int> sub(nq);                       // qubit -> sub-state id
@@ -49,45 +56,54 @@ Sweep order_once(const Graph &g, double alpha, double beta, double gamma, double
     members[q] = {q};
   }
   std::vector<std::vector<int>> pending = g.nbr;  // neighbours not yet entangled
-  std::vector<char> touched(nq, 0), measured(nq, 0);
-  std::vector<int> dependents(nq, 0);             // unmeasured qubits depending on q
-  for (int v : g.meas)
-    for (int d : g.deps[v]) ++dependents[d];
-  Sweep out;
-  std::vector<int> ids;
-  for (size_t step = 0; step < g.meas.size(); ++step) {
-    int best = -1, best_ms = 0;
-    double best_cost = 0.0;
-    for (int v : g.meas) {
-      if (measured[v]) continue;
-      bool ready = true;
-      if (!free_order)
-        for (int d : g.deps[v]) ready = ready && measured[d];
-      if (!ready) continue;
-      ids.assign(1, sub[v]);
-      for (int u : pending[v]) ids.push_back(sub[u]);
-      std::sort(ids.begin(), ids.end());
-      ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
-      int ms = 0;
-      for (int s : ids) ms += (int)members[s].size();
-      int os = 0;
-      for (int u : g.nbr[v]) os += g.is_out[u] ? 1 : 0;
-      const int ss = dependents[v];
-      const double cost = touched[v] ? alpha * ms + beta * os - gamma * ss
-                                     : alpha * ((ms + 1) * delta) + beta * os - gamma * ss;
-      if (best < 0 || cost < best_cost) {
-        best = v;
-        best_cost = cost;
-        best_ms = ms;
-      }
+  std::vector<char> touched(nq, 0);
+  std::vector<int> dependents(nq, 0);             // SS: unmeasured qubits whose domains hold q
+  std::vector<int> waiting(nq, 0);                // unmeasured qubits in q's domains
+  std::vector<std::vector<int>> needs_me(nq);     // q -> measured qubits whose domains hold q
+  std::vector<int> os(nq, 0);                     // OS: edges to outputs
+  for (int v : g.meas) {
+    for (int d : g.deps[v]) {
+      ++dependents[d];
+      ++waiting[v];
+      needs_me[d].push_back(v);
     }
-    if (best < 0) return Sweep{};  // circular dependencies (validated patterns cannot have them)
-    const int v = best;
-    // merge into v's state-space, then drop v
+    for (int u : g.nbr[v]) os[v] += g.is_out[u] ? 1 : 0;
+  }
+  std::vector<int> ids;
+  auto ms_of = [&](int v) {
     ids.assign(1, sub[v]);
     for (int u : pending[v]) ids.push_back(sub[u]);
     std::sort(ids.begin(), ids.end());
     ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    int ms = 0;
+    for (int s : ids) ms += (int)members[s].size();
+    return ms;
+  };
+  auto cost_of = [&](int v) {
+    const int ms = ms_of(v);
+    return touched[v] ? alpha * ms + beta * os[v] - gamma * dependents[v]
+                      : alpha * ((ms + 1) * delta) + beta * os[v] - gamma * dependents[v];
+  };
+  std::set<std::pair<double, int>> ready;
+  std::vector<double> key(nq, 0.0);
+  std::vector<char> queued(nq, 0);
+  auto enqueue = [&](int v) {
+    key[v] = cost_of(v);
+    ready.insert({key[v], v});
+    queued[v] = 1;
+  };
+  for (int v : g.meas)
+    if (free_order || waiting[v] == 0) enqueue(v);
+  std::vector<int> stamp(nq, -1), affected;
+  Sweep out;
+  for (size_t step = 0; step < g.meas.size(); ++step) {
+    if (ready.empty()) return Sweep{};  // circular dependencies (validated patterns cannot have them)
+    const int v = ready.begin()->second;
+    ready.erase(ready.begin());
+    queued[v] = 0;
+    out.m = std::max(out.m, ms_of(v));
+    out.order.push_back(v);
+    // merge into v's state-space (ids holds its sub-states), then drop v
     std::vector<int> merged;
     for (int s : ids) {
       merged.insert(merged.end(), members[s].begin(), members[s].end());
@@ -103,10 +119,29 @@ Sweep order_once(const Graph &g, double alpha, double beta, double gamma, double
       pu.erase(std::remove(pu.begin(), pu.end(), v), pu.end());
     }
     pending[v].clear();
-    measured[v] = 1;
     for (int d : g.deps[v]) --dependents[d];
-    out.order.push_back(v);
-    out.m = std::max(out.m, best_ms);
+    // re-key what changed
+    affected.clear();
+    auto mark = [&](int q) {
+      if (stamp[q] != (int)step) {
+        stamp[q] = (int)step;
+        affected.push_back(q);
+      }
+    };
+    for (int q : merged) {
+      mark(q);
+      for (int u : pending[q]) mark(u);
+    }
+    for (int d : g.deps[v]) mark(d);
+    for (int q : affected)
+      if (queued[q]) {
+        ready.erase({key[q], q});
+        key[q] = cost_of(q);
+        ready.insert({key[q], q});
+      }
+    if (!free_order)
+      for (int u : needs_me[v])
+        if (--waiting[u] == 0) enqueue(u);
   }
   return out;
 }
