@@ -100,8 +100,27 @@ typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 
  * windows/E/X/Z whose paired slots fit an LDS tile run as one
  * pass per run (2^12-amplitude tiles by default).  AUTO (default): the fused plan, run as one workgroup with
  * the whole vector in LDS when its width is <= 14, else as FUSED.  All give
- * the same result to FP32 rounding. */
-typedef enum { OWQS_EXEC_PLAIN = 0, OWQS_EXEC_FUSED = 1, OWQS_EXEC_AUTO = 2 } owqs_exec;
+ * the same result to FP32 rounding.
+ * SUBSTATES: the state is a list of sub-states (Sec. 4.1), each group of
+ * qubits entangled so far in its own vector: N makes a one-qubit |+>
+ * sub-state, E across two sub-states first forms their tensor product
+ * (Sec. 4.4.1: the wider one keeps its buffer and takes the other's qubits on
+ * its top bits), M eliminates its qubit inside its sub-state (with the
+ * sub-state's own FP64 scale in OWQS mode), one kernel per command.  Memory
+ * is the sum of the sub-states' largest sizes, not 2^(live width), and the
+ * width limit OWQS_MAX_WIDTH applies to each sub-state, so patterns whose
+ * graph stays in separate components can be wider than the limit.  Runs
+ * with owqs_run (the input as one sub-state) or owqs_run_factors; read with
+ * owqs_read_state (the tensor product, if the outputs fit) or
+ * owqs_read_substates.  Batches, basis runs, adjoints, ranged, profiled and
+ * sampled runs and the tuner refuse it (OWQS_E_STATE).  The input state is
+ * taken to be normalised (each sub-state's p is relative to its own norm). */
+typedef enum {
+  OWQS_EXEC_PLAIN = 0,
+  OWQS_EXEC_FUSED = 1,
+  OWQS_EXEC_AUTO = 2,
+  OWQS_EXEC_SUBSTATES = 3
+} owqs_exec;
 
 typedef struct owqs_ctx owqs_ctx;
 typedef struct owqs_pattern owqs_pattern;
@@ -126,8 +145,8 @@ const char *owqs_last_error(const owqs_ctx *ctx);
  * is computed; no device memory is allocated yet.  Every M starts with its
  * outcome forced to 0.  A pattern wider than OWQS_MAX_WIDTH loads (it can be
  * read back and reordered, owqs_pattern_reorder), but every call that plans
- * or runs it returns OWQS_E_WIDTH.  More than OWQS_MAX_WIDTH inputs or
- * outputs is OWQS_E_WIDTH here. */
+ * or runs it returns OWQS_E_WIDTH (the sub-state executor checks its widest
+ * sub-state instead; owqs_read_state checks the number of outputs). */
 owqs_status owqs_pattern_create(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds,
                                 const int32_t *domain_ids, size_t ndom,
                                 const int32_t *inputs, int32_t nin,
@@ -201,8 +220,9 @@ owqs_status owqs_tune(owqs_pattern *pat, const void *input_c64, size_t n_amps, i
  * largest live width it reaches (plain plans: max_live; fused windows keep
  * the width of the window's input), its number of steps (one per
  * non-trivial command or fused window) and the number of passes over the
- * state in global memory (steps after grouping runs into tile passes).  Any
- * pointer may be NULL. */
+ * state in global memory (steps after grouping runs into tile passes).  For
+ * the sub-state executor: the widest sub-state, and its steps (one kernel
+ * each, both counts).  Any pointer may be NULL. */
 owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps, size_t *npasses);
 
 /* Recognition problem (Sec. 1: which unitary does a pattern implement):
@@ -344,6 +364,41 @@ owqs_status owqs_run_range(owqs_pattern *pat, const void *input_c64, size_t n_am
  * device buffer of 2^n entries. */
 owqs_status owqs_read_live(owqs_pattern *pat, void *out_c64, size_t n_amps, int32_t *qubits,
                            int32_t *n_live, void *stream);
+
+/* Sub-state executor: how the inputs split into initial sub-states, for
+ * planning before a run (owqs_plan_info); owqs_run_factors sets it too.
+ * factor_nq[k] >= 1 qubits each, in input order, covering the inputs;
+ * nfactors = 0 or 1 means one sub-state for all inputs (the default). */
+owqs_status owqs_set_input_factors(owqs_pattern *pat, const int32_t *factor_nq, size_t nfactors);
+
+/* Sub-state executor (OWQS_EXEC_SUBSTATES, Sec. 4.1): run with the input
+ * given as a tensor product of factors, each its own initial sub-state.
+ * Factor k is 2^factor_nq[k] complex64 amplitudes (device memory if
+ * input_on_device, else host) over the next factor_nq[k] inputs in input
+ * order (bit j of factor k = inputs[f_k + j], f_k the inputs before it); the
+ * factors cover the inputs exactly once, each factor_nq[k] >= 1 (a pattern
+ * without inputs takes nfactors = 0).  A different factorization from the
+ * previous run recompiles the plan.  Otherwise as owqs_run.  OWQS_E_STATE in
+ * another executor. */
+owqs_status owqs_run_factors(owqs_pattern *pat, const void *const *factors, const int32_t *factor_nq,
+                             size_t nfactors, int input_on_device, void *stream);
+
+/* After a sub-state run: the output state as its factors.  Factor f holds
+ * the outputs that ended in one sub-state; factors are ordered by their first
+ * output (outputs order) and each lists its qubits in outputs order.
+ * *n_factors and *n_amps (sum over factors of 2^factor_nq[f]) are written
+ * when non-NULL.  factor_nq[f] and qubits (the caller's ids of factor 0, then
+ * factor 1, ...) are written when non-NULL (factor_cap >= *n_factors).
+ * out_c64 (host, amp_cap >= *n_amps, may be NULL) receives the factors'
+ * amplitudes one after the other, bit j of factor f = its j-th qubit, each
+ * scaled to the true state (normalised in OWQS mode); scalar_c64 (host, one
+ * complex64, may be NULL) receives the product of the sub-states whose qubits
+ * were all measured (modulus 1 in OWQS mode).  The full output state is
+ * scalar x the tensor product of the factors.  Waits for `stream`; reports a
+ * pending device error like owqs_check. */
+owqs_status owqs_read_substates(owqs_pattern *pat, void *out_c64, size_t amp_cap, int32_t *factor_nq,
+                                int32_t *qubits, size_t factor_cap, int32_t *n_factors, size_t *n_amps,
+                                void *scalar_c64, void *stream);
 
 /* The pattern's commands in execution order, in the form owqs_pattern_create
  * takes: the caller's qubit ids, the current angles (owqs_set_angles), the

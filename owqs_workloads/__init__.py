@@ -596,3 +596,34 @@ def random_standard_pattern(g: np.random.Generator, n_qubits: int = 9, n_in: int
             if k:
                 cmds.append((op, q, tuple(int(x) for x in g.choice(done, size=k, replace=False))))
     return Pattern(inputs, outputs, cmds, "random_standard")
+
+
+def disjoint_union(patterns: Sequence[Pattern], offset: int = 1000, name: str = "") -> Pattern:
+    """Several patterns side by side on disjoint qubits (pattern k's ids plus
+    k * offset), their commands interleaved one by one; inputs and outputs
+    concatenated in pattern order.  The entanglement graph has at least one
+    component per pattern, so the state stays a product across them."""
+    shifted = []
+    ins: List[int] = []
+    outs: List[int] = []
+    for k, pat in enumerate(patterns):
+        d = k * offset
+        cm = []
+        for c in pat.cmds:
+            if c[0] == "N":
+                cm.append(("N", c[1] + d))
+            elif c[0] == "E":
+                cm.append(("E", c[1] + d, c[2] + d))
+            elif c[0] == "M":
+                cm.append(("M", c[1] + d, c[2], tuple(q + d for q in c[3]), tuple(q + d for q in c[4])))
+            else:
+                cm.append((c[0], c[1] + d, tuple(q + d for q in c[2])))
+        shifted.append(cm)
+        ins += [q + d for q in pat.inputs]
+        outs += [q + d for q in pat.outputs]
+    cmds = []
+    for i in range(max((len(c) for c in shifted), default=0)):
+        for cm in shifted:
+            if i < len(cm):
+                cmds.append(cm[i])
+    return Pattern(ins, outs, cmds, name or "disjoint")

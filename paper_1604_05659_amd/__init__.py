@@ -41,7 +41,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK = 0
 E_INVALID_ARG, E_PATTERN, E_ZERO_PROB, E_WIDTH, E_NOMEM, E_HIP, E_NOT_DETERMINISTIC, E_STATE = range(-1, -9, -1)
 MODE_OWQS, MODE_EOWQS, MODE_EOWQS_CHECK = 0, 1, 2
-EXEC_PLAIN, EXEC_FUSED, EXEC_AUTO = 0, 1, 2
+EXEC_PLAIN, EXEC_FUSED, EXEC_AUTO, EXEC_SUBSTATES = 0, 1, 2, 3
 OPS = {"N": 0, "E": 1, "M": 2, "X": 3, "Z": 4}
 KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)", 7: "tile(group)"}
 NUM_KINDS = 8
@@ -100,6 +100,10 @@ _sig = {
                                              _i32p, _i32p, ctypes.POINTER(ctypes.c_size_t),
                                              ctypes.POINTER(ctypes.c_size_t)]),
     "owqs_pattern_reorder": (ctypes.c_int, [_vp, ctypes.c_void_p, ctypes.POINTER(_vp), ctypes.c_void_p]),
+    "owqs_set_input_factors": (ctypes.c_int, [_vp, _i32p, ctypes.c_size_t]),
+    "owqs_run_factors": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32p, ctypes.c_size_t, ctypes.c_int, _vp]),
+    "owqs_read_substates": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _i32p, ctypes.c_size_t, _i32p,
+                                           ctypes.POINTER(ctypes.c_size_t), _vp, _vp]),
     "owqs_run_profiled": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
@@ -424,6 +428,48 @@ class Pattern:
         if psi_in.dtype != torch.complex64 or not psi_in.is_cuda or not psi_in.is_contiguous():
             raise TypeError("input must be a contiguous complex64 CUDA tensor")
         self.ctx.check(_lib.owqs_run(self._h, psi_in.data_ptr(), psi_in.numel(), 1, _stream_handle(stream)))
+
+    def set_input_factors(self, factor_nq: Sequence[int]):
+        """Split the inputs into initial sub-states of these sizes (input order)."""
+        a = np.array(list(factor_nq) or [0], np.int32)
+        self.ctx.check(_lib.owqs_set_input_factors(self._h, a.ctypes.data_as(_i32p), len(factor_nq)))
+
+    def run_factors(self, factors, stream=None):
+        """Sub-state executor: run with the input as a tensor product of
+        complex64 CUDA tensors, factor k over the next log2(len) inputs
+        (owqs_run_factors)."""
+        import torch
+        for f in factors:
+            if f.dtype != torch.complex64 or not f.is_cuda or not f.is_contiguous():
+                raise TypeError("factors must be contiguous complex64 CUDA tensors")
+        nq = np.array([max(int(f.numel()).bit_length() - 1, 0) for f in factors] or [0], np.int32)
+        ptrs = (_vp * max(len(factors), 1))(*[f.data_ptr() for f in factors])
+        self.ctx.check(_lib.owqs_run_factors(self._h, ptrs, nq.ctypes.data_as(_i32p), len(factors), 1,
+                                             _stream_handle(stream)))
+
+    def read_substates(self, stream=None):
+        """After a sub-state run: ([(qubit ids, complex64 numpy vector), ...],
+        complex scalar) with the output state = scalar x the tensor product
+        (owqs_read_substates)."""
+        nf = ctypes.c_int32()
+        na = ctypes.c_size_t()
+        h = _stream_handle(stream)
+        self.ctx.check(_lib.owqs_read_substates(self._h, None, 0, None, None, 0, ctypes.byref(nf), ctypes.byref(na),
+                                                None, h))
+        fq = np.zeros(max(nf.value, 1), np.int32)
+        qs = np.zeros(max(self.n_out, 1), np.int32)
+        amps = np.zeros(max(na.value, 1), np.complex64)
+        sc = np.zeros(1, np.complex64)
+        self.ctx.check(_lib.owqs_read_substates(self._h, amps.ctypes.data, amps.size, fq.ctypes.data_as(_i32p),
+                                                qs.ctypes.data_as(_i32p), fq.size, ctypes.byref(nf),
+                                                ctypes.byref(na), sc.ctypes.data, h))
+        out, a, q = [], 0, 0
+        for f in range(nf.value):
+            k = int(fq[f])
+            out.append(([int(x) for x in qs[q:q + k]], amps[a:a + (1 << k)].copy()))
+            a += 1 << k
+            q += k
+        return out, complex(sc[0])
 
     def run_profiled(self, psi_in=None, stream=None) -> dict:
         """Run once with HIP events between launches; returns, per kernel kind,

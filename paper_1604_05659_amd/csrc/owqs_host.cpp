@@ -65,6 +65,37 @@ struct TileGroup {
   size_t m_off;   // first window's measurement index in the pattern's m table
 };
 
+// Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's
+// region of the arena, kept by the sub-state that is the base of every merge
+// it takes part in.
+enum SubKind : int { SS_INIT = 0, SS_N = 1, SS_E = 2, SS_X = 3, SS_Z = 4, SS_M = 5, SS_KRON = 6 };
+
+struct SubStep {
+  int kind;
+  int chain;         // the sub-state acted on
+  int n;             // its width before the step
+  int b0, b1;        // slots
+  int top, top_n;    // SS_KRON: the sub-state merged in, and its width
+  float2 coef;       // SS_M: (-1)^o e^{-i theta}
+  double host_factor;
+  int m_index;
+};
+
+struct SubChain {
+  size_t off = 0;               // first amplitude in the arena
+  int maxw = 0;                 // widest it gets (its region holds 2^maxw amplitudes, at least 4)
+  std::vector<int> at;          // dense qubit at each slot, at the end of the plan
+  double pend = 1.0;            // host factor at the end of the plan
+  bool merged = false;          // merged into another chain
+};
+
+struct SubFactor {
+  int chain;
+  std::vector<int> qubits;      // dense, in output order
+  std::vector<int> where;       // slot of each, same order
+  uint64_t mask = 0;            // output bits held
+};
+
 struct Cmd {
   int op;
   int q0, q1;  // dense qubit indices
@@ -163,6 +194,26 @@ struct owqs_pattern {
   hipGraph_t s_graph = nullptr;
   hipGraphExec_t s_exec = nullptr;
   bool sampled_ran = false;
+
+  // sub-state executor (OWQS_EXEC_SUBSTATES)
+  std::vector<int32_t> ss_in_nq;    // input factorization (qubits per factor, input order); empty: one factor
+  std::vector<SubStep> ss_steps;
+  std::vector<SubChain> ss_chains;
+  std::vector<SubFactor> ss_factors;
+  std::vector<int> ss_vanished;     // chains whose qubits were all measured (a scalar each)
+  int ss_width = 0;                 // widest sub-state
+  bool ss_plan_ok = true;           // every step fits its sub-state's region
+  size_t ss_arena = 0;              // amplitudes
+  float2 *ss_mem = nullptr;
+  size_t ss_mem_cap = 0;
+  double *ss_sigma = nullptr;       // one FP64 scale per chain
+  size_t ss_sigma_cap = 0;
+  float2 *ss_stage = nullptr;       // read-out: factors, then the scalars
+  size_t ss_stage_cap = 0;
+  hipGraph_t ss_graph = nullptr;
+  hipGraphExec_t ss_exec = nullptr;
+  int ss_graph_reduce = -1;
+  bool ss_ran = false;
 
   bool ran = false;
   bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
@@ -557,8 +608,208 @@ void compile_plan(owqs_pattern *p, bool fused, std::vector<Step> &steps, std::ve
   final_factor = pending;
 }
 
+// Sub-state plan (Sec. 4.1, Sec. 4.4.1): every input factor starts as a
+// sub-state; N makes a fresh |+> qubit that stays implicit until a command
+// touches it; E with a fresh qubit appends it to the other qubit's sub-state
+// (a prepare step, as in the single-vector plan), E across two sub-states
+// merges them (SS_KRON, the wider one is the base and keeps its region), and
+// M eliminates its qubit inside its sub-state (the top qubit moves into the
+// freed slot).  Each sub-state keeps its own host factor and FP64 scale.
+void compile_substates(owqs_pattern *p) {
+  p->ss_steps.clear();
+  p->ss_chains.clear();
+  p->ss_factors.clear();
+  p->ss_vanished.clear();
+  const int nq = p->nq;
+  std::vector<int> chain_of(nq, -1), slot_of(nq, -1), outcome_of(nq, 0);
+  std::vector<char> fresh(nq, 0);
+  std::vector<SubChain> &ch = p->ss_chains;
+  const double r2 = 1.0 / std::sqrt(2.0);
+  auto widen = [&](int c) { ch[c].maxw = std::max(ch[c].maxw, (int)ch[c].at.size()); };
+  // input factors
+  std::vector<int32_t> nqs = p->ss_in_nq;
+  if (nqs.empty() && !p->inputs.empty()) nqs.push_back((int32_t)p->inputs.size());
+  size_t off = 0;
+  for (int32_t k : nqs) {
+    ch.emplace_back();
+    const int c = (int)ch.size() - 1;
+    for (int32_t j = 0; j < k; ++j) {
+      const int q = p->inputs[off + j];
+      chain_of[q] = c;
+      slot_of[q] = j;
+      ch[c].at.push_back(q);
+    }
+    off += (size_t)k;
+    widen(c);
+  }
+  auto emit = [&](int kind, int c) -> SubStep & {
+    SubStep st{};
+    st.kind = kind;
+    st.chain = c;
+    st.n = (int)ch[c].at.size();
+    p->ss_steps.push_back(st);
+    return p->ss_steps.back();
+  };
+  auto prep = [&](int c, int q) {
+    emit(SS_N, c);
+    slot_of[q] = (int)ch[c].at.size();
+    chain_of[q] = c;
+    fresh[q] = 0;
+    ch[c].at.push_back(q);
+    ch[c].pend *= r2;
+    widen(c);
+  };
+  auto materialize = [&](int q) {
+    ch.emplace_back();
+    const int c = (int)ch.size() - 1;
+    emit(SS_INIT, c);
+    prep(c, q);
+    return c;
+  };
+  int m = 0;
+  for (const Cmd &c : p->cmds) {
+    switch (c.op) {
+      case OWQS_OP_N:
+        fresh[c.q0] = 1;
+        break;
+      case OWQS_OP_E: {
+        const int u = c.q0, v = c.q1;
+        if (fresh[u] && fresh[v]) {
+          prep(materialize(u), v);
+        } else if (fresh[u]) {
+          prep(chain_of[v], u);
+        } else if (fresh[v]) {
+          prep(chain_of[u], v);
+        } else if (chain_of[u] != chain_of[v]) {
+          int a = chain_of[u], b = chain_of[v];
+          if (ch[b].at.size() > ch[a].at.size() || (ch[b].at.size() == ch[a].at.size() && b < a)) std::swap(a, b);
+          SubStep &st = emit(SS_KRON, a);
+          st.top = b;
+          st.top_n = (int)ch[b].at.size();
+          const int base_n = (int)ch[a].at.size();
+          for (size_t j = 0; j < ch[b].at.size(); ++j) {
+            const int q = ch[b].at[j];
+            chain_of[q] = a;
+            slot_of[q] = base_n + (int)j;
+            ch[a].at.push_back(q);
+          }
+          ch[a].pend *= ch[b].pend;
+          ch[b].at.clear();
+          ch[b].merged = true;
+          widen(a);
+        }
+        SubStep &st = emit(SS_E, chain_of[u]);
+        st.b0 = slot_of[u];
+        st.b1 = slot_of[v];
+        break;
+      }
+      case OWQS_OP_X:
+      case OWQS_OP_Z: {
+        if (!signal(c.s, outcome_of)) break;
+        if (fresh[c.q0]) materialize(c.q0);
+        SubStep &st = emit(c.op == OWQS_OP_X ? SS_X : SS_Z, chain_of[c.q0]);
+        st.b0 = slot_of[c.q0];
+        break;
+      }
+      case OWQS_OP_M: {
+        const int q = c.q0;
+        if (fresh[q]) materialize(q);
+        const int k = chain_of[q];
+        const int s = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
+        const double theta = (s ? -p->angles[m] : p->angles[m]) + (t ? M_PI : 0.0);  // Eq. 2
+        const int o = p->outcomes[m] & 1;
+        double cr = std::cos(theta), ci = -std::sin(theta);  // (-1)^o e^{-i theta}  (Eqs. 11-12)
+        if (o) { cr = -cr; ci = -ci; }
+        SubStep &st = emit(SS_M, k);
+        st.b0 = slot_of[q];
+        st.coef = make_float2((float)cr, (float)ci);
+        st.host_factor = ch[k].pend;
+        st.m_index = m;
+        ch[k].pend = 1.0;
+        outcome_of[q] = o;
+        ++m;
+        std::vector<int> &at = ch[k].at;
+        const int top = at.back();
+        if (top != q) {
+          at[slot_of[q]] = top;
+          slot_of[top] = slot_of[q];
+        }
+        at.pop_back();
+        chain_of[q] = -1;
+        slot_of[q] = -1;
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  for (int q : p->outputs)
+    if (fresh[q]) materialize(q);
+  // read-out factors, ordered by their first output; vanished sub-states
+  std::vector<int> pos(nq, -1);
+  for (size_t k = 0; k < p->outputs.size(); ++k) pos[p->outputs[k]] = (int)k;
+  std::vector<int> factor_of(ch.size(), -1);
+  for (size_t k = 0; k < p->outputs.size(); ++k) {
+    const int q = p->outputs[k], c = chain_of[q];
+    if (factor_of[c] < 0) {
+      factor_of[c] = (int)p->ss_factors.size();
+      SubFactor f{};
+      f.chain = c;
+      p->ss_factors.push_back(f);
+    }
+    SubFactor &f = p->ss_factors[factor_of[c]];
+    f.qubits.push_back(q);
+    f.where.push_back(slot_of[q]);
+    f.mask |= uint64_t(1) << k;
+  }
+  for (size_t c = 0; c < ch.size(); ++c)
+    if (!ch[c].merged && ch[c].at.empty()) p->ss_vanished.push_back((int)c);
+  p->ss_width = 0;
+  for (const SubChain &c : ch) p->ss_width = std::max(p->ss_width, c.maxw);
+  // every step stays inside its sub-state's region (checked before any launch)
+  p->ss_plan_ok = true;
+  for (const SubStep &x : p->ss_steps) {
+    const int w = ch[x.chain].maxw;
+    bool ok = x.n <= w;
+    switch (x.kind) {
+      case SS_N: ok = ok && x.n + 1 <= w; break;
+      case SS_E: ok = ok && x.b0 >= 0 && x.b1 >= 0 && x.b0 < x.n && x.b1 < x.n && x.b0 != x.b1; break;
+      case SS_X:
+      case SS_Z:
+      case SS_M: ok = ok && x.b0 >= 0 && x.b0 < x.n; break;
+      case SS_KRON:
+        ok = ok && x.top != x.chain && x.n >= 1 && x.top_n >= 1 && x.n + x.top_n <= w &&
+             x.top_n <= ch[x.top].maxw;
+        break;
+      default: break;
+    }
+    if (!ok) p->ss_plan_ok = false;
+  }
+  p->ss_arena = 0;
+  if (p->ss_width <= OWQS_MAX_WIDTH) {
+    for (SubChain &c : ch) {
+      c.off = p->ss_arena;
+      const size_t amps = std::max<size_t>(size_t(1) << c.maxw, 4);
+      p->ss_arena += (amps + 63) / 64 * 64;  // 512-byte aligned regions
+    }
+  }
+}
+
+void drop_ss_graph(owqs_pattern *p) {
+  if (p->ss_exec || p->ss_graph) (void)hipDeviceSynchronize();
+  if (p->ss_exec) { (void)hipGraphExecDestroy(p->ss_exec); p->ss_exec = nullptr; }
+  if (p->ss_graph) { (void)hipGraphDestroy(p->ss_graph); p->ss_graph = nullptr; }
+}
+
 // Compile the command list into device steps for the current settings.
 void compile(owqs_pattern *p) {
+  if (p->exec == OWQS_EXEC_SUBSTATES) {
+    compile_substates(p);
+    drop_ss_graph(p);
+    p->plan_width = std::max(p->ss_width, 1);
+    p->dirty = false;
+    return;
+  }
   compile_plan(p, p->exec != OWQS_EXEC_PLAIN, p->steps, p->final_where, p->final_factor, nullptr);
   p->lk_valid = false;
   p->lk_next = SIZE_MAX;
@@ -576,7 +827,16 @@ void compile(owqs_pattern *p) {
 
 // Patterns of any width load (so they can be reordered and read back); only
 // those within OWQS_MAX_WIDTH compile and run.
+void compile(owqs_pattern *p);
+
 owqs_status width_guard(owqs_pattern *p) {
+  if (p->exec == OWQS_EXEC_SUBSTATES) {
+    if (p->dirty) compile(p);
+    if (p->ss_width > OWQS_MAX_WIDTH)
+      return fail(p->ctx, OWQS_E_WIDTH, "sub-state width " + std::to_string(p->ss_width) + " above OWQS_MAX_WIDTH");
+    if (!p->ss_plan_ok) return fail(p->ctx, OWQS_E_STATE, "internal error: a sub-state step outside its region");
+    return OWQS_OK;
+  }
   if (p->max_live > OWQS_MAX_WIDTH)
     return fail(p->ctx, OWQS_E_WIDTH, "live width " + std::to_string(p->max_live) +
                                           " above OWQS_MAX_WIDTH (owqs_pattern_reorder can narrow it)");
@@ -619,7 +879,6 @@ owqs_status build_pattern(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, con
   if (!ctx || !out || (ncmds && !cmds) || (ndom && !dom) || nin < 0 || nout < 0 || (nin && !inputs) ||
       (nout && !outputs))
     return fail(ctx, OWQS_E_INVALID_ARG, "null pointer or negative size");
-  if (nin > OWQS_MAX_WIDTH || nout > OWQS_MAX_WIDTH) return fail(ctx, OWQS_E_WIDTH, "too many inputs/outputs");
   auto *p = new owqs_pattern();
   p->ctx = ctx;
   std::unordered_map<int32_t, int> dense;
@@ -970,6 +1229,7 @@ hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
 
 owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream) {
   const size_t nin = p->inputs.size();
+  if (owqs_status w = width_guard(p)) return w;
   const size_t want = size_t(1) << nin;
   if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
   if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
@@ -1034,6 +1294,7 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
   }
   if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
   p->ran = true;
+  p->ss_ran = false;
   p->batch_ran = false;
   p->out_in_order = false;
   p->sampled_ran = true;
@@ -1041,14 +1302,197 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
   return OWQS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// sub-state executor runs
+// ---------------------------------------------------------------------------
+hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s) {
+  hipError_t e = launch_sub_start(p->ss_sigma, (int)p->ss_chains.size(), p->book.err, s);
+  for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
+    const SubStep &x = p->ss_steps[i];
+    float2 *psi = p->ss_mem + p->ss_chains[x.chain].off;
+    switch (x.kind) {
+      case SS_INIT: e = launch_sub_init(psi, s); break;
+      case SS_N: e = launch_prepare(psi, x.n, s); break;
+      case SS_E: e = launch_cz(psi, x.n, x.b0, x.b1, s); break;
+      case SS_X: e = launch_pauli_x(psi, x.n, x.b0, s); break;
+      case SS_Z: e = launch_pauli_z(psi, x.n, x.b0, s); break;
+      case SS_KRON:
+        e = launch_kron(psi, x.n, p->ss_mem + p->ss_chains[x.top].off, x.top_n, p->ss_sigma + x.chain,
+                        p->ss_sigma + x.top, s);
+        break;
+      case SS_M: {
+        MeasureArgs a{};
+        a.reduce = reduce;
+        a.book = p->book;
+        a.book.sigma = p->ss_sigma + x.chain;
+        a.coef = x.coef;
+        a.host_factor = x.host_factor;
+        a.m_index = x.m_index;
+        unsigned grid = 0;
+        e = launch_measure(psi, x.n, x.b0, a, s, &grid);
+        if (e == hipSuccess) e = launch_finish(a, grid, s);
+        break;
+      }
+      default: break;
+    }
+  }
+  return e;
+}
+
+bool substates(const owqs_pattern *p) { return p->exec == OWQS_EXEC_SUBSTATES; }
+
+owqs_status refuse_substates(owqs_pattern *p, const char *what) {
+  return fail(p->ctx, OWQS_E_STATE, std::string(what) + " does not run the sub-state executor (OWQS_EXEC_SUBSTATES)");
+}
+
+// Input factor k (2^nqs[k] complex64) holds the next nqs[k] inputs.
+owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int32_t *nqs, size_t nf,
+                          int on_device, void *stream) {
+  if (nf && (!factors || !nqs)) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input factors");
+  size_t total = 0;
+  for (size_t k = 0; k < nf; ++k) {
+    if (nqs[k] < 1 || nqs[k] > OWQS_MAX_WIDTH || !factors[k])
+      return fail(p->ctx, OWQS_E_INVALID_ARG, "input factor with no qubits, too many, or no data");
+    total += (size_t)nqs[k];
+  }
+  if (total != p->inputs.size()) return fail(p->ctx, OWQS_E_INVALID_ARG, "input factors must cover the inputs");
+  std::vector<int32_t> want(nqs, nqs + nf);
+  if (nf == 1) want.clear();  // one factor is the default plan
+  if (want != p->ss_in_nq) {
+    p->ss_in_nq = want;
+    p->dirty = true;
+  }
+  if (p->sampling) return fail(p->ctx, OWQS_E_STATE, "drawn outcomes do not run the sub-state executor");
+  owqs_status st = ensure_device(p, false);  // compiles the sub-state plan and checks its width
+  if (st != OWQS_OK) return st;
+  if (p->dirty) compile(p);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  const size_t arena = std::max<size_t>(p->ss_arena, 64);
+  if (p->ss_mem_cap < arena) {
+    drop_ss_graph(p);
+    if (p->ss_mem) (void)hipFree(p->ss_mem);
+    p->ss_mem = nullptr;
+    p->ss_mem_cap = 0;
+    e = hipMalloc(&p->ss_mem, arena * sizeof(float2));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, std::string("sub-state arena: ") + hipGetErrorString(e));
+    p->ss_mem_cap = arena;
+  }
+  if (p->ss_sigma_cap < std::max<size_t>(p->ss_chains.size(), 1)) {
+    drop_ss_graph(p);
+    if (p->ss_sigma) (void)hipFree(p->ss_sigma);
+    p->ss_sigma = nullptr;
+    p->ss_sigma_cap = 0;
+    const size_t n = std::max<size_t>(p->ss_chains.size(), 1);
+    e = hipMalloc(&p->ss_sigma, n * sizeof(double));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sub-state scales");
+    p->ss_sigma_cap = n;
+  }
+  end_ranged(p);
+  p->sampled_ran = false;
+  p->ran = false;
+  p->ss_ran = false;
+  for (size_t k = 0; k < nf; ++k) {
+    e = hipMemcpyAsync(p->ss_mem + p->ss_chains[k].off, factors[k], (size_t(1) << nqs[k]) * sizeof(float2),
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "input copy");
+  }
+  const int reduce = p->mode == OWQS_MODE_OWQS ? kReduceRenorm
+                     : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck
+                                                        : kReduceNone;
+  if (p->use_graph) {
+    if (p->ss_exec && p->ss_graph_reduce != reduce) drop_ss_graph(p);
+    if (!p->ss_exec) {
+      if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(p->ctx, e, "capture stream");
+      }
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(p->ctx, e, "begin capture");
+      hipError_t le = launch_substeps(p, reduce, p->cap_stream);
+      e = hipStreamEndCapture(p->cap_stream, &p->ss_graph);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->ss_exec, p->ss_graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (p->ss_graph) { (void)hipGraphDestroy(p->ss_graph); p->ss_graph = nullptr; }
+        p->ss_exec = nullptr;
+        return hip_fail(p->ctx, e, "graph capture");
+      }
+      p->ss_graph_reduce = reduce;
+    }
+    e = hipGraphLaunch(p->ss_exec, s);
+  } else {
+    e = launch_substeps(p, reduce, s);
+  }
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
+  p->ran = true;
+  p->ss_ran = true;
+  p->batch_ran = false;
+  p->out_in_order = false;
+  p->ran_mode = reduce;
+  return OWQS_OK;
+}
+
+// Read every factor (scaled, its qubits in output order) and the scalar of
+// the vanished sub-states into ss_stage: factor f at offs[f], the scalar at
+// offs.back().
+owqs_status stage_substates(owqs_pattern *p, hipStream_t s, std::vector<uint64_t> &offs) {
+  offs.clear();
+  uint64_t at = 0;
+  for (const SubFactor &f : p->ss_factors) {
+    offs.push_back(at);
+    at += uint64_t(1) << f.qubits.size();
+  }
+  offs.push_back(at);
+  const size_t need = at + std::max<size_t>(p->ss_vanished.size(), 1);
+  hipError_t e = hipSuccess;
+  if (p->ss_stage_cap < need) {
+    if (p->ss_stage) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(p->ss_stage);
+    }
+    p->ss_stage = nullptr;
+    p->ss_stage_cap = 0;
+    e = hipMalloc(&p->ss_stage, need * sizeof(float2));
+    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sub-state read-out buffer");
+    p->ss_stage_cap = need;
+  }
+  const bool renorm = p->ran_mode == kReduceRenorm;
+  for (size_t k = 0; k < p->ss_factors.size() && e == hipSuccess; ++k) {
+    const SubFactor &f = p->ss_factors[k];
+    const SubChain &c = p->ss_chains[f.chain];
+    e = launch_read(p->ss_mem + c.off, p->ss_stage + offs[k], (int)f.qubits.size(), f.where.data(), c.pend,
+                    renorm ? p->ss_sigma + f.chain : nullptr, s);
+  }
+  for (size_t k = 0; k < p->ss_vanished.size() && e == hipSuccess; ++k) {
+    const int v = p->ss_vanished[k];
+    const SubChain &c = p->ss_chains[v];
+    e = launch_read(p->ss_mem + c.off, p->ss_stage + offs.back() + k, 0, nullptr, c.pend,
+                    renorm ? p->ss_sigma + v : nullptr, s);
+  }
+  if (e == hipSuccess) e = launch_cprod(p->ss_stage + offs.back(), (int)p->ss_vanished.size(), s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "sub-state read");
+  return OWQS_OK;
+}
+
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                      Profile *prof) {
+  if (p && substates(p)) {
+    if (prof) return refuse_substates(p, "owqs_run_profiled");
+    const size_t nin = p->inputs.size();
+    if (nin > OWQS_MAX_WIDTH) return fail(p->ctx, OWQS_E_WIDTH, "more inputs than OWQS_MAX_WIDTH: give them as factors");
+    if (n_amps != (size_t(1) << nin)) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
+    if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
+    const int32_t k = (int32_t)nin;
+    return run_substates(p, &input, &k, nin ? 1 : 0, input_on_device, stream);
+  }
   if (p && p->sampling) {
     if (prof) return fail(p->ctx, OWQS_E_STATE, "profiled runs take forced outcomes");
     return run_sampled(p, input, n_amps, input_on_device, stream);
   }
   if (!p) return OWQS_E_INVALID_ARG;
   const size_t nin = p->inputs.size();
+  if (owqs_status w = width_guard(p)) return w;
   const size_t want = size_t(1) << nin;
   if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
   if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
@@ -1082,6 +1526,7 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
     e = launch_lds_shared(proto, 1, p->plan_width, reduce, 0, 0, (size_t)p->n_meas, s);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "LDS run");
     p->ran = true;
+  p->ss_ran = false;
     p->out_in_order = true;
     p->batch_ran = false;
     p->ran_mode = reduce;
@@ -1129,6 +1574,7 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
     return hip_fail(p->ctx, e, "kernel launch");
   }
   p->ran = true;
+  p->ss_ran = false;
   p->batch_ran = false;
   p->ran_mode = reduce;
   if (prof) {
@@ -1360,7 +1806,7 @@ owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, 
 
 void owqs_pattern_destroy(owqs_pattern *p) {
   if (!p) return;
-  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem || p->s_mem) {
+  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem || p->s_mem || p->ss_mem) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->psi) (void)hipFree(p->psi);
@@ -1371,6 +1817,11 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   if (p->dev_fuse) (void)hipFree(p->dev_fuse);
   if (p->adj_mem) (void)hipFree(p->adj_mem);
   if (p->s_mem) (void)hipFree(p->s_mem);
+  if (p->ss_mem) (void)hipFree(p->ss_mem);
+  if (p->ss_sigma) (void)hipFree(p->ss_sigma);
+  if (p->ss_stage) (void)hipFree(p->ss_stage);
+  if (p->ss_exec) (void)hipGraphExecDestroy(p->ss_exec);
+  if (p->ss_graph) (void)hipGraphDestroy(p->ss_graph);
   if (p->s_exec) (void)hipGraphExecDestroy(p->s_exec);
   if (p->s_graph) (void)hipGraphDestroy(p->s_graph);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -1415,8 +1866,9 @@ owqs_status owqs_set_mode(owqs_pattern *p, owqs_mode mode) {
 }
 
 owqs_status owqs_set_exec(owqs_pattern *p, owqs_exec exec) {
-  if (!p || exec < OWQS_EXEC_PLAIN || exec > OWQS_EXEC_AUTO) return OWQS_E_INVALID_ARG;
+  if (!p || exec < OWQS_EXEC_PLAIN || exec > OWQS_EXEC_SUBSTATES) return OWQS_E_INVALID_ARG;
   if ((p->exec == OWQS_EXEC_PLAIN) != (exec == OWQS_EXEC_PLAIN)) p->dirty = true;
+  if ((p->exec == OWQS_EXEC_SUBSTATES) != (exec == OWQS_EXEC_SUBSTATES)) p->dirty = true;
   p->exec = exec;
   return OWQS_OK;
 }
@@ -1468,6 +1920,7 @@ owqs_status owqs_set_tile_bits(owqs_pattern *p, int32_t bits) {
 owqs_status owqs_tune(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                       int32_t *best_bits, float *best_ms) {
   if (!p) return OWQS_E_INVALID_ARG;
+  if (substates(p)) return refuse_substates(p, "owqs_tune");
   if (owqs_status w = width_guard(p)) return w;
   if (p->dirty) compile(p);
   // only plans with tile passes have a schedule to choose
@@ -1528,8 +1981,8 @@ owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps,
   if (owqs_status w = width_guard(p)) return w;
   if (p->dirty) compile(p);
   if (plan_width) *plan_width = p->plan_width;
-  if (nsteps) *nsteps = p->steps.size();
-  if (npasses) *npasses = p->xsteps.size();
+  if (nsteps) *nsteps = substates(p) ? p->ss_steps.size() : p->steps.size();
+  if (npasses) *npasses = substates(p) ? p->ss_steps.size() : p->xsteps.size();
   return OWQS_OK;
 }
 
@@ -1537,6 +1990,7 @@ static owqs_status run_shared(owqs_pattern *p, const void *in, uint32_t first, u
                               double *probs, void *stream, int basis_mode) {
   // every item runs the pattern's one command table in its own workgroup
   if (!p || !out) return OWQS_E_INVALID_ARG;
+  if (substates(p)) return refuse_substates(p, basis_mode ? "owqs_run_basis" : "owqs_run_states");
   if (count == 0) return OWQS_OK;
   if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context");
   if (basis_mode && (p->inputs.size() > 31 || uint64_t(first) + count > (uint64_t(1) << p->inputs.size())))
@@ -1569,6 +2023,7 @@ static owqs_status run_shared(owqs_pattern *p, const void *in, uint32_t first, u
   e = launch_lds_shared(proto, (int)count, p->plan_width, reduce, first, basis_mode, (size_t)p->n_meas, s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "LDS kernel");
   p->ran = false;  // the pattern's own state buffer was not written
+  p->ss_ran = false;
   p->batch_ran = true;
   return OWQS_OK;
 }
@@ -1607,6 +2062,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     owqs_pattern *p = pats[i];
     if (!p || p->ctx != ctx || !outputs[i]) return fail(ctx, OWQS_E_INVALID_ARG, "pattern " + std::to_string(i));
     if (!p->inputs.empty() && (!inputs || !inputs[i])) return fail(ctx, OWQS_E_INVALID_ARG, "null input");
+    if (substates(p)) return refuse_substates(p, "owqs_run_batch");
     if (owqs_status w = width_guard(p)) return w;
     if (p->dirty) compile(p);
     owqs_status st = ensure_device(p, p->plan_width > kLdsMaxWidth);
@@ -1627,6 +2083,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
       items.push_back(it);
       width = std::max(width, p->plan_width);
       p->ran = false;
+  p->ss_ran = false;
       p->batch_ran = true;
     } else {
       wide.push_back(i);
@@ -1716,6 +2173,7 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
   if (!p || !alpha || !loss || !grad || batch == 0 || (nobs && !obs) || nobs < 0)
     return fail(p ? p->ctx : nullptr, OWQS_E_INVALID_ARG, "null pointer or bad size");
   if (batch > 65535) return fail(p->ctx, OWQS_E_INVALID_ARG, "batch above 65535");
+  if (substates(p)) return refuse_substates(p, "owqs_adjoint");
   if (!p->inputs.empty() && !input_c64) return fail(p->ctx, OWQS_E_INVALID_ARG, "the pattern needs an input state");
   for (int32_t k = 0; k < nobs; ++k)
     if (obs[k] < 0 || obs[k] >= (int32_t)p->outputs.size())
@@ -1982,8 +2440,39 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
     return fail(p->ctx, OWQS_E_STATE, p->lk_ran ? "the last run was a ranged run: read it with owqs_read_live"
                                                 : "no run yet");
   const size_t nout = p->outputs.size();
+  if (nout > OWQS_MAX_WIDTH)
+    return fail(p->ctx, OWQS_E_WIDTH, "more outputs than OWQS_MAX_WIDTH: read the factors (owqs_read_substates)");
   if (n_amps != (size_t(1) << nout)) return fail(p->ctx, OWQS_E_INVALID_ARG, "output size must be 2^(outputs)");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->ss_ran) {
+    // the tensor product of the factors and the scalar, in output bit order
+    std::vector<uint64_t> offs;
+    owqs_status st = stage_substates(p, s, offs);
+    if (st != OWQS_OK) return st;
+    AssembleArgs aa{};
+    aa.nf = (int)p->ss_factors.size();
+    for (int f = 0; f < aa.nf; ++f) {
+      aa.off[f] = offs[f];
+      aa.mask[f] = p->ss_factors[f].mask;
+    }
+    aa.scalar_off = offs.back();
+    hipError_t e = hipSuccess;
+    float2 *dst = static_cast<float2 *>(out);
+    if (!out_on_device) {
+      if (!p->stage) {
+        e = hipMalloc(reinterpret_cast<void **>(&p->stage), n_amps * sizeof(float2));
+        if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "read staging buffer");
+      }
+      dst = p->stage;
+    }
+    e = launch_assemble(dst, (int)nout, p->ss_stage, aa, s);
+    if (e == hipSuccess && !out_on_device) {
+      e = hipMemcpyAsync(out, p->stage, n_amps * sizeof(float2), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+    return out_on_device ? OWQS_OK : owqs_check(p, stream);
+  }
   const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
   const int *where = p->sampled_ran ? p->s_final_where.data() : p->final_where.data();
   const double factor = p->sampled_ran ? p->s_final_factor : p->final_factor;
@@ -2010,6 +2499,65 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
   if (e == hipSuccess) e = hipMemcpyAsync(out, p->stage, n_amps * sizeof(float2), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "read");
+  return owqs_check(p, stream);
+}
+
+owqs_status owqs_set_input_factors(owqs_pattern *p, const int32_t *factor_nq, size_t nfactors) {
+  if (!p || (nfactors && !factor_nq)) return OWQS_E_INVALID_ARG;
+  size_t total = 0;
+  for (size_t k = 0; k < nfactors; ++k) {
+    if (factor_nq[k] < 1 || factor_nq[k] > OWQS_MAX_WIDTH)
+      return fail(p->ctx, OWQS_E_INVALID_ARG, "an input factor holds 1 .. OWQS_MAX_WIDTH qubits");
+    total += (size_t)factor_nq[k];
+  }
+  if (nfactors && total != p->inputs.size())
+    return fail(p->ctx, OWQS_E_INVALID_ARG, "input factors must cover the inputs");
+  std::vector<int32_t> want(factor_nq, factor_nq + nfactors);
+  if (nfactors == 1) want.clear();
+  if (want != p->ss_in_nq) {
+    p->ss_in_nq = want;
+    if (substates(p)) p->dirty = true;
+  }
+  return OWQS_OK;
+}
+
+owqs_status owqs_run_factors(owqs_pattern *p, const void *const *factors, const int32_t *factor_nq, size_t nfactors,
+                             int input_on_device, void *stream) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (!substates(p)) return fail(p->ctx, OWQS_E_STATE, "input factors need the sub-state executor (OWQS_EXEC_SUBSTATES)");
+  return run_substates(p, factors, factor_nq, nfactors, input_on_device, stream);
+}
+
+owqs_status owqs_read_substates(owqs_pattern *p, void *out_c64, size_t amp_cap, int32_t *factor_nq, int32_t *qubits,
+                                size_t factor_cap, int32_t *n_factors, size_t *n_amps, void *scalar_c64,
+                                void *stream) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (!p->ss_ran) return fail(p->ctx, OWQS_E_STATE, "the last run did not use the sub-state executor");
+  size_t amps = 0;
+  for (const SubFactor &f : p->ss_factors) amps += size_t(1) << f.qubits.size();
+  if (n_factors) *n_factors = (int32_t)p->ss_factors.size();
+  if (n_amps) *n_amps = amps;
+  if (factor_nq || qubits) {
+    if (factor_cap < p->ss_factors.size()) return fail(p->ctx, OWQS_E_INVALID_ARG, "factor arrays too small");
+    size_t k = 0;
+    for (size_t f = 0; f < p->ss_factors.size(); ++f) {
+      if (factor_nq) factor_nq[f] = (int32_t)p->ss_factors[f].qubits.size();
+      for (int q : p->ss_factors[f].qubits)
+        if (qubits) qubits[k++] = p->user_id[q];
+    }
+  }
+  if (!out_c64 && !scalar_c64) return OWQS_OK;
+  if (out_c64 && amp_cap < amps) return fail(p->ctx, OWQS_E_INVALID_ARG, "amplitude buffer too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<uint64_t> offs;
+  owqs_status st = stage_substates(p, s, offs);
+  if (st != OWQS_OK) return st;
+  hipError_t e = hipSuccess;
+  if (out_c64 && amps) e = hipMemcpyAsync(out_c64, p->ss_stage, amps * sizeof(float2), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && scalar_c64)
+    e = hipMemcpyAsync(scalar_c64, p->ss_stage + offs.back(), sizeof(float2), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(p->ctx, e, "sub-state read");
   return owqs_check(p, stream);
 }
 
@@ -2092,6 +2640,7 @@ owqs_status owqs_run_range(owqs_pattern *p, const void *input, size_t n_amps, in
   if (!p) return OWQS_E_INVALID_ARG;
   const size_t nc = p->cmds.size();
   if (cmd_begin > cmd_end || cmd_end > nc) return fail(p->ctx, OWQS_E_INVALID_ARG, "command range outside the pattern");
+  if (substates(p)) return refuse_substates(p, "owqs_run_range");
   owqs_status st = ensure_device(p);
   if (st != OWQS_OK) return st;
   if (p->dirty) compile(p);
@@ -2111,6 +2660,7 @@ owqs_status owqs_run_range(owqs_pattern *p, const void *input, size_t n_amps, in
     if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
     end_ranged(p);
     p->ran = false;
+  p->ss_ran = false;
     p->batch_ran = false;
     p->out_in_order = false;
     e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);

@@ -224,4 +224,27 @@ hipError_t launch_s_decide(const double *partials, unsigned nparts, const double
                            SigRef sg, SigRef tg, const int *dom, int *outc, float2 *coef, hipStream_t s);
 
 
+// ---- sub-state executor (owqs_substate.hip)
+constexpr int kMaxFactors = kWhereMax;  // factors of a read-out (each holds >= 1 output)
+// Read-out of a product state: factor f was read into stage[off[f] ..) with
+// its qubits in output order and owns the output bits mask[f]; the scalar
+// (product of the fully measured sub-states) is stage[scalar_off].
+struct AssembleArgs {
+  uint64_t off[kMaxFactors];
+  uint64_t mask[kMaxFactors];
+  uint64_t scalar_off;
+  int nf;
+};
+// sigma[0 .. nchains) = 1 and the error word cleared.
+hipError_t launch_sub_start(double *sigma, int nchains, int *err, hipStream_t s);
+// psi[0] = 1 (a sub-state with no qubit yet).
+hipError_t launch_sub_init(float2 *psi, hipStream_t s);
+// In place: base (2^a amplitudes, capacity 2^(a+b)) becomes base (x) top,
+// base's qubits on the low a bits; *sig_a *= *sig_b.  a, b >= 1.
+hipError_t launch_kron(float2 *base, int a, const float2 *top, int b, double *sig_a, const double *sig_b,
+                       hipStream_t s);
+// v[0] = v[0] v[1] ... v[count - 1] (count may be 0: v[0] = 1).
+hipError_t launch_cprod(float2 *v, int count, hipStream_t s);
+hipError_t launch_assemble(float2 *out, int nout, const float2 *stage, const AssembleArgs &a, hipStream_t s);
+
 }  // namespace owqs
