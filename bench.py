@@ -341,6 +341,70 @@ def bench_proa(owqs, torch, W, ctx, wl, steps):
     return res
 
 
+def bench_substates(owqs, torch, W, ctx, steps):
+    """Sub-state executor (Sec. 4.1): (1) three 16-qubit circuits side by side
+    (48 inputs and outputs, one vector would need 2^51 amplitudes), input as
+    three factors; (2) two 13-qubit circuits merged by one E at the end: a
+    2^13 x 2^13 tensor product (k_kron) timed with events."""
+    g = np.random.default_rng([160405659, 9, 0])
+    parts = [W.circuit_to_pattern(16, W.random_jcz_circuit(16, 400, 60, g)) for _ in range(3)]
+    pat_def = W.disjoint_union(parts)
+    outc = g.integers(0, 2, pat_def.n_meas()).astype(np.uint8)
+    ins = [torch.as_tensor(W.gaussian_state(16, g)).cuda() for _ in parts]
+    p = owqs.Pattern(ctx, pat_def)
+    p.set_exec(owqs.EXEC_SUBSTATES)
+    p.set_outcomes(outc)
+    p.run_factors(ins)
+    p.read_substates()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p.run_factors(ins)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    p.check()
+    nt = pat_def.nontrivial_count(outc)
+    res = {"components": {
+        "workload": "3 random J/CZ circuits of 16 logical qubits (400 J + 60 CZ each) side by side, "
+                    "inputs as 3 factors, OWQS",
+        "single_vector_live_width": pat_def.max_live(), "widest_substate": p.plan_info()[0],
+        "commands_nontrivial": nt, "ms_per_run": round(1e3 * t, 3), "commands_per_s": round(nt / t, 1)}}
+    p.close()
+    # one large merge: two 13-qubit path graph states (N and E only: each
+    # grows by prepares, no merge), then one E across them, a 2^13 x 2^13
+    # tensor product; no measurement
+    na = 13
+    cmds = []
+    for base in (0, 100):
+        for k in range(na):
+            cmds.append(("N", base + k))
+            if k:
+                cmds.append(("E", base + k - 1, base + k))
+    cmds.append(("E", 0, 100))
+    pat_def = W.Pattern([], [k for k in range(na)] + [100 + k for k in range(na)], cmds)
+    outc = np.zeros(0, np.uint8)
+    p = owqs.Pattern(ctx, pat_def)
+    p.set_exec(owqs.EXEC_SUBSTATES)
+    p.set_outcomes(outc)
+    p.run(None)
+    kr_ms, kr_bytes, n = 0.0, 0.0, 0
+    for _ in range(max(steps, 3)):
+        k = p.run_profiled(None).get("kron(merge)", {"ms": 0.0, "bytes": 0.0, "launches": 0})
+        kr_ms += k["ms"]
+        kr_bytes += k["bytes"]
+        n += k["launches"]
+    p.check()
+    avg_us = 1e3 * kr_ms / max(n, 1)
+    gbs = kr_bytes / max(kr_ms, 1e-12) / 1e6
+    res["merge"] = {"workload": f"two {na}-qubit path graph states, then one E across them: "
+                                f"a 2^{na} x 2^{na} tensor product (2^{2 * na} amplitudes written)",
+                    "kron_launches": n, "kron_avg_us": round(avg_us, 2),
+                    "kron_bytes_per_launch": kr_bytes / max(n, 1),
+                    "kron_GBs": round(gbs, 1), "kron_frac_of_8TBs": round(gbs / 8000.0, 4)}
+    p.close()
+    return res
+
+
 def bench_sampled(owqs, torch, pat, inp, out, n_nontriv, steps, warmup):
     """The same large pattern with its outcomes drawn on the device from seeded
     uniforms (plain plan, signals resolved on the GPU, replayed as a graph).
@@ -430,6 +494,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sampled", action="store_true")
+    ap.add_argument("--no-substates", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the extra event-timed step (for counter collection runs)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -446,6 +511,7 @@ def main():
         sys.exit(2)
     if args.only_plain:
         args.no_fused = args.no_batch = args.no_adjoint = args.no_sampled = args.no_cpu_baseline = True
+        args.no_substates = True
 
     import torch
     import owqs_workloads as W
@@ -551,6 +617,9 @@ def main():
         result["cluster"] = bench_cluster(owqs, torch, W, ctx, args.steps)
         log("[bench] small workload")
         result["small"] = bench_small(owqs, torch, W, ctx, args.steps)
+    if not args.no_substates:
+        log("[bench] sub-state executor")
+        result["substates"] = bench_substates(owqs, torch, W, ctx, args.steps)
     if not args.no_adjoint:
         log("[bench] differentiated workload")
         result["adjoint"] = bench_adjoint(owqs, torch, W, ctx, args.steps)

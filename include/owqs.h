@@ -112,8 +112,9 @@ typedef enum { OWQS_MODE_OWQS = 0, OWQS_MODE_EOWQS = 1, OWQS_MODE_EOWQS_CHECK = 
  * graph stays in separate components can be wider than the limit.  Runs
  * with owqs_run (the input as one sub-state) or owqs_run_factors; read with
  * owqs_read_state (the tensor product, if the outputs fit) or
- * owqs_read_substates.  Batches, basis runs, adjoints, ranged, profiled and
- * sampled runs and the tuner refuse it (OWQS_E_STATE).  The input state is
+ * owqs_read_substates.  Batches, basis runs, adjoints, ranged and sampled
+ * runs and the tuner refuse it (OWQS_E_STATE); profiled runs time each
+ * step (kinds N, E, M, X, Z, FINISH and KRON).  The input state is
  * taken to be normalised (each sub-state's p is relative to its own norm). */
 typedef enum {
   OWQS_EXEC_PLAIN = 0,
@@ -294,7 +295,8 @@ enum {
   OWQS_KIND_J = 5,      /* fused window N w; E u w; M u; X/Z w: 16 * 2^n */
   OWQS_KIND_FINISH = 6, /* one-block FP64 finish of an M/window probability (bytes not counted) */
   OWQS_KIND_TILE = 7,   /* a group of windows/E/X/Z steps in one pass: 16 * 2^n */
-  OWQS_NUM_KINDS = 8
+  OWQS_KIND_KRON = 8,   /* sub-state merge of 2^a and 2^b amplitudes: 8 (2^a + 2^b + 2^(a+b)) */
+  OWQS_NUM_KINDS = 9
 };
 
 /* As owqs_run, and also times every kernel of the run with HIP events

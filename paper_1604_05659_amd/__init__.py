@@ -43,8 +43,9 @@ E_INVALID_ARG, E_PATTERN, E_ZERO_PROB, E_WIDTH, E_NOMEM, E_HIP, E_NOT_DETERMINIS
 MODE_OWQS, MODE_EOWQS, MODE_EOWQS_CHECK = 0, 1, 2
 EXEC_PLAIN, EXEC_FUSED, EXEC_AUTO, EXEC_SUBSTATES = 0, 1, 2, 3
 OPS = {"N": 0, "E": 1, "M": 2, "X": 3, "Z": 4}
-KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)", 6: "finish(FP64)", 7: "tile(group)"}
-NUM_KINDS = 8
+KINDS = {0: "prepare(N)", 1: "cz(E)", 2: "measure(M)", 3: "pauli_x(X)", 4: "pauli_z(Z)", 5: "jwindow(NEMX)",
+         6: "finish(FP64)", 7: "tile(group)", 8: "kron(merge)"}
+NUM_KINDS = 9
 
 
 class OwqsCmd(ctypes.Structure):

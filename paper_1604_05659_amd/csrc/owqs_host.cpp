@@ -1305,10 +1305,15 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
 // ---------------------------------------------------------------------------
 // sub-state executor runs
 // ---------------------------------------------------------------------------
-hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s) {
+// With `ev`: ev[2i] before step i's main kernel, ev[2i+1] after it, ev[2i+2]
+// after the step (its FP64 finishing kernel, if any).
+hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev = nullptr) {
   hipError_t e = launch_sub_start(p->ss_sigma, (int)p->ss_chains.size(), p->book.err, s);
+  if (ev && e == hipSuccess) e = hipEventRecord((*ev)[0], s);
   for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
     const SubStep &x = p->ss_steps[i];
+    if (ev && i > 0) e = hipEventRecord((*ev)[2 * i], s);
+    if (e != hipSuccess) break;
     float2 *psi = p->ss_mem + p->ss_chains[x.chain].off;
     switch (x.kind) {
       case SS_INIT: e = launch_sub_init(psi, s); break;
@@ -1330,13 +1335,30 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s) {
         a.m_index = x.m_index;
         unsigned grid = 0;
         e = launch_measure(psi, x.n, x.b0, a, s, &grid);
+        if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
         if (e == hipSuccess) e = launch_finish(a, grid, s);
         break;
       }
       default: break;
     }
+    if (ev && x.kind != SS_M && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
+    if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
   }
   return e;
+}
+
+// Algorithmic bytes of one sub-state step (element level, complex64).
+double substep_bytes(const SubStep &x) {
+  const double a = std::ldexp(8.0, x.n);
+  switch (x.kind) {
+    case SS_N: return 2.0 * a;
+    case SS_E: return 0.5 * a;
+    case SS_M: return 1.5 * a;
+    case SS_X: return 2.0 * a;
+    case SS_Z: return 1.0 * a;
+    case SS_KRON: return a + std::ldexp(8.0, x.top_n) + std::ldexp(8.0, x.n + x.top_n);
+  }
+  return 0.0;
 }
 
 bool substates(const owqs_pattern *p) { return p->exec == OWQS_EXEC_SUBSTATES; }
@@ -1347,7 +1369,7 @@ owqs_status refuse_substates(owqs_pattern *p, const char *what) {
 
 // Input factor k (2^nqs[k] complex64) holds the next nqs[k] inputs.
 owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int32_t *nqs, size_t nf,
-                          int on_device, void *stream) {
+                          int on_device, void *stream, Profile *prof = nullptr) {
   if (nf && (!factors || !nqs)) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input factors");
   size_t total = 0;
   for (size_t k = 0; k < nf; ++k) {
@@ -1400,7 +1422,15 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
   const int reduce = p->mode == OWQS_MODE_OWQS ? kReduceRenorm
                      : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck
                                                         : kReduceNone;
-  if (p->use_graph) {
+  std::vector<hipEvent_t> ev;
+  if (prof) {
+    ev.resize(2 * p->ss_steps.size() + 1);
+    for (auto &x : ev) {
+      e = hipEventCreate(&x);
+      if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
+    }
+    e = launch_substeps(p, reduce, s, &ev);
+  } else if (p->use_graph) {
     if (p->ss_exec && p->ss_graph_reduce != reduce) drop_ss_graph(p);
     if (!p->ss_exec) {
       if (!p->cap_stream) {
@@ -1424,12 +1454,37 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
   } else {
     e = launch_substeps(p, reduce, s);
   }
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
+  if (e != hipSuccess) {
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return hip_fail(p->ctx, e, "kernel launch");
+  }
   p->ran = true;
   p->ss_ran = true;
   p->batch_ran = false;
   p->out_in_order = false;
   p->ran_mode = reduce;
+  if (prof) {
+    static const int kind_of[] = {-1, OWQS_KIND_N, OWQS_KIND_E, OWQS_KIND_X, OWQS_KIND_Z, OWQS_KIND_M,
+                                  OWQS_KIND_KRON};
+    e = hipStreamSynchronize(s);
+    for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
+      const SubStep &x = p->ss_steps[i];
+      float t = 0.f, f = 0.f;
+      e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * i + 1], ev[2 * i + 2]);
+      const int k = kind_of[x.kind];
+      if (k < 0) continue;  // a new sub-state's scalar 1
+      prof->counts[k] += 1;
+      prof->ms[k] += t;
+      prof->bytes[k] += substep_bytes(x);
+      if (x.kind == SS_M && reduce != kReduceNone) {
+        prof->counts[OWQS_KIND_FINISH] += 1;
+        prof->ms[OWQS_KIND_FINISH] += f;
+      }
+    }
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "profile events");
+  }
   return OWQS_OK;
 }
 
@@ -1478,13 +1533,12 @@ owqs_status stage_substates(owqs_pattern *p, hipStream_t s, std::vector<uint64_t
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
                      Profile *prof) {
   if (p && substates(p)) {
-    if (prof) return refuse_substates(p, "owqs_run_profiled");
     const size_t nin = p->inputs.size();
     if (nin > OWQS_MAX_WIDTH) return fail(p->ctx, OWQS_E_WIDTH, "more inputs than OWQS_MAX_WIDTH: give them as factors");
     if (n_amps != (size_t(1) << nin)) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
     if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
     const int32_t k = (int32_t)nin;
-    return run_substates(p, &input, &k, nin ? 1 : 0, input_on_device, stream);
+    return run_substates(p, &input, &k, nin ? 1 : 0, input_on_device, stream, prof);
   }
   if (p && p->sampling) {
     if (prof) return fail(p->ctx, OWQS_E_STATE, "profiled runs take forced outcomes");

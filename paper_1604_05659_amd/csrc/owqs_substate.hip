@@ -6,11 +6,10 @@
 // in place in the wider sub-state's region: with A (a qubits, lower bits) and
 // B (b qubits, upper bits),
 //   C[i + 2^a j] = A[i] B[j],   0 <= i < 2^a, 0 <= j < 2^b.
-// Each thread owns a pair of A's amplitudes: it reads them once, writes their
-// products with B[1 .. 2^b) (outside A's region, so nothing another thread
-// reads), and last overwrites its own pair with the products with B[0].  No
-// two threads touch the same element, so one kernel suffices.  The sub-state
-// scales multiply as well: sigma_C = sigma_A sigma_B (FP64, on the device).
+// The blocks j >= 1 lie outside A's region and are written in parallel over
+// (j, i) by one kernel, which only reads A; a second kernel then scales A's
+// own block by B[0].  The kernel boundary is the only ordering needed.  The
+// sub-state scales multiply as well: sigma_C = sigma_A sigma_B (FP64).
 //
 // The other commands of the executor reuse the single-vector kernels on a
 // sub-state's region with that sub-state's scale (see owqs_host.cpp).
@@ -21,6 +20,7 @@ namespace {
 
 constexpr int kB = 256;
 constexpr unsigned kCap = 4096;
+constexpr int kOwnUnitsLog2 = 19;  // 2^19 units of A: enough threads to stream the product alone
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -40,21 +40,67 @@ __global__ void k_sub_init(float2 *psi) {
   if (threadIdx.x == 0) psi[0] = make_float2(1.f, 0.f);
 }
 
-// In-place tensor product, a >= 1: units of two amplitudes of A.
-__global__ __launch_bounds__(kB) void k_kron(float2 *__restrict__ base, uint64_t units, int a,
-                                             const float2 *__restrict__ top, uint64_t ntop, double *sig_a,
-                                             const double *sig_b) {
+// In-place tensor product, a >= 1, first kernel: the blocks j >= 1,
+// C[i + 2^a j] = A[i] B[j], written outside A's region (which is only read).
+// A unit is two amplitudes of one block; consecutive threads take
+// consecutive units, so the stores of a wave are contiguous.  A is re-read
+// once per block j (from cache: it is the smaller read stream).
+__global__ __launch_bounds__(kB) void k_kron_hi(float2 *__restrict__ base, uint64_t units, int ah, int a,
+                                                const float2 *__restrict__ top) {
+  const uint64_t mask = (uint64_t(1) << ah) - 1;
+  for (uint64_t t = uint64_t(blockIdx.x) * (2 * kB) + threadIdx.x; t < units; t += uint64_t(gridDim.x) * (2 * kB)) {
+    const uint64_t t1 = t + kB;
+    const uint64_t u0 = t & mask, j0 = 1 + (t >> ah);
+    const uint64_t u1 = t1 & mask, j1 = 1 + (t1 >> ah);
+    const bool has1 = t1 < units;
+    const float4 v0 = *reinterpret_cast<const float4 *>(base + 2 * u0);
+    const float2 c0 = top[j0];
+    float4 v1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 c1 = make_float2(0.f, 0.f);
+    if (has1) {
+      v1 = *reinterpret_cast<const float4 *>(base + 2 * u1);
+      c1 = top[j1];
+    }
+    const float2 p00 = cmul(make_float2(v0.x, v0.y), c0), p01 = cmul(make_float2(v0.z, v0.w), c0);
+    *reinterpret_cast<float4 *>(base + 2 * u0 + (j0 << a)) = make_float4(p00.x, p00.y, p01.x, p01.y);
+    if (has1) {
+      const float2 p10 = cmul(make_float2(v1.x, v1.y), c1), p11 = cmul(make_float2(v1.z, v1.w), c1);
+      *reinterpret_cast<float4 *>(base + 2 * u1 + (j1 << a)) = make_float4(p10.x, p10.y, p11.x, p11.y);
+    }
+  }
+}
+
+// Wide A (2^(a-1) units fill the chip by themselves): one kernel, each
+// thread owning a unit of A.  It reads the unit once, writes its products
+// with B[1 .. 2^b) (outside A's region, which no thread writes yet), and last
+// overwrites the unit with its product with B[0]; no other thread reads it.
+__global__ __launch_bounds__(kB) void k_kron_own(float2 *__restrict__ base, uint64_t units, int a,
+                                                 const float2 *__restrict__ top, uint64_t ntop, double *sig_a,
+                                                 const double *sig_b) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *sig_a = *sig_a * *sig_b;  // no thread here reads sig_a
   for (uint64_t u = uint64_t(blockIdx.x) * kB + threadIdx.x; u < units; u += uint64_t(gridDim.x) * kB) {
     const float4 v = *reinterpret_cast<const float4 *>(base + 2 * u);
     const float2 v0 = make_float2(v.x, v.y), v1 = make_float2(v.z, v.w);
     for (uint64_t j = 1; j < ntop; ++j) {
-      const float2 t = top[j];
-      const float2 p0 = cmul(v0, t), p1 = cmul(v1, t);
+      const float2 c = top[j];
+      const float2 p0 = cmul(v0, c), p1 = cmul(v1, c);
       *reinterpret_cast<float4 *>(base + 2 * u + (j << a)) = make_float4(p0.x, p0.y, p1.x, p1.y);
     }
-    const float2 t0 = top[0];
-    const float2 p0 = cmul(v0, t0), p1 = cmul(v1, t0);
+    const float2 c = top[0];
+    const float2 p0 = cmul(v0, c), p1 = cmul(v1, c);
+    *reinterpret_cast<float4 *>(base + 2 * u) = make_float4(p0.x, p0.y, p1.x, p1.y);
+  }
+}
+
+// Second kernel (after the first on the same stream): block j = 0 in place,
+// A[i] B[0], and sigma_A *= sigma_B.
+__global__ __launch_bounds__(kB) void k_kron_lo(float2 *__restrict__ base, uint64_t units,
+                                                const float2 *__restrict__ top, double *sig_a, const double *sig_b) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sig_a = *sig_a * *sig_b;  // no thread here reads sig_a
+  const float2 c = top[0];
+  for (uint64_t u = uint64_t(blockIdx.x) * kB + threadIdx.x; u < units; u += uint64_t(gridDim.x) * kB) {
+    const float4 v = *reinterpret_cast<const float4 *>(base + 2 * u);
+    const float2 p0 = cmul(make_float2(v.x, v.y), c), p1 = cmul(make_float2(v.z, v.w), c);
     *reinterpret_cast<float4 *>(base + 2 * u) = make_float4(p0.x, p0.y, p1.x, p1.y);
   }
 }
@@ -118,9 +164,17 @@ hipError_t launch_sub_init(float2 *psi, hipStream_t s) {
 hipError_t launch_kron(float2 *base, int a, const float2 *top, int b, double *sig_a, const double *sig_b,
                        hipStream_t s) {
   if (a < 1 || b < 1 || a + b > kWhereMax) return hipErrorInvalidValue;
-  const uint64_t units = uint64_t(1) << (a - 1);
-  hipLaunchKernelGGL(k_kron, dim3(grid_of(units)), dim3(kB), 0, s, base, units, a, top, uint64_t(1) << b, sig_a,
-                     sig_b);
+  const uint64_t lo = uint64_t(1) << (a - 1);              // units of block 0
+  if (a - 1 >= kOwnUnitsLog2) {
+    hipLaunchKernelGGL(k_kron_own, dim3(grid_of(lo)), dim3(kB), 0, s, base, lo, a, top, uint64_t(1) << b, sig_a,
+                       sig_b);
+    return hipGetLastError();
+  }
+  const uint64_t hi = lo * ((uint64_t(1) << b) - 1);       // units of blocks 1 .. 2^b - 1
+  uint64_t g = (hi + 2 * kB - 1) / (2 * kB);
+  if (g > kCap) g = kCap;
+  hipLaunchKernelGGL(k_kron_hi, dim3(unsigned(g)), dim3(kB), 0, s, base, hi, a - 1, a, top);
+  hipLaunchKernelGGL(k_kron_lo, dim3(grid_of(lo)), dim3(kB), 0, s, base, lo, top, sig_a, sig_b);
   return hipGetLastError();
 }
 

@@ -218,3 +218,28 @@ def test_proa_order_of_the_cluster_as_substates(ctx):
     assert np.max(np.abs(got - want)) <= AMP_TOL
     re.close()
     src.close()
+
+
+@pytest.mark.parametrize("na,nb", [(6, 6), (13, 13), (20, 2), (19, 3)])
+def test_profiled_run_times_every_step(ctx, na, nb):
+    """Two path graph states merged by one E (both merge kernels: A below and
+    above 2^20 amplitudes): the profiled run reports one merge
+    (8 (2^a + 2^b + 2^(a+b)) bytes) and the state equals the oracle's."""
+    cmds = []
+    for base, n in ((0, na), (100, nb)):
+        for k in range(n):
+            cmds.append(("N", base + k))
+            if k:
+                cmds.append(("E", base + k - 1, base + k))
+    cmds.append(("E", na // 2, 100))
+    pat = W.Pattern([], list(range(na)) + [100 + k for k in range(nb)], cmds)
+    st, _ = so.run(pat, [], None)
+    p = owqs.Pattern(ctx, pat)
+    p.set_exec(owqs.EXEC_SUBSTATES)
+    prof = p.run_profiled(None)
+    assert prof["kron(merge)"]["launches"] == 1
+    assert prof["kron(merge)"]["bytes"] == 8 * (2 ** na + 2 ** nb + 2 ** (na + nb))
+    assert prof["prepare(N)"]["launches"] == na + nb
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - so.assemble(st, pat.outputs))) <= AMP_TOL
+    p.close()
