@@ -10,6 +10,8 @@ with the HIP library ``paper_1604_05659_amd`` and is never on its path.
 * ``oracle.substates`` -- sub-state execution: one vector per group of
                           entangled qubits, merged by tensor product on E
                           (Sec. 4.1, Sec. 4.4.1, Fig. 8).
+* ``oracle.gflow``     -- generalised flow of a pattern's open graph by
+                          exhaustive search (the EOWQS premise, Sec. 4.5).
 * ``oracle.reference`` -- independent numpy references: a full-tensor brute
                           force with projectors and no elimination, and a
                           J/CZ circuit simulator.
