@@ -296,6 +296,14 @@ def bench_cluster(owqs, torch, W, ctx, steps):
         p.check()
         res[name] = {"ms_per_run": round(1e3 * t, 3), "commands_per_s": round(nt / t, 1),
                      "plan_steps": p.plan_info()[1], "passes": p.plan_info()[2]}
+    t0 = time.perf_counter()
+    ok, first = p.certify()
+    t_cert = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ex, depth, _ = p.gflow()
+    t_gf = time.perf_counter() - t0
+    res["eowqs_certificate"] = {"all_certified": bool(ok.all()), "host_ms": round(1e3 * t_cert, 1),
+                                "gflow_exists": ex, "gflow_depth": depth, "gflow_host_ms": round(1e3 * t_gf, 1)}
     p.close()
     res["proa"] = bench_proa(owqs, torch, W, ctx, wl, steps)
     return res

@@ -454,6 +454,33 @@ typedef struct {
 owqs_status owqs_pattern_reorder(const owqs_pattern *pat, const owqs_proa_opts *opts,
                                  owqs_pattern **out, owqs_proa_stats *stats);
 
+/* EOWQS certificate for the pattern's own measurement order (Sec. 4.5).
+ * EOWQS takes every outcome probability to be 1/2.  For measurement i (XY
+ * plane) that is exact when some set K of non-input qubits, each measured
+ * after i or an output, has an odd neighbourhood in the entanglement graph
+ * (an edge per odd count of E's on a pair) that meets i and the qubits
+ * measured before i in exactly {i}: the set g(i) of a generalised flow
+ * (gflow, the paper's reference [13]) ordered like the pattern.  Then i's
+ * outcome is unbiased for any angles, input and earlier outcomes.  For each
+ * M in execution order witness[m] (NULL to skip; n_meas entries) is 1 when
+ * such K exists, found by elimination over GF(2); *n_certified counts them
+ * and *first_missing is the first m without one (-1 if none).  A pattern
+ * with every M certified runs exactly in EOWQS mode.  Host only. */
+owqs_status owqs_pattern_certify(const owqs_pattern *pat, uint8_t *witness, size_t n_meas,
+                                 int32_t *n_certified, int32_t *first_missing);
+
+/* Generalised flow of the pattern's open graph in any order (Sec. 4.5; the
+ * layered construction of a maximally delayed gflow, the paper's reference
+ * [25]): outputs are layer 0; round r adds every unadded qubit u for which
+ * the added non-input qubits hold a K whose odd neighbourhood meets the
+ * unadded qubits in exactly {u}.  *exists = 1 when every measured qubit gets
+ * a layer, *depth is then the number of rounds; layer[m] (NULL to skip;
+ * n_meas entries) is the layer of the m-th M's qubit, 0 when it got none.
+ * Measuring higher layers first is an order in which every M is certified.
+ * Host only. */
+owqs_status owqs_pattern_gflow(const owqs_pattern *pat, int32_t *exists, int32_t *depth, int32_t *layer,
+                               size_t n_meas);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,8 @@ _sig = {
                                              _i32p, _i32p, ctypes.POINTER(ctypes.c_size_t),
                                              ctypes.POINTER(ctypes.c_size_t)]),
     "owqs_pattern_reorder": (ctypes.c_int, [_vp, ctypes.c_void_p, ctypes.POINTER(_vp), ctypes.c_void_p]),
+    "owqs_pattern_certify": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint8), ctypes.c_size_t, _i32p, _i32p]),
+    "owqs_pattern_gflow": (ctypes.c_int, [_vp, _i32p, _i32p, _i32p, ctypes.c_size_t]),
     "owqs_set_input_factors": (ctypes.c_int, [_vp, _i32p, ctypes.c_size_t]),
     "owqs_run_factors": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _i32p, ctypes.c_size_t, ctypes.c_int, _vp]),
     "owqs_read_substates": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _i32p, ctypes.c_size_t, _i32p,
@@ -272,6 +274,24 @@ class Pattern:
         self.ctx.check(_lib.owqs_pattern_reorder(self._h, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(st)))
         return Pattern._from_handle(self.ctx, h), {"max_state_space": st.max_state_space,
                                                    "max_live": st.max_live, "alpha": st.alpha}
+
+    def certify(self):
+        """EOWQS certificate for this order (owqs_pattern_certify): per M,
+        whether a gflow witness exists; plus the first M without one (-1)."""
+        w = np.zeros(max(self.n_meas, 1), np.uint8)
+        nc, fm = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(_lib.owqs_pattern_certify(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                                 self.n_meas, ctypes.byref(nc), ctypes.byref(fm)))
+        return w[: self.n_meas].astype(bool), fm.value
+
+    def gflow(self):
+        """(exists, depth, layer of each M's qubit) of a maximally delayed gflow
+        of the open graph (owqs_pattern_gflow)."""
+        lay = np.zeros(max(self.n_meas, 1), np.int32)
+        ex, dp = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(_lib.owqs_pattern_gflow(self._h, ctypes.byref(ex), ctypes.byref(dp),
+                                               lay.ctypes.data_as(_i32p), self.n_meas))
+        return bool(ex.value), dp.value, lay[: self.n_meas].copy()
 
     def set_mode(self, mode: int):
         self.ctx.check(_lib.owqs_set_mode(self._h, int(mode)))
