@@ -413,6 +413,44 @@ def bench_substates(owqs, torch, W, ctx, steps):
     return res
 
 
+def bench_widths(owqs, torch, W, ctx):
+    """The plain kernels at live widths 24..28 (128 MiB .. 2 GiB of complex64):
+    at 2^24 and 2^25 the vector is close to the 256 MB Infinity Cache, so
+    wider runs show the HBM-only rate.  A short random J/CZ circuit per
+    width, profiled with events (element-level algorithmic bytes)."""
+    out = {}
+    for nl in (23, 24, 25, 26, 27):
+        g = np.random.default_rng([160405659, 10, 0, nl])
+        pat_def = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, 12, 4, g))
+        outc = g.integers(0, 2, pat_def.n_meas()).astype(np.uint8)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(nl)
+        re = torch.randn(1 << nl, device="cuda", generator=gen, dtype=torch.float32)
+        im = torch.randn(1 << nl, device="cuda", generator=gen, dtype=torch.float32)
+        inp = torch.complex(re, im)
+        inp /= torch.linalg.vector_norm(inp)
+        del re, im
+        p = owqs.Pattern(ctx, pat_def)
+        p.set_exec(owqs.EXEC_PLAIN)
+        p.set_outcomes(outc)
+        p.run(inp)
+        p.check()
+        prof = p.run_profiled(inp)
+        p.check()
+        row = {}
+        for k, name in (("measure(M)", "M"), ("prepare(N)", "N"), ("pauli_x(X)", "X"), ("cz(E)", "E")):
+            v = prof.get(k)
+            if v:
+                gbs = v["bytes"] / (v["ms"] / 1e3) / 1e9
+                row[name] = {"avg_us": round(1e3 * v["ms"] / v["launches"], 2), "GB/s": round(gbs, 1),
+                             "frac": round(gbs / 8000.0, 3)}
+        out[f"2^{nl + 1}"] = row
+        p.close()
+        del inp
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_sampled(owqs, torch, pat, inp, out, n_nontriv, steps, warmup):
     """The same large pattern with its outcomes drawn on the device from seeded
     uniforms (plain plan, signals resolved on the GPU, replayed as a graph).
@@ -503,6 +541,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-sampled", action="store_true")
     ap.add_argument("--no-substates", action="store_true")
+    ap.add_argument("--no-widths", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the extra event-timed step (for counter collection runs)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -520,6 +559,7 @@ def main():
     if args.only_plain:
         args.no_fused = args.no_batch = args.no_adjoint = args.no_sampled = args.no_cpu_baseline = True
         args.no_substates = True
+        args.no_widths = True
 
     import torch
     import owqs_workloads as W
@@ -625,6 +665,9 @@ def main():
         result["cluster"] = bench_cluster(owqs, torch, W, ctx, args.steps)
         log("[bench] small workload")
         result["small"] = bench_small(owqs, torch, W, ctx, args.steps)
+    if not args.no_widths:
+        log("[bench] plain kernels at widths 24..28")
+        result["widths"] = bench_widths(owqs, torch, W, ctx)
     if not args.no_substates:
         log("[bench] sub-state executor")
         result["substates"] = bench_substates(owqs, torch, W, ctx, args.steps)

@@ -45,6 +45,31 @@ __device__ __forceinline__ float4 ld4(const float2 *p, uint64_t i) {
 __device__ __forceinline__ void st4(float2 *p, uint64_t i, float4 v) {
   *reinterpret_cast<float4 *>(p + i) = v;
 }
+
+// Streaming forms with the non-temporal hint (loads and stores).  Measured on
+// MI355X: above the 256 MB Infinity Cache (live width >= 26) they lift N and
+// M from about 0.60 to 0.70 of HBM peak; at 2^24 and 2^25, where the next
+// kernel re-reads the vector from that cache, the plain forms are faster.
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <bool kNT>
+__device__ __forceinline__ float4 ldv(const float2 *p, uint64_t i) {
+  if (kNT) {
+    const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p + i));
+    return make_float4(x.x, x.y, x.z, x.w);
+  }
+  return ld4(p, i);
+}
+template <bool kNT>
+__device__ __forceinline__ void stv(float2 *p, uint64_t i, float4 v) {
+  if (kNT) {
+    const f4v x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4v *>(p + i));
+  } else {
+    st4(p, i, v);
+  }
+}
+constexpr int kNtWidthNM = 26;  // M at live width n >= 26, N producing width >= 26
+constexpr int kNtWidthX = 26;   // X at live width n >= 26 (at 25 the plain form measured faster)
 __device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
 __device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
 __device__ __forceinline__ float4 pack(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
@@ -155,18 +180,19 @@ __global__ void k_init(float2 *psi, DevBook book, int set_one) {
 }
 
 // N: psi[i + 2^n] = psi[i]; units of two amplitudes (n >= 1).
+template <bool kNT>
 __global__ __launch_bounds__(kBlock) void k_prepare(float2 *__restrict__ psi, uint64_t units, uint64_t dim) {
   GRID_STRIDE_UNITS(units) {
     float4 v[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint64_t u = base_ + uint64_t(k) * kBlock;
-      if (u < units) v[k] = ld4(psi, 2 * u);
+      if (u < units) v[k] = ldv<kNT>(psi, 2 * u);
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint64_t u = base_ + uint64_t(k) * kBlock;
-      if (u < units) st4(psi, 2 * u + dim, v[k]);
+      if (u < units) stv<kNT>(psi, 2 * u + dim, v[k]);
     }
   }
 }
@@ -212,6 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_cz_b0(float2 *__restrict__ psi, uint
 }
 
 // X on bit b >= 1: swap unit j with unit j + 2^b.
+template <bool kNT>
 __global__ __launch_bounds__(kBlock) void k_x_v(float2 *__restrict__ psi, uint64_t units, int b) {
   const uint64_t step = uint64_t(1) << b;
   GRID_STRIDE_UNITS(units) {
@@ -222,34 +249,35 @@ __global__ __launch_bounds__(kBlock) void k_x_v(float2 *__restrict__ psi, uint64
       const uint64_t u = base_ + uint64_t(k) * kBlock;
       j[k] = ins0(2 * u, b);
       if (u < units) {
-        x[k] = ld4(psi, j[k]);
-        y[k] = ld4(psi, j[k] + step);
+        x[k] = ldv<kNT>(psi, j[k]);
+        y[k] = ldv<kNT>(psi, j[k] + step);
       }
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint64_t u = base_ + uint64_t(k) * kBlock;
       if (u < units) {
-        st4(psi, j[k], y[k]);
-        st4(psi, j[k] + step, x[k]);
+        stv<kNT>(psi, j[k], y[k]);
+        stv<kNT>(psi, j[k] + step, x[k]);
       }
     }
   }
 }
 
 // X on bit 0: swap the two amplitudes inside every unit.
+template <bool kNT>
 __global__ __launch_bounds__(kBlock) void k_x_b0(float2 *__restrict__ psi, uint64_t units) {
   GRID_STRIDE_UNITS(units) {
     float4 v[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint64_t u = base_ + uint64_t(k) * kBlock;
-      if (u < units) v[k] = ld4(psi, 2 * u);
+      if (u < units) v[k] = ldv<kNT>(psi, 2 * u);
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const uint64_t u = base_ + uint64_t(k) * kBlock;
-      if (u < units) st4(psi, 2 * u, make_float4(v[k].z, v[k].w, v[k].x, v[k].y));
+      if (u < units) stv<kNT>(psi, 2 * u, make_float4(v[k].z, v[k].w, v[k].x, v[k].y));
     }
   }
 }
@@ -319,7 +347,7 @@ __global__ void k_small_cmd(float2 *psi, int n, int op, int b0, int b1) {
 // Each thread reads only the four (two) amplitudes it writes, so the update
 // is race-free in place.
 // ---------------------------------------------------------------------------
-template <int kCase>  // 0: b == t, 1: b == 0 < t, 2: 1 <= b < t
+template <int kCase, bool kNT>  // kCase 0: b == t, 1: b == 0 < t, 2: 1 <= b < t
 __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, uint64_t units, int b,
                                                      uint64_t half, MeasureArgs a) {
   const float f = scale_of(a);
@@ -335,10 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, ui
         const uint64_t u = base_ + uint64_t(k) * kBlock;
         j[k] = ins0(2 * u, b);
         if (u < units) {
-          A[k] = ld4(psi, j[k]);
-          B[k] = ld4(psi, j[k] + step);
-          C[k] = ld4(psi, j[k] + half);
-          D[k] = ld4(psi, j[k] + step + half);
+          A[k] = ldv<kNT>(psi, j[k]);
+          B[k] = ldv<kNT>(psi, j[k] + step);
+          C[k] = ldv<kNT>(psi, j[k] + half);
+          D[k] = ldv<kNT>(psi, j[k] + step + half);
         }
       }
 #pragma unroll
@@ -349,8 +377,8 @@ __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, ui
           const float2 o1 = axpc(hi2(A[k]), c, hi2(B[k]), f);
           const float2 o2 = axpc(lo2(C[k]), c, lo2(D[k]), f);
           const float2 o3 = axpc(hi2(C[k]), c, hi2(D[k]), f);
-          st4(psi, j[k], pack(o0, o1));
-          st4(psi, j[k] + step, pack(o2, o3));
+          stv<kNT>(psi, j[k], pack(o0, o1));
+          stv<kNT>(psi, j[k] + step, pack(o2, o3));
           acc += nrm2(o0) + nrm2(o1) + nrm2(o2) + nrm2(o3);
         }
       }
@@ -360,8 +388,8 @@ __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, ui
       for (int k = 0; k < kUnroll; ++k) {
         const uint64_t u = base_ + uint64_t(k) * kBlock;
         if (u < units) {
-          X[k] = ld4(psi, 2 * u);
-          Y[k] = ld4(psi, 2 * u + half);
+          X[k] = ldv<kNT>(psi, 2 * u);
+          Y[k] = ldv<kNT>(psi, 2 * u + half);
         }
       }
 #pragma unroll
@@ -376,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_measure(float2 *__restrict__ psi, ui
             o0 = axpc(lo2(X[k]), c, hi2(X[k]), f);
             o1 = axpc(lo2(Y[k]), c, hi2(Y[k]), f);
           }
-          st4(psi, 2 * u, pack(o0, o1));
+          stv<kNT>(psi, 2 * u, pack(o0, o1));
           acc += nrm2(o0) + nrm2(o1);
         }
       }
@@ -521,7 +549,10 @@ hipError_t launch_prepare(float2 *psi, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_prepare_scalar, dim3(1), dim3(1), 0, s, psi);
   } else {
     const uint64_t units = uint64_t(1) << (n - 1);
-    hipLaunchKernelGGL(k_prepare, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, uint64_t(1) << n);
+    if (n + 1 >= kNtWidthNM)
+      hipLaunchKernelGGL(k_prepare<true>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, uint64_t(1) << n);
+    else
+      hipLaunchKernelGGL(k_prepare<false>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, uint64_t(1) << n);
   }
   return hipGetLastError();
 }
@@ -545,10 +576,16 @@ hipError_t launch_pauli_x(float2 *psi, int n, int b, hipStream_t s) {
     hipLaunchKernelGGL(k_small_cmd, dim3(1), dim3(64), 0, s, psi, n, 3, b, 0);
   } else if (b >= 1) {
     const uint64_t units = uint64_t(1) << (n - 2);
-    hipLaunchKernelGGL(k_x_v, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, b);
+    if (n >= kNtWidthX)
+      hipLaunchKernelGGL(k_x_v<true>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, b);
+    else
+      hipLaunchKernelGGL(k_x_v<false>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units, b);
   } else {
     const uint64_t units = uint64_t(1) << (n - 1);
-    hipLaunchKernelGGL(k_x_b0, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units);
+    if (n >= kNtWidthX)
+      hipLaunchKernelGGL(k_x_b0<true>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units);
+    else
+      hipLaunchKernelGGL(k_x_b0<false>, dim3(grid_for(units)), dim3(kBlock), 0, s, psi, units);
   }
   return hipGetLastError();
 }
@@ -581,15 +618,24 @@ hipError_t launch_measure(float2 *psi, int n, int b, const MeasureArgs &a, hipSt
   } else if (b == t) {
     const uint64_t units = uint64_t(1) << (n - 2);
     g = grid_for(units);
-    hipLaunchKernelGGL(k_measure<0>, dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    if (n >= kNtWidthNM)
+      hipLaunchKernelGGL((k_measure<0, true>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    else
+      hipLaunchKernelGGL((k_measure<0, false>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
   } else if (b == 0) {
     const uint64_t units = uint64_t(1) << (n - 2);
     g = grid_for(units);
-    hipLaunchKernelGGL(k_measure<1>, dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    if (n >= kNtWidthNM)
+      hipLaunchKernelGGL((k_measure<1, true>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    else
+      hipLaunchKernelGGL((k_measure<1, false>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
   } else {
     const uint64_t units = uint64_t(1) << (n - 3);
     g = grid_for(units);
-    hipLaunchKernelGGL(k_measure<2>, dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    if (n >= kNtWidthNM)
+      hipLaunchKernelGGL((k_measure<2, true>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
+    else
+      hipLaunchKernelGGL((k_measure<2, false>), dim3(g), dim3(kBlock), 0, s, psi, units, b, half, a);
   }
   *grid = g;
   return hipGetLastError();

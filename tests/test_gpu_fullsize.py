@@ -109,3 +109,22 @@ def test_full_pattern_then_inverse_returns_input(ctx, large, parity_report):
         assert err <= AMP_TOL, err
         assert one_minus_f <= 1e-8, one_minus_f
         assert np.max(np.abs(probs - 0.5)) <= 1e-5
+
+
+@pytest.mark.parametrize("nl", [25, 26])
+def test_plain_kernels_above_the_cache_against_oracle(ctx, nl, parity_report):
+    """Live widths nl <-> nl + 1 (2^26 and 2^27 amplitudes, above the 256 MB
+    Infinity Cache), where N, M and X stream with the non-temporal hint: a
+    short circuit element by element against the FP64 oracle."""
+    g = np.random.default_rng([160405659, 11, 0, nl])
+    pat = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, 4, 2, g))
+    outc = g.integers(0, 2, pat.n_meas()).astype(np.uint8)
+    inp = W.gaussian_state(nl, g)
+    print(f"[fullsize] width {nl}<->{nl + 1}, {len(pat.cmds)} commands", flush=True)
+    got, probs = _run(ctx, pat, outc, torch.as_tensor(inp).cuda(), owqs.EXEC_PLAIN)
+    got = got.cpu().numpy().astype(np.complex128)
+    want, pw = oc.run(pat, outc, inp.astype(np.complex128))
+    err = float(np.max(np.abs(got - want)))
+    parity_report(f"plain kernels at 2^{nl + 1}", max_err=err, infidelity=1 - _fidelity(got, want))
+    assert err <= AMP_TOL
+    np.testing.assert_allclose(probs, pw, atol=1e-5)
