@@ -228,6 +228,91 @@ __device__ __forceinline__ float window_any(bool masked, bool sw, char *lds, uin
             : window_pass<false, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, 0u, 0u);
 }
 
+// A window's per-tile parameters: the tile-constant signs and the folded
+// corrections resolved into fa, fb, fc0 and the sign of t in o1.
+struct WinP {
+  float fa, fb;
+  float2 fc0;
+  uint32_t rsign;
+  int lb, widx;
+  bool sw;
+};
+
+__device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, double sg, const TileArgs &ta) {
+  WinP w;
+  const float f = float((op.flags & 16u) ? sg * op.f : double(op.f));
+  w.sw = op.flags & 1u;
+  float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
+  if (op.flags & 2u) { if (w.sw) fb = -fb; else fa = -fa; }
+  if (op.flags & 4u) { if (w.sw) fa = -fa; else fb = -fb; }
+  float2 cw = make_float2(op.coef.x, op.coef.y);
+  if (ta.coefs) cw = set_coef(ta, op.m_index);
+  const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
+  w.fa = fa;
+  w.fb = fb;
+  w.fc0 = make_float2(fa * c0.x, fa * c0.y);
+  // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
+  const bool s1neg = !(op.flags & 8u);
+  w.rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
+  w.lb = op.lb;
+  w.widx = op.widx;
+  return w;
+}
+
+// An unmasked window on one pair in registers (a: bit lb = 0, b: bit lb = 1).
+template <bool kSw>
+__device__ __forceinline__ void win_apply(const WinP &w, float2 &a, float2 &b) {
+  const float2 t = make_float2(w.fc0.x * b.x - w.fc0.y * b.y, w.fc0.x * b.y + w.fc0.y * b.x);
+  const float2 p0 = make_float2(fmaf(w.fa, a.x, t.x), fmaf(w.fa, a.y, t.y));
+  const float2 te = xsign2(t, w.rsign);
+  const float2 p1 = make_float2(fmaf(w.fb, a.x, te.x), fmaf(w.fb, a.y, te.y));
+  a = kSw ? p1 : p0;
+  b = kSw ? p0 : p1;
+}
+
+__device__ __forceinline__ float nrm4(float2 a, float2 b, float2 c, float2 d) {
+  return a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y + d.x * d.x + d.y * d.y;
+}
+
+// Two consecutive unmasked windows A, B on different local bits in one LDS
+// pass: each thread takes quads of elements (all values of the two bits),
+// applies A to its two pairs, then B to its two pairs, in registers.  Half
+// the LDS traffic and barriers of two passes.
+template <bool kAcc, bool kSwA, bool kSwB, int kTB, int kT>
+__device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
+                                            float &acc_b) {
+  constexpr int kQuads = (1 << kTB) / kT / 4;
+  const int lo = A.lb < B.lb ? A.lb : B.lb, hi = A.lb < B.lb ? B.lb : A.lb;
+  const uint32_t ba = 8u << A.lb, bb = 8u << B.lb;
+#pragma unroll
+  for (int r = 0; r < kQuads; ++r) {
+    const uint32_t e = ins0u(ins0u(tid + uint32_t(r) * kT, lo), hi) << 3;
+    float2 x00 = at(lds, e), x10 = at(lds, e | ba), x01 = at(lds, e | bb), x11 = at(lds, e | ba | bb);
+    win_apply<kSwA>(A, x00, x10);
+    win_apply<kSwA>(A, x01, x11);
+    if (kAcc) acc_a += nrm4(x00, x10, x01, x11);
+    win_apply<kSwB>(B, x00, x01);
+    win_apply<kSwB>(B, x10, x11);
+    if (kAcc) acc_b += nrm4(x00, x10, x01, x11);
+    at(lds, e) = x00;
+    at(lds, e | ba) = x10;
+    at(lds, e | bb) = x01;
+    at(lds, e | ba | bb) = x11;
+  }
+}
+
+template <bool kAcc, int kTB, int kT>
+__device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
+                                                float &acc_b) {
+  if (A.sw) {
+    if (B.sw) window_pair<kAcc, true, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair<kAcc, true, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+  } else {
+    if (B.sw) window_pair<kAcc, false, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair<kAcc, false, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+  }
+}
+
 // kTB = tile bits (ta.k).  Global memory <-> LDS: each thread moves
 // kPer = 2^kTB / kT amplitudes per tile, all loads issued before the first
 // LDS store (and all LDS reads before the first global store), so the memory
@@ -284,6 +369,26 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     __syncthreads();
     for (int o = 0; o < ta.nops; ++o) {
       const FuseOp op = load_op(ops, o);
+      if (op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 1 < ta.nops) {
+        const FuseOp nx = load_op(ops, o + 1);
+        if (nx.kind == DK_J && (nx.lmask_b | nx.lmask_o1) == 0 && nx.lb != op.lb) {
+          const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
+          float acc_a = 0.f, acc_b = 0.f;
+          if (reduce) {
+            window_pair_any<true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+            const double da = wave_sum_to_last(acc_a), db = wave_sum_to_last(acc_b);
+            if (lane == 63) {
+              wacc[A.widx][wave] += da;
+              wacc[B.widx][wave] += db;
+            }
+          } else {
+            window_pair_any<false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+          }
+          __syncthreads();
+          ++o;
+          continue;
+        }
+      }
       if (op.kind == DK_E || op.kind == DK_Z) {
         if ((ob & op.omask_b) == op.omask_b) diag_flip<kTB, kT>(lds, tid, op.lmask_b);
       } else if (op.kind == DK_X) {
