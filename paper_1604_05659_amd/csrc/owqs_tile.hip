@@ -313,6 +313,60 @@ __device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const W
   }
 }
 
+// Three consecutive unmasked windows A, B, C on three different local bits:
+// octets of elements (all values of the three bits) in registers, each
+// window applied to its four pairs in turn; one LDS round for three commands.
+template <bool kAcc, bool kSwA, bool kSwB, bool kSwC, int kTB, int kT>
+__device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const WinP &A, const WinP &B, const WinP &C,
+                                              float *acc) {
+  constexpr int kOcts = (1 << kTB) / kT / 8;
+  int b0 = A.lb, b1 = B.lb, b2 = C.lb;  // sorted copy for the zero insertions
+  if (b0 > b1) { const int t = b0; b0 = b1; b1 = t; }
+  if (b1 > b2) { const int t = b1; b1 = b2; b2 = t; }
+  if (b0 > b1) { const int t = b0; b0 = b1; b1 = t; }
+  const uint32_t ba = 8u << A.lb, bb = 8u << B.lb, bc = 8u << C.lb;
+#pragma unroll
+  for (int r = 0; r < kOcts; ++r) {
+    const uint32_t e = ins0u(ins0u(ins0u(tid + uint32_t(r) * kT, b0), b1), b2) << 3;
+    float2 x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u));
+    win_apply<kSwA>(A, x[0], x[1]);
+    win_apply<kSwA>(A, x[2], x[3]);
+    win_apply<kSwA>(A, x[4], x[5]);
+    win_apply<kSwA>(A, x[6], x[7]);
+    if (kAcc) acc[0] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
+    win_apply<kSwB>(B, x[0], x[2]);
+    win_apply<kSwB>(B, x[1], x[3]);
+    win_apply<kSwB>(B, x[4], x[6]);
+    win_apply<kSwB>(B, x[5], x[7]);
+    if (kAcc) acc[1] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
+    win_apply<kSwC>(C, x[0], x[4]);
+    win_apply<kSwC>(C, x[1], x[5]);
+    win_apply<kSwC>(C, x[2], x[6]);
+    win_apply<kSwC>(C, x[3], x[7]);
+    if (kAcc) acc[2] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u)) = x[q];
+  }
+}
+
+template <bool kAcc, int kTB, int kT>
+__device__ __forceinline__ void window_triple_any(char *lds, uint32_t tid, const WinP &A, const WinP &B,
+                                                  const WinP &C, float *acc) {
+  const int sel = (A.sw ? 1 : 0) | (B.sw ? 2 : 0) | (C.sw ? 4 : 0);
+  switch (sel) {
+    case 0: window_triple<kAcc, false, false, false, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 1: window_triple<kAcc, true, false, false, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 2: window_triple<kAcc, false, true, false, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 3: window_triple<kAcc, true, true, false, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 4: window_triple<kAcc, false, false, true, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 5: window_triple<kAcc, true, false, true, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 6: window_triple<kAcc, false, true, true, kTB, kT>(lds, tid, A, B, C, acc); break;
+    default: window_triple<kAcc, true, true, true, kTB, kT>(lds, tid, A, B, C, acc); break;
+  }
+}
+
 // kTB = tile bits (ta.k).  Global memory <-> LDS: each thread moves
 // kPer = 2^kTB / kT amplitudes per tile, all loads issued before the first
 // LDS store (and all LDS reads before the first global store), so the memory
@@ -369,6 +423,28 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     __syncthreads();
     for (int o = 0; o < ta.nops; ++o) {
       const FuseOp op = load_op(ops, o);
+      if (op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
+        const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
+        if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
+            n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
+          const WinP A = prep_window(op, ob, sg, ta), B = prep_window(n1, ob, sg, ta), C = prep_window(n2, ob, sg, ta);
+          float acc[3] = {0.f, 0.f, 0.f};
+          if (reduce) {
+            window_triple_any<true, kTB, kT>(lds, tid, A, B, C, acc);
+            const double da = wave_sum_to_last(acc[0]), db = wave_sum_to_last(acc[1]), dc = wave_sum_to_last(acc[2]);
+            if (lane == 63) {
+              wacc[A.widx][wave] += da;
+              wacc[B.widx][wave] += db;
+              wacc[C.widx][wave] += dc;
+            }
+          } else {
+            window_triple_any<false, kTB, kT>(lds, tid, A, B, C, acc);
+          }
+          __syncthreads();
+          o += 2;
+          continue;
+        }
+      }
       if (op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 1 < ta.nops) {
         const FuseOp nx = load_op(ops, o + 1);
         if (nx.kind == DK_J && (nx.lmask_b | nx.lmask_o1) == 0 && nx.lb != op.lb) {
