@@ -114,6 +114,7 @@ struct TileArgs {
   const float2 *coefs;
   int nsets;
   int n, k, nops, nwin;
+  int runs;          // 1: some consecutive unmasked windows run in registers (see k_tile)
   uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
 };

@@ -374,7 +374,9 @@ __device__ __forceinline__ void window_triple_any(char *lds, uint32_t tid, const
 // whose outer bits are `ob` sits at global index ob | pdep(e, tmask); with
 // e = tid + r kT that is ob | pdep(tid, tmask) | (a uniform part from r).
 // Every command of the group is then one pass over the tile in LDS.
-template <int kTB>
+// kRuns: the run-in-registers paths are compiled in (they raise the VGPR
+// count, which lowers occupancy for groups that cannot use them).
+template <int kTB, bool kRuns>
 __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__ psi, TileArgs ta,
                                                             const FuseOp *__restrict__ ops, MeasureArgs ma,
                                                             double *__restrict__ partials) {
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     __syncthreads();
     for (int o = 0; o < ta.nops; ++o) {
       const FuseOp op = load_op(ops, o);
-      if (op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
+      if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
         const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
         if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
             n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
           continue;
         }
       }
-      if (op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 1 < ta.nops) {
+      if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 1 < ta.nops) {
         const FuseOp nx = load_op(ops, o + 1);
         if (nx.kind == DK_J && (nx.lmask_b | nx.lmask_o1) == 0 && nx.lb != op.lb) {
           const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
@@ -723,12 +725,18 @@ unsigned tile_grid(const TileArgs &ta) {
 
 hipError_t tile_prepare() {
   hipError_t e = hipSuccess;
-  const void *fns[] = {reinterpret_cast<const void *>(k_tile<10>), reinterpret_cast<const void *>(k_tile<11>),
-                       reinterpret_cast<const void *>(k_tile<12>), reinterpret_cast<const void *>(k_tile<13>)};
+  const void *fns[] = {reinterpret_cast<const void *>(k_tile<10, false>),
+                       reinterpret_cast<const void *>(k_tile<11, false>),
+                       reinterpret_cast<const void *>(k_tile<12, false>),
+                       reinterpret_cast<const void *>(k_tile<13, false>)};
+  const void *fnr[] = {reinterpret_cast<const void *>(k_tile<10, true>), reinterpret_cast<const void *>(k_tile<11, true>),
+                       reinterpret_cast<const void *>(k_tile<12, true>), reinterpret_cast<const void *>(k_tile<13, true>)};
   const void *rev[] = {reinterpret_cast<const void *>(k_tile_rev<10>), reinterpret_cast<const void *>(k_tile_rev<11>),
                        reinterpret_cast<const void *>(k_tile_rev<12>), reinterpret_cast<const void *>(k_tile_rev<13>)};
   for (int i = 0; i < 4 && e == hipSuccess; ++i) {
     e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(fnr[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
     if (e == hipSuccess)
       e = hipFuncSetAttribute(rev[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(2 * sizeof(float2) << (10 + i)));
   }
@@ -740,10 +748,22 @@ hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const
   const size_t bytes = sizeof(float2) << ta.k;
   const unsigned g = tile_grid(ta);
   switch (ta.k) {
-    case 10: hipLaunchKernelGGL(k_tile<10>, dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 11: hipLaunchKernelGGL(k_tile<11>, dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 12: hipLaunchKernelGGL(k_tile<12>, dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials); break;
-    case 13: hipLaunchKernelGGL(k_tile<13>, dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials); break;
+    case 10:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<10, true>), dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials);
+      else hipLaunchKernelGGL((k_tile<10, false>), dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials);
+      break;
+    case 11:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<11, true>), dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials);
+      else hipLaunchKernelGGL((k_tile<11, false>), dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials);
+      break;
+    case 12:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<12, true>), dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials);
+      else hipLaunchKernelGGL((k_tile<12, false>), dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials);
+      break;
+    case 13:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<13, true>), dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials);
+      else hipLaunchKernelGGL((k_tile<13, false>), dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials);
+      break;
     default: return hipErrorInvalidValue;
   }
   *grid = g;
@@ -761,10 +781,22 @@ hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta0, const FuseOp *ops,
   const size_t bytes = sizeof(float2) << ta.k;
   const dim3 grid(tile_grid(ta), unsigned(nsets));
   switch (ta.k) {
-    case 10: hipLaunchKernelGGL(k_tile<10>, grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr); break;
-    case 11: hipLaunchKernelGGL(k_tile<11>, grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr); break;
-    case 12: hipLaunchKernelGGL(k_tile<12>, grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr); break;
-    case 13: hipLaunchKernelGGL(k_tile<13>, grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr); break;
+    case 10:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<10, true>), grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr);
+      else hipLaunchKernelGGL((k_tile<10, false>), grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr);
+      break;
+    case 11:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<11, true>), grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr);
+      else hipLaunchKernelGGL((k_tile<11, false>), grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr);
+      break;
+    case 12:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<12, true>), grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr);
+      else hipLaunchKernelGGL((k_tile<12, false>), grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr);
+      break;
+    case 13:
+      if (ta.runs) hipLaunchKernelGGL((k_tile<13, true>), grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr);
+      else hipLaunchKernelGGL((k_tile<13, false>), grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
