@@ -243,3 +243,32 @@ def test_profiled_run_times_every_step(ctx, na, nb):
     got = p.read_state().cpu().numpy().astype(np.complex128)
     assert np.max(np.abs(got - so.assemble(st, pat.outputs))) <= AMP_TOL
     p.close()
+
+
+@pytest.mark.parametrize("case", ["identity", "permuted", "all_measured", "fresh_outputs", "empty"])
+def test_degenerate_patterns(ctx, case):
+    """No commands (the input factors are the output, in output order), every
+    qubit measured (one amplitude: the scalar), outputs never entangled
+    (one |+> factor each), and the empty pattern (the scalar 1)."""
+    g = np.random.default_rng(4901)
+    if case == "identity":
+        pat, factors, outc = W.Pattern([0, 1, 2], [0, 1, 2], []), [([0, 1], None), ([2], None)], []
+    elif case == "permuted":
+        pat, factors, outc = W.Pattern([0, 1, 2], [2, 0, 1], []), [([0], None), ([1, 2], None)], []
+    elif case == "all_measured":
+        pat = W.Pattern([0], [], [("N", 1), ("E", 0, 1), ("M", 0, 0.7, (), ()), ("N", 2), ("M", 1, 1.3, (0,), ()),
+                                  ("M", 2, 0.2, (), ())])
+        factors, outc = [([0], None)], [1, 0, 1]
+    elif case == "fresh_outputs":
+        pat = W.Pattern([], [3, 4], [("N", 3), ("N", 5), ("N", 4), ("M", 5, 0.4, (), ()), ("Z", 3, (5,))])
+        factors, outc = [], [1]
+    else:
+        pat, factors, outc = W.Pattern([], [], []), [], []
+    factors = [(qs, W.gaussian_state(len(qs), g).astype(np.complex64).astype(np.complex128)) for qs, _ in factors]
+    st, pw = so.run(pat, outc, factors or None)
+    p = run_sub(ctx, pat, outc, factors)
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - so.assemble(st, pat.outputs))) <= AMP_TOL
+    np.testing.assert_allclose(p.read_probs(), pw, atol=P_TOL)
+    compare_factors(p, st, pat)
+    p.close()
