@@ -600,7 +600,8 @@ def random_standard_pattern(g: np.random.Generator, n_qubits: int = 9, n_in: int
 
 def disjoint_union(patterns: Sequence[Pattern], offset: int = 1000, name: str = "") -> Pattern:
     """Several patterns side by side on disjoint qubits (pattern k's ids plus
-    k * offset), their commands interleaved one by one; inputs and outputs
+    k * offset), interleaved chunk by chunk (a chunk ends after an M and the
+    corrections right after it, e.g. one J gate); inputs and outputs
     concatenated in pattern order.  The entanglement graph has at least one
     component per pattern, so the state stays a product across them."""
     shifted = []
@@ -621,9 +622,22 @@ def disjoint_union(patterns: Sequence[Pattern], offset: int = 1000, name: str = 
         shifted.append(cm)
         ins += [q + d for q in pat.inputs]
         outs += [q + d for q in pat.outputs]
+    chunked = []
+    for cm in shifted:
+        chunks, cur = [], []
+        for k, c in enumerate(cm):
+            cur.append(c)
+            nxt = cm[k + 1] if k + 1 < len(cm) else None
+            if c[0] in ("M", "X", "Z") and not (nxt and nxt[0] in ("X", "Z")):
+                if any(x[0] == "M" for x in cur):
+                    chunks.append(cur)
+                    cur = []
+        if cur:
+            chunks.append(cur)
+        chunked.append(chunks)
     cmds = []
-    for i in range(max((len(c) for c in shifted), default=0)):
-        for cm in shifted:
-            if i < len(cm):
-                cmds.append(cm[i])
+    for i in range(max((len(c) for c in chunked), default=0)):
+        for chunks in chunked:
+            if i < len(chunks):
+                cmds.extend(chunks[i])
     return Pattern(ins, outs, cmds, name or "disjoint")

@@ -68,7 +68,7 @@ struct TileGroup {
 // Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's
 // region of the arena, kept by the sub-state that is the base of every merge
 // it takes part in.
-enum SubKind : int { SS_INIT = 0, SS_N = 1, SS_E = 2, SS_X = 3, SS_Z = 4, SS_M = 5, SS_KRON = 6 };
+enum SubKind : int { SS_INIT = 0, SS_N = 1, SS_E = 2, SS_X = 3, SS_Z = 4, SS_M = 5, SS_KRON = 6, SS_J = 7 };
 
 struct SubStep {
   int kind;
@@ -76,9 +76,10 @@ struct SubStep {
   int n;             // its width before the step
   int b0, b1;        // slots
   int top, top_n;    // SS_KRON: the sub-state merged in, and its width
-  float2 coef;       // SS_M: (-1)^o e^{-i theta}
+  float2 coef;       // SS_M, SS_J: (-1)^o e^{-i theta}
   double host_factor;
   int m_index;
+  Window win;        // SS_J: the fused window N w; E's; M v; X/Z on w
 };
 
 struct SubChain {
@@ -675,7 +676,87 @@ void compile_substates(owqs_pattern *p) {
     return c;
   };
   int m = 0;
-  for (const Cmd &c : p->cmds) {
+  auto m_coef = [&](const Cmd &c, int mi, int &o) {
+    const int sgn = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
+    const double theta = (sgn ? -p->angles[mi] : p->angles[mi]) + (t ? M_PI : 0.0);  // Eq. 2
+    o = p->outcomes[mi] & 1;
+    double cr = std::cos(theta), ci = -std::sin(theta);  // (-1)^o e^{-i theta}  (Eqs. 11-12)
+    if (o) { cr = -cr; ci = -ci; }
+    return make_float2((float)cr, (float)ci);
+  };
+  const size_t nc = p->cmds.size();
+  for (size_t i = 0; i < nc; ++i) {
+    const Cmd &c = p->cmds[i];
+    // the window N w; E's on v or w; M v; X/Z on w as one 2x2 pass inside v's
+    // sub-state (as in the single-vector plan), when every E partner already
+    // sits in v's sub-state
+    if (c.op == OWQS_OP_N && i + 2 < nc) {
+      const int w = c.q0;
+      size_t j = i + 1;
+      while (j < nc && p->cmds[j].op == OWQS_OP_E) ++j;
+      if (j > i + 1 && j < nc && p->cmds[j].op == OWQS_OP_M && p->cmds[j].q0 != w && !fresh[p->cmds[j].q0] &&
+          chain_of[p->cmds[j].q0] >= 0) {
+        const Cmd &mm = p->cmds[j];
+        const int v = mm.q0, k = chain_of[v];
+        bool ok = true;
+        int vw = 0;
+        uint64_t mask_b = 0, mask_o1 = 0;
+        for (size_t e = i + 1; e < j && ok; ++e) {
+          const int a = p->cmds[e].q0, b = p->cmds[e].q1;
+          if ((a == v && b == w) || (a == w && b == v)) {
+            ++vw;
+          } else if (a == v || b == v || a == w || b == w) {
+            const int x = (a == v || a == w) ? b : a;
+            ok = chain_of[x] == k;
+            if (ok) {
+              if (a == v || b == v) mask_b ^= uint64_t(1) << slot_of[x];
+              else mask_o1 ^= uint64_t(1) << slot_of[x];
+            }
+          } else {
+            ok = false;  // an E on two other qubits ends the window
+          }
+        }
+        if (ok && vw > 0) {
+          int o = 0;
+          SubStep &st = emit(SS_J, k);
+          st.b0 = slot_of[v];
+          st.coef = m_coef(mm, m, o);
+          st.host_factor = ch[k].pend * r2;
+          st.m_index = m;
+          st.win.mask_b = mask_b;
+          st.win.mask_o1 = mask_o1;
+          st.win.vw_even = (vw % 2 == 0) ? 1 : 0;
+          outcome_of[v] = o;
+          ++m;
+          ch[k].pend = 1.0;
+          int idx[2] = {0, 1}, sgn[2] = {1, 1};
+          size_t q = j + 1;
+          while (q < nc && (p->cmds[q].op == OWQS_OP_X || p->cmds[q].op == OWQS_OP_Z) && p->cmds[q].q0 == w) {
+            if (signal(p->cmds[q].s, outcome_of)) {
+              if (p->cmds[q].op == OWQS_OP_X) {
+                std::swap(idx[0], idx[1]);
+                std::swap(sgn[0], sgn[1]);
+              } else {
+                sgn[1] = -sgn[1];
+              }
+            }
+            ++q;
+          }
+          st.win.swap = idx[0] == 1;
+          st.win.neg0 = sgn[0] < 0;
+          st.win.neg1 = sgn[1] < 0;
+          // w takes v's slot
+          slot_of[w] = slot_of[v];
+          chain_of[w] = k;
+          fresh[w] = 0;
+          ch[k].at[slot_of[v]] = w;
+          chain_of[v] = -1;
+          slot_of[v] = -1;
+          i = q - 1;
+          continue;
+        }
+      }
+    }
     switch (c.op) {
       case OWQS_OP_N:
         fresh[c.q0] = 1;
@@ -723,14 +804,11 @@ void compile_substates(owqs_pattern *p) {
         const int q = c.q0;
         if (fresh[q]) materialize(q);
         const int k = chain_of[q];
-        const int s = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
-        const double theta = (s ? -p->angles[m] : p->angles[m]) + (t ? M_PI : 0.0);  // Eq. 2
-        const int o = p->outcomes[m] & 1;
-        double cr = std::cos(theta), ci = -std::sin(theta);  // (-1)^o e^{-i theta}  (Eqs. 11-12)
-        if (o) { cr = -cr; ci = -ci; }
+        int o = 0;
+        const float2 cf = m_coef(c, m, o);
         SubStep &st = emit(SS_M, k);
         st.b0 = slot_of[q];
-        st.coef = make_float2((float)cr, (float)ci);
+        st.coef = cf;
         st.host_factor = ch[k].pend;
         st.m_index = m;
         ch[k].pend = 1.0;
@@ -784,7 +862,8 @@ void compile_substates(owqs_pattern *p) {
       case SS_E: ok = ok && x.b0 >= 0 && x.b1 >= 0 && x.b0 < x.n && x.b1 < x.n && x.b0 != x.b1; break;
       case SS_X:
       case SS_Z:
-      case SS_M: ok = ok && x.b0 >= 0 && x.b0 < x.n; break;
+      case SS_M:
+      case SS_J: ok = ok && x.b0 >= 0 && x.b0 < x.n; break;
       case SS_KRON:
         ok = ok && x.top != x.chain && x.n >= 1 && x.top_n >= 1 && x.n + x.top_n <= w &&
              x.top_n <= ch[x.top].maxw;
@@ -1333,7 +1412,8 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
         e = launch_kron(psi, x.n, p->ss_mem + p->ss_chains[x.top].off, x.top_n, p->ss_sigma + x.chain,
                         p->ss_sigma + x.top, s);
         break;
-      case SS_M: {
+      case SS_M:
+      case SS_J: {
         MeasureArgs a{};
         a.reduce = reduce;
         a.book = p->book;
@@ -1342,14 +1422,15 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
         a.host_factor = x.host_factor;
         a.m_index = x.m_index;
         unsigned grid = 0;
-        e = launch_measure(psi, x.n, x.b0, a, s, &grid);
+        e = x.kind == SS_M ? launch_measure(psi, x.n, x.b0, a, s, &grid)
+                           : launch_jwindow(psi, x.n, x.b0, a, x.win, s, &grid);
         if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
         if (e == hipSuccess) e = launch_finish(a, grid, s);
         break;
       }
       default: break;
     }
-    if (ev && x.kind != SS_M && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
+    if (ev && x.kind != SS_M && x.kind != SS_J && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
     if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
   }
   return e;
@@ -1365,6 +1446,7 @@ double substep_bytes(const SubStep &x) {
     case SS_X: return 2.0 * a;
     case SS_Z: return 1.0 * a;
     case SS_KRON: return a + std::ldexp(8.0, x.top_n) + std::ldexp(8.0, x.n + x.top_n);
+    case SS_J: return 2.0 * a;
   }
   return 0.0;
 }
@@ -1473,7 +1555,7 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
   p->ran_mode = reduce;
   if (prof) {
     static const int kind_of[] = {-1, OWQS_KIND_N, OWQS_KIND_E, OWQS_KIND_X, OWQS_KIND_Z, OWQS_KIND_M,
-                                  OWQS_KIND_KRON};
+                                  OWQS_KIND_KRON, OWQS_KIND_J};
     e = hipStreamSynchronize(s);
     for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
       const SubStep &x = p->ss_steps[i];
@@ -1485,7 +1567,7 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
       prof->counts[k] += 1;
       prof->ms[k] += t;
       prof->bytes[k] += substep_bytes(x);
-      if (x.kind == SS_M && reduce != kReduceNone) {
+      if ((x.kind == SS_M || x.kind == SS_J) && reduce != kReduceNone) {
         prof->counts[OWQS_KIND_FINISH] += 1;
         prof->ms[OWQS_KIND_FINISH] += f;
       }
