@@ -389,8 +389,9 @@ owqs_status owqs_run_factors(owqs_pattern *pat, const void *const *factors, cons
  * the outputs that ended in one sub-state; factors are ordered by their first
  * output (outputs order) and each lists its qubits in outputs order.
  * *n_factors and *n_amps (sum over factors of 2^factor_nq[f]) are written
- * when non-NULL.  factor_nq[f] and qubits (the caller's ids of factor 0, then
- * factor 1, ...) are written when non-NULL (factor_cap >= *n_factors).
+ * when non-NULL.  factor_nq[f] (factor_cap >= *n_factors entries) and qubits
+ * (the caller's ids of factor 0, then factor 1, ...: n_out entries in all,
+ * every output once) are written when non-NULL.
  * out_c64 (host, amp_cap >= *n_amps, may be NULL) receives the factors'
  * amplitudes one after the other, bit j of factor f = its j-th qubit, each
  * scaled to the true state (normalised in OWQS mode); scalar_c64 (host, one
