@@ -406,13 +406,12 @@ void group_tiles(owqs_pattern *p) {
     }
     tg.ta.nops = (int)(j - i);
     tg.ta.nwin = widx;
-    // compile the register runs in only where two unmasked windows on
-    // different bits follow each other (they cost occupancy elsewhere)
+    // compile the register runs in only where two windows on different bits
+    // follow each other (they cost occupancy elsewhere)
     tg.ta.runs = 0;
     for (size_t q = tg.op_off; q + 1 < p->fuse_ops.size(); ++q) {
       const FuseOp &a = p->fuse_ops[q], &b = p->fuse_ops[q + 1];
-      if (a.kind == S_J && b.kind == S_J && !(a.lmask_b | a.lmask_o1) && !(b.lmask_b | b.lmask_o1) && a.lb != b.lb)
-        tg.ta.runs = 1;
+      if (a.kind == S_J && b.kind == S_J && a.lb != b.lb) tg.ta.runs = 1;
     }
     Step gs{};
     gs.kind = S_F;

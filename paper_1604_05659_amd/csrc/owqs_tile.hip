@@ -233,9 +233,9 @@ __device__ __forceinline__ float window_any(bool masked, bool sw, char *lds, uin
 struct WinP {
   float fa, fb;
   float2 fc0;
-  uint32_t rsign;
+  uint32_t rsign, lmb, lmo;
   int lb, widx;
-  bool sw;
+  bool sw, masked;
 };
 
 __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, double sg, const TileArgs &ta) {
@@ -254,18 +254,33 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, doubl
   // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
   const bool s1neg = !(op.flags & 8u);
   w.rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
+  w.lmb = op.lmask_b;
+  w.lmo = op.lmask_o1;
+  w.masked = (op.lmask_b | op.lmask_o1) != 0;
   w.lb = op.lb;
   w.widx = op.widx;
   return w;
 }
 
-// An unmasked window on one pair in registers (a: bit lb = 0, b: bit lb = 1).
-template <bool kSw>
-__device__ __forceinline__ void win_apply(const WinP &w, float2 &a, float2 &b) {
-  const float2 t = make_float2(w.fc0.x * b.x - w.fc0.y * b.y, w.fc0.x * b.y + w.fc0.y * b.x);
+// A window on one pair in registers (a: local index e0 with bit lb = 0, b:
+// the same with bit lb = 1).  For a masked window (kMasked) b is negated
+// where e0 has odd parity under lmb, and o1 where it has odd parity under
+// lmo.
+template <bool kSw, bool kMasked = false>
+__device__ __forceinline__ void win_apply(const WinP &w, uint32_t e0, float2 &a, float2 &b) {
+  float fbe = w.fb;
+  uint32_t ts = w.rsign;
+  float2 bb = b;
+  if (kMasked) {
+    bb = xsign2(bb, par32(e0 & w.lmb) << 31);
+    const uint32_t so = par32(e0 & w.lmo) << 31;
+    fbe = xsign(w.fb, so);
+    ts ^= so;
+  }
+  const float2 t = make_float2(w.fc0.x * bb.x - w.fc0.y * bb.y, w.fc0.x * bb.y + w.fc0.y * bb.x);
   const float2 p0 = make_float2(fmaf(w.fa, a.x, t.x), fmaf(w.fa, a.y, t.y));
-  const float2 te = xsign2(t, w.rsign);
-  const float2 p1 = make_float2(fmaf(w.fb, a.x, te.x), fmaf(w.fb, a.y, te.y));
+  const float2 te = xsign2(t, ts);
+  const float2 p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
   a = kSw ? p1 : p0;
   b = kSw ? p0 : p1;
 }
@@ -278,7 +293,7 @@ __device__ __forceinline__ float nrm4(float2 a, float2 b, float2 c, float2 d) {
 // pass: each thread takes quads of elements (all values of the two bits),
 // applies A to its two pairs, then B to its two pairs, in registers.  Half
 // the LDS traffic and barriers of two passes.
-template <bool kAcc, bool kSwA, bool kSwB, int kTB, int kT>
+template <bool kAcc, bool kSwA, bool kSwB, bool kMA, bool kMB, int kTB, int kT>
 __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
                                             float &acc_b) {
   constexpr int kQuads = (1 << kTB) / kT / 4;
@@ -286,13 +301,13 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
   const uint32_t ba = 8u << A.lb, bb = 8u << B.lb;
 #pragma unroll
   for (int r = 0; r < kQuads; ++r) {
-    const uint32_t e = ins0u(ins0u(tid + uint32_t(r) * kT, lo), hi) << 3;
+    const uint32_t el = ins0u(ins0u(tid + uint32_t(r) * kT, lo), hi), e = el << 3;
     float2 x00 = at(lds, e), x10 = at(lds, e | ba), x01 = at(lds, e | bb), x11 = at(lds, e | ba | bb);
-    win_apply<kSwA>(A, x00, x10);
-    win_apply<kSwA>(A, x01, x11);
+    win_apply<kSwA, kMA>(A, el, x00, x10);
+    win_apply<kSwA, kMA>(A, el | (bb >> 3), x01, x11);
     if (kAcc) acc_a += nrm4(x00, x10, x01, x11);
-    win_apply<kSwB>(B, x00, x01);
-    win_apply<kSwB>(B, x10, x11);
+    win_apply<kSwB, kMB>(B, el, x00, x01);
+    win_apply<kSwB, kMB>(B, el | (ba >> 3), x10, x11);
     if (kAcc) acc_b += nrm4(x00, x10, x01, x11);
     at(lds, e) = x00;
     at(lds, e | ba) = x10;
@@ -301,15 +316,27 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
   }
 }
 
+template <bool kAcc, bool kMA, bool kMB, int kTB, int kT>
+__device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
+                                               float &acc_b) {
+  if (A.sw) {
+    if (B.sw) window_pair<kAcc, true, true, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair<kAcc, true, false, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+  } else {
+    if (B.sw) window_pair<kAcc, false, true, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair<kAcc, false, false, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+  }
+}
+
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
                                                 float &acc_b) {
-  if (A.sw) {
-    if (B.sw) window_pair<kAcc, true, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair<kAcc, true, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+  if (A.masked) {
+    if (B.masked) window_pair_sw<kAcc, true, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair_sw<kAcc, true, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
   } else {
-    if (B.sw) window_pair<kAcc, false, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair<kAcc, false, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    if (B.masked) window_pair_sw<kAcc, false, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    else window_pair_sw<kAcc, false, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
   }
 }
 
@@ -327,24 +354,25 @@ __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const Win
   const uint32_t ba = 8u << A.lb, bb = 8u << B.lb, bc = 8u << C.lb;
 #pragma unroll
   for (int r = 0; r < kOcts; ++r) {
-    const uint32_t e = ins0u(ins0u(ins0u(tid + uint32_t(r) * kT, b0), b1), b2) << 3;
+    const uint32_t el = ins0u(ins0u(ins0u(tid + uint32_t(r) * kT, b0), b1), b2), e = el << 3;
+    const uint32_t la = ba >> 3, lb_ = bb >> 3, lc = bc >> 3;
     float2 x[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) x[q] = at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u));
-    win_apply<kSwA>(A, x[0], x[1]);
-    win_apply<kSwA>(A, x[2], x[3]);
-    win_apply<kSwA>(A, x[4], x[5]);
-    win_apply<kSwA>(A, x[6], x[7]);
+    win_apply<kSwA>(A, el, x[0], x[1]);
+    win_apply<kSwA>(A, el | lb_, x[2], x[3]);
+    win_apply<kSwA>(A, el | lc, x[4], x[5]);
+    win_apply<kSwA>(A, el | lb_ | lc, x[6], x[7]);
     if (kAcc) acc[0] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
-    win_apply<kSwB>(B, x[0], x[2]);
-    win_apply<kSwB>(B, x[1], x[3]);
-    win_apply<kSwB>(B, x[4], x[6]);
-    win_apply<kSwB>(B, x[5], x[7]);
+    win_apply<kSwB>(B, el, x[0], x[2]);
+    win_apply<kSwB>(B, el | la, x[1], x[3]);
+    win_apply<kSwB>(B, el | lc, x[4], x[6]);
+    win_apply<kSwB>(B, el | la | lc, x[5], x[7]);
     if (kAcc) acc[1] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
-    win_apply<kSwC>(C, x[0], x[4]);
-    win_apply<kSwC>(C, x[1], x[5]);
-    win_apply<kSwC>(C, x[2], x[6]);
-    win_apply<kSwC>(C, x[3], x[7]);
+    win_apply<kSwC>(C, el, x[0], x[4]);
+    win_apply<kSwC>(C, el | la, x[1], x[5]);
+    win_apply<kSwC>(C, el | lb_, x[2], x[6]);
+    win_apply<kSwC>(C, el | la | lb_, x[3], x[7]);
     if (kAcc) acc[2] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
 #pragma unroll
     for (int q = 0; q < 8; ++q) at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u)) = x[q];
@@ -447,9 +475,9 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
           continue;
         }
       }
-      if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 1 < ta.nops) {
+      if (kRuns && op.kind == DK_J && o + 1 < ta.nops) {
         const FuseOp nx = load_op(ops, o + 1);
-        if (nx.kind == DK_J && (nx.lmask_b | nx.lmask_o1) == 0 && nx.lb != op.lb) {
+        if (nx.kind == DK_J && nx.lb != op.lb) {
           const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
           float acc_a = 0.f, acc_b = 0.f;
           if (reduce) {
