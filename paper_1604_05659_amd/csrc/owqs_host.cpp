@@ -407,11 +407,16 @@ void group_tiles(owqs_pattern *p) {
     tg.ta.nops = (int)(j - i);
     tg.ta.nwin = widx;
     // compile the register runs in only where two windows on different bits
-    // follow each other (they cost occupancy elsewhere)
+    // follow each other, possibly with an E or Z between (they cost occupancy
+    // elsewhere)
     tg.ta.runs = 0;
     for (size_t q = tg.op_off; q + 1 < p->fuse_ops.size(); ++q) {
       const FuseOp &a = p->fuse_ops[q], &b = p->fuse_ops[q + 1];
       if (a.kind == S_J && b.kind == S_J && a.lb != b.lb) tg.ta.runs = 1;
+      // a window, an E or Z, a window (the E / Z is applied between them)
+      if (q + 2 < p->fuse_ops.size() && a.kind == S_J && (b.kind == S_E || b.kind == S_Z) &&
+          p->fuse_ops[q + 2].kind == S_J && p->fuse_ops[q + 2].lb != a.lb)
+        tg.ta.runs = 1;
     }
     Step gs{};
     gs.kind = S_F;

@@ -293,9 +293,9 @@ __device__ __forceinline__ float nrm4(float2 a, float2 b, float2 c, float2 d) {
 // pass: each thread takes quads of elements (all values of the two bits),
 // applies A to its two pairs, then B to its two pairs, in registers.  Half
 // the LDS traffic and barriers of two passes.
-template <bool kAcc, bool kSwA, bool kSwB, bool kMA, bool kMB, int kTB, int kT>
-__device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
-                                            float &acc_b) {
+template <bool kAcc, bool kSwA, bool kSwB, bool kMA, bool kMB, bool kMid, int kTB, int kT>
+__device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
+                                            float &acc_a, float &acc_b) {
   constexpr int kQuads = (1 << kTB) / kT / 4;
   const int lo = A.lb < B.lb ? A.lb : B.lb, hi = A.lb < B.lb ? B.lb : A.lb;
   const uint32_t ba = 8u << A.lb, bb = 8u << B.lb;
@@ -306,6 +306,12 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
     win_apply<kSwA, kMA>(A, el, x00, x10);
     win_apply<kSwA, kMA>(A, el | (bb >> 3), x01, x11);
     if (kAcc) acc_a += nrm4(x00, x10, x01, x11);
+    if (kMid) {  // an E / Z between the windows: negate where its local bits are all set
+      if ((el & mid) == mid) x00 = xsign2(x00, 0x80000000u);
+      if (((el | (ba >> 3)) & mid) == mid) x10 = xsign2(x10, 0x80000000u);
+      if (((el | (bb >> 3)) & mid) == mid) x01 = xsign2(x01, 0x80000000u);
+      if (((el | ((ba | bb) >> 3)) & mid) == mid) x11 = xsign2(x11, 0x80000000u);
+    }
     win_apply<kSwB, kMB>(B, el, x00, x01);
     win_apply<kSwB, kMB>(B, el | (ba >> 3), x10, x11);
     if (kAcc) acc_b += nrm4(x00, x10, x01, x11);
@@ -316,28 +322,37 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
   }
 }
 
-template <bool kAcc, bool kMA, bool kMB, int kTB, int kT>
-__device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
-                                               float &acc_b) {
+template <bool kAcc, bool kMA, bool kMB, bool kMid, int kTB, int kT>
+__device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
+                                               float &acc_a, float &acc_b) {
   if (A.sw) {
-    if (B.sw) window_pair<kAcc, true, true, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair<kAcc, true, false, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    if (B.sw) window_pair<kAcc, true, true, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+    else window_pair<kAcc, true, false, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
   } else {
-    if (B.sw) window_pair<kAcc, false, true, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair<kAcc, false, false, kMA, kMB, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    if (B.sw) window_pair<kAcc, false, true, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+    else window_pair<kAcc, false, false, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
   }
 }
 
-template <bool kAcc, int kTB, int kT>
-__device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, float &acc_a,
-                                                float &acc_b) {
+template <bool kAcc, bool kMid, int kTB, int kT>
+__device__ __forceinline__ void window_pair_m(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
+                                              float &acc_a, float &acc_b) {
   if (A.masked) {
-    if (B.masked) window_pair_sw<kAcc, true, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair_sw<kAcc, true, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    if (B.masked) window_pair_sw<kAcc, true, true, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+    else window_pair_sw<kAcc, true, false, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
   } else {
-    if (B.masked) window_pair_sw<kAcc, false, true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
-    else window_pair_sw<kAcc, false, false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+    if (B.masked) window_pair_sw<kAcc, false, true, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+    else window_pair_sw<kAcc, false, false, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
   }
+}
+
+// Two windows on different bits, with an optional E / Z between them (its
+// local bits `mid`, applied when has_mid: the tile's outer bits satisfy it).
+template <bool kAcc, int kTB, int kT>
+__device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, bool has_mid,
+                                                uint32_t mid, float &acc_a, float &acc_b) {
+  if (has_mid) window_pair_m<kAcc, true, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+  else window_pair_m<kAcc, false, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
 }
 
 // Three consecutive unmasked windows A, B, C on three different local bits:
@@ -476,22 +491,35 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
         }
       }
       if (kRuns && op.kind == DK_J && o + 1 < ta.nops) {
-        const FuseOp nx = load_op(ops, o + 1);
+        FuseOp nx = load_op(ops, o + 1);
+        // an E or Z between two windows joins them (applied in registers)
+        int skip = 1;
+        bool has_mid = false;
+        uint32_t mid = 0;
+        if ((nx.kind == DK_E || nx.kind == DK_Z) && o + 2 < ta.nops) {
+          const FuseOp n2 = load_op(ops, o + 2);
+          if (n2.kind == DK_J && n2.lb != op.lb) {
+            has_mid = (ob & nx.omask_b) == nx.omask_b;
+            mid = nx.lmask_b;
+            nx = n2;
+            skip = 2;
+          }
+        }
         if (nx.kind == DK_J && nx.lb != op.lb) {
           const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
           float acc_a = 0.f, acc_b = 0.f;
           if (reduce) {
-            window_pair_any<true, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+            window_pair_any<true, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
             const double da = wave_sum_to_last(acc_a), db = wave_sum_to_last(acc_b);
             if (lane == 63) {
               wacc[A.widx][wave] += da;
               wacc[B.widx][wave] += db;
             }
           } else {
-            window_pair_any<false, kTB, kT>(lds, tid, A, B, acc_a, acc_b);
+            window_pair_any<false, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
           }
           __syncthreads();
-          ++o;
+          o += skip;
           continue;
         }
       }
