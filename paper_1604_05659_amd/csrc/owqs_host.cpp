@@ -181,12 +181,15 @@ struct owqs_pattern {
     int kind, n, b0, b1, m;
     double alpha, host_factor;
     SigRef s, t;
+    Window win;             // S_J: the window's sign masks (its folds are resolved on the device)
+    int fold_off, fold_len; // S_J: its corrections in s_folds
   };
   bool sampling = false;
   std::vector<double> uniforms;
   bool s_valid = false;
   std::vector<SStep> s_steps;
   std::vector<int> s_dom;           // measurement indices of the signal domains
+  std::vector<FoldRef> s_folds;     // corrections folded into drawn windows
   std::vector<int> s_final_where;
   double s_final_factor = 1.0;
   void *s_mem = nullptr;            // uniforms, outcomes, coefficient, domains
@@ -1205,12 +1208,75 @@ void compile_sampled(owqs_pattern *p) {
   int m = 0;
   p->s_steps.clear();
   p->s_dom.clear();
+  p->s_folds.clear();
   auto dom = [&](const std::vector<int> &qs) {
     SigRef r{(int)p->s_dom.size(), (int)qs.size()};
     for (int q : qs) p->s_dom.push_back(m_of[q]);  // D0: measured before
     return r;
   };
-  for (const Cmd &c : p->cmds) {
+  const size_t nc = p->cmds.size();
+  for (size_t i = 0; i < nc; ++i) {
+    const Cmd &c = p->cmds[i];
+    // a window N w; E's on v or w; M v; X/Z on w with an odd number of
+    // E(v, w): its outcome has probability exactly 1/2 (w is a fresh |+>
+    // neighbour of v), so it is drawn without a probability pass and runs as
+    // one 2x2 pass; the corrections on w are resolved on the device
+    if (c.op == OWQS_OP_N && i + 2 < nc) {
+      const int w = c.q0;
+      size_t j = i + 1;
+      while (j < nc && p->cmds[j].op == OWQS_OP_E) ++j;
+      if (j > i + 1 && j < nc && p->cmds[j].op == OWQS_OP_M && p->cmds[j].q0 != w && slot_of[p->cmds[j].q0] >= 0) {
+        const Cmd &mm = p->cmds[j];
+        const int v = mm.q0;
+        bool ok = true;
+        int vw = 0;
+        uint64_t mask_b = 0, mask_o1 = 0;
+        for (size_t e = i + 1; e < j && ok; ++e) {
+          const int a = p->cmds[e].q0, b = p->cmds[e].q1;
+          if ((a == v && b == w) || (a == w && b == v)) {
+            ++vw;
+          } else if (a == v || b == v || a == w || b == w) {
+            const int x = (a == v || a == w) ? b : a;
+            ok = slot_of[x] >= 0;
+            if (ok) {
+              if (a == v || b == v) mask_b ^= uint64_t(1) << slot_of[x];
+              else mask_o1 ^= uint64_t(1) << slot_of[x];
+            }
+          } else {
+            ok = false;
+          }
+        }
+        if (ok && vw % 2 == 1) {
+          owqs_pattern::SStep st{};
+          st.kind = S_J;
+          st.n = n;
+          st.b0 = slot_of[v];
+          st.m = m;
+          st.alpha = p->angles[m];
+          st.host_factor = pending * r2;
+          st.s = dom(mm.s);
+          st.t = dom(mm.t);
+          st.win.mask_b = mask_b;
+          st.win.mask_o1 = mask_o1;
+          st.win.vw_even = 0;
+          m_of[v] = m++;
+          st.fold_off = (int)p->s_folds.size();
+          size_t q = j + 1;
+          while (q < nc && (p->cmds[q].op == OWQS_OP_X || p->cmds[q].op == OWQS_OP_Z) && p->cmds[q].q0 == w) {
+            p->s_folds.push_back(FoldRef{p->cmds[q].op == OWQS_OP_X ? 1 : 0, dom(p->cmds[q].s)});
+            ++q;
+          }
+          st.fold_len = (int)p->s_folds.size() - st.fold_off;
+          p->s_steps.push_back(st);
+          slot_of[w] = slot_of[v];
+          qubit_at[slot_of[v]] = w;
+          slot_of[v] = -1;
+          pending = 1.0;
+          i = q - 1;
+          continue;
+        }
+      }
+    }
     owqs_pattern::SStep st{};
     st.n = n;
     switch (c.op) {
@@ -1268,12 +1334,15 @@ void compile_sampled(owqs_pattern *p) {
 }
 
 // Device layout of s_mem: uniforms (double), outcomes (int), coefficient
-// (float2), domains (int), each 256-byte aligned.
+// (float2) and a window's folds (3 int) in one 256-byte slot, domains (int),
+// folded corrections (FoldRef), each 256-byte aligned.
 struct SampleMem {
   double *u;
   int *outc;
   float2 *coef;
+  int *fold;
   int *dom;
+  FoldRef *folds;
 };
 SampleMem sample_mem(owqs_pattern *p) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -1283,7 +1352,10 @@ SampleMem sample_mem(owqs_pattern *p) {
   sm.u = reinterpret_cast<double *>(b);
   sm.outc = reinterpret_cast<int *>(b + up(nm * sizeof(double)));
   sm.coef = reinterpret_cast<float2 *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)));
+  sm.fold = reinterpret_cast<int *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 16);
   sm.dom = reinterpret_cast<int *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256);
+  sm.folds = reinterpret_cast<FoldRef *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 +
+                                         up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int)));
   return sm;
 }
 
@@ -1312,6 +1384,21 @@ hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
         if (e == hipSuccess) e = launch_finish(a, g2, s);
         break;
       }
+      case S_J: {
+        unsigned g = 0;
+        e = launch_s_jdecide(sm.u, x.m, x.alpha, x.s, x.t, sm.dom, sm.outc, sm.coef, sm.folds + x.fold_off, x.fold_len,
+                             sm.fold, s);
+        MeasureArgs a{};
+        a.coef_dev = sm.coef;
+        a.fold_dev = sm.fold;
+        a.host_factor = x.host_factor;
+        a.reduce = kReduceRenorm;
+        a.m_index = x.m;
+        a.book = p->book;
+        if (e == hipSuccess) e = launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &g);
+        if (e == hipSuccess) e = launch_finish(a, g, s);
+        break;
+      }
       default: break;
     }
   }
@@ -1330,7 +1417,9 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
   if (!p->s_valid) compile_sampled(p);
   const size_t nm = std::max<size_t>(p->n_meas, 1);
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t need = up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 + up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int));
+  const size_t need = up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 +
+                      up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int)) +
+                      up(std::max<size_t>(p->s_folds.size(), 1) * sizeof(FoldRef));
   hipError_t e = hipSuccess;
   if (p->s_cap < need) {
     if (p->s_mem) {
@@ -1351,6 +1440,8 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
     if (p->n_meas) e = hipMemcpy(sm.u, p->uniforms.data(), p->n_meas * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess && !p->s_dom.empty())
       e = hipMemcpy(sm.dom, p->s_dom.data(), p->s_dom.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->s_folds.empty())
+      e = hipMemcpy(sm.folds, p->s_folds.data(), p->s_folds.size() * sizeof(FoldRef), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(p->ctx, e, "sampling tables upload");
     p->s_uploaded = true;
   }

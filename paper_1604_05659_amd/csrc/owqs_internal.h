@@ -33,6 +33,7 @@ enum ReduceMode : int {
 struct MeasureArgs {
   float2 coef;          // (-1)^o e^{-i theta} rounded to complex64
   const float2 *coef_dev;  // non-null: read the coefficient from device memory instead (drawn outcomes)
+  const int *fold_dev;     // non-null (windows): swap, neg0, neg1 of the folded corrections from device memory
   double host_factor;   // (1/sqrt 2)^(N commands since the previous M)
   int reduce;           // ReduceMode
   int m_index;          // index of this M (probs slot)
@@ -223,6 +224,18 @@ hipError_t launch_s_prob(const float2 *psi, int n, int b, double alpha, SigRef s
 // outc[m] and the collapse coefficient (-1)^o e^{-i theta} into *coef.
 hipError_t launch_s_decide(const double *partials, unsigned nparts, const double *u, int m, double alpha,
                            SigRef sg, SigRef tg, const int *dom, int *outc, float2 *coef, hipStream_t s);
+// A correction folded into a drawn window: X (x = 1) or Z on the new qubit w
+// when the signal sig is 1.
+struct FoldRef {
+  int x;
+  SigRef sig;
+};
+// One thread, for a window whose E count between v and w is odd (outcome
+// probability exactly 1/2, Sec. 4.5): o = (u[m] <= 1/2 ? 0 : 1) into outc[m],
+// the coefficient into *coef, then the folded corrections folds[0 .. nf)
+// resolved with the drawn outcomes into fold[0..2] = {swap, neg0, neg1}.
+hipError_t launch_s_jdecide(const double *u, int m, double alpha, SigRef sg, SigRef tg, const int *dom, int *outc,
+                            float2 *coef, const FoldRef *folds, int nf, int *fold, hipStream_t s);
 
 
 // ---- sub-state executor (owqs_substate.hip)

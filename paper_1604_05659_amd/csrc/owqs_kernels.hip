@@ -466,6 +466,11 @@ __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, ui
                                                      MeasureArgs a, Window win) {
   const float f = scale_of(a);
   const float2 c = a.coef_dev ? *a.coef_dev : a.coef;
+  if (a.fold_dev) {  // corrections resolved on the device (drawn outcomes)
+    win.swap = a.fold_dev[0];
+    win.neg0 = a.fold_dev[1];
+    win.neg1 = a.fold_dev[2];
+  }
   const uint64_t step = uint64_t(1) << b;
   double acc = 0.0;
   GRID_STRIDE_UNITS(units) {

@@ -114,6 +114,33 @@ __global__ __launch_bounds__(kB) void k_s_decide(const double *__restrict__ part
   }
 }
 
+__global__ void k_s_jdecide(const double *__restrict__ u, int m, double alpha, SigRef sg, SigRef tg,
+                            const int *__restrict__ dom, int *outc, float2 *coef, const FoldRef *__restrict__ folds,
+                            int nf, int *fold) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int o = u[m] <= 0.5 ? 0 : 1;
+  double2 c = c_of(alpha, signal_of(dom, sg, outc), signal_of(dom, tg, outc));
+  if (o) c = make_double2(-c.x, -c.y);
+  outc[m] = o;
+  *coef = make_float2(float(c.x), float(c.y));
+  // the corrections on w after M v, in order, as a signed permutation
+  int i0 = 0, s0 = 1, s1 = 1;
+  for (int k = 0; k < nf; ++k) {
+    if (!signal_of(dom, folds[k].sig, outc)) continue;
+    if (folds[k].x) {
+      i0 ^= 1;
+      const int t = s0;
+      s0 = s1;
+      s1 = t;
+    } else {
+      s1 = -s1;
+    }
+  }
+  fold[0] = i0;
+  fold[1] = s0 < 0;
+  fold[2] = s1 < 0;
+}
+
 unsigned grid_of(uint64_t units) {
   uint64_t g = (units + kB - 1) / kB;
   if (g < 1) g = 1;
@@ -142,6 +169,12 @@ hipError_t launch_s_prob(const float2 *psi, int n, int b, double alpha, SigRef s
 hipError_t launch_s_decide(const double *partials, unsigned nparts, const double *u, int m, double alpha,
                            SigRef sg, SigRef tg, const int *dom, int *outc, float2 *coef, hipStream_t s) {
   hipLaunchKernelGGL(k_s_decide, dim3(1), dim3(kB), 0, s, partials, nparts, u, m, alpha, sg, tg, dom, outc, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_s_jdecide(const double *u, int m, double alpha, SigRef sg, SigRef tg, const int *dom, int *outc,
+                            float2 *coef, const FoldRef *folds, int nf, int *fold, hipStream_t s) {
+  hipLaunchKernelGGL(k_s_jdecide, dim3(1), dim3(64), 0, s, u, m, alpha, sg, tg, dom, outc, coef, folds, nf, fold);
   return hipGetLastError();
 }
 
