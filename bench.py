@@ -471,10 +471,28 @@ def bench_sampled(owqs, torch, pat, inp, out, n_nontriv, steps, warmup):
     dt = (time.perf_counter() - t0) / steps
     pat.read_state(out)
     drawn = pat.read_outcomes()
-    res = {"workload": "plain_large with outcomes drawn on the device (u <= p_0 gives 0; seeded uniforms)",
+    res = {"workload": "plain_large with outcomes drawn on the device (u <= p_0 gives 0; seeded uniforms), "
+                       "plain plan: every window drawn by one thread (p = 1/2), every other step one kernel",
            "ms_per_run": round(1e3 * dt, 3), "commands_per_s": round(n_nontriv / dt, 1),
            "ones_drawn": int(drawn.sum()), "max_abs_diff_vs_forced": float((out - forced).abs().max().item())}
+    # the fused plan: every M is a window with p = 1/2, so the outcomes follow
+    # from the uniforms and the tile passes run with per-run coefficient tables
+    pat.set_exec(owqs.EXEC_FUSED)
+    for _ in range(warmup):
+        pat.run(inp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pat.run(inp)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    pat.read_state(out)
+    same = bool((pat.read_outcomes() == drawn).all())
+    res["fused"] = {"ms_per_run": round(1e3 * dt, 3), "commands_per_s": round(n_nontriv / dt, 1),
+                    "same_outcomes_as_plain": same,
+                    "max_abs_diff_vs_forced": float((out - forced).abs().max().item())}
     pat.set_uniforms(None)
+    pat.set_exec(owqs.EXEC_PLAIN)
     return res
 
 

@@ -190,6 +190,15 @@ struct owqs_pattern {
   std::vector<SStep> s_steps;
   std::vector<int> s_dom;           // measurement indices of the signal domains
   std::vector<FoldRef> s_folds;     // corrections folded into drawn windows
+  // every M a window with p = 1/2 and no other correction: the outcomes follow
+  // from the uniforms alone, so a run is the fused plan with its window
+  // coefficients and folds taken from a per-run device table
+  bool s_analytic = false;
+  void *a_mem = nullptr;            // coefficients (float2 per M), then folds (3 int per M)
+  size_t a_cap = 0;
+  hipGraph_t a_graph = nullptr;
+  hipGraphExec_t a_exec = nullptr;
+  bool an_ran = false;
   std::vector<int> s_final_where;
   double s_final_factor = 1.0;
   void *s_mem = nullptr;            // uniforms, outcomes, coefficient, domains
@@ -914,9 +923,11 @@ void compile(owqs_pattern *p) {
   p->dirty = false;
   p->dev_steps_valid = false;
   p->dev_fuse_valid = false;
-  if (p->graph_exec || p->graph) (void)hipDeviceSynchronize();  // a replay may still be in flight
+  if (p->graph_exec || p->graph || p->a_exec) (void)hipDeviceSynchronize();  // a replay may still be in flight
   if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
+  if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
 }
 
 // Patterns of any width load (so they can be reordered and read back); only
@@ -952,6 +963,8 @@ owqs_status ensure_device(owqs_pattern *p, bool need_psi = true) {
     p->psi_cap = need;
     if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
     if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
+    if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
   }
   if (!p->book_mem) {
     const size_t nprob = std::max(p->n_meas, 1);
@@ -1062,8 +1075,11 @@ double step_bytes(const Step &x) {
 // main kernel and the finishing kernel of each step (see run_impl).
 int *fuse_m_dev(owqs_pattern *p) { return reinterpret_cast<int *>(p->dev_fuse + p->fuse_ops.size()); }
 
+// With ctab / ftab: the windows take their coefficient and folds from these
+// per-run device tables (coefficient of M m at ctab[m], folds at ftab[3 m]).
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
-                        hipStream_t s, std::vector<hipEvent_t> *ev) {
+                        hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab = nullptr,
+                        const int *ftab = nullptr) {
   hipError_t e = hipSuccess;
   for (size_t i = i0; i < i1 && e == hipSuccess; ++i) {
     const Step &x = xs[i];
@@ -1082,13 +1098,25 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
         a.coef = x.coef;
         a.host_factor = x.host_factor;
         a.m_index = x.m_index;
+        if (ctab && x.kind == S_J) {
+          a.coef_dev = ctab + x.m_index;
+          a.fold_dev = ftab + 3 * x.m_index;
+        }
         e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
                           : launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &grid);
         break;
       case S_F: {
         const TileGroup &tg = p->groups[x.group];
         ops = p->dev_fuse + tg.op_off;
-        e = launch_tile(p->psi, tg.ta, ops, a, s, &grid);
+        if (ctab) {
+          TileArgs ta = tg.ta;
+          ta.coefs = ctab;
+          ta.nsets = 1;
+          ta.folds = ftab;
+          e = launch_tile(p->psi, ta, ops, a, s, &grid);
+        } else {
+          e = launch_tile(p->psi, tg.ta, ops, a, s, &grid);
+        }
         break;
       }
       default: break;
@@ -1327,6 +1355,9 @@ void compile_sampled(owqs_pattern *p) {
   p->s_final_where.assign(p->outputs.size(), 0);
   for (size_t k = 0; k < p->outputs.size(); ++k) p->s_final_where[k] = slot_of[p->outputs[k]];
   p->s_final_factor = pending;
+  p->s_analytic = true;
+  for (const owqs_pattern::SStep &x : p->s_steps)
+    if (x.kind != S_N && x.kind != S_E && x.kind != S_J) p->s_analytic = false;
   p->s_valid = true;
   p->s_uploaded = false;
   if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
@@ -1405,6 +1436,119 @@ hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
   return e;
 }
 
+// Drawn outcomes when every M is a window with p = 1/2 (s_analytic): each
+// outcome is u[m] <= 1/2, known before the run, so the signals, coefficients
+// and folded corrections are resolved on the host in measurement order and
+// the fused plan (tile passes) runs with them from a device table.  Returns
+// false (nothing done) when the fused plan has steps whose form depends on
+// the outcomes (a separate M, X or Z).
+bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_device, hipStream_t s,
+                  owqs_status &st) {
+  st = OWQS_OK;
+  if (p->dirty) compile(p);
+  for (const Step &x : p->xsteps)
+    if (x.kind == S_M || x.kind == S_X || x.kind == S_Z) return false;
+  for (const FuseOp &op : p->fuse_ops)
+    if (op.kind == DK_X || op.kind == DK_Z) return false;
+  const size_t nm = std::max<size_t>(p->n_meas, 1);
+  std::vector<int> outc(nm, 0), fold(3 * nm, 0);
+  std::vector<float2> coef(nm, make_float2(1.f, 0.f));
+  auto sig = [&](SigRef r) {
+    int v = 0;
+    for (int k = 0; k < r.len; ++k) v ^= outc[p->s_dom[r.off + k]];
+    return v & 1;
+  };
+  for (const owqs_pattern::SStep &x : p->s_steps) {
+    if (x.kind != S_J) continue;
+    const int o = p->uniforms[x.m] <= 0.5 ? 0 : 1;
+    const double theta = (sig(x.s) ? -x.alpha : x.alpha) + (sig(x.t) ? M_PI : 0.0);  // Eq. 2
+    double cr = std::cos(theta), ci = -std::sin(theta);                                // Eqs. 11-12
+    if (o) { cr = -cr; ci = -ci; }
+    outc[x.m] = o;
+    coef[x.m] = make_float2((float)cr, (float)ci);
+    int i0 = 0, s0 = 1, s1 = 1;
+    for (int k = 0; k < x.fold_len; ++k) {
+      const FoldRef &f = p->s_folds[x.fold_off + k];
+      if (!sig(f.sig)) continue;
+      if (f.x) {
+        i0 ^= 1;
+        std::swap(s0, s1);
+      } else {
+        s1 = -s1;
+      }
+    }
+    fold[3 * x.m] = i0;
+    fold[3 * x.m + 1] = s0 < 0;
+    fold[3 * x.m + 2] = s1 < 0;
+  }
+  hipError_t e = hipSuccess;
+  const size_t cbytes = (nm * sizeof(float2) + 255) & ~size_t(255);
+  const size_t need = cbytes + 3 * nm * sizeof(int);
+  if (p->a_cap < need) {
+    if (p->a_mem) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p->a_mem);
+    }
+    if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
+    if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
+    p->a_mem = nullptr;
+    p->a_cap = 0;
+    e = hipMalloc(&p->a_mem, need);
+    if (e != hipSuccess) { st = fail(p->ctx, OWQS_E_NOMEM, "drawn-window tables"); return true; }
+    p->a_cap = need;
+  }
+  float2 *ctab = static_cast<float2 *>(p->a_mem);
+  int *ftab = reinterpret_cast<int *>(static_cast<char *>(p->a_mem) + cbytes);
+  // synchronous: the previous run may still read the tables
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(ctab, coef.data(), nm * sizeof(float2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ftab, fold.data(), 3 * nm * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->n_meas)
+    e = hipMemcpy(sample_mem(p).outc, outc.data(), p->n_meas * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "drawn-window tables"); return true; }
+  st = upload_fuse(p);
+  if (st != OWQS_OK) return true;
+  end_ranged(p);
+  const size_t nin = p->inputs.size();
+  e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
+  if (e == hipSuccess && (nin > 0 || input != nullptr))
+    e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
+                       input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "input"); return true; }
+  if (p->use_graph && !p->xsteps.empty()) {
+    if (!p->a_exec) {
+      if (!p->cap_stream) {
+        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { st = hip_fail(p->ctx, e, "capture stream"); return true; }
+      }
+      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) { st = hip_fail(p->ctx, e, "begin capture"); return true; }
+      hipError_t le = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, p->cap_stream, nullptr, ctab, ftab);
+      e = hipStreamEndCapture(p->cap_stream, &p->a_graph);
+      if (le != hipSuccess) e = le;
+      if (e == hipSuccess) e = hipGraphInstantiate(&p->a_exec, p->a_graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
+        p->a_exec = nullptr;
+        st = hip_fail(p->ctx, e, "graph capture");
+        return true;
+      }
+    }
+    e = hipGraphLaunch(p->a_exec, s);
+  } else {
+    e = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, s, nullptr, ctab, ftab);
+  }
+  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "kernel launch"); return true; }
+  p->ran = true;
+  p->ss_ran = false;
+  p->batch_ran = false;
+  p->out_in_order = false;
+  p->sampled_ran = true;
+  p->an_ran = true;
+  p->ran_mode = kReduceRenorm;
+  return true;
+}
+
 owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream) {
   const size_t nin = p->inputs.size();
   if (owqs_status w = width_guard(p)) return w;
@@ -1446,6 +1590,10 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
     p->s_uploaded = true;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->s_analytic && p->exec != OWQS_EXEC_PLAIN) {
+    owqs_status ast = OWQS_OK;
+    if (run_analytic(p, input, want, input_on_device, s, ast)) return ast;
+  }
   end_ranged(p);
   e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
   if (e == hipSuccess && (nin > 0 || input != nullptr))
@@ -1480,6 +1628,7 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
   p->batch_ran = false;
   p->out_in_order = false;
   p->sampled_ran = true;
+  p->an_ran = false;
   p->ran_mode = kReduceRenorm;
   return OWQS_OK;
 }
@@ -2045,7 +2194,8 @@ owqs_status owqs_pattern_from_text(owqs_ctx *ctx, const char *text, size_t len, 
 
 void owqs_pattern_destroy(owqs_pattern *p) {
   if (!p) return;
-  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem || p->s_mem || p->ss_mem) {
+  if (p->psi || p->book_mem || p->stage || p->dev_steps || p->graph_exec || p->adj_mem || p->s_mem || p->ss_mem ||
+      p->a_mem) {
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
     if (p->psi) (void)hipFree(p->psi);
@@ -2057,6 +2207,9 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   if (p->adj_mem) (void)hipFree(p->adj_mem);
   if (p->s_mem) (void)hipFree(p->s_mem);
   if (p->ss_mem) (void)hipFree(p->ss_mem);
+  if (p->a_mem) (void)hipFree(p->a_mem);
+  if (p->a_exec) (void)hipGraphExecDestroy(p->a_exec);
+  if (p->a_graph) (void)hipGraphDestroy(p->a_graph);
   if (p->ss_sigma) (void)hipFree(p->ss_sigma);
   if (p->ss_stage) (void)hipFree(p->ss_stage);
   if (p->ss_exec) (void)hipGraphExecDestroy(p->ss_exec);
@@ -2713,8 +2866,9 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
     return out_on_device ? OWQS_OK : owqs_check(p, stream);
   }
   const double *sigma = p->ran_mode == kReduceRenorm ? p->book.sigma : nullptr;
-  const int *where = p->sampled_ran ? p->s_final_where.data() : p->final_where.data();
-  const double factor = p->sampled_ran ? p->s_final_factor : p->final_factor;
+  const bool s_plan = p->sampled_ran && !p->an_ran;  // the drawn-window fused plan reads like a forced run
+  const int *where = s_plan ? p->s_final_where.data() : p->final_where.data();
+  const double factor = s_plan ? p->s_final_factor : p->final_factor;
   hipError_t e;
   if (p->out_in_order) {
     e = hipMemcpyAsync(out, p->psi, n_amps * sizeof(float2),

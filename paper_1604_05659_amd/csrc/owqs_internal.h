@@ -113,6 +113,9 @@ struct TileArgs {
   // coefficients of the command table)
   uint64_t set_stride;
   const float2 *coefs;
+  // non-null: the folded corrections of window m are folds[3 m .. 3 m + 2] =
+  // {swap, neg0, neg1} (resolved per run from drawn outcomes)
+  const int *folds;
   int nsets;
   int n, k, nops, nwin;
   int runs;          // 1: some consecutive unmasked windows run in registers (see k_tile)

@@ -84,6 +84,18 @@ __device__ __forceinline__ float2 set_coef(const TileArgs &ta, int m) {
   return make_float2(tab[0], tab[1]);
 }
 
+// A window's flags, with the folded corrections (bits 0-2) from the device
+// table when they were resolved per run (drawn outcomes).
+__device__ __forceinline__ uint32_t op_flags(const FuseOp &op, const TileArgs &ta) {
+  uint32_t fl = op.flags;
+  if (ta.folds) {
+    typedef const __attribute__((address_space(4))) int ci;
+    ci *t = reinterpret_cast<ci *>(reinterpret_cast<uintptr_t>(ta.folds)) + 3 * op.m_index;
+    fl = (fl & ~7u) | (t[0] ? 1u : 0u) | (t[1] ? 2u : 0u) | (t[2] ? 4u : 0u);
+  }
+  return fl;
+}
+
 // Deposit the low bits of x, lowest first, into the set bits of mask.
 __device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
   uint64_t r = 0;
@@ -240,11 +252,12 @@ struct WinP {
 
 __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, double sg, const TileArgs &ta) {
   WinP w;
-  const float f = float((op.flags & 16u) ? sg * op.f : double(op.f));
-  w.sw = op.flags & 1u;
+  const uint32_t fl = op_flags(op, ta);
+  const float f = float((fl & 16u) ? sg * op.f : double(op.f));
+  w.sw = fl & 1u;
   float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
-  if (op.flags & 2u) { if (w.sw) fb = -fb; else fa = -fa; }
-  if (op.flags & 4u) { if (w.sw) fa = -fa; else fb = -fb; }
+  if (fl & 2u) { if (w.sw) fb = -fb; else fa = -fa; }
+  if (fl & 4u) { if (w.sw) fa = -fa; else fb = -fb; }
   float2 cw = make_float2(op.coef.x, op.coef.y);
   if (ta.coefs) cw = set_coef(ta, op.m_index);
   const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
@@ -252,7 +265,7 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, doubl
   w.fb = fb;
   w.fc0 = make_float2(fa * c0.x, fa * c0.y);
   // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
-  const bool s1neg = !(op.flags & 8u);
+  const bool s1neg = !(fl & 8u);
   w.rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
   w.lmb = op.lmask_b;
   w.lmo = op.lmask_o1;
@@ -528,17 +541,18 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
       } else if (op.kind == DK_X) {
         pair_swap<kTB, kT>(lds, tid, op.lb);
       } else {  // window: fold the tile-constant signs and the corrections
-        const float f = float((op.flags & 16u) ? sg * op.f : double(op.f));
-        const bool sw = op.flags & 1u;
+        const uint32_t fl = op_flags(op, ta);
+        const float f = float((fl & 16u) ? sg * op.f : double(op.f));
+        const bool sw = fl & 1u;
         float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
-        if (op.flags & 2u) { if (sw) fb = -fb; else fa = -fa; }
-        if (op.flags & 4u) { if (sw) fa = -fa; else fb = -fb; }
+        if (fl & 2u) { if (sw) fb = -fb; else fa = -fa; }
+        if (fl & 4u) { if (sw) fa = -fa; else fb = -fb; }
         float2 cw = make_float2(op.coef.x, op.coef.y);
         if (ta.coefs) cw = set_coef(ta, op.m_index);
         const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
         const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
         // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
-        const bool s1neg = !(op.flags & 8u);
+        const bool s1neg = !(fl & 8u);
         const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
         const bool masked = (op.lmask_b | op.lmask_o1) != 0;
         if (reduce) {

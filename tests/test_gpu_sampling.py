@@ -119,3 +119,28 @@ def test_sampling_state_rules(ctx):
     p.set_uniforms(None)
     owqs.run_batch(ctx, [p], [None], [out])
     p.close()
+
+
+@pytest.mark.parametrize("nl,nj,ncz", [(6, 60, 12), (17, 80, 16)])
+def test_drawn_windows_on_the_fused_plan(ctx, nl, nj, ncz):
+    """Every M of a J/CZ circuit is a window with p = 1/2, so with the fused
+    executors the outcomes are resolved on the host and the fused plan (tile
+    passes at width 17) runs with per-run coefficient and fold tables; the
+    plain executor draws on the device.  Both give the oracle's outcome
+    string and output, on two draws in a row."""
+    g = np.random.default_rng(nl)
+    pat = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, nj, ncz, g))
+    inp = W.gaussian_state(nl, g)
+    for draw in range(2):
+        u, want, pw, ow = safe_uniforms(pat, inp, g)
+        for ex in (owqs.EXEC_AUTO, owqs.EXEC_FUSED, owqs.EXEC_PLAIN):
+            p = owqs.Pattern(ctx, pat)
+            p.set_exec(ex)
+            p.set_uniforms(u)
+            for rep in range(2):  # the second run replays the captured graph
+                p.run(torch.as_tensor(inp).cuda())
+                got = p.read_state().cpu().numpy().astype(np.complex128)
+                assert np.array_equal(p.read_outcomes(), ow), (draw, ex, rep)
+                assert np.max(np.abs(got - want)) <= AMP_TOL, (draw, ex, rep)
+                np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+            p.close()
