@@ -331,7 +331,13 @@ owqs_status owqs_get_outcomes(const owqs_pattern *pat, uint8_t *bits, size_t n_m
  * of outcome 0 (Eq. 13 with the operator of Eq. 11) of the state at that
  * point; signals and angles of later commands (Eq. 2) use the drawn
  * outcomes, so no host round trip happens during a run (the run is replayed
- * as a HIP graph like a forced one).  u: host, n_meas values in [0, 1),
+ * as a HIP graph like a forced one).  A fused window N w; E's; M v; X/Z on w
+ * with an odd number of E(v, w) has p_0 = 1/2 exactly and is drawn without a
+ * probability pass.  When every M is such a window and no other correction
+ * exists, the outcomes follow from u alone: with the FUSED or AUTO executor
+ * the host resolves them (and the signals, coefficients and corrections) at
+ * each owqs_run, which waits for `stream` to upload them, and the tile passes
+ * run as in a forced run.  u: host, n_meas values in [0, 1),
  * copied (the call waits for earlier device work).  u = NULL (n_meas = 0)
  * returns to forced outcomes, as do owqs_set_outcomes and
  * owqs_set_outcome_seed.  Needs OWQS mode (else owqs_run returns
