@@ -12,230 +12,10 @@
 //     zero signal emit nothing;
 //   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
 //     into its pass (with the device FP64 sigma in OWQS mode).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <climits>
-#include <cmath>
-#include <cstdint>
-#include <cstdio>
-#include <cstdlib>
-#include <cstring>
-#include <string>
-#include <unordered_map>
-#include <vector>
-
-#include "../../include/owqs.h"
+#include "owqs_host_impl.h"
 #include "owqs_pattern_access.h"
-#include "owqs_internal.h"
 
-using namespace owqs;
-
-struct owqs_ctx {
-  int device = 0;
-  std::string last_error;
-  // batch runs: side streams (default priority) for patterns too wide for LDS
-  std::vector<hipStream_t> side;
-  hipEvent_t fork = nullptr;
-  std::vector<hipEvent_t> join;
-  owqs::LdsItem *dev_items = nullptr;  // device copy of an LDS batch's item table
-  size_t dev_items_cap = 0;
-  hipEvent_t items_done = nullptr;     // recorded after the kernel that reads dev_items
-};
-
-namespace {
-
-enum StepKind : int { S_N = 0, S_E = 1, S_M = 2, S_X = 3, S_Z = 4, S_J = 5, S_F = 7 };
-
-struct Step {
-  int kind;
-  int n;       // live width before the step
-  int b0, b1;  // slots
-  float2 coef;
-  double host_factor;
-  int m_index;
-  Window win;
-  int sig_s, sig_t, outcome;  // M / window: resolved signals and forced outcome
-  int group;                  // S_F: index into the pattern's tile groups
-};
-
-struct TileGroup {
-  TileArgs ta;
-  size_t op_off;  // first FuseOp of the group in the pattern's table
-  size_t m_off;   // first window's measurement index in the pattern's m table
-};
-
-// Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's
-// region of the arena, kept by the sub-state that is the base of every merge
-// it takes part in.
-enum SubKind : int { SS_INIT = 0, SS_N = 1, SS_E = 2, SS_X = 3, SS_Z = 4, SS_M = 5, SS_KRON = 6, SS_J = 7 };
-
-struct SubStep {
-  int kind;
-  int chain;         // the sub-state acted on
-  int n;             // its width before the step
-  int b0, b1;        // slots
-  int top, top_n;    // SS_KRON: the sub-state merged in, and its width
-  float2 coef;       // SS_M, SS_J: (-1)^o e^{-i theta}
-  double host_factor;
-  int m_index;
-  Window win;        // SS_J: the fused window N w; E's; M v; X/Z on w
-};
-
-struct SubChain {
-  size_t off = 0;               // first amplitude in the arena
-  int maxw = 0;                 // widest it gets (its region holds 2^maxw amplitudes, at least 4)
-  std::vector<int> at;          // dense qubit at each slot, at the end of the plan
-  double pend = 1.0;            // host factor at the end of the plan
-  bool merged = false;          // merged into another chain
-};
-
-struct SubFactor {
-  int chain;
-  std::vector<int> qubits;      // dense, in output order
-  std::vector<int> where;       // slot of each, same order
-  uint64_t mask = 0;            // output bits held
-};
-
-struct Cmd {
-  int op;
-  int q0, q1;  // dense qubit indices
-  double angle;
-  std::vector<int> s, t;  // dense qubit indices
-};
-
-}  // namespace
-
-constexpr size_t kTraceStride = OWQS_MAX_WIDTH + 1;
-
-struct owqs_pattern {
-  owqs_ctx *ctx = nullptr;
-  std::vector<Cmd> cmds;
-  std::vector<int> inputs, outputs;  // dense
-  int nq = 0;
-  int n_meas = 0;
-  int max_live = 0;
-  std::vector<double> angles;     // per M
-  std::vector<uint8_t> outcomes;  // per M
-  owqs_mode mode = OWQS_MODE_OWQS;
-  owqs_exec exec = OWQS_EXEC_AUTO;
-
-  // compiled plan
-  bool dirty = true;
-  std::vector<Step> steps;
-  std::vector<int> final_where;  // slot of outputs[k]
-  double final_factor = 1.0;
-  int plan_width = 0;            // largest live width the plan reaches
-
-  int tile_bits = 0;  // 0: automatic (max(10, min(12, n - 8))); else 10..13
-  // execution steps of the global-memory path: the plan with runs of
-  // window/E/X/Z steps grouped into tile passes (S_F)
-  std::vector<Step> xsteps;
-  std::vector<TileGroup> groups;
-  std::vector<FuseOp> fuse_ops;
-  std::vector<int> fuse_m;        // measurement index of every window of every group
-  FuseOp *dev_fuse = nullptr;     // fuse_ops, then fuse_m (as int) in one allocation
-  size_t dev_fuse_cap = 0;
-  bool dev_fuse_valid = false;
-
-  // the plan as a device command table (LDS-resident runs)
-  DevStep *dev_steps = nullptr;
-  size_t dev_steps_cap = 0;
-  bool dev_steps_valid = false;
-
-  // the plan captured as a HIP graph (kernels only; replayed by owqs_run)
-  bool use_graph = true;
-  hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t graph_exec = nullptr;
-
-  // device memory
-  float2 *psi = nullptr;
-  size_t psi_cap = 0;  // amplitudes
-  void *book_mem = nullptr;
-  float2 *stage = nullptr;  // device staging for reads into host memory (2^nout)
-  DevBook book{};
-  // adjoint buffers (owqs_adjoint), grown on demand
-  void *adj_mem = nullptr;
-  size_t adj_cap = 0;
-  std::vector<float2> adj_coefs;   // host copies kept alive for the async uploads
-  std::vector<int> adj_cols;
-  std::vector<double> adj_scale;
-
-  // lockstep runs (owqs_run_range): the plain plan, one step per non-trivial
-  // command, with the state after every command
-  bool lk_valid = false;
-  std::vector<Step> lk_steps;
-  std::vector<size_t> lk_step_end;   // steps emitted by commands 0..i
-  std::vector<int> lk_width;         // live width after command i
-  std::vector<double> lk_pending;    // host factor of the live vector after command i
-  std::vector<int> lk_qubits;        // dense qubit at each bit after command i (stride kTraceStride)
-  size_t lk_next = SIZE_MAX;         // first command not yet run by the ranged run in progress
-  bool lk_ran = false;
-
-  std::vector<int32_t> user_id;  // dense qubit index -> caller's id
-
-  // drawn outcomes (owqs_set_uniforms): the plain plan with every signal and
-  // measurement coefficient resolved on the device
-  struct SStep {
-    int kind, n, b0, b1, m;
-    double alpha, host_factor;
-    SigRef s, t;
-    Window win;             // S_J: the window's sign masks (its folds are resolved on the device)
-    int fold_off, fold_len; // S_J: its corrections in s_folds
-  };
-  bool sampling = false;
-  std::vector<double> uniforms;
-  bool s_valid = false;
-  std::vector<SStep> s_steps;
-  std::vector<int> s_dom;           // measurement indices of the signal domains
-  std::vector<FoldRef> s_folds;     // corrections folded into drawn windows
-  // every M a window with p = 1/2 and no other correction: the outcomes follow
-  // from the uniforms alone, so a run is the fused plan with its window
-  // coefficients and folds taken from a per-run device table
-  bool s_analytic = false;
-  void *a_mem = nullptr;            // coefficients (float2 per M), then folds (3 int per M)
-  size_t a_cap = 0;
-  hipGraph_t a_graph = nullptr;
-  hipGraphExec_t a_exec = nullptr;
-  bool an_ran = false;
-  std::vector<int> s_final_where;
-  double s_final_factor = 1.0;
-  void *s_mem = nullptr;            // uniforms, outcomes, coefficient, domains
-  size_t s_cap = 0;
-  bool s_uploaded = false;          // uniforms and domains are on the device
-  hipGraph_t s_graph = nullptr;
-  hipGraphExec_t s_exec = nullptr;
-  bool sampled_ran = false;
-
-  // sub-state executor (OWQS_EXEC_SUBSTATES)
-  std::vector<int32_t> ss_in_nq;    // input factorization (qubits per factor, input order); empty: one factor
-  std::vector<SubStep> ss_steps;
-  std::vector<SubChain> ss_chains;
-  std::vector<SubFactor> ss_factors;
-  std::vector<int> ss_vanished;     // chains whose qubits were all measured (a scalar each)
-  int ss_width = 0;                 // widest sub-state
-  bool ss_plan_ok = true;           // every step fits its sub-state's region
-  size_t ss_arena = 0;              // amplitudes
-  float2 *ss_mem = nullptr;
-  size_t ss_mem_cap = 0;
-  double *ss_sigma = nullptr;       // one FP64 scale per chain
-  size_t ss_sigma_cap = 0;
-  float2 *ss_stage = nullptr;       // read-out: factors, then the scalars
-  size_t ss_stage_cap = 0;
-  hipGraph_t ss_graph = nullptr;
-  hipGraphExec_t ss_exec = nullptr;
-  int ss_graph_reduce = -1;
-  bool ss_ran = false;
-
-  bool ran = false;
-  bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
-  bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)
-  int ran_mode = 0;
-  int graph_reduce = -1;
-};
-
-namespace {
+namespace owqs {
 
 owqs_status fail(owqs_ctx *ctx, owqs_status st, const std::string &msg) {
   if (ctx) ctx->last_error = msg;
@@ -633,277 +413,6 @@ void compile_plan(owqs_pattern *p, bool fused, std::vector<Step> &steps, std::ve
   final_factor = pending;
 }
 
-// Sub-state plan (Sec. 4.1, Sec. 4.4.1): every input factor starts as a
-// sub-state; N makes a fresh |+> qubit that stays implicit until a command
-// touches it; E with a fresh qubit appends it to the other qubit's sub-state
-// (a prepare step, as in the single-vector plan), E across two sub-states
-// merges them (SS_KRON, the wider one is the base and keeps its region), and
-// M eliminates its qubit inside its sub-state (the top qubit moves into the
-// freed slot).  Each sub-state keeps its own host factor and FP64 scale.
-void compile_substates(owqs_pattern *p) {
-  p->ss_steps.clear();
-  p->ss_chains.clear();
-  p->ss_factors.clear();
-  p->ss_vanished.clear();
-  const int nq = p->nq;
-  std::vector<int> chain_of(nq, -1), slot_of(nq, -1), outcome_of(nq, 0);
-  std::vector<char> fresh(nq, 0);
-  std::vector<SubChain> &ch = p->ss_chains;
-  const double r2 = 1.0 / std::sqrt(2.0);
-  auto widen = [&](int c) { ch[c].maxw = std::max(ch[c].maxw, (int)ch[c].at.size()); };
-  // input factors
-  std::vector<int32_t> nqs = p->ss_in_nq;
-  if (nqs.empty() && !p->inputs.empty()) nqs.push_back((int32_t)p->inputs.size());
-  size_t off = 0;
-  for (int32_t k : nqs) {
-    ch.emplace_back();
-    const int c = (int)ch.size() - 1;
-    for (int32_t j = 0; j < k; ++j) {
-      const int q = p->inputs[off + j];
-      chain_of[q] = c;
-      slot_of[q] = j;
-      ch[c].at.push_back(q);
-    }
-    off += (size_t)k;
-    widen(c);
-  }
-  auto emit = [&](int kind, int c) -> SubStep & {
-    SubStep st{};
-    st.kind = kind;
-    st.chain = c;
-    st.n = (int)ch[c].at.size();
-    p->ss_steps.push_back(st);
-    return p->ss_steps.back();
-  };
-  auto prep = [&](int c, int q) {
-    emit(SS_N, c);
-    slot_of[q] = (int)ch[c].at.size();
-    chain_of[q] = c;
-    fresh[q] = 0;
-    ch[c].at.push_back(q);
-    ch[c].pend *= r2;
-    widen(c);
-  };
-  auto materialize = [&](int q) {
-    ch.emplace_back();
-    const int c = (int)ch.size() - 1;
-    emit(SS_INIT, c);
-    prep(c, q);
-    return c;
-  };
-  int m = 0;
-  auto m_coef = [&](const Cmd &c, int mi, int &o) {
-    const int sgn = signal(c.s, outcome_of), t = signal(c.t, outcome_of);
-    const double theta = (sgn ? -p->angles[mi] : p->angles[mi]) + (t ? M_PI : 0.0);  // Eq. 2
-    o = p->outcomes[mi] & 1;
-    double cr = std::cos(theta), ci = -std::sin(theta);  // (-1)^o e^{-i theta}  (Eqs. 11-12)
-    if (o) { cr = -cr; ci = -ci; }
-    return make_float2((float)cr, (float)ci);
-  };
-  const size_t nc = p->cmds.size();
-  for (size_t i = 0; i < nc; ++i) {
-    const Cmd &c = p->cmds[i];
-    // the window N w; E's on v or w; M v; X/Z on w as one 2x2 pass inside v's
-    // sub-state (as in the single-vector plan), when every E partner already
-    // sits in v's sub-state
-    if (c.op == OWQS_OP_N && i + 2 < nc) {
-      const int w = c.q0;
-      size_t j = i + 1;
-      while (j < nc && p->cmds[j].op == OWQS_OP_E) ++j;
-      if (j > i + 1 && j < nc && p->cmds[j].op == OWQS_OP_M && p->cmds[j].q0 != w && !fresh[p->cmds[j].q0] &&
-          chain_of[p->cmds[j].q0] >= 0) {
-        const Cmd &mm = p->cmds[j];
-        const int v = mm.q0, k = chain_of[v];
-        bool ok = true;
-        int vw = 0;
-        uint64_t mask_b = 0, mask_o1 = 0;
-        for (size_t e = i + 1; e < j && ok; ++e) {
-          const int a = p->cmds[e].q0, b = p->cmds[e].q1;
-          if ((a == v && b == w) || (a == w && b == v)) {
-            ++vw;
-          } else if (a == v || b == v || a == w || b == w) {
-            const int x = (a == v || a == w) ? b : a;
-            ok = chain_of[x] == k;
-            if (ok) {
-              if (a == v || b == v) mask_b ^= uint64_t(1) << slot_of[x];
-              else mask_o1 ^= uint64_t(1) << slot_of[x];
-            }
-          } else {
-            ok = false;  // an E on two other qubits ends the window
-          }
-        }
-        if (ok && vw > 0) {
-          int o = 0;
-          SubStep &st = emit(SS_J, k);
-          st.b0 = slot_of[v];
-          st.coef = m_coef(mm, m, o);
-          st.host_factor = ch[k].pend * r2;
-          st.m_index = m;
-          st.win.mask_b = mask_b;
-          st.win.mask_o1 = mask_o1;
-          st.win.vw_even = (vw % 2 == 0) ? 1 : 0;
-          outcome_of[v] = o;
-          ++m;
-          ch[k].pend = 1.0;
-          int idx[2] = {0, 1}, sgn[2] = {1, 1};
-          size_t q = j + 1;
-          while (q < nc && (p->cmds[q].op == OWQS_OP_X || p->cmds[q].op == OWQS_OP_Z) && p->cmds[q].q0 == w) {
-            if (signal(p->cmds[q].s, outcome_of)) {
-              if (p->cmds[q].op == OWQS_OP_X) {
-                std::swap(idx[0], idx[1]);
-                std::swap(sgn[0], sgn[1]);
-              } else {
-                sgn[1] = -sgn[1];
-              }
-            }
-            ++q;
-          }
-          st.win.swap = idx[0] == 1;
-          st.win.neg0 = sgn[0] < 0;
-          st.win.neg1 = sgn[1] < 0;
-          // w takes v's slot
-          slot_of[w] = slot_of[v];
-          chain_of[w] = k;
-          fresh[w] = 0;
-          ch[k].at[slot_of[v]] = w;
-          chain_of[v] = -1;
-          slot_of[v] = -1;
-          i = q - 1;
-          continue;
-        }
-      }
-    }
-    switch (c.op) {
-      case OWQS_OP_N:
-        fresh[c.q0] = 1;
-        break;
-      case OWQS_OP_E: {
-        const int u = c.q0, v = c.q1;
-        if (fresh[u] && fresh[v]) {
-          prep(materialize(u), v);
-        } else if (fresh[u]) {
-          prep(chain_of[v], u);
-        } else if (fresh[v]) {
-          prep(chain_of[u], v);
-        } else if (chain_of[u] != chain_of[v]) {
-          int a = chain_of[u], b = chain_of[v];
-          if (ch[b].at.size() > ch[a].at.size() || (ch[b].at.size() == ch[a].at.size() && b < a)) std::swap(a, b);
-          SubStep &st = emit(SS_KRON, a);
-          st.top = b;
-          st.top_n = (int)ch[b].at.size();
-          const int base_n = (int)ch[a].at.size();
-          for (size_t j = 0; j < ch[b].at.size(); ++j) {
-            const int q = ch[b].at[j];
-            chain_of[q] = a;
-            slot_of[q] = base_n + (int)j;
-            ch[a].at.push_back(q);
-          }
-          ch[a].pend *= ch[b].pend;
-          ch[b].at.clear();
-          ch[b].merged = true;
-          widen(a);
-        }
-        SubStep &st = emit(SS_E, chain_of[u]);
-        st.b0 = slot_of[u];
-        st.b1 = slot_of[v];
-        break;
-      }
-      case OWQS_OP_X:
-      case OWQS_OP_Z: {
-        if (!signal(c.s, outcome_of)) break;
-        if (fresh[c.q0]) materialize(c.q0);
-        SubStep &st = emit(c.op == OWQS_OP_X ? SS_X : SS_Z, chain_of[c.q0]);
-        st.b0 = slot_of[c.q0];
-        break;
-      }
-      case OWQS_OP_M: {
-        const int q = c.q0;
-        if (fresh[q]) materialize(q);
-        const int k = chain_of[q];
-        int o = 0;
-        const float2 cf = m_coef(c, m, o);
-        SubStep &st = emit(SS_M, k);
-        st.b0 = slot_of[q];
-        st.coef = cf;
-        st.host_factor = ch[k].pend;
-        st.m_index = m;
-        ch[k].pend = 1.0;
-        outcome_of[q] = o;
-        ++m;
-        std::vector<int> &at = ch[k].at;
-        const int top = at.back();
-        if (top != q) {
-          at[slot_of[q]] = top;
-          slot_of[top] = slot_of[q];
-        }
-        at.pop_back();
-        chain_of[q] = -1;
-        slot_of[q] = -1;
-        break;
-      }
-      default:
-        break;
-    }
-  }
-  for (int q : p->outputs)
-    if (fresh[q]) materialize(q);
-  // read-out factors, ordered by their first output; vanished sub-states
-  std::vector<int> pos(nq, -1);
-  for (size_t k = 0; k < p->outputs.size(); ++k) pos[p->outputs[k]] = (int)k;
-  std::vector<int> factor_of(ch.size(), -1);
-  for (size_t k = 0; k < p->outputs.size(); ++k) {
-    const int q = p->outputs[k], c = chain_of[q];
-    if (factor_of[c] < 0) {
-      factor_of[c] = (int)p->ss_factors.size();
-      SubFactor f{};
-      f.chain = c;
-      p->ss_factors.push_back(f);
-    }
-    SubFactor &f = p->ss_factors[factor_of[c]];
-    f.qubits.push_back(q);
-    f.where.push_back(slot_of[q]);
-    f.mask |= uint64_t(1) << k;
-  }
-  for (size_t c = 0; c < ch.size(); ++c)
-    if (!ch[c].merged && ch[c].at.empty()) p->ss_vanished.push_back((int)c);
-  p->ss_width = 0;
-  for (const SubChain &c : ch) p->ss_width = std::max(p->ss_width, c.maxw);
-  // every step stays inside its sub-state's region (checked before any launch)
-  p->ss_plan_ok = true;
-  for (const SubStep &x : p->ss_steps) {
-    const int w = ch[x.chain].maxw;
-    bool ok = x.n <= w;
-    switch (x.kind) {
-      case SS_N: ok = ok && x.n + 1 <= w; break;
-      case SS_E: ok = ok && x.b0 >= 0 && x.b1 >= 0 && x.b0 < x.n && x.b1 < x.n && x.b0 != x.b1; break;
-      case SS_X:
-      case SS_Z:
-      case SS_M:
-      case SS_J: ok = ok && x.b0 >= 0 && x.b0 < x.n; break;
-      case SS_KRON:
-        ok = ok && x.top != x.chain && x.n >= 1 && x.top_n >= 1 && x.n + x.top_n <= w &&
-             x.top_n <= ch[x.top].maxw;
-        break;
-      default: break;
-    }
-    if (!ok) p->ss_plan_ok = false;
-  }
-  p->ss_arena = 0;
-  if (p->ss_width <= OWQS_MAX_WIDTH) {
-    for (SubChain &c : ch) {
-      c.off = p->ss_arena;
-      const size_t amps = std::max<size_t>(size_t(1) << c.maxw, 4);
-      p->ss_arena += (amps + 63) / 64 * 64;  // 512-byte aligned regions
-    }
-  }
-}
-
-void drop_ss_graph(owqs_pattern *p) {
-  if (p->ss_exec || p->ss_graph) (void)hipDeviceSynchronize();
-  if (p->ss_exec) { (void)hipGraphExecDestroy(p->ss_exec); p->ss_exec = nullptr; }
-  if (p->ss_graph) { (void)hipGraphDestroy(p->ss_graph); p->ss_graph = nullptr; }
-}
-
 // Compile the command list into device steps for the current settings.
 void compile(owqs_pattern *p) {
   if (p->exec == OWQS_EXEC_SUBSTATES) {
@@ -948,7 +457,7 @@ owqs_status width_guard(owqs_pattern *p) {
   return OWQS_OK;
 }
 
-owqs_status ensure_device(owqs_pattern *p, bool need_psi = true) {
+owqs_status ensure_device(owqs_pattern *p, bool need_psi) {
   if (owqs_status w = width_guard(p)) return w;
   if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
   hipError_t e = hipSetDevice(p->ctx->device);
@@ -1050,12 +559,6 @@ owqs_status build_pattern(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, con
   return OWQS_OK;
 }
 
-struct Profile {
-  int64_t *counts;
-  double *ms;
-  double *bytes;
-};
-
 // Algorithmic bytes of one step (element level, complex64).
 double step_bytes(const Step &x) {
   const double a = std::ldexp(8.0, x.n);  // 8 bytes * 2^n
@@ -1075,11 +578,8 @@ double step_bytes(const Step &x) {
 // main kernel and the finishing kernel of each step (see run_impl).
 int *fuse_m_dev(owqs_pattern *p) { return reinterpret_cast<int *>(p->dev_fuse + p->fuse_ops.size()); }
 
-// With ctab / ftab: the windows take their coefficient and folds from these
-// per-run device tables (coefficient of M m at ctab[m], folds at ftab[3 m]).
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
-                        hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab = nullptr,
-                        const int *ftab = nullptr) {
+                        hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab, const int *ftab) {
   hipError_t e = hipSuccess;
   for (size_t i = i0; i < i1 && e == hipSuccess; ++i) {
     const Step &x = xs[i];
@@ -1218,650 +718,6 @@ LdsItem lds_proto(const owqs_pattern *p) {
 void end_ranged(owqs_pattern *p) {
   p->lk_next = SIZE_MAX;
   p->lk_ran = false;
-}
-
-// The plan for drawn outcomes: one step per command in execution order (N
-// appends the top slot, M moves the top qubit into the measured slot, as in
-// compile_plan); every X/Z is kept (its signal is known only on the device)
-// and the signal domains become lists of measurement indices.
-void compile_sampled(owqs_pattern *p) {
-  std::vector<int> slot_of(p->nq, -1), qubit_at(OWQS_MAX_WIDTH + 1, -1), m_of(p->nq, -1);
-  int n = (int)p->inputs.size();
-  for (int k = 0; k < n; ++k) {
-    slot_of[p->inputs[k]] = k;
-    qubit_at[k] = p->inputs[k];
-  }
-  const double r2 = 1.0 / std::sqrt(2.0);
-  double pending = 1.0;
-  int m = 0;
-  p->s_steps.clear();
-  p->s_dom.clear();
-  p->s_folds.clear();
-  auto dom = [&](const std::vector<int> &qs) {
-    SigRef r{(int)p->s_dom.size(), (int)qs.size()};
-    for (int q : qs) p->s_dom.push_back(m_of[q]);  // D0: measured before
-    return r;
-  };
-  const size_t nc = p->cmds.size();
-  for (size_t i = 0; i < nc; ++i) {
-    const Cmd &c = p->cmds[i];
-    // a window N w; E's on v or w; M v; X/Z on w with an odd number of
-    // E(v, w): its outcome has probability exactly 1/2 (w is a fresh |+>
-    // neighbour of v), so it is drawn without a probability pass and runs as
-    // one 2x2 pass; the corrections on w are resolved on the device
-    if (c.op == OWQS_OP_N && i + 2 < nc) {
-      const int w = c.q0;
-      size_t j = i + 1;
-      while (j < nc && p->cmds[j].op == OWQS_OP_E) ++j;
-      if (j > i + 1 && j < nc && p->cmds[j].op == OWQS_OP_M && p->cmds[j].q0 != w && slot_of[p->cmds[j].q0] >= 0) {
-        const Cmd &mm = p->cmds[j];
-        const int v = mm.q0;
-        bool ok = true;
-        int vw = 0;
-        uint64_t mask_b = 0, mask_o1 = 0;
-        for (size_t e = i + 1; e < j && ok; ++e) {
-          const int a = p->cmds[e].q0, b = p->cmds[e].q1;
-          if ((a == v && b == w) || (a == w && b == v)) {
-            ++vw;
-          } else if (a == v || b == v || a == w || b == w) {
-            const int x = (a == v || a == w) ? b : a;
-            ok = slot_of[x] >= 0;
-            if (ok) {
-              if (a == v || b == v) mask_b ^= uint64_t(1) << slot_of[x];
-              else mask_o1 ^= uint64_t(1) << slot_of[x];
-            }
-          } else {
-            ok = false;
-          }
-        }
-        if (ok && vw % 2 == 1) {
-          owqs_pattern::SStep st{};
-          st.kind = S_J;
-          st.n = n;
-          st.b0 = slot_of[v];
-          st.m = m;
-          st.alpha = p->angles[m];
-          st.host_factor = pending * r2;
-          st.s = dom(mm.s);
-          st.t = dom(mm.t);
-          st.win.mask_b = mask_b;
-          st.win.mask_o1 = mask_o1;
-          st.win.vw_even = 0;
-          m_of[v] = m++;
-          st.fold_off = (int)p->s_folds.size();
-          size_t q = j + 1;
-          while (q < nc && (p->cmds[q].op == OWQS_OP_X || p->cmds[q].op == OWQS_OP_Z) && p->cmds[q].q0 == w) {
-            p->s_folds.push_back(FoldRef{p->cmds[q].op == OWQS_OP_X ? 1 : 0, dom(p->cmds[q].s)});
-            ++q;
-          }
-          st.fold_len = (int)p->s_folds.size() - st.fold_off;
-          p->s_steps.push_back(st);
-          slot_of[w] = slot_of[v];
-          qubit_at[slot_of[v]] = w;
-          slot_of[v] = -1;
-          pending = 1.0;
-          i = q - 1;
-          continue;
-        }
-      }
-    }
-    owqs_pattern::SStep st{};
-    st.n = n;
-    switch (c.op) {
-      case OWQS_OP_N:
-        st.kind = S_N;
-        slot_of[c.q0] = n;
-        qubit_at[n] = c.q0;
-        ++n;
-        pending *= r2;
-        break;
-      case OWQS_OP_E:
-        st.kind = S_E;
-        st.b0 = slot_of[c.q0];
-        st.b1 = slot_of[c.q1];
-        break;
-      case OWQS_OP_X:
-      case OWQS_OP_Z:
-        st.kind = c.op == OWQS_OP_X ? S_X : S_Z;
-        st.b0 = slot_of[c.q0];
-        st.s = dom(c.s);
-        break;
-      case OWQS_OP_M: {
-        st.kind = S_M;
-        st.b0 = slot_of[c.q0];
-        st.m = m;
-        st.alpha = p->angles[m];
-        st.host_factor = pending;
-        st.s = dom(c.s);
-        st.t = dom(c.t);
-        m_of[c.q0] = m++;
-        const int t = n - 1;
-        if (st.b0 != t) {
-          const int top = qubit_at[t];
-          slot_of[top] = st.b0;
-          qubit_at[st.b0] = top;
-        }
-        qubit_at[t] = -1;
-        slot_of[c.q0] = -1;
-        --n;
-        pending = 1.0;
-        break;
-      }
-      default:
-        continue;
-    }
-    p->s_steps.push_back(st);
-  }
-  p->s_final_where.assign(p->outputs.size(), 0);
-  for (size_t k = 0; k < p->outputs.size(); ++k) p->s_final_where[k] = slot_of[p->outputs[k]];
-  p->s_final_factor = pending;
-  p->s_analytic = true;
-  for (const owqs_pattern::SStep &x : p->s_steps)
-    if (x.kind != S_N && x.kind != S_E && x.kind != S_J) p->s_analytic = false;
-  p->s_valid = true;
-  p->s_uploaded = false;
-  if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
-  if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
-}
-
-// Device layout of s_mem: uniforms (double), outcomes (int), coefficient
-// (float2) and a window's folds (3 int) in one 256-byte slot, domains (int),
-// folded corrections (FoldRef), each 256-byte aligned.
-struct SampleMem {
-  double *u;
-  int *outc;
-  float2 *coef;
-  int *fold;
-  int *dom;
-  FoldRef *folds;
-};
-SampleMem sample_mem(owqs_pattern *p) {
-  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  char *b = static_cast<char *>(p->s_mem);
-  const size_t nm = std::max<size_t>(p->n_meas, 1);
-  SampleMem sm{};
-  sm.u = reinterpret_cast<double *>(b);
-  sm.outc = reinterpret_cast<int *>(b + up(nm * sizeof(double)));
-  sm.coef = reinterpret_cast<float2 *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)));
-  sm.fold = reinterpret_cast<int *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 16);
-  sm.dom = reinterpret_cast<int *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256);
-  sm.folds = reinterpret_cast<FoldRef *>(b + up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 +
-                                         up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int)));
-  return sm;
-}
-
-hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
-  const SampleMem sm = sample_mem(p);
-  hipError_t e = hipSuccess;
-  for (const owqs_pattern::SStep &x : p->s_steps) {
-    if (e != hipSuccess) break;
-    switch (x.kind) {
-      case S_N: e = launch_prepare(p->psi, x.n, s); break;
-      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
-      case S_X:
-      case S_Z: e = launch_s_pauli(p->psi, x.n, x.b0, x.kind == S_X, x.s, sm.dom, sm.outc, s); break;
-      case S_M: {
-        unsigned g = 0, g2 = 0;
-        e = launch_s_prob(p->psi, x.n, x.b0, x.alpha, x.s, x.t, sm.dom, sm.outc, p->book.partials, &g, s);
-        if (e == hipSuccess)
-          e = launch_s_decide(p->book.partials, g, sm.u, x.m, x.alpha, x.s, x.t, sm.dom, sm.outc, sm.coef, s);
-        MeasureArgs a{};
-        a.coef_dev = sm.coef;
-        a.host_factor = x.host_factor;
-        a.reduce = kReduceRenorm;
-        a.m_index = x.m;
-        a.book = p->book;
-        if (e == hipSuccess) e = launch_measure(p->psi, x.n, x.b0, a, s, &g2);
-        if (e == hipSuccess) e = launch_finish(a, g2, s);
-        break;
-      }
-      case S_J: {
-        unsigned g = 0;
-        e = launch_s_jdecide(sm.u, x.m, x.alpha, x.s, x.t, sm.dom, sm.outc, sm.coef, sm.folds + x.fold_off, x.fold_len,
-                             sm.fold, s);
-        MeasureArgs a{};
-        a.coef_dev = sm.coef;
-        a.fold_dev = sm.fold;
-        a.host_factor = x.host_factor;
-        a.reduce = kReduceRenorm;
-        a.m_index = x.m;
-        a.book = p->book;
-        if (e == hipSuccess) e = launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &g);
-        if (e == hipSuccess) e = launch_finish(a, g, s);
-        break;
-      }
-      default: break;
-    }
-  }
-  return e;
-}
-
-// Drawn outcomes when every M is a window with p = 1/2 (s_analytic): each
-// outcome is u[m] <= 1/2, known before the run, so the signals, coefficients
-// and folded corrections are resolved on the host in measurement order and
-// the fused plan (tile passes) runs with them from a device table.  Returns
-// false (nothing done) when the fused plan has steps whose form depends on
-// the outcomes (a separate M, X or Z).
-bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_device, hipStream_t s,
-                  owqs_status &st) {
-  st = OWQS_OK;
-  if (p->dirty) compile(p);
-  for (const Step &x : p->xsteps)
-    if (x.kind == S_M || x.kind == S_X || x.kind == S_Z) return false;
-  for (const FuseOp &op : p->fuse_ops)
-    if (op.kind == DK_X || op.kind == DK_Z) return false;
-  const size_t nm = std::max<size_t>(p->n_meas, 1);
-  std::vector<int> outc(nm, 0), fold(3 * nm, 0);
-  std::vector<float2> coef(nm, make_float2(1.f, 0.f));
-  auto sig = [&](SigRef r) {
-    int v = 0;
-    for (int k = 0; k < r.len; ++k) v ^= outc[p->s_dom[r.off + k]];
-    return v & 1;
-  };
-  for (const owqs_pattern::SStep &x : p->s_steps) {
-    if (x.kind != S_J) continue;
-    const int o = p->uniforms[x.m] <= 0.5 ? 0 : 1;
-    const double theta = (sig(x.s) ? -x.alpha : x.alpha) + (sig(x.t) ? M_PI : 0.0);  // Eq. 2
-    double cr = std::cos(theta), ci = -std::sin(theta);                                // Eqs. 11-12
-    if (o) { cr = -cr; ci = -ci; }
-    outc[x.m] = o;
-    coef[x.m] = make_float2((float)cr, (float)ci);
-    int i0 = 0, s0 = 1, s1 = 1;
-    for (int k = 0; k < x.fold_len; ++k) {
-      const FoldRef &f = p->s_folds[x.fold_off + k];
-      if (!sig(f.sig)) continue;
-      if (f.x) {
-        i0 ^= 1;
-        std::swap(s0, s1);
-      } else {
-        s1 = -s1;
-      }
-    }
-    fold[3 * x.m] = i0;
-    fold[3 * x.m + 1] = s0 < 0;
-    fold[3 * x.m + 2] = s1 < 0;
-  }
-  hipError_t e = hipSuccess;
-  const size_t cbytes = (nm * sizeof(float2) + 255) & ~size_t(255);
-  const size_t need = cbytes + 3 * nm * sizeof(int);
-  if (p->a_cap < need) {
-    if (p->a_mem) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p->a_mem);
-    }
-    if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
-    if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
-    p->a_mem = nullptr;
-    p->a_cap = 0;
-    e = hipMalloc(&p->a_mem, need);
-    if (e != hipSuccess) { st = fail(p->ctx, OWQS_E_NOMEM, "drawn-window tables"); return true; }
-    p->a_cap = need;
-  }
-  float2 *ctab = static_cast<float2 *>(p->a_mem);
-  int *ftab = reinterpret_cast<int *>(static_cast<char *>(p->a_mem) + cbytes);
-  // synchronous: the previous run may still read the tables
-  e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = hipMemcpy(ctab, coef.data(), nm * sizeof(float2), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ftab, fold.data(), 3 * nm * sizeof(int), hipMemcpyHostToDevice);
-  if (e == hipSuccess && p->n_meas)
-    e = hipMemcpy(sample_mem(p).outc, outc.data(), p->n_meas * sizeof(int), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "drawn-window tables"); return true; }
-  st = upload_fuse(p);
-  if (st != OWQS_OK) return true;
-  end_ranged(p);
-  const size_t nin = p->inputs.size();
-  e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
-  if (e == hipSuccess && (nin > 0 || input != nullptr))
-    e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
-                       input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "input"); return true; }
-  if (p->use_graph && !p->xsteps.empty()) {
-    if (!p->a_exec) {
-      if (!p->cap_stream) {
-        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) { st = hip_fail(p->ctx, e, "capture stream"); return true; }
-      }
-      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) { st = hip_fail(p->ctx, e, "begin capture"); return true; }
-      hipError_t le = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, p->cap_stream, nullptr, ctab, ftab);
-      e = hipStreamEndCapture(p->cap_stream, &p->a_graph);
-      if (le != hipSuccess) e = le;
-      if (e == hipSuccess) e = hipGraphInstantiate(&p->a_exec, p->a_graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
-        p->a_exec = nullptr;
-        st = hip_fail(p->ctx, e, "graph capture");
-        return true;
-      }
-    }
-    e = hipGraphLaunch(p->a_exec, s);
-  } else {
-    e = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, s, nullptr, ctab, ftab);
-  }
-  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "kernel launch"); return true; }
-  p->ran = true;
-  p->ss_ran = false;
-  p->batch_ran = false;
-  p->out_in_order = false;
-  p->sampled_ran = true;
-  p->an_ran = true;
-  p->ran_mode = kReduceRenorm;
-  return true;
-}
-
-owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream) {
-  const size_t nin = p->inputs.size();
-  if (owqs_status w = width_guard(p)) return w;
-  const size_t want = size_t(1) << nin;
-  if (n_amps != want) return fail(p->ctx, OWQS_E_INVALID_ARG, "input size must be 2^(number of inputs)");
-  if (nin > 0 && !input) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input");
-  if (p->mode != OWQS_MODE_OWQS) return fail(p->ctx, OWQS_E_STATE, "drawn outcomes need OWQS mode (probabilities)");
-  owqs_status st = ensure_device(p);
-  if (st != OWQS_OK) return st;
-  if (!p->s_valid) compile_sampled(p);
-  const size_t nm = std::max<size_t>(p->n_meas, 1);
-  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t need = up(nm * sizeof(double)) + up(nm * sizeof(int)) + 256 +
-                      up(std::max<size_t>(p->s_dom.size(), 1) * sizeof(int)) +
-                      up(std::max<size_t>(p->s_folds.size(), 1) * sizeof(FoldRef));
-  hipError_t e = hipSuccess;
-  if (p->s_cap < need) {
-    if (p->s_mem) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p->s_mem);
-    }
-    p->s_mem = nullptr;
-    p->s_cap = 0;
-    e = hipMalloc(&p->s_mem, need);
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sampling tables");
-    p->s_cap = need;
-    p->s_uploaded = false;
-    if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
-    if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
-  }
-  const SampleMem sm = sample_mem(p);
-  if (!p->s_uploaded) {  // synchronous: the host tables may change after this call
-    if (p->n_meas) e = hipMemcpy(sm.u, p->uniforms.data(), p->n_meas * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !p->s_dom.empty())
-      e = hipMemcpy(sm.dom, p->s_dom.data(), p->s_dom.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !p->s_folds.empty())
-      e = hipMemcpy(sm.folds, p->s_folds.data(), p->s_folds.size() * sizeof(FoldRef), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "sampling tables upload");
-    p->s_uploaded = true;
-  }
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (p->s_analytic && p->exec != OWQS_EXEC_PLAIN) {
-    owqs_status ast = OWQS_OK;
-    if (run_analytic(p, input, want, input_on_device, s, ast)) return ast;
-  }
-  end_ranged(p);
-  e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
-  if (e == hipSuccess && (nin > 0 || input != nullptr))
-    e = hipMemcpyAsync(p->psi, input, want * sizeof(float2),
-                       input_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "input");
-  if (p->use_graph && !p->s_steps.empty()) {
-    if (!p->s_exec) {
-      if (!p->cap_stream) {
-        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return hip_fail(p->ctx, e, "capture stream");
-      }
-      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return hip_fail(p->ctx, e, "begin capture");
-      hipError_t le = launch_sampled(p, p->cap_stream);
-      e = hipStreamEndCapture(p->cap_stream, &p->s_graph);
-      if (le != hipSuccess) e = le;
-      if (e == hipSuccess) e = hipGraphInstantiate(&p->s_exec, p->s_graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
-        p->s_exec = nullptr;
-        return hip_fail(p->ctx, e, "graph capture");
-      }
-    }
-    e = hipGraphLaunch(p->s_exec, s);
-  } else {
-    e = launch_sampled(p, s);
-  }
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "kernel launch");
-  p->ran = true;
-  p->ss_ran = false;
-  p->batch_ran = false;
-  p->out_in_order = false;
-  p->sampled_ran = true;
-  p->an_ran = false;
-  p->ran_mode = kReduceRenorm;
-  return OWQS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// sub-state executor runs
-// ---------------------------------------------------------------------------
-// With `ev`: ev[2i] before step i's main kernel, ev[2i+1] after it, ev[2i+2]
-// after the step (its FP64 finishing kernel, if any).
-hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev = nullptr) {
-  hipError_t e = launch_sub_start(p->ss_sigma, (int)p->ss_chains.size(), p->book.err, s);
-  if (ev && e == hipSuccess) e = hipEventRecord((*ev)[0], s);
-  for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
-    const SubStep &x = p->ss_steps[i];
-    if (ev && i > 0) e = hipEventRecord((*ev)[2 * i], s);
-    if (e != hipSuccess) break;
-    float2 *psi = p->ss_mem + p->ss_chains[x.chain].off;
-    switch (x.kind) {
-      case SS_INIT: e = launch_sub_init(psi, s); break;
-      case SS_N: e = launch_prepare(psi, x.n, s); break;
-      case SS_E: e = launch_cz(psi, x.n, x.b0, x.b1, s); break;
-      case SS_X: e = launch_pauli_x(psi, x.n, x.b0, s); break;
-      case SS_Z: e = launch_pauli_z(psi, x.n, x.b0, s); break;
-      case SS_KRON:
-        e = launch_kron(psi, x.n, p->ss_mem + p->ss_chains[x.top].off, x.top_n, p->ss_sigma + x.chain,
-                        p->ss_sigma + x.top, s);
-        break;
-      case SS_M:
-      case SS_J: {
-        MeasureArgs a{};
-        a.reduce = reduce;
-        a.book = p->book;
-        a.book.sigma = p->ss_sigma + x.chain;
-        a.coef = x.coef;
-        a.host_factor = x.host_factor;
-        a.m_index = x.m_index;
-        unsigned grid = 0;
-        e = x.kind == SS_M ? launch_measure(psi, x.n, x.b0, a, s, &grid)
-                           : launch_jwindow(psi, x.n, x.b0, a, x.win, s, &grid);
-        if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
-        if (e == hipSuccess) e = launch_finish(a, grid, s);
-        break;
-      }
-      default: break;
-    }
-    if (ev && x.kind != SS_M && x.kind != SS_J && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
-    if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
-  }
-  return e;
-}
-
-// Algorithmic bytes of one sub-state step (element level, complex64).
-double substep_bytes(const SubStep &x) {
-  const double a = std::ldexp(8.0, x.n);
-  switch (x.kind) {
-    case SS_N: return 2.0 * a;
-    case SS_E: return 0.5 * a;
-    case SS_M: return 1.5 * a;
-    case SS_X: return 2.0 * a;
-    case SS_Z: return 1.0 * a;
-    case SS_KRON: return a + std::ldexp(8.0, x.top_n) + std::ldexp(8.0, x.n + x.top_n);
-    case SS_J: return 2.0 * a;
-  }
-  return 0.0;
-}
-
-bool substates(const owqs_pattern *p) { return p->exec == OWQS_EXEC_SUBSTATES; }
-
-owqs_status refuse_substates(owqs_pattern *p, const char *what) {
-  return fail(p->ctx, OWQS_E_STATE, std::string(what) + " does not run the sub-state executor (OWQS_EXEC_SUBSTATES)");
-}
-
-// Input factor k (2^nqs[k] complex64) holds the next nqs[k] inputs.
-owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int32_t *nqs, size_t nf,
-                          int on_device, void *stream, Profile *prof = nullptr) {
-  if (nf && (!factors || !nqs)) return fail(p->ctx, OWQS_E_INVALID_ARG, "null input factors");
-  size_t total = 0;
-  for (size_t k = 0; k < nf; ++k) {
-    if (nqs[k] < 1 || nqs[k] > OWQS_MAX_WIDTH || !factors[k])
-      return fail(p->ctx, OWQS_E_INVALID_ARG, "input factor with no qubits, too many, or no data");
-    total += (size_t)nqs[k];
-  }
-  if (total != p->inputs.size()) return fail(p->ctx, OWQS_E_INVALID_ARG, "input factors must cover the inputs");
-  std::vector<int32_t> want(nqs, nqs + nf);
-  if (nf == 1) want.clear();  // one factor is the default plan
-  if (want != p->ss_in_nq) {
-    p->ss_in_nq = want;
-    p->dirty = true;
-  }
-  if (p->sampling) return fail(p->ctx, OWQS_E_STATE, "drawn outcomes do not run the sub-state executor");
-  owqs_status st = ensure_device(p, false);  // compiles the sub-state plan and checks its width
-  if (st != OWQS_OK) return st;
-  if (p->dirty) compile(p);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
-  const size_t arena = std::max<size_t>(p->ss_arena, 64);
-  if (p->ss_mem_cap < arena) {
-    drop_ss_graph(p);
-    if (p->ss_mem) (void)hipFree(p->ss_mem);
-    p->ss_mem = nullptr;
-    p->ss_mem_cap = 0;
-    e = hipMalloc(&p->ss_mem, arena * sizeof(float2));
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, std::string("sub-state arena: ") + hipGetErrorString(e));
-    p->ss_mem_cap = arena;
-  }
-  if (p->ss_sigma_cap < std::max<size_t>(p->ss_chains.size(), 1)) {
-    drop_ss_graph(p);
-    if (p->ss_sigma) (void)hipFree(p->ss_sigma);
-    p->ss_sigma = nullptr;
-    p->ss_sigma_cap = 0;
-    const size_t n = std::max<size_t>(p->ss_chains.size(), 1);
-    e = hipMalloc(&p->ss_sigma, n * sizeof(double));
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sub-state scales");
-    p->ss_sigma_cap = n;
-  }
-  end_ranged(p);
-  p->sampled_ran = false;
-  p->ran = false;
-  p->ss_ran = false;
-  for (size_t k = 0; k < nf; ++k) {
-    e = hipMemcpyAsync(p->ss_mem + p->ss_chains[k].off, factors[k], (size_t(1) << nqs[k]) * sizeof(float2),
-                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "input copy");
-  }
-  const int reduce = p->mode == OWQS_MODE_OWQS ? kReduceRenorm
-                     : p->mode == OWQS_MODE_EOWQS_CHECK ? kReduceCheck
-                                                        : kReduceNone;
-  std::vector<hipEvent_t> ev;
-  if (prof) {
-    ev.resize(2 * p->ss_steps.size() + 1);
-    for (auto &x : ev) {
-      e = hipEventCreate(&x);
-      if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
-    }
-    e = launch_substeps(p, reduce, s, &ev);
-  } else if (p->use_graph) {
-    if (p->ss_exec && p->ss_graph_reduce != reduce) drop_ss_graph(p);
-    if (!p->ss_exec) {
-      if (!p->cap_stream) {
-        e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return hip_fail(p->ctx, e, "capture stream");
-      }
-      e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return hip_fail(p->ctx, e, "begin capture");
-      hipError_t le = launch_substeps(p, reduce, p->cap_stream);
-      e = hipStreamEndCapture(p->cap_stream, &p->ss_graph);
-      if (le != hipSuccess) e = le;
-      if (e == hipSuccess) e = hipGraphInstantiate(&p->ss_exec, p->ss_graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        if (p->ss_graph) { (void)hipGraphDestroy(p->ss_graph); p->ss_graph = nullptr; }
-        p->ss_exec = nullptr;
-        return hip_fail(p->ctx, e, "graph capture");
-      }
-      p->ss_graph_reduce = reduce;
-    }
-    e = hipGraphLaunch(p->ss_exec, s);
-  } else {
-    e = launch_substeps(p, reduce, s);
-  }
-  if (e != hipSuccess) {
-    for (auto &x : ev) (void)hipEventDestroy(x);
-    return hip_fail(p->ctx, e, "kernel launch");
-  }
-  p->ran = true;
-  p->ss_ran = true;
-  p->batch_ran = false;
-  p->out_in_order = false;
-  p->ran_mode = reduce;
-  if (prof) {
-    static const int kind_of[] = {-1, OWQS_KIND_N, OWQS_KIND_E, OWQS_KIND_X, OWQS_KIND_Z, OWQS_KIND_M,
-                                  OWQS_KIND_KRON, OWQS_KIND_J};
-    e = hipStreamSynchronize(s);
-    for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
-      const SubStep &x = p->ss_steps[i];
-      float t = 0.f, f = 0.f;
-      e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
-      if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * i + 1], ev[2 * i + 2]);
-      const int k = kind_of[x.kind];
-      if (k < 0) continue;  // a new sub-state's scalar 1
-      prof->counts[k] += 1;
-      prof->ms[k] += t;
-      prof->bytes[k] += substep_bytes(x);
-      if ((x.kind == SS_M || x.kind == SS_J) && reduce != kReduceNone) {
-        prof->counts[OWQS_KIND_FINISH] += 1;
-        prof->ms[OWQS_KIND_FINISH] += f;
-      }
-    }
-    for (auto &x : ev) (void)hipEventDestroy(x);
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "profile events");
-  }
-  return OWQS_OK;
-}
-
-// Read every factor (scaled, its qubits in output order) and the scalar of
-// the vanished sub-states into ss_stage: factor f at offs[f], the scalar at
-// offs.back().
-owqs_status stage_substates(owqs_pattern *p, hipStream_t s, std::vector<uint64_t> &offs) {
-  offs.clear();
-  uint64_t at = 0;
-  for (const SubFactor &f : p->ss_factors) {
-    offs.push_back(at);
-    at += uint64_t(1) << f.qubits.size();
-  }
-  offs.push_back(at);
-  const size_t need = at + std::max<size_t>(p->ss_vanished.size(), 1);
-  hipError_t e = hipSuccess;
-  if (p->ss_stage_cap < need) {
-    if (p->ss_stage) {
-      (void)hipStreamSynchronize(s);
-      (void)hipFree(p->ss_stage);
-    }
-    p->ss_stage = nullptr;
-    p->ss_stage_cap = 0;
-    e = hipMalloc(&p->ss_stage, need * sizeof(float2));
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sub-state read-out buffer");
-    p->ss_stage_cap = need;
-  }
-  const bool renorm = p->ran_mode == kReduceRenorm;
-  for (size_t k = 0; k < p->ss_factors.size() && e == hipSuccess; ++k) {
-    const SubFactor &f = p->ss_factors[k];
-    const SubChain &c = p->ss_chains[f.chain];
-    e = launch_read(p->ss_mem + c.off, p->ss_stage + offs[k], (int)f.qubits.size(), f.where.data(), c.pend,
-                    renorm ? p->ss_sigma + f.chain : nullptr, s);
-  }
-  for (size_t k = 0; k < p->ss_vanished.size() && e == hipSuccess; ++k) {
-    const int v = p->ss_vanished[k];
-    const SubChain &c = p->ss_chains[v];
-    e = launch_read(p->ss_mem + c.off, p->ss_stage + offs.back() + k, 0, nullptr, c.pend,
-                    renorm ? p->ss_sigma + v : nullptr, s);
-  }
-  if (e == hipSuccess) e = launch_cprod(p->ss_stage + offs.back(), (int)p->ss_vanished.size(), s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "sub-state read");
-  return OWQS_OK;
 }
 
 owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int input_on_device, void *stream,
@@ -2087,7 +943,7 @@ bool parse_text(const char *text, size_t len, std::vector<owqs_cmd> &cmds, std::
   return true;
 }
 
-}  // namespace
+}  // namespace owqs
 
 // ===========================================================================
 // C ABI
@@ -2559,256 +1415,6 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
   return OWQS_OK;
 }
 
-owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *alpha, size_t batch,
-                         const int32_t *obs, int32_t nobs, double *loss, double *grad, int32_t ckpt_stride,
-                         void *stream) {
-  if (!p || !alpha || !loss || !grad || batch == 0 || (nobs && !obs) || nobs < 0)
-    return fail(p ? p->ctx : nullptr, OWQS_E_INVALID_ARG, "null pointer or bad size");
-  if (batch > 65535) return fail(p->ctx, OWQS_E_INVALID_ARG, "batch above 65535");
-  if (substates(p)) return refuse_substates(p, "owqs_adjoint");
-  if (!p->inputs.empty() && !input_c64) return fail(p->ctx, OWQS_E_INVALID_ARG, "the pattern needs an input state");
-  for (int32_t k = 0; k < nobs; ++k)
-    if (obs[k] < 0 || obs[k] >= (int32_t)p->outputs.size())
-      return fail(p->ctx, OWQS_E_INVALID_ARG, "observable index outside the outputs");
-  owqs_status st = ensure_device(p, false);
-  if (st != OWQS_OK) return st;
-  end_ranged(p);
-  if (p->exec == OWQS_EXEC_PLAIN) {
-    p->exec = OWQS_EXEC_AUTO;
-    p->dirty = true;
-  }
-  if (p->dirty) compile(p);
-  // structure: a prefix without measurements, then windows and E/X/Z steps
-  const size_t ns = p->steps.size();
-  size_t fw = ns;
-  for (size_t i = 0; i < ns; ++i) {
-    if (p->steps[i].kind == S_J) { fw = i; break; }
-    if (p->steps[i].kind == S_M)
-      return fail(p->ctx, OWQS_E_STATE, "adjoint: a measurement outside an N-E-M window comes before the first window");
-  }
-  std::vector<size_t> wins;
-  for (size_t i = fw; i < ns; ++i) {
-    const int k = p->steps[i].kind;
-    if (k == S_J) wins.push_back(i);
-    else if (k == S_N || k == S_M)
-      return fail(p->ctx, OWQS_E_STATE, "adjoint: only windows and E/X/Z steps may follow the first window");
-  }
-  const int nw = fw < ns ? p->steps[fw].n : p->plan_width;
-  const int W = p->plan_width;
-  const size_t stride = size_t(1) << W;
-  const size_t nwin = wins.size();
-  const int cs = ckpt_stride != 0 ? (ckpt_stride > 0 ? ckpt_stride : -ckpt_stride) : 16;
-  const size_t nseg = nwin ? (nwin + cs - 1) / cs : 0;
-  const unsigned nblk = adj_blocks(nw);
-  const unsigned lblk = loss_blocks((int)p->outputs.size());
-  // windows with an odd number of E between their two qubits are invertible:
-  // the reverse sweep then recovers each window's input from its output
-  // (no forward recompute, no stash), restarting from the forward checkpoint
-  // at every segment so that rounding cannot build up over more than one
-  bool reversible = ckpt_stride >= 0;  // a negative stride asks for the recompute sweep
-  for (size_t q : wins) reversible = reversible && !p->steps[q].win.vw_even;
-  // the reversing sweep walks the grouped plan: a tile group runs on every
-  // set in one launch, forward and backward.  Partials of window q, set b sit
-  // in row (q * batch + b) of nblk_row blocks (at least every launch's grid).
-  unsigned nblk_row = nblk;
-  if (reversible)
-    for (const TileGroup &tg : p->groups) nblk_row = std::max(nblk_row, tile_grid(tg.ta));
-  // device memory: psi, lam, checkpoints, stash, partials, coefs, cols, scales
-  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };  // keep every region 256-byte aligned
-  const size_t vec = up(batch * stride * sizeof(float2));
-  // the grouped plan checkpoints at the first unit start after every cs
-  // windows, so each interval but the last holds at least cs windows
-  const size_t nckpt_cap = reversible ? nseg + 1 : nseg;
-  const size_t off_lam = vec, off_ckpt = 2 * vec, off_stash = off_ckpt + nckpt_cap * vec;
-  const size_t off_part = off_stash + (reversible ? 0 : size_t(cs)) * vec;
-  const size_t npart = std::max<size_t>(nwin * batch * nblk_row, batch * lblk);
-  const size_t nm = std::max<size_t>(p->n_meas, 1);
-  const size_t off_coef = off_part + up(npart * sizeof(double));
-  const size_t off_cols = off_coef + up(nm * batch * sizeof(float2));
-  const size_t off_scale = off_cols + up((std::max<size_t>(nwin, 1) + 1) * sizeof(int));
-  const size_t total = off_scale + up((std::max<size_t>(nwin, 1) + 1) * sizeof(double));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
-  if (p->adj_cap < total) {
-    if (p->adj_mem) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p->adj_mem);
-    }
-    p->adj_mem = nullptr;
-    p->adj_cap = 0;
-    e = hipMalloc(&p->adj_mem, total);
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "adjoint buffers");
-    p->adj_cap = total;
-  } else {
-    e = hipStreamSynchronize(s);  // the host tables below are reused
-    if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint");
-  }
-  char *base = static_cast<char *>(p->adj_mem);
-  float2 *psi = reinterpret_cast<float2 *>(base);
-  float2 *lam = reinterpret_cast<float2 *>(base + off_lam);
-  auto ckpt = [&](size_t j) { return reinterpret_cast<float2 *>(base + off_ckpt + j * vec); };
-  auto stash = [&](size_t j) { return reinterpret_cast<float2 *>(base + off_stash + j * vec); };
-  double *part = reinterpret_cast<double *>(base + off_part);
-  float2 *coefs = reinterpret_cast<float2 *>(base + off_coef);  // [m_index * batch + set]
-  int *cols = reinterpret_cast<int *>(base + off_cols);
-  double *scales = reinterpret_cast<double *>(base + off_scale);
-  // per-set window coefficients c = (-1)^o e^{-i theta}, theta = (-1)^s alpha + t pi (Eq. 2)
-  p->adj_coefs.assign(nm * batch, make_float2(0.f, 0.f));
-  p->adj_cols.assign(std::max<size_t>(nwin, 1) + 1, 0);
-  p->adj_scale.assign(std::max<size_t>(nwin, 1) + 1, 1.0);
-  for (size_t q = 0; q < nwin; ++q) {
-    const Step &x = p->steps[wins[q]];
-    for (size_t b = 0; b < batch; ++b) {
-      const double a = alpha[b * p->n_meas + x.m_index];
-      const double th = (x.sig_s ? -a : a) + (x.sig_t ? M_PI : 0.0);
-      double cr = std::cos(th), ci = -std::sin(th);
-      if (x.outcome) { cr = -cr; ci = -ci; }
-      p->adj_coefs[size_t(x.m_index) * batch + b] = make_float2((float)cr, (float)ci);
-    }
-    p->adj_cols[q] = x.m_index;
-    p->adj_scale[q] = x.sig_s ? -1.0 : 1.0;  // dtheta/dalpha
-  }
-  e = hipMemcpyAsync(coefs, p->adj_coefs.data(), p->adj_coefs.size() * sizeof(float2), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(cols, p->adj_cols.data(), p->adj_cols.size() * sizeof(int), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(scales, p->adj_scale.data(), p->adj_scale.size() * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(grad, 0, batch * std::max(p->n_meas, 1) * sizeof(double), s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint tables");
-  auto dev_step = [](const Step &x) {
-    DevStep d{};
-    d.kind = (uint8_t)x.kind;
-    d.n = (uint8_t)x.n;
-    d.b0 = (uint8_t)x.b0;
-    d.b1 = (uint8_t)x.b1;
-    d.m_index = x.m_index;
-    d.host_factor = (float)x.host_factor;
-    d.pp = (x.win.swap ? 1u : 0u) | (x.win.neg0 ? 2u : 0u) | (x.win.neg1 ? 4u : 0u) | (x.win.vw_even ? 8u : 0u);
-    d.mask_b = x.win.mask_b;
-    d.mask_o1 = x.win.mask_o1;
-    return d;
-  };
-  std::vector<DevStep> d(ns);
-  for (size_t i = 0; i < ns; ++i) d[i] = dev_step(p->steps[i]);
-  std::vector<size_t> win_of(ns, SIZE_MAX);
-  for (size_t q = 0; q < nwin; ++q) win_of[wins[q]] = q;
-  const int nsets = (int)batch;
-  const size_t seg_bytes = vec;
-  std::vector<int> obs_bits(nobs);
-  for (int32_t k = 0; k < nobs; ++k) obs_bits[k] = p->final_where[obs[k]];
-  auto loss_and_seed = [&]() {
-    // loss and the adjoint seed lambda = ff^2 W psi; the loss reduction reads
-    // `part` before the window partials overwrite it (same stream), and
-    // cols[nwin] = 0, scales[nwin] = 1 were uploaded above
-    hipError_t r = launch_b_loss(psi, lam, stride, nsets, (int)p->outputs.size(), obs_bits.data(), nobs,
-                                 p->final_factor * p->final_factor, part, s);
-    if (r == hipSuccess) r = launch_b_reduce(part, 1, nsets, (int)lblk, cols + nwin, scales + nwin, loss, 1, s);
-    return r;
-  };
-  e = launch_b_init(psi, stride, nsets, (int)p->inputs.size(), static_cast<const float2 *>(input_c64), s);
-  if (reversible) {
-    owqs_status us = upload_fuse(p);
-    if (us != OWQS_OK) return us;
-    const std::vector<Step> &xs = p->xsteps;
-    const size_t nx = xs.size();
-    // units of the grouped plan: windows they hold, first window index
-    std::vector<size_t> unit_wins(nx, 0), unit_q(nx, 0);
-    for (size_t u = 0, q = 0; u < nx; ++u) {
-      unit_q[u] = q;
-      unit_wins[u] = xs[u].kind == S_F ? size_t(p->groups[xs[u].group].ta.nwin) : xs[u].kind == S_J ? 1 : 0;
-      q += unit_wins[u];
-    }
-    // forward, with a checkpoint at the start of a unit once cs more windows
-    // have gone by (the first at the first unit that holds a window)
-    std::vector<size_t> seg_start;
-    size_t done = 0, next = 0;
-    for (size_t u = 0; u < nx && e == hipSuccess; ++u) {
-      const Step &x = xs[u];
-      if (unit_wins[u] && done >= next) {
-        if (seg_start.size() == nckpt_cap) { e = hipErrorInvalidValue; break; }  // cannot happen (see nckpt_cap)
-        e = hipMemcpyAsync(ckpt(seg_start.size()), psi, seg_bytes, hipMemcpyDeviceToDevice, s);
-        seg_start.push_back(u);
-        next = done + size_t(cs);
-      }
-      if (e != hipSuccess) break;
-      if (x.kind == S_F) {
-        const TileGroup &tg = p->groups[x.group];
-        e = launch_tile_sets(psi, tg.ta, p->dev_fuse + tg.op_off, nsets, stride, coefs, s);
-      } else {
-        e = launch_b_step(dev_step(x), psi, stride, nsets,
-                          x.kind == S_J ? coefs + size_t(x.m_index) * batch : nullptr, s);
-      }
-      done += unit_wins[u];
-    }
-    if (e == hipSuccess) e = loss_and_seed();
-    // rows of blocks a launch does not fill must read as zero
-    if (e == hipSuccess && nwin) e = hipMemsetAsync(part, 0, nwin * batch * nblk_row * sizeof(double), s);
-    // backward, one segment at a time from its end state (the next segment's
-    // checkpoint, or the final state): each window recovers its input and
-    // moves lambda back in the same pass; E, X and Z are their own inverses
-    // and adjoints, applied to psi and lambda together (lam is the buffer
-    // after psi, so the two are 2 * batch sets of one array when vec holds
-    // exactly batch vectors)
-    const bool joint = vec == batch * stride * sizeof(float2) && 2 * batch <= 65535;
-    for (size_t j = seg_start.size(); j-- > 0 && e == hipSuccess;) {
-      const size_t first = seg_start[j], last = j + 1 < seg_start.size() ? seg_start[j + 1] : nx;
-      if (j + 1 < seg_start.size()) e = hipMemcpyAsync(psi, ckpt(j + 1), seg_bytes, hipMemcpyDeviceToDevice, s);
-      for (size_t u = last; u-- > first && e == hipSuccess;) {
-        const Step &x = xs[u];
-        if (x.kind == S_F) {
-          const TileGroup &tg = p->groups[x.group];
-          e = launch_tile_rev(psi, lam, tg.ta, p->dev_fuse + tg.op_off, nsets, stride, coefs, part, (int)unit_q[u],
-                              nblk_row, s);
-        } else if (x.kind == S_J) {
-          e = launch_b_window_rev(dev_step(x), psi, lam, stride, nsets, coefs + size_t(x.m_index) * batch,
-                                  part + unit_q[u] * batch * nblk_row, nblk_row, s);
-        } else if (joint) {
-          e = launch_b_step(dev_step(x), psi, stride, 2 * nsets, nullptr, s);
-        } else {
-          e = launch_b_step(dev_step(x), psi, stride, nsets, nullptr, s);
-          if (e == hipSuccess) e = launch_b_step(dev_step(x), lam, stride, nsets, nullptr, s);
-        }
-      }
-    }
-  } else {
-    // forward: prefix, then the windowed part with a checkpoint at each segment start
-    for (size_t i = 0; i < ns && e == hipSuccess; ++i) {
-      const size_t q = win_of[i];
-      if (q != SIZE_MAX && q % cs == 0) e = hipMemcpyAsync(ckpt(q / cs), psi, seg_bytes, hipMemcpyDeviceToDevice, s);
-      if (e == hipSuccess)
-        e = launch_b_step(d[i], psi, stride, nsets, q != SIZE_MAX ? coefs + size_t(d[i].m_index) * batch : nullptr, s);
-    }
-    if (e == hipSuccess) e = loss_and_seed();
-    // backward, one segment at a time: restore, recompute with a stash of the
-    // window inputs, then sweep lambda back through the segment
-    for (size_t j = nseg; j-- > 0 && e == hipSuccess;) {
-      const size_t first = wins[j * cs];
-      const size_t last = (j + 1) * cs < nwin ? wins[(j + 1) * cs] : ns;
-      e = hipMemcpyAsync(psi, ckpt(j), seg_bytes, hipMemcpyDeviceToDevice, s);
-      for (size_t i = first; i < last && e == hipSuccess; ++i) {
-        const size_t q = win_of[i];
-        if (q != SIZE_MAX) e = hipMemcpyAsync(stash(q - j * cs), psi, seg_bytes, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-          e = launch_b_step(d[i], psi, stride, nsets, q != SIZE_MAX ? coefs + size_t(d[i].m_index) * batch : nullptr,
-                            s);
-      }
-      for (size_t i = last; i-- > first && e == hipSuccess;) {
-        const size_t q = win_of[i];
-        if (q != SIZE_MAX)
-          e = launch_b_window_adj(d[i], stash(q - j * cs), lam, stride, nsets, coefs + size_t(d[i].m_index) * batch,
-                                  part + q * batch * nblk, s);
-        else
-          e = launch_b_step(d[i], lam, stride, nsets, nullptr, s);  // E, X, Z are self-adjoint
-      }
-    }
-  }
-  if (e == hipSuccess && nwin)
-    e = launch_b_reduce(part, (int)nwin, nsets, (int)(reversible ? nblk_row : nblk), cols, scales, grad,
-                        (size_t)p->n_meas, s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "adjoint");
-  return OWQS_OK;
-}
-
 owqs_status owqs_check(owqs_pattern *p, void *stream) {
   if (!p) return OWQS_E_INVALID_ARG;
   if (!p->ran && !p->batch_ran && !p->lk_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
@@ -2895,65 +1501,6 @@ owqs_status owqs_read_state(owqs_pattern *p, void *out, size_t n_amps, int out_o
   return owqs_check(p, stream);
 }
 
-owqs_status owqs_set_input_factors(owqs_pattern *p, const int32_t *factor_nq, size_t nfactors) {
-  if (!p || (nfactors && !factor_nq)) return OWQS_E_INVALID_ARG;
-  size_t total = 0;
-  for (size_t k = 0; k < nfactors; ++k) {
-    if (factor_nq[k] < 1 || factor_nq[k] > OWQS_MAX_WIDTH)
-      return fail(p->ctx, OWQS_E_INVALID_ARG, "an input factor holds 1 .. OWQS_MAX_WIDTH qubits");
-    total += (size_t)factor_nq[k];
-  }
-  if (nfactors && total != p->inputs.size())
-    return fail(p->ctx, OWQS_E_INVALID_ARG, "input factors must cover the inputs");
-  std::vector<int32_t> want(factor_nq, factor_nq + nfactors);
-  if (nfactors == 1) want.clear();
-  if (want != p->ss_in_nq) {
-    p->ss_in_nq = want;
-    if (substates(p)) p->dirty = true;
-  }
-  return OWQS_OK;
-}
-
-owqs_status owqs_run_factors(owqs_pattern *p, const void *const *factors, const int32_t *factor_nq, size_t nfactors,
-                             int input_on_device, void *stream) {
-  if (!p) return OWQS_E_INVALID_ARG;
-  if (!substates(p)) return fail(p->ctx, OWQS_E_STATE, "input factors need the sub-state executor (OWQS_EXEC_SUBSTATES)");
-  return run_substates(p, factors, factor_nq, nfactors, input_on_device, stream);
-}
-
-owqs_status owqs_read_substates(owqs_pattern *p, void *out_c64, size_t amp_cap, int32_t *factor_nq, int32_t *qubits,
-                                size_t factor_cap, int32_t *n_factors, size_t *n_amps, void *scalar_c64,
-                                void *stream) {
-  if (!p) return OWQS_E_INVALID_ARG;
-  if (!p->ss_ran) return fail(p->ctx, OWQS_E_STATE, "the last run did not use the sub-state executor");
-  size_t amps = 0;
-  for (const SubFactor &f : p->ss_factors) amps += size_t(1) << f.qubits.size();
-  if (n_factors) *n_factors = (int32_t)p->ss_factors.size();
-  if (n_amps) *n_amps = amps;
-  if (factor_nq || qubits) {
-    if (factor_cap < p->ss_factors.size()) return fail(p->ctx, OWQS_E_INVALID_ARG, "factor arrays too small");
-    size_t k = 0;
-    for (size_t f = 0; f < p->ss_factors.size(); ++f) {
-      if (factor_nq) factor_nq[f] = (int32_t)p->ss_factors[f].qubits.size();
-      for (int q : p->ss_factors[f].qubits)
-        if (qubits) qubits[k++] = p->user_id[q];
-    }
-  }
-  if (!out_c64 && !scalar_c64) return OWQS_OK;
-  if (out_c64 && amp_cap < amps) return fail(p->ctx, OWQS_E_INVALID_ARG, "amplitude buffer too small");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<uint64_t> offs;
-  owqs_status st = stage_substates(p, s, offs);
-  if (st != OWQS_OK) return st;
-  hipError_t e = hipSuccess;
-  if (out_c64 && amps) e = hipMemcpyAsync(out_c64, p->ss_stage, amps * sizeof(float2), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && scalar_c64)
-    e = hipMemcpyAsync(scalar_c64, p->ss_stage + offs.back(), sizeof(float2), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "sub-state read");
-  return owqs_check(p, stream);
-}
-
 owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void *stream) {
   if (!p || (n_meas && !probs)) return OWQS_E_INVALID_ARG;
   if (!p->ran && !p->batch_ran && !p->lk_ran) return fail(p->ctx, OWQS_E_STATE, "no run yet");
@@ -2967,64 +1514,6 @@ owqs_status owqs_read_probs(owqs_pattern *p, double *probs, size_t n_meas, void 
   if (n_meas) e = hipMemcpyAsync(probs, p->book.probs, n_meas * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "read probs");
-  return OWQS_OK;
-}
-
-// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k (k = 0, 1, ...)
-// of the generator started at `seed` is mix(seed + (k + 1) * gamma); the
-// outcome of the m-th M is the top bit of output m.
-owqs_status owqs_set_outcome_seed(owqs_pattern *p, uint64_t seed) {
-  if (!p) return OWQS_E_INVALID_ARG;
-  uint64_t x = seed;
-  for (int m = 0; m < p->n_meas; ++m) {
-    x += 0x9E3779B97F4A7C15ull;
-    uint64_t z = x;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    p->outcomes[m] = uint8_t(z >> 63);
-  }
-  p->dirty = true;
-  p->sampling = false;
-  return OWQS_OK;
-}
-
-owqs_status owqs_get_outcomes(const owqs_pattern *p, uint8_t *bits, size_t n_meas) {
-  if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
-  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
-  std::copy(p->outcomes.begin(), p->outcomes.end(), bits);
-  return OWQS_OK;
-}
-
-owqs_status owqs_set_uniforms(owqs_pattern *p, const double *u, size_t n_meas) {
-  if (!p) return OWQS_E_INVALID_ARG;
-  if (!u) {
-    if (n_meas) return OWQS_E_INVALID_ARG;
-    p->sampling = false;
-    return OWQS_OK;
-  }
-  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "uniform count != number of M commands");
-  for (size_t k = 0; k < n_meas; ++k)
-    if (!(u[k] >= 0.0 && u[k] < 1.0)) return fail(p->ctx, OWQS_E_INVALID_ARG, "uniforms must lie in [0, 1)");
-  // a run in flight may still read the device copy: let it finish first
-  if (p->s_mem && p->ctx->device >= 0) (void)hipDeviceSynchronize();
-  p->uniforms.assign(u, u + n_meas);
-  p->sampling = true;
-  p->s_uploaded = false;
-  return OWQS_OK;
-}
-
-owqs_status owqs_read_outcomes(owqs_pattern *p, uint8_t *bits, size_t n_meas, void *stream) {
-  if (!p || (n_meas && !bits)) return OWQS_E_INVALID_ARG;
-  if (n_meas != (size_t)p->n_meas) return fail(p->ctx, OWQS_E_INVALID_ARG, "outcome count != number of M commands");
-  if (!p->sampled_ran) return owqs_get_outcomes(p, bits, n_meas);
-  std::vector<int> o(std::max<size_t>(n_meas, 1));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
-  if (n_meas) e = hipMemcpyAsync(o.data(), sample_mem(p).outc, n_meas * sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "read outcomes");
-  for (size_t k = 0; k < n_meas; ++k) bits[k] = uint8_t(o[k] & 1);
   return OWQS_OK;
 }
 
@@ -3104,3 +1593,4 @@ owqs_status owqs_read_live(owqs_pattern *p, void *out_c64, size_t n_amps, int32_
 }
 
 }  // extern "C"
+
