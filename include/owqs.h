@@ -222,8 +222,9 @@ owqs_status owqs_tune(owqs_pattern *pat, const void *input_c64, size_t n_amps, i
  * the width of the window's input), its number of steps (one per
  * non-trivial command or fused window) and the number of passes over the
  * state in global memory (steps after grouping runs into tile passes).  For
- * the sub-state executor: the widest sub-state, and its steps (one kernel
- * each, both counts).  Any pointer may be NULL. */
+ * the sub-state executor: the widest sub-state, its steps, and its launches
+ * after each sub-state's runs of window/E/X/Z steps at width >= 15 are
+ * grouped into tile passes.  Any pointer may be NULL. */
 owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps, size_t *npasses);
 
 /* Recognition problem (Sec. 1: which unitary does a pattern implement):

@@ -95,32 +95,32 @@ int signal(const std::vector<int> &dom, const std::vector<int> &outcome_of) {
 // when a new mixing slot would not fit the tile, or when it holds the largest
 // number of windows that one pass may chain (16 when probabilities are
 // computed: the windows of a pass are not renormalised one by one, and 16
-// windows keep the FP32 norm in range down to p ~ 1e-4 per window).
-void group_tiles(owqs_pattern *p) {
-  p->xsteps.clear();
-  p->groups.clear();
-  p->fuse_ops.clear();
-  p->fuse_m.clear();
-  const size_t ns = p->steps.size();
-  const bool fused = p->exec != OWQS_EXEC_PLAIN;
-  const int win_cap = p->mode == OWQS_MODE_EOWQS ? kMaxGroupWindows : 16;
+// windows keep the FP32 norm in range down to p ~ 1e-4 per window).  The
+// result goes to `out`: a step that joins no group is copied unchanged (all
+// its fields), a group becomes one S_F step whose TileGroup is appended to
+// `groups`, its commands to `fops` and its windows' measurement indices to
+// `fm`.
+void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
+                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm) {
+  const size_t ns = steps.size();
+  const int win_cap = mode == OWQS_MODE_EOWQS ? kMaxGroupWindows : 16;
   auto groupable = [](int k) { return k == S_J || k == S_E || k == S_X || k == S_Z; };
   size_t i = 0;
   while (i < ns) {
-    const Step &x0 = p->steps[i];
-    if (!fused || !groupable(x0.kind) || x0.n < kTileMinWidth) {
-      p->xsteps.push_back(x0);
+    const Step &x0 = steps[i];
+    if (!groupable(x0.kind) || x0.n < kTileMinWidth) {
+      out.push_back(x0);
       ++i;
       continue;
     }
     const int n = x0.n;
     int k = std::max(kMinTileBits, std::min(kDefaultTileBits, n - 8));
-    if (p->tile_bits) k = std::min(p->tile_bits, n - 2);
+    if (tile_bits) k = std::min(tile_bits, n - 2);
     uint64_t tmask = (uint64_t(1) << kLowBits) - 1;
     int used = kLowBits, nwin = 0;
     size_t j = i;
     for (; j < ns; ++j) {
-      const Step &x = p->steps[j];
+      const Step &x = steps[j];
       if (!groupable(x.kind) || x.n != n) break;
       if (x.kind == S_J && nwin == win_cap) break;
       if (j - i == 128) break;
@@ -135,7 +135,7 @@ void group_tiles(owqs_pattern *p) {
       nwin += x.kind == S_J;
     }
     if (j - i < 2) {
-      p->xsteps.push_back(x0);
+      out.push_back(x0);
       ++i;
       continue;
     }
@@ -169,11 +169,11 @@ void group_tiles(owqs_pattern *p) {
           else om |= uint64_t(1) << b;
         }
     };
-    tg.op_off = p->fuse_ops.size();
-    tg.m_off = p->fuse_m.size();
+    tg.op_off = fops.size();
+    tg.m_off = fm.size();
     int widx = 0;
     for (size_t q = i; q < j; ++q) {
-      const Step &x = p->steps[q];
+      const Step &x = steps[q];
       FuseOp op{};
       op.kind = (uint8_t)x.kind;
       if (x.kind == S_J) {
@@ -182,7 +182,7 @@ void group_tiles(owqs_pattern *p) {
                    (widx == 0 ? 16 : 0);
         op.widx = (uint8_t)widx++;
         op.m_index = x.m_index;
-        p->fuse_m.push_back(x.m_index);
+        fm.push_back(x.m_index);
         op.coef = x.coef;
         op.f = (float)x.host_factor;
         split(x.win.mask_b, op.lmask_b, op.omask_b);
@@ -194,7 +194,7 @@ void group_tiles(owqs_pattern *p) {
       } else {  // S_Z
         split(uint64_t(1) << x.b0, op.lmask_b, op.omask_b);
       }
-      p->fuse_ops.push_back(op);
+      fops.push_back(op);
     }
     tg.ta.nops = (int)(j - i);
     tg.ta.nwin = widx;
@@ -202,22 +202,34 @@ void group_tiles(owqs_pattern *p) {
     // follow each other, possibly with an E or Z between (they cost occupancy
     // elsewhere)
     tg.ta.runs = 0;
-    for (size_t q = tg.op_off; q + 1 < p->fuse_ops.size(); ++q) {
-      const FuseOp &a = p->fuse_ops[q], &b = p->fuse_ops[q + 1];
+    for (size_t q = tg.op_off; q + 1 < fops.size(); ++q) {
+      const FuseOp &a = fops[q], &b = fops[q + 1];
       if (a.kind == S_J && b.kind == S_J && a.lb != b.lb) tg.ta.runs = 1;
       // a window, an E or Z, a window (the E / Z is applied between them)
-      if (q + 2 < p->fuse_ops.size() && a.kind == S_J && (b.kind == S_E || b.kind == S_Z) &&
-          p->fuse_ops[q + 2].kind == S_J && p->fuse_ops[q + 2].lb != a.lb)
+      if (q + 2 < fops.size() && a.kind == S_J && (b.kind == S_E || b.kind == S_Z) &&
+          fops[q + 2].kind == S_J && fops[q + 2].lb != a.lb)
         tg.ta.runs = 1;
     }
     Step gs{};
     gs.kind = S_F;
     gs.n = n;
-    gs.group = (int)p->groups.size();
-    p->groups.push_back(tg);
-    p->xsteps.push_back(gs);
+    gs.group = (int)groups.size();
+    groups.push_back(tg);
+    out.push_back(gs);
     i = j;
   }
+}
+
+void group_tiles(owqs_pattern *p) {
+  p->xsteps.clear();
+  p->groups.clear();
+  p->fuse_ops.clear();
+  p->fuse_m.clear();
+  if (p->exec == OWQS_EXEC_PLAIN) {
+    p->xsteps = p->steps;
+    return;
+  }
+  group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m);
 }
 
 // State after each command of a plain plan (for ranged runs).
@@ -638,31 +650,35 @@ hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<
 
 // Upload the tile groups' command table: FuseOps, then the windows'
 // measurement indices.
+owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, const std::vector<int> &fm,
+                              FuseOp *&dev, size_t &cap) {
+  static const hipError_t prep = tile_prepare();  // once per process, outside any capture
+  if (prep != hipSuccess) return hip_fail(ctx, prep, "tile kernel attribute");
+  const size_t mints = (fm.size() * sizeof(int) + sizeof(FuseOp) - 1) / sizeof(FuseOp);
+  const size_t need = std::max<size_t>(fops.size() + mints, 1);
+  hipError_t e = hipSuccess;
+  if (dev) (void)hipDeviceSynchronize();  // a run in flight may still read the old table
+  if (cap < need) {
+    if (dev) (void)hipFree(dev);
+    dev = nullptr;
+    cap = 0;
+    e = hipMalloc(&dev, need * sizeof(FuseOp));
+    if (e != hipSuccess) return fail(ctx, OWQS_E_NOMEM, "fused command table");
+    cap = need;
+  }
+  if (!fops.empty()) e = hipMemcpy(dev, fops.data(), fops.size() * sizeof(FuseOp), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !fm.empty())
+    e = hipMemcpy(reinterpret_cast<int *>(dev + fops.size()), fm.data(), fm.size() * sizeof(int),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fused command table upload");
+  return OWQS_OK;
+}
+
 owqs_status upload_fuse(owqs_pattern *p) {
   if (p->dev_fuse_valid) return OWQS_OK;
-  static const hipError_t prep = tile_prepare();  // once per process, outside any capture
-  if (prep != hipSuccess) return hip_fail(p->ctx, prep, "tile kernel attribute");
-  const size_t mints = (p->fuse_m.size() * sizeof(int) + sizeof(FuseOp) - 1) / sizeof(FuseOp);
-  const size_t need = std::max<size_t>(p->fuse_ops.size() + mints, 1);
-  hipError_t e = hipSuccess;
-  if (p->dev_fuse_cap < need) {
-    if (p->dev_fuse) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p->dev_fuse);
-    }
-    p->dev_fuse = nullptr;
-    p->dev_fuse_cap = 0;
-    e = hipMalloc(&p->dev_fuse, need * sizeof(FuseOp));
-    if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "fused command table");
-    p->dev_fuse_cap = need;
-  }
-  if (!p->fuse_ops.empty())
-    e = hipMemcpy(p->dev_fuse, p->fuse_ops.data(), p->fuse_ops.size() * sizeof(FuseOp), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !p->fuse_m.empty())
-    e = hipMemcpy(fuse_m_dev(p), p->fuse_m.data(), p->fuse_m.size() * sizeof(int), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(p->ctx, e, "fused command table upload");
-  p->dev_fuse_valid = true;
-  return OWQS_OK;
+  const owqs_status st = upload_fuse_table(p->ctx, p->fuse_ops, p->fuse_m, p->dev_fuse, p->dev_fuse_cap);
+  if (st == OWQS_OK) p->dev_fuse_valid = true;
+  return st;
 }
 
 // Upload the plan as a DevStep table (for the LDS-resident kernels).
@@ -1067,6 +1083,7 @@ void owqs_pattern_destroy(owqs_pattern *p) {
   if (p->a_exec) (void)hipGraphExecDestroy(p->a_exec);
   if (p->a_graph) (void)hipGraphDestroy(p->a_graph);
   if (p->ss_sigma) (void)hipFree(p->ss_sigma);
+  if (p->ss_dev_fuse) (void)hipFree(p->ss_dev_fuse);
   if (p->ss_stage) (void)hipFree(p->ss_stage);
   if (p->ss_exec) (void)hipGraphExecDestroy(p->ss_exec);
   if (p->ss_graph) (void)hipGraphDestroy(p->ss_graph);
@@ -1230,7 +1247,7 @@ owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps,
   if (p->dirty) compile(p);
   if (plan_width) *plan_width = p->plan_width;
   if (nsteps) *nsteps = substates(p) ? p->ss_steps.size() : p->steps.size();
-  if (npasses) *npasses = substates(p) ? p->ss_steps.size() : p->xsteps.size();
+  if (npasses) *npasses = substates(p) ? p->ss_run.size() : p->xsteps.size();
   return OWQS_OK;
 }
 

@@ -73,6 +73,14 @@ struct SubStep {
   Window win;        // SS_J: the fused window N w; E's; M v; X/Z on w
 };
 
+// One entry of the sub-state executor's launch order: a plan step, or a tile
+// pass over a run of one sub-state's window/E/X/Z steps.
+struct SubRun {
+  int step;   // index into ss_steps; -1 for a tile pass
+  int group;  // index into ss_groups; -1 for a plan step
+  int chain;  // the sub-state acted on
+};
+
 struct SubChain {
   size_t off = 0;               // first amplitude in the arena
   int maxw = 0;                 // widest it gets (its region holds 2^maxw amplitudes, at least 4)
@@ -208,6 +216,13 @@ struct owqs_pattern {
   std::vector<SubChain> ss_chains;
   std::vector<SubFactor> ss_factors;
   std::vector<int> ss_vanished;     // chains whose qubits were all measured (a scalar each)
+  std::vector<SubRun> ss_run;       // launch order (tile passes per sub-state)
+  std::vector<TileGroup> ss_groups;
+  std::vector<FuseOp> ss_fuse_ops;
+  std::vector<int> ss_fuse_m;
+  FuseOp *ss_dev_fuse = nullptr;    // ss_fuse_ops, then ss_fuse_m (as int)
+  size_t ss_dev_fuse_cap = 0;
+  bool ss_dev_fuse_valid = false;
   int ss_width = 0;                 // widest sub-state
   bool ss_plan_ok = true;           // every step fits its sub-state's region
   size_t ss_arena = 0;              // amplitudes
@@ -240,6 +255,13 @@ owqs_status width_guard(owqs_pattern *p);
 owqs_status ensure_device(owqs_pattern *p, bool need_psi = true);
 void end_ranged(owqs_pattern *p);
 owqs_status upload_fuse(owqs_pattern *p);
+// Group runs of window/E/X/Z steps into tile passes (S_F steps in `out`).
+void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
+                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm);
+// Copy a tile-pass command table (FuseOps, then the windows' measurement
+// indices as int) to the device, growing `dev` as needed.
+owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, const std::vector<int> &fm,
+                              FuseOp *&dev, size_t &cap);
 int *fuse_m_dev(owqs_pattern *p);
 int reduce_of(const owqs_pattern *p);
 struct Profile {

@@ -5,6 +5,61 @@
 
 namespace owqs {
 
+// The launch order of the sub-state plan, with each sub-state's runs of
+// window/E/X/Z steps grouped into tile passes as in the single-vector plan.
+// Sub-states occupy disjoint regions and scales, so a step of one commutes
+// with every step of another: a sub-state's groupable steps are held back
+// (in order) until a step of that sub-state that cannot join them, or a merge
+// that involves it, and then go out as tile passes, ahead of that step.  The
+// order inside each sub-state is the plan's.
+void group_substates(owqs_pattern *p) {
+  p->ss_run.clear();
+  p->ss_groups.clear();
+  p->ss_fuse_ops.clear();
+  p->ss_fuse_m.clear();
+  p->ss_dev_fuse_valid = false;
+  const size_t nch = p->ss_chains.size();
+  std::vector<std::vector<int>> held(nch);
+  auto groupable = [](int k) { return k == SS_J || k == SS_E || k == SS_X || k == SS_Z; };
+  auto flush = [&](int c) {
+    std::vector<int> &h = held[c];
+    if (h.empty()) return;
+    std::vector<Step> run;
+    for (int i : h) {
+      const SubStep &x = p->ss_steps[i];
+      Step st{};
+      st.kind = x.kind == SS_J ? S_J : x.kind == SS_E ? S_E : x.kind == SS_X ? S_X : S_Z;
+      st.n = x.n;
+      st.b0 = x.b0;
+      st.b1 = x.b1;
+      st.coef = x.coef;
+      st.host_factor = x.host_factor;
+      st.m_index = x.m_index;
+      st.win = x.win;
+      st.group = i;  // a step left ungrouped keeps its plan index here
+      run.push_back(st);
+    }
+    std::vector<Step> out;
+    group_steps(run, p->mode, p->tile_bits, out, p->ss_groups, p->ss_fuse_ops, p->ss_fuse_m);
+    for (const Step &x : out)
+      p->ss_run.push_back(x.kind == S_F ? SubRun{-1, x.group, c} : SubRun{x.group, -1, c});
+    h.clear();
+  };
+  for (size_t i = 0; i < p->ss_steps.size(); ++i) {
+    const SubStep &x = p->ss_steps[i];
+    std::vector<int> &h = held[x.chain];
+    if (groupable(x.kind) && x.n >= kTileMinWidth) {
+      if (!h.empty() && p->ss_steps[h.front()].n != x.n) flush(x.chain);
+      h.push_back((int)i);
+      continue;
+    }
+    flush(x.chain);
+    if (x.kind == SS_KRON) flush(x.top);
+    p->ss_run.push_back(SubRun{(int)i, -1, x.chain});
+  }
+  for (size_t c = 0; c < nch; ++c) flush((int)c);
+}
+
 // Sub-state plan (Sec. 4.1, Sec. 4.4.1): every input factor starts as a
 // sub-state; N makes a fresh |+> qubit that stays implicit until a command
 // touches it; E with a fresh qubit appends it to the other qubit's sub-state
@@ -260,6 +315,7 @@ void compile_substates(owqs_pattern *p) {
     }
     if (!ok) p->ss_plan_ok = false;
   }
+  group_substates(p);
   p->ss_arena = 0;
   if (p->ss_width <= OWQS_MAX_WIDTH) {
     for (SubChain &c : ch) {
@@ -280,16 +336,33 @@ void drop_ss_graph(owqs_pattern *p) {
 // ---------------------------------------------------------------------------
 // sub-state executor runs
 // ---------------------------------------------------------------------------
-// With `ev`: ev[2i] before step i's main kernel, ev[2i+1] after it, ev[2i+2]
-// after the step (its FP64 finishing kernel, if any).
+// Launch the plan in ss_run order.  With `ev`: ev[2i] before entry i's main
+// kernel, ev[2i+1] after it, ev[2i+2] after the entry (its FP64 finishing
+// kernel, if any).
 hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<hipEvent_t> *ev = nullptr) {
   hipError_t e = launch_sub_start(p->ss_sigma, (int)p->ss_chains.size(), p->book.err, s);
   if (ev && e == hipSuccess) e = hipEventRecord((*ev)[0], s);
-  for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
-    const SubStep &x = p->ss_steps[i];
+  for (size_t i = 0; i < p->ss_run.size() && e == hipSuccess; ++i) {
+    const SubRun &r = p->ss_run[i];
     if (ev && i > 0) e = hipEventRecord((*ev)[2 * i], s);
     if (e != hipSuccess) break;
-    float2 *psi = p->ss_mem + p->ss_chains[x.chain].off;
+    float2 *psi = p->ss_mem + p->ss_chains[r.chain].off;
+    MeasureArgs a{};
+    a.reduce = reduce;
+    a.book = p->book;
+    a.book.sigma = p->ss_sigma + r.chain;
+    unsigned grid = 0;
+    if (r.group >= 0) {  // a tile pass on this sub-state's region, with its scale
+      const TileGroup &tg = p->ss_groups[r.group];
+      e = launch_tile(psi, tg.ta, p->ss_dev_fuse + tg.op_off, a, s, &grid);
+      if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
+      if (e == hipSuccess)
+        e = launch_finish_group(a, reinterpret_cast<const int *>(p->ss_dev_fuse + p->ss_fuse_ops.size()) + tg.m_off,
+                                tg.ta.nwin, grid, s);
+      if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
+      continue;
+    }
+    const SubStep &x = p->ss_steps[r.step];
     switch (x.kind) {
       case SS_INIT: e = launch_sub_init(psi, s); break;
       case SS_N: e = launch_prepare(psi, x.n, s); break;
@@ -302,14 +375,9 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
         break;
       case SS_M:
       case SS_J: {
-        MeasureArgs a{};
-        a.reduce = reduce;
-        a.book = p->book;
-        a.book.sigma = p->ss_sigma + x.chain;
         a.coef = x.coef;
         a.host_factor = x.host_factor;
         a.m_index = x.m_index;
-        unsigned grid = 0;
         e = x.kind == SS_M ? launch_measure(psi, x.n, x.b0, a, s, &grid)
                            : launch_jwindow(psi, x.n, x.b0, a, x.win, s, &grid);
         if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
@@ -388,6 +456,12 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
     if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sub-state scales");
     p->ss_sigma_cap = n;
   }
+  if (!p->ss_dev_fuse_valid) {  // before any capture: the graph holds the table's address
+    drop_ss_graph(p);
+    st = upload_fuse_table(p->ctx, p->ss_fuse_ops, p->ss_fuse_m, p->ss_dev_fuse, p->ss_dev_fuse_cap);
+    if (st != OWQS_OK) return st;
+    p->ss_dev_fuse_valid = true;
+  }
   end_ranged(p);
   p->sampled_ran = false;
   p->ran = false;
@@ -402,7 +476,7 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
                                                         : kReduceNone;
   std::vector<hipEvent_t> ev;
   if (prof) {
-    ev.resize(2 * p->ss_steps.size() + 1);
+    ev.resize(2 * p->ss_run.size() + 1);
     for (auto &x : ev) {
       e = hipEventCreate(&x);
       if (e != hipSuccess) return hip_fail(p->ctx, e, "event");
@@ -445,11 +519,23 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
     static const int kind_of[] = {-1, OWQS_KIND_N, OWQS_KIND_E, OWQS_KIND_X, OWQS_KIND_Z, OWQS_KIND_M,
                                   OWQS_KIND_KRON, OWQS_KIND_J};
     e = hipStreamSynchronize(s);
-    for (size_t i = 0; i < p->ss_steps.size() && e == hipSuccess; ++i) {
-      const SubStep &x = p->ss_steps[i];
+    for (size_t i = 0; i < p->ss_run.size() && e == hipSuccess; ++i) {
+      const SubRun &r = p->ss_run[i];
       float t = 0.f, f = 0.f;
       e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
       if (e == hipSuccess) e = hipEventElapsedTime(&f, ev[2 * i + 1], ev[2 * i + 2]);
+      if (r.group >= 0) {
+        const TileGroup &tg = p->ss_groups[r.group];
+        prof->counts[OWQS_KIND_TILE] += 1;
+        prof->ms[OWQS_KIND_TILE] += t;
+        prof->bytes[OWQS_KIND_TILE] += std::ldexp(16.0, tg.ta.n);  // one read and one write
+        if (reduce != kReduceNone) {
+          prof->counts[OWQS_KIND_FINISH] += 1;
+          prof->ms[OWQS_KIND_FINISH] += f;
+        }
+        continue;
+      }
+      const SubStep &x = p->ss_steps[r.step];
       const int k = kind_of[x.kind];
       if (k < 0) continue;  // a new sub-state's scalar 1
       prof->counts[k] += 1;

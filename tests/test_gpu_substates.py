@@ -272,3 +272,76 @@ def test_degenerate_patterns(ctx, case):
     np.testing.assert_allclose(p.read_probs(), pw, atol=P_TOL)
     compare_factors(p, st, pat)
     p.close()
+
+
+def with_extra_corrections(pat, g, count):
+    """The pattern with `count` X/Z commands inserted after random gate ends,
+    each on an entangled live qubit, its domain one or two measured qubits
+    (standalone corrections inside the tile passes)."""
+    live, touched, measured, cmds = set(pat.inputs), set(pat.inputs), [], []
+    ends = []
+    for k, c in enumerate(pat.cmds):
+        nxt = pat.cmds[k + 1] if k + 1 < len(pat.cmds) else None
+        if c[0] in ("M", "X", "Z") and not (nxt and nxt[0] in ("X", "Z")) and measured:
+            ends.append(k)
+        if c[0] == "M":
+            measured.append(c[1])
+    picks = set(g.choice(ends, size=min(count, len(ends)), replace=False).tolist())
+    measured = []
+    for k, c in enumerate(pat.cmds):
+        cmds.append(c)
+        if c[0] == "N":
+            live.add(c[1])
+        elif c[0] == "E":
+            touched.update(c[1:3])
+        elif c[0] == "M":
+            live.discard(c[1])
+            measured.append(c[1])
+        if k in picks:
+            q = int(g.choice(sorted(live & touched)))
+            dom = tuple(int(x) for x in g.choice(measured, size=int(g.integers(1, 3)), replace=False))
+            cmds.append(("X" if g.integers(0, 2) else "Z", q, dom))
+    return W.Pattern(pat.inputs, pat.outputs, cmds)
+
+
+@pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS, owqs.MODE_EOWQS_CHECK])
+def test_tile_passes_per_substate(ctx, mode):
+    """Two circuits of 15 and 16 logical qubits side by side, with extra X/Z
+    corrections: each sub-state's windows, E, X and Z at width >= 15 run as
+    tile passes (far fewer launches than steps), interleaved with the other
+    sub-state's; factors and probabilities against the sub-state oracle,
+    with and without graph capture, and the profiled run counts tile passes."""
+    g = np.random.default_rng(4810 + mode)
+    parts = [with_extra_corrections(W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, 70, 14, g)), g, 12)
+             for nl in (15, 16)]
+    pat = W.disjoint_union(parts)
+    outc = g.integers(0, 2, pat.n_meas()).astype(np.uint8)
+    vecs = [W.gaussian_state(len(x.inputs), g).astype(np.complex64).astype(np.complex128) for x in parts]
+    factors = [(list(np.array(x.inputs) + 1000 * k), v) for k, (x, v) in enumerate(zip(parts, vecs))]
+    st, pw = so.run(pat, outc, factors, mode=so.MODE_OWQS if mode == owqs.MODE_OWQS else so.MODE_EOWQS)
+    for graph in (True, False):
+        print(f"[substates] tile passes mode {mode} graph {graph}", flush=True)
+        p = run_sub(ctx, pat, outc, factors, mode, graph)
+        width, nsteps, npasses = p.plan_info()
+        assert width == 16 and npasses < nsteps // 4, (width, nsteps, npasses)
+        compare_factors(p, st, pat)
+        if mode != owqs.MODE_EOWQS:
+            np.testing.assert_allclose(p.read_probs(), pw, atol=P_TOL)
+        p.check()
+        p.close()
+    # one circuit, its input as one factor: the profiled run times the passes
+    one = parts[1]
+    o1 = g.integers(0, 2, one.n_meas()).astype(np.uint8)
+    st1, pw1 = so.run(one, o1, [(list(one.inputs), vecs[1])],
+                      mode=so.MODE_OWQS if mode == owqs.MODE_OWQS else so.MODE_EOWQS)
+    p = owqs.Pattern(ctx, one)
+    p.set_exec(owqs.EXEC_SUBSTATES)
+    p.set_mode(mode)
+    p.set_outcomes(o1)
+    prof = p.run_profiled(cuda(vecs[1]))
+    assert prof["tile(group)"]["launches"] > 0
+    assert prof["tile(group)"]["bytes"] == prof["tile(group)"]["launches"] * 16 * 2 ** 16
+    compare_factors(p, st1, one)
+    if mode != owqs.MODE_EOWQS:
+        np.testing.assert_allclose(p.read_probs(), pw1, atol=P_TOL)
+    p.close()
