@@ -311,7 +311,11 @@ owqs_status owqs_run_profiled(owqs_pattern *pat, const void *input_c64, size_t n
                               double *bytes);
 
 /* FP64 outcome probability of every M of the last run (OWQS and EOWQS_CHECK
- * modes; 0.5 in EOWQS mode).  Waits for `stream`. */
+ * modes; 0.5 in EOWQS mode).  In OWQS mode a fused window whose new qubit
+ * meets the measured one through an odd number of E has probability exactly
+ * 1/2 for every state (Eqs. 11-13), and the fused executors record 0.5 for it
+ * without summing the state (at most 128 such windows in a row; the next
+ * reduces and renormalises as usual).  Waits for `stream`. */
 owqs_status owqs_read_probs(owqs_pattern *pat, double *p, size_t n_meas, void *stream);
 
 /* Forced outcomes from a documented bit stream (outcomes are forced so that

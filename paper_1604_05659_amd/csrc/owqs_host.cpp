@@ -198,6 +198,9 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     }
     tg.ta.nops = (int)(j - i);
     tg.ta.nwin = widx;
+    tg.half = widx > 0;
+    for (size_t q = i; q < j; ++q)
+      if (steps[q].kind == S_J && steps[q].win.vw_even) tg.half = false;
     // compile the register runs in only where two windows on different bits
     // follow each other, possibly with an E or Z between (they cost occupancy
     // elsewhere)
@@ -230,6 +233,9 @@ void group_tiles(owqs_pattern *p) {
     return;
   }
   group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m);
+  if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups);
+  else
+    for (TileGroup &tg : p->groups) tg.half = false;
 }
 
 // State after each command of a plain plan (for ranged runs).
@@ -435,6 +441,13 @@ void compile(owqs_pattern *p) {
     return;
   }
   compile_plan(p, p->exec != OWQS_EXEC_PLAIN, p->steps, p->final_where, p->final_factor, nullptr);
+  if (p->mode == OWQS_MODE_OWQS) {  // windows with p = 1/2 do not renormalise (half_prob)
+    double e = 1.0;
+    for (Step &x : p->steps) {
+      if (x.kind == S_J && !x.win.vw_even) x.host_factor = rounded_factor(x.host_factor, e);
+      else if (x.kind == S_M || x.kind == S_J) e = 1.0;
+    }
+  }
   p->lk_valid = false;
   p->lk_next = SIZE_MAX;
   int w = std::max<int>((int)p->inputs.size(), (int)p->outputs.size());
@@ -590,6 +603,50 @@ double step_bytes(const Step &x) {
 // main kernel and the finishing kernel of each step (see run_impl).
 int *fuse_m_dev(owqs_pattern *p) { return reinterpret_cast<int *>(p->dev_fuse + p->fuse_ops.size()); }
 
+// A window whose fresh qubit w meets v through an odd number of E has outcome
+// probability exactly 1/2 for every state (Eqs. 11-13: the two outputs are
+// f (a + t) and +-f (a - t) with |t| = f |b|, so their squared norms add up
+// to 2 f^2 (|a|^2 + |b|^2) whatever the coefficient).  In OWQS mode such a
+// window needs no reduction: p = 1/2 is recorded, and since the pass then
+// keeps the norm of its input, sigma is left for the next measurement.
+bool half_prob(const Step &x, int reduce) { return reduce == kReduceRenorm && x.kind == S_J && x.half; }
+
+// Such windows scale the vector by their factor rounded to FP32, and no
+// reduction renormalises it after them, so the rounding would compound (for
+// 1/sqrt 2, by 3.4e-8 in |psi|^2 per window).  The factors are chosen in
+// execution order with error feedback instead: `e` is the ratio of the
+// vector's scale to the exact one so far; the next factor aims at h / e and
+// e takes up what its FP32 rounding leaves, so |e - 1| stays within one
+// rounding.  Returns the factor to use (its FP32 rounding is what the
+// kernels apply).
+double rounded_factor(double h, double &e) {
+  const double t = h / e;
+  e *= double(float(t)) / h;
+  return t;
+}
+
+// What the FP32 arithmetic of a window leaves in |psi|^2 beyond its factor
+// (the rounding of the coefficient, at most a few 1e-8 per window) would
+// still add up over a long run without reductions, so at most kHalfRun such
+// windows follow each other: the window or group that would exceed it
+// reduces (and renormalises) as usual.  Groups are taken whole.
+void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups) {
+  int run = 0;
+  for (Step &x : xs) {
+    if (x.kind == S_M) {
+      run = 0;
+    } else if (x.kind == S_J) {
+      x.half = !x.win.vw_even && run + 1 <= kHalfRun;
+      run = x.half ? run + 1 : 0;
+    } else if (x.kind == S_F) {
+      TileGroup &tg = groups[x.group];
+      if (tg.ta.nwin == 0) continue;  // no norm changes, no reduction
+      tg.half = tg.half && run + tg.ta.nwin <= kHalfRun;
+      run = tg.half ? run + tg.ta.nwin : 0;
+    }
+  }
+}
+
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
                         hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab, const int *ftab) {
   hipError_t e = hipSuccess;
@@ -610,6 +667,10 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
         a.coef = x.coef;
         a.host_factor = x.host_factor;
         a.m_index = x.m_index;
+        if (half_prob(x, reduce)) {  // p = 1/2 exactly: no reduction, sigma carried to the next M
+          a.reduce = kReduceNone;
+          a.prob_half = 1;
+        }
         if (ctab && x.kind == S_J) {
           a.coef_dev = ctab + x.m_index;
           a.fold_dev = ftab + 3 * x.m_index;
@@ -620,15 +681,17 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
       case S_F: {
         const TileGroup &tg = p->groups[x.group];
         ops = p->dev_fuse + tg.op_off;
+        TileArgs ta = tg.ta;
         if (ctab) {
-          TileArgs ta = tg.ta;
           ta.coefs = ctab;
           ta.nsets = 1;
           ta.folds = ftab;
-          e = launch_tile(p->psi, ta, ops, a, s, &grid);
-        } else {
-          e = launch_tile(p->psi, tg.ta, ops, a, s, &grid);
         }
+        if (reduce == kReduceRenorm && tg.half) {  // every window has p = 1/2 exactly
+          a.reduce = kReduceNone;
+          ta.half_m = fuse_m_dev(p) + tg.m_off;
+        }
+        e = launch_tile(p->psi, ta, ops, a, s, &grid);
         break;
       }
       default: break;
@@ -847,7 +910,9 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
       prof->counts[k] += 1;
       prof->ms[k] += t;
       prof->bytes[k] += step_bytes(p->xsteps[i]);
-      if ((k == S_M || k == S_J || k == S_F) && reduce != kReduceNone) {
+      const bool half = half_prob(p->xsteps[i], reduce) ||
+                        (k == S_F && reduce == kReduceRenorm && p->groups[p->xsteps[i].group].half);
+      if ((k == S_M || k == S_J || k == S_F) && reduce != kReduceNone && !half) {
         prof->counts[OWQS_KIND_FINISH] += 1;
         prof->ms[OWQS_KIND_FINISH] += f;
       }

@@ -48,12 +48,15 @@ struct Step {
   Window win;
   int sig_s, sig_t, outcome;  // M / window: resolved signals and forced outcome
   int group;                  // S_F: index into the pattern's tile groups
+  bool half;                  // S_J in OWQS mode: p = 1/2 is recorded without a reduction (half_prob)
 };
 
 struct TileGroup {
   TileArgs ta;
   size_t op_off;  // first FuseOp of the group in the pattern's table
   size_t m_off;   // first window's measurement index in the pattern's m table
+  bool half;      // OWQS mode: it has windows, each with an odd E(v, w) count (p = 1/2 exactly), and
+                  // runs without a reduction (mark_half)
 };
 
 // Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's
@@ -71,6 +74,7 @@ struct SubStep {
   double host_factor;
   int m_index;
   Window win;        // SS_J: the fused window N w; E's; M v; X/Z on w
+  bool half;         // SS_J in OWQS mode: p = 1/2 recorded without a reduction
 };
 
 // One entry of the sub-state executor's launch order: a plan step, or a tile
@@ -263,6 +267,13 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
 owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, const std::vector<int> &fm,
                               FuseOp *&dev, size_t &cap);
 int *fuse_m_dev(owqs_pattern *p);
+// An OWQS window with an odd E(v, w) count: p = 1/2 exactly, no reduction.
+bool half_prob(const Step &x, int reduce);
+// Error feedback for the FP32 rounding of the factors of such windows.
+double rounded_factor(double h, double &e);
+// Decide which windows and tile groups with p = 1/2 skip their reduction.
+constexpr int kHalfRun = 128;
+void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups);
 int reduce_of(const owqs_pattern *p);
 struct Profile {
   int64_t *counts;

@@ -37,6 +37,7 @@ struct MeasureArgs {
   double host_factor;   // (1/sqrt 2)^(N commands since the previous M)
   int reduce;           // ReduceMode
   int m_index;          // index of this M (probs slot)
+  int prob_half;        // windows: p = 1/2 exactly (odd E(v, w) count); with kReduceNone, probs[m_index] = 1/2
   DevBook book;
 };
 
@@ -116,6 +117,10 @@ struct TileArgs {
   // non-null: the folded corrections of window m are folds[3 m .. 3 m + 2] =
   // {swap, neg0, neg1} (resolved per run from drawn outcomes)
   const int *folds;
+  // non-null: every window of the group has p = 1/2 exactly (an odd E(v, w)
+  // count) and the pass runs without a reduction; workgroup (0, 0) writes
+  // book.probs[half_m[i]] = 1/2 for its nwin windows
+  const int *half_m;
   int nsets;
   int n, k, nops, nwin;
   int runs;          // 1: some consecutive unmasked windows run in registers (see k_tile)

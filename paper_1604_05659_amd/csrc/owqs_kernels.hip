@@ -518,6 +518,7 @@ __global__ __launch_bounds__(kBlock) void k_jwindow(float2 *__restrict__ psi, ui
     }
   }
   if (a.reduce != kReduceNone) block_partial(acc, a.book.partials);
+  if (a.prob_half && blockIdx.x == 0 && threadIdx.x == 0) a.book.probs[a.m_index] = 0.5;
 }
 
 // ---------------------------------------------------------------------------

@@ -58,6 +58,27 @@ void group_substates(owqs_pattern *p) {
     p->ss_run.push_back(SubRun{(int)i, -1, x.chain});
   }
   for (size_t c = 0; c < nch; ++c) flush((int)c);
+  // windows with p = 1/2 that skip their reduction, at most kHalfRun in a
+  // row per sub-state (mark_half); a merged sub-state inherits both runs
+  std::vector<int> run(nch, 0);
+  for (const SubRun &r : p->ss_run) {
+    if (r.group >= 0) {
+      TileGroup &tg = p->ss_groups[r.group];
+      if (tg.ta.nwin == 0) continue;
+      tg.half = p->mode == OWQS_MODE_OWQS && tg.half && run[r.chain] + tg.ta.nwin <= kHalfRun;
+      run[r.chain] = tg.half ? run[r.chain] + tg.ta.nwin : 0;
+      continue;
+    }
+    SubStep &x = p->ss_steps[r.step];
+    if (x.kind == SS_M) {
+      run[r.chain] = 0;
+    } else if (x.kind == SS_J) {
+      x.half = p->mode == OWQS_MODE_OWQS && !x.win.vw_even && run[r.chain] + 1 <= kHalfRun;
+      run[r.chain] = x.half ? run[r.chain] + 1 : 0;
+    } else if (x.kind == SS_KRON) {
+      run[r.chain] += run[x.top];
+    }
+  }
 }
 
 // Sub-state plan (Sec. 4.1, Sec. 4.4.1): every input factor starts as a
@@ -315,6 +336,14 @@ void compile_substates(owqs_pattern *p) {
     }
     if (!ok) p->ss_plan_ok = false;
   }
+  if (p->mode == OWQS_MODE_OWQS) {  // FP32 factors of p = 1/2 windows with error feedback (rounded_factor)
+    std::vector<double> e(ch.size(), 1.0);
+    for (SubStep &x : p->ss_steps) {
+      if (x.kind == SS_J && !x.win.vw_even) x.host_factor = rounded_factor(x.host_factor, e[x.chain]);
+      else if (x.kind == SS_M || x.kind == SS_J) e[x.chain] = 1.0;
+      else if (x.kind == SS_KRON) e[x.chain] *= e[x.top];
+    }
+  }
   group_substates(p);
   p->ss_arena = 0;
   if (p->ss_width <= OWQS_MAX_WIDTH) {
@@ -354,11 +383,15 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
     unsigned grid = 0;
     if (r.group >= 0) {  // a tile pass on this sub-state's region, with its scale
       const TileGroup &tg = p->ss_groups[r.group];
-      e = launch_tile(psi, tg.ta, p->ss_dev_fuse + tg.op_off, a, s, &grid);
+      const int *m_of = reinterpret_cast<const int *>(p->ss_dev_fuse + p->ss_fuse_ops.size()) + tg.m_off;
+      TileArgs ta = tg.ta;
+      if (reduce == kReduceRenorm && tg.half) {  // every window has p = 1/2 exactly
+        a.reduce = kReduceNone;
+        ta.half_m = m_of;
+      }
+      e = launch_tile(psi, ta, p->ss_dev_fuse + tg.op_off, a, s, &grid);
       if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
-      if (e == hipSuccess)
-        e = launch_finish_group(a, reinterpret_cast<const int *>(p->ss_dev_fuse + p->ss_fuse_ops.size()) + tg.m_off,
-                                tg.ta.nwin, grid, s);
+      if (e == hipSuccess) e = launch_finish_group(a, m_of, tg.ta.nwin, grid, s);
       if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
       continue;
     }
@@ -378,6 +411,10 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
         a.coef = x.coef;
         a.host_factor = x.host_factor;
         a.m_index = x.m_index;
+        if (reduce == kReduceRenorm && x.kind == SS_J && x.half) {  // p = 1/2 exactly (see half_prob)
+          a.reduce = kReduceNone;
+          a.prob_half = 1;
+        }
         e = x.kind == SS_M ? launch_measure(psi, x.n, x.b0, a, s, &grid)
                            : launch_jwindow(psi, x.n, x.b0, a, x.win, s, &grid);
         if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
@@ -529,7 +566,7 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
         prof->counts[OWQS_KIND_TILE] += 1;
         prof->ms[OWQS_KIND_TILE] += t;
         prof->bytes[OWQS_KIND_TILE] += std::ldexp(16.0, tg.ta.n);  // one read and one write
-        if (reduce != kReduceNone) {
+        if (reduce != kReduceNone && !(reduce == kReduceRenorm && tg.half) && tg.ta.nwin > 0) {
           prof->counts[OWQS_KIND_FINISH] += 1;
           prof->ms[OWQS_KIND_FINISH] += f;
         }
@@ -541,7 +578,8 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
       prof->counts[k] += 1;
       prof->ms[k] += t;
       prof->bytes[k] += substep_bytes(x);
-      if ((x.kind == SS_M || x.kind == SS_J) && reduce != kReduceNone) {
+      const bool half = reduce == kReduceRenorm && x.kind == SS_J && x.half;
+      if ((x.kind == SS_M || x.kind == SS_J) && reduce != kReduceNone && !half) {
         prof->counts[OWQS_KIND_FINISH] += 1;
         prof->ms[OWQS_KIND_FINISH] += f;
       }

@@ -461,6 +461,8 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     }
   }
   psi += size_t(blockIdx.y) * ta.set_stride;
+  if (ta.half_m && blockIdx.x == 0 && blockIdx.y == 0)  // windows with p = 1/2 exactly
+    for (int i = tid; i < ta.nwin; i += kT) ma.book.probs[ta.half_m[i]] = 0.5;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t ob = pdep64(t, ta.omask);

@@ -159,3 +159,74 @@ def test_autotuner_keeps_results(ctx):
     assert q.tune() == (0, 0.0)
     p.close()
     q.close()
+
+
+def odd_even_window_pattern(g, n, n_win, even=True):
+    """n input qubits; n_win windows N w; E's; M v; X w, each with E(v, w)
+    once, twice (only if `even`) or three times, plus E's from v or w to
+    other live qubits, and a standalone E now and then.  Returns the pattern
+    and, per M, whether its E(v, w) count is odd."""
+    live = list(range(n))
+    nxt = n
+    cmds, odd = [], []
+    for _ in range(n_win):
+        v = live[int(g.integers(len(live)))]
+        w = nxt
+        nxt += 1
+        nvw = int(g.integers(1, 4)) if even else int(g.choice([1, 3]))
+        others = [q for q in live if q != v]
+        es = [("E", v, w)] * nvw
+        es += [("E", v, int(x)) for x in g.choice(others, size=int(g.integers(0, 3)), replace=False)]
+        es += [("E", w, int(y)) for y in g.choice(others, size=int(g.integers(0, 2)), replace=False)]
+        es = [es[i] for i in g.permutation(len(es))]
+        cmds += [("N", w)] + es + [("M", v, float(g.uniform(0, 2 * math.pi)), (), ()), ("X", w, (v,))]
+        odd.append(nvw % 2 == 1)
+        live[live.index(v)] = w
+        if g.random() < 0.2:
+            a, b = g.choice(len(live), size=2, replace=False)
+            cmds.append(("E", live[a], live[b]))
+    return W.Pattern(list(range(n)), live, cmds), np.array(odd)
+
+
+@pytest.mark.parametrize("n,kind", [(10, "mixed"), (16, "mixed"), (16, "odd")])
+@pytest.mark.parametrize("graph", [True, False])
+def test_half_probability_windows(ctx, n, kind, graph):
+    """OWQS mode: a window with an odd E(v, w) count has p = 1/2 exactly; run
+    on its own (n = 10: one kernel per window) or in a tile pass whose
+    windows are all such (kind "odd"), it records p = 1/2 without a
+    reduction and leaves sigma to the next measurement that reduces.  Windows
+    with an even count, and passes that hold one, reduce as before.  Against
+    the oracle: the state and every probability, on two runs in a row."""
+    g = np.random.default_rng(1900 + n + 7 * graph + (50 if kind == "odd" else 0))
+    pat, odd = odd_even_window_pattern(g, n, 90, even=kind == "mixed")
+    assert odd.any() and (kind == "odd" or not odd.all())
+    inp = W.gaussian_state(n, g)
+    for _ in range(20):   # forced outcomes of reasonable probability
+        outc = g.integers(0, 2, size=pat.n_meas()).astype(np.uint8)
+        want, pw = oc.run(pat, outc, inp.astype(np.complex128), oc.MODE_OWQS)
+        if pw.min() > 1e-3:
+            break
+    assert pw.min() > 1e-3
+    p = owqs.Pattern(ctx, pat)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_exec(owqs.EXEC_FUSED)
+    p.set_graph(graph)
+    p.set_outcomes(outc)
+    x = torch.as_tensor(inp).cuda()
+    for rep in range(2):   # the second run starts from the scale the first left
+        p.run(x)
+        got = p.read_state().cpu().numpy().astype(np.complex128)
+        probs = p.read_probs()
+        assert np.max(np.abs(got - want)) <= AMP_TOL, rep
+        np.testing.assert_allclose(probs, pw, atol=1e-5)
+        if n < 15 or kind == "odd":
+            assert np.all(probs[odd] == 0.5)
+    prof = p.run_profiled(x)
+    if n >= 15:
+        assert p.plan_info()[2] < p.plan_info()[1]
+        assert prof["tile(group)"]["launches"] > 0
+    if kind == "odd":   # no reduction anywhere: no finishing kernel
+        assert prof.get("finish(FP64)", {"launches": 0})["launches"] == 0
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - want)) <= AMP_TOL
+    p.close()

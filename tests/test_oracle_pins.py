@@ -142,6 +142,44 @@ def test_measurement_probability_matches_projectors():
             assert probs[0] == pytest.approx(p_exp, rel=1e-12, abs=1e-15)
 
 
+def test_window_with_odd_vw_count_has_probability_one_half():
+    """N w; E's on v or w; M v with E(v, w) an odd number of times: the
+    outcome has probability 1/2 for every input state and angle (the two
+    halves of the new qubit are f (a + t) and +-f (a - t), Eqs. 11-13); with
+    an even count it depends on the state.  Brute force: the projector of
+    Eqs. 9-10 applied to the dense state after the CZs."""
+    g = np.random.default_rng(1313)
+    even_dev = 0.0
+    for trial in range(40):
+        k = int(g.integers(1, 4))                 # inputs 0 .. k-1, v = 0, w = k
+        nvw = int(g.integers(1, 4))
+        ev = [(0, k)] * nvw
+        ev += [(0, x) for x in range(1, k) if g.integers(0, 2)]
+        ev += [(k, y) for y in range(1, k) if g.integers(0, 2)]
+        ev = [ev[i] for i in g.permutation(len(ev))]
+        alpha = g.uniform(0, 2 * math.pi)
+        psi = g.standard_normal(1 << k) + 1j * g.standard_normal(1 << k)
+        psi /= np.linalg.norm(psi)
+        dense = np.kron(np.array([1.0, 1.0]) / SQ2, psi)  # w is the top bit
+        idx = np.arange(1 << (k + 1))
+        for a, b in ev:
+            dense = np.where(((idx >> a) & 1) & ((idx >> b) & 1), -dense, dense)
+        for o in (0, 1):
+            e = np.exp(-1j * alpha)
+            p_mat = 0.5 * (np.array([[1, e], [np.conj(e), 1]]) if o == 0
+                           else np.array([[1, -e], [-np.conj(e), 1]]))
+            p_exp = float(np.vdot(dense, np.kron(np.eye(1 << k), p_mat) @ dense).real)
+            cmds = [("N", k)] + [("E", a, b) for a, b in ev] + [("M", 0, alpha, (), ())]
+            pat = W.Pattern(list(range(k)), list(range(1, k + 1)), cmds)
+            _, probs = oc.run(pat, [o], psi)
+            assert probs[0] == pytest.approx(p_exp, abs=1e-12)
+            if nvw % 2:
+                assert probs[0] == pytest.approx(0.5, abs=1e-12), (trial, ev)
+            else:
+                even_dev = max(even_dev, abs(probs[0] - 0.5))
+    assert even_dev > 1e-3   # the even case is a real test of the state
+
+
 def test_j_pattern_is_j_gate_for_both_outcomes():
     g = np.random.default_rng(2)
     for trial in range(10):
