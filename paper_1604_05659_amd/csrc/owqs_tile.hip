@@ -15,7 +15,10 @@
 // Probabilities (Eq. 13): windows inside a group do not renormalise; each
 // workgroup sums the squared norm after every window, and the finishing
 // kernel chains p_g = n_g / (2 n_{g-1}) (n_0 = 1: the first window of the
-// group applies sigma) and sets sigma = 1 / sqrt(n_last).
+// group applies sigma) and sets sigma = 1 / sqrt(n_last).  A group whose
+// windows all have p = 1/2 exactly (an odd E(v, w) count) runs without the
+// sums when the host says so (TileArgs::half_m): it records p = 1/2, keeps
+// the norm of its input, and leaves sigma as it is.
 #include "owqs_internal.h"
 
 namespace owqs {
