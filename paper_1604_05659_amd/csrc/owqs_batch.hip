@@ -78,6 +78,7 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
     lds[i] = v;
   }
   double sigma = 1.0;
+  int half_run = 0;  // windows in a row recorded with p = 1/2 and no sum (at most kHalfRun)
   __syncthreads();
   for (int s = 0; s < nsteps; ++s) {
     const DevStep st = load_step(steps, s);
@@ -105,7 +106,11 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
         lds[j] = neg(lds[j]);
       }
     } else {  // DK_M or DK_J
-      const float f = float((reduce == kReduceRenorm ? sigma : 1.0) * st.host_factor);
+      // OWQS: a window with an odd E(v, w) count has p = 1/2 exactly for every
+      // state (Eqs. 11-13): it is recorded without the block sum and sigma is
+      // left for the next measurement that sums (at most kHalfRun in a row)
+      const bool half = reduce == kReduceRenorm && st.kind == DK_J && !(st.pp & 8u) && half_run < kHalfRun;
+      const float f = float((reduce == kReduceRenorm && !half ? sigma : 1.0) * st.host_factor);
       const float2 c = st.coef;
       double acc = 0.0;
       if (st.kind == DK_M) {
@@ -145,7 +150,11 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
           acc += n2(o0) + n2(o1);
         }
       }
-      if (reduce != kReduceNone) {
+      if (half) {
+        if (probs && threadIdx.x == 0) probs[st.m_index] = 0.5;
+        ++half_run;
+      } else if (reduce != kReduceNone) {
+        half_run = 0;
         const double sum = block_sum<kT>(acc, red);
         const double p = 0.5 * sum;
         if (probs && threadIdx.x == 0) probs[st.m_index] = p;

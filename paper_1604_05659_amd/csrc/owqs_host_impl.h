@@ -272,7 +272,6 @@ bool half_prob(const Step &x, int reduce);
 // Error feedback for the FP32 rounding of the factors of such windows.
 double rounded_factor(double h, double &e);
 // Decide which windows and tile groups with p = 1/2 skip their reduction.
-constexpr int kHalfRun = 128;
 void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups);
 int reduce_of(const owqs_pattern *p);
 struct Profile {

@@ -18,6 +18,9 @@ struct DevBook {
 };
 
 constexpr int kMaxPartials = 1 << 16;
+// OWQS: windows with p = 1/2 exactly (an odd E(v, w) count) recorded in a row
+// without summing the state; the next one sums and renormalises.
+constexpr int kHalfRun = 128;
 constexpr int kWhereMax = 40;     // >= OWQS_MAX_WIDTH
 constexpr int kErrNone = 0x7fffffff;
 constexpr int kErrZeroProb = 1;

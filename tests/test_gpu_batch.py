@@ -93,6 +93,28 @@ def test_run_states_matches_oracle(ctx):
     p.close()
 
 
+def test_run_states_long_runs_of_half_windows(ctx):
+    """OWQS, LDS-resident: 300 windows with p = 1/2 (odd E(v, w) count) are
+    recorded without the block sum, at most 128 in a row before one sums
+    and renormalises; states, norms and probabilities against the oracle."""
+    wl = W.plain_large(index=3, n_logical=8, n_j=300, n_cz=40)
+    p = _load(ctx, wl.pattern, wl.outcomes)
+    assert p.plan_info()[0] <= 14
+    g = np.random.default_rng(31)
+    states = np.stack([W.gaussian_state(8, g) for _ in range(6)])
+    probs = torch.zeros((6, p.n_meas), dtype=torch.float64, device="cuda")
+    out = p.run_states(torch.as_tensor(states).cuda(), probs=probs)
+    p.check()
+    got = out.cpu().numpy().astype(np.complex128)
+    pr = probs.cpu().numpy()
+    for k in range(6):
+        want, pw = oc.run(wl.pattern, wl.outcomes, states[k].astype(np.complex128))
+        np.testing.assert_allclose(got[k], want, atol=AMP_TOL)
+        assert abs(np.linalg.norm(got[k]) - 1) <= 1e-5
+        np.testing.assert_allclose(pr[k], pw, atol=1e-5)
+    p.close()
+
+
 def test_heterogeneous_batch(ctx, parity_report):
     """Batch of patterns with uneven widths (LDS-resident and wide ones),
     against the oracle one by one."""
