@@ -102,6 +102,7 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
   p->adj_coefs.assign(nm * batch, make_float2(0.f, 0.f));
   p->adj_cols.assign(std::max<size_t>(nwin, 1) + 1, 0);
   p->adj_scale.assign(std::max<size_t>(nwin, 1) + 1, 1.0);
+  std::vector<double> dth(nm, 1.0);  // dtheta/dalpha of each window's measurement
   for (size_t q = 0; q < nwin; ++q) {
     const Step &x = p->steps[wins[q]];
     for (size_t b = 0; b < batch; ++b) {
@@ -111,9 +112,22 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
       if (x.outcome) { cr = -cr; ci = -ci; }
       p->adj_coefs[size_t(x.m_index) * batch + b] = make_float2((float)cr, (float)ci);
     }
+    dth[x.m_index] = x.sig_s ? -1.0 : 1.0;
     p->adj_cols[q] = x.m_index;
-    p->adj_scale[q] = x.sig_s ? -1.0 : 1.0;  // dtheta/dalpha
   }
+  if (reversible) {  // partial rows follow the grouped plan's window order (a pass may take later windows first)
+    size_t q = 0;
+    for (const Step &x : p->xsteps) {
+      if (x.kind == S_F) {
+        const TileGroup &tg = p->groups[x.group];
+        for (int w = 0; w < tg.ta.nwin && q < nwin; ++w) p->adj_cols[q++] = p->fuse_m[tg.m_off + w];
+      } else if (x.kind == S_J && q < nwin) {
+        p->adj_cols[q++] = x.m_index;
+      }
+    }
+    if (q != nwin) return fail(p->ctx, OWQS_E_STATE, "internal error: the grouped plan lost a window");
+  }
+  for (size_t q = 0; q < nwin; ++q) p->adj_scale[q] = dth[p->adj_cols[q]];
   e = hipMemcpyAsync(coefs, p->adj_coefs.data(), p->adj_coefs.size() * sizeof(float2), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(cols, p->adj_cols.data(), p->adj_cols.size() * sizeof(int), hipMemcpyHostToDevice, s);

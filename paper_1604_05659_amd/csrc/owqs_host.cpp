@@ -90,27 +90,54 @@ int signal(const std::vector<int> &dom, const std::vector<int> &outcome_of) {
   return s;
 }
 
+// Whether two window/E/X/Z steps at one width may swap: neither mixes a slot
+// (a window's or an X's) that the other mixes or reads as a sign (E and Z
+// slots, a window's masks), and they are not two windows whose probability
+// depends on the state (an even E(v, w) count): swapping those would change
+// what each records.  Windows with an odd count act as a unitary times 1/2
+// of the norm, so the other's probability is the same on either side.
+bool commute_steps(const Step &a, const Step &b) {
+  auto mix = [](const Step &x) -> uint64_t {
+    return (x.kind == S_J || x.kind == S_X) ? uint64_t(1) << x.b0 : 0;
+  };
+  auto diag = [](const Step &x) -> uint64_t {
+    if (x.kind == S_E) return (uint64_t(1) << x.b0) | (uint64_t(1) << x.b1);
+    if (x.kind == S_Z) return uint64_t(1) << x.b0;
+    if (x.kind == S_J) return x.win.mask_b | x.win.mask_o1;
+    return 0;
+  };
+  if (mix(a) & (mix(b) | diag(b))) return false;
+  if (mix(b) & (mix(a) | diag(a))) return false;
+  return !(a.kind == S_J && b.kind == S_J && a.win.vw_even && b.win.vw_even);
+}
+
 // Group runs of window/E/X/Z steps at one width >= kTileMinWidth into tile
-// passes (see owqs_tile.hip).  A run ends at N or M steps, at a width change,
-// when a new mixing slot would not fit the tile, or when it holds the largest
-// number of windows that one pass may chain (16 when probabilities are
-// computed: the windows of a pass are not renormalised one by one, and 16
-// windows keep the FP32 norm in range down to p ~ 1e-4 per window).  The
-// result goes to `out`: a step that joins no group is copied unchanged (all
+// passes (see owqs_tile.hip).  A pass ends at N or M steps and at a width
+// change; steps whose mixing slot would not fit the tile, or windows beyond
+// the largest number one pass may chain (win_cap), are left for later passes
+// while commuting steps after them still join.  The result goes to `out`: a step that joins no group is copied unchanged (all
 // its fields), a group becomes one S_F step whose TileGroup is appended to
 // `groups`, its commands to `fops` and its windows' measurement indices to
 // `fm`.
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm) {
   const size_t ns = steps.size();
-  const int win_cap = mode == OWQS_MODE_EOWQS ? kMaxGroupWindows : 16;
+  // windows of a pass chain their norms in FP32 without renormalising: 16
+  // keep it in range down to p ~ 1e-4 per window; windows with p = 1/2
+  // exactly (an odd E(v, w) count) keep the norm, so a pass of only those
+  // (and EOWQS, which computes no norm) may hold kMaxGroupWindows
+  auto win_cap = [mode](bool even) { return mode == OWQS_MODE_EOWQS || !even ? kMaxGroupWindows : 16; };
   auto groupable = [](int k) { return k == S_J || k == S_E || k == S_X || k == S_Z; };
+  std::vector<char> done(ns, 0);
+  std::vector<size_t> taken, skipped;
   size_t i = 0;
-  while (i < ns) {
+  while (true) {
+    while (i < ns && done[i]) ++i;
+    if (i == ns) break;
     const Step &x0 = steps[i];
     if (!groupable(x0.kind) || x0.n < kTileMinWidth) {
       out.push_back(x0);
-      ++i;
+      done[i] = 1;
       continue;
     }
     const int n = x0.n;
@@ -118,27 +145,44 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     if (tile_bits) k = std::min(tile_bits, n - 2);
     uint64_t tmask = (uint64_t(1) << kLowBits) - 1;
     int used = kLowBits, nwin = 0;
-    size_t j = i;
-    for (; j < ns; ++j) {
+    bool even = false;  // the pass holds a window with an even E(v, w) count
+    // Take the run's steps in order; a step that does not fit (its mixing
+    // slot would overflow the tile, or the window count is reached) is left
+    // for a later pass, and a later step may join only if it commutes with
+    // every step left behind (commute_steps), up to kGroupLookahead steps.
+    taken.clear();
+    skipped.clear();
+    for (size_t j = i; j < ns && j - i < kGroupLookahead; ++j) {
+      if (done[j]) continue;
       const Step &x = steps[j];
-      if (!groupable(x.kind) || x.n != n) break;
-      if (x.kind == S_J && nwin == win_cap) break;
-      if (j - i == 128) break;
-      if (x.kind == S_J || x.kind == S_X) {
-        const uint64_t bit = uint64_t(1) << x.b0;
-        if (!(tmask & bit)) {
-          if (used == k) break;
-          tmask |= bit;
-          ++used;
-        }
+      if (!groupable(x.kind) || x.n != n || taken.size() == 128) break;
+      bool ok = !(x.kind == S_J && nwin >= win_cap(even || x.win.vw_even));
+      uint64_t bit = 0;
+      if (ok && (x.kind == S_J || x.kind == S_X)) {
+        bit = uint64_t(1) << x.b0;
+        if (tmask & bit) bit = 0;
+        else if (used == k) ok = false;
+      }
+      for (size_t q = 0; ok && q < skipped.size(); ++q) ok = commute_steps(steps[skipped[q]], x);
+      if (!ok) {
+        skipped.push_back(j);
+        if (skipped.size() > kGroupSkipMax) break;
+        continue;
+      }
+      taken.push_back(j);
+      if (bit) {
+        tmask |= bit;
+        ++used;
       }
       nwin += x.kind == S_J;
+      even = even || (x.kind == S_J && x.win.vw_even);
     }
-    if (j - i < 2) {
+    if (taken.size() < 2) {
       out.push_back(x0);
-      ++i;
+      done[i] = 1;
       continue;
     }
+    for (size_t q : taken) done[q] = 1;
     // fill the tile up to k bits with the lowest unused slots (more work per pass)
     for (int b = 0; used < k && b < n; ++b)
       if (!(tmask & (uint64_t(1) << b))) {
@@ -172,7 +216,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     tg.op_off = fops.size();
     tg.m_off = fm.size();
     int widx = 0;
-    for (size_t q = i; q < j; ++q) {
+    for (size_t q : taken) {
       const Step &x = steps[q];
       FuseOp op{};
       op.kind = (uint8_t)x.kind;
@@ -196,10 +240,10 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
       }
       fops.push_back(op);
     }
-    tg.ta.nops = (int)(j - i);
+    tg.ta.nops = (int)taken.size();
     tg.ta.nwin = widx;
     tg.half = widx > 0;
-    for (size_t q = i; q < j; ++q)
+    for (size_t q : taken)
       if (steps[q].kind == S_J && steps[q].win.vw_even) tg.half = false;
     // compile the register runs in only where two windows on different bits
     // follow each other, possibly with an E or Z between (they cost occupancy
@@ -219,7 +263,6 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     gs.group = (int)groups.size();
     groups.push_back(tg);
     out.push_back(gs);
-    i = j;
   }
 }
 

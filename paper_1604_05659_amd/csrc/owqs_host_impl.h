@@ -259,7 +259,12 @@ owqs_status width_guard(owqs_pattern *p);
 owqs_status ensure_device(owqs_pattern *p, bool need_psi = true);
 void end_ranged(owqs_pattern *p);
 owqs_status upload_fuse(owqs_pattern *p);
-// Group runs of window/E/X/Z steps into tile passes (S_F steps in `out`).
+// Group runs of window/E/X/Z steps into tile passes (S_F steps in `out`),
+// looking up to kGroupLookahead steps ahead past at most kGroupSkipMax steps
+// left for later passes.
+constexpr size_t kGroupLookahead = 96;
+constexpr size_t kGroupSkipMax = 24;
+bool commute_steps(const Step &a, const Step &b);
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm);
 // Copy a tile-pass command table (FuseOps, then the windows' measurement
