@@ -669,6 +669,12 @@ def main():
             _, roof_f = roofline_of(prof_f, names)
             result["fused"]["roofline"] = roof_f
             result["fused"]["kernels"] = kernel_table(prof_f)
+        if prof:
+            # each tile pass carries about nontrivial / passes commands in one
+            # HBM round trip: the plain executor's algorithmic bytes for the
+            # same result, over the fused run time
+            result["fused"]["commands_per_pass"] = round(n_nontriv / max(fused_passes, 1), 1)
+            result["fused"]["plain_equivalent_GBs"] = round(step_bytes / (ms_f / 1e3) / 1e9, 1)
     if not args.no_sampled:
         log("[bench] drawn outcomes")
         result["sampled"] = bench_sampled(owqs, torch, pat, inp, out, n_nontriv, args.steps, args.warmup)
