@@ -14,8 +14,9 @@ amplitudes into a device buffer.
 
 Printed: one JSON line with the metric (non-trivial pattern commands per
 second), the roofline of the dominant kernel (HIP events around every launch
-of one extra profiled step), the fused-window executor's figures, and the FP64
-oracle timed on the host cores on a bounded sample of the same workload.
+of one extra profiled step), a measured device-copy ceiling, the fused
+executor's figures and the other workloads' legs, and the FP64 oracle timed
+on the host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -496,6 +497,29 @@ def bench_sampled(owqs, torch, pat, inp, out, n_nontriv, steps, warmup):
     return res
 
 
+def copy_ceiling(torch):
+    """A measured copy ceiling next to the 8 TB/s peak: torch's device copy
+    of 2^25 complex64 (256 MiB, about the size of the Infinity Cache) and of
+    2^28 (2 GiB, beyond it), event-timed; bytes = read + write."""
+    out = {}
+    for n in (25, 28):
+        a = torch.empty(1 << n, dtype=torch.complex64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"2^{n}"] = {"us": round(1e3 * ms, 2), "GB/s": round(2 * a.numel() * 8 / (ms / 1e3) / 1e9, 1)}
+        del a, b
+    return out
+
+
 def bench_small(owqs, torch, W, ctx, steps):
     """The small plain pattern (4 logical qubits, 106 commands): latency of
     one run plus read-out through the C ABI (fused plan replayed as a graph)."""
@@ -640,6 +664,8 @@ def main():
         result["hbm_gbs_step"] = round(step_bytes / (ms_step / 1e3) / 1e9, 1)
         result["roofline"] = roof
         result["kernels"] = kernel_table(prof)
+
+    result["copy_ceiling"] = copy_ceiling(torch)
 
     if not args.no_fused:
         log("[bench] fused executor (tile size picked by the autotuner)")
