@@ -148,6 +148,30 @@ def test_fused_plan_forms_windows(host_ctx):
     assert x3 < n3  # runs of windows group into tile passes at width >= 18
 
 
+def test_tile_grouping_looks_ahead(host_ctx):
+    """Host plan of the large circuit (24 logical qubits, 2000 J + 300 CZ):
+    a step whose slot does not fit the tile no longer ends the pass, so the
+    2300 steps go into about 70 passes (each at most 128 steps, at most 32
+    windows), in OWQS and EOWQS mode alike; the sub-state plan of three
+    16-qubit circuits groups each sub-state's steps the same way."""
+    wl = W.plain_large()
+    p = owqs.Pattern(host_ctx, wl.pattern)
+    p.set_outcomes(wl.outcomes)
+    p.set_exec(owqs.EXEC_FUSED)
+    for mode in (owqs.MODE_OWQS, owqs.MODE_EOWQS):
+        p.set_mode(mode)
+        w, n, passes = p.plan_info()
+        assert (w, n) == (24, 2300)
+        assert 2300 / 128 <= passes <= 80, passes
+    g = np.random.default_rng([160405659, 9, 0])
+    parts = [W.circuit_to_pattern(16, W.random_jcz_circuit(16, 400, 60, g)) for _ in range(3)]
+    q = owqs.Pattern(host_ctx, W.disjoint_union(parts))
+    q.set_exec(owqs.EXEC_SUBSTATES)
+    q.set_input_factors([16, 16, 16])
+    w, n, launches = q.plan_info()
+    assert w == 16 and n == 1380 and launches <= 120, (w, n, launches)
+
+
 def test_outcome_seed_follows_the_oracle_stream(host_ctx):
     from oracle import core as oc
     for wl in (W.plain_small(), W.cluster(rows=4, cols=6)):
