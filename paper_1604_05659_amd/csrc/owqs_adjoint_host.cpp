@@ -53,6 +53,8 @@ owqs_status owqs_adjoint(owqs_pattern *p, const void *input_c64, const double *a
   // at every segment so that rounding cannot build up over more than one
   bool reversible = ckpt_stride >= 0;  // a negative stride asks for the recompute sweep
   for (size_t q : wins) reversible = reversible && !p->steps[q].win.vw_even;
+  for (const TileGroup &tg : p->groups)  // the reverse pass sums at most kMaxGroupWindows windows
+    reversible = reversible && tg.ta.nwin <= kMaxGroupWindows;
   // the reversing sweep walks the grouped plan: a tile group runs on every
   // set in one launch, forward and backward.  Partials of window q, set b sit
   // in row (q * batch + b) of nblk_row blocks (at least every launch's grid).

@@ -120,13 +120,31 @@ bool commute_steps(const Step &a, const Step &b) {
 // `groups`, its commands to `fops` and its windows' measurement indices to
 // `fm`.
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
-                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm) {
+                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm, bool big_half) {
   const size_t ns = steps.size();
   // windows of a pass chain their norms in FP32 without renormalising: 16
   // keep it in range down to p ~ 1e-4 per window; windows with p = 1/2
   // exactly (an odd E(v, w) count) keep the norm, so a pass of only those
-  // (and EOWQS, which computes no norm) may hold kMaxGroupWindows
-  auto win_cap = [mode](bool even) { return mode == OWQS_MODE_EOWQS || !even ? kMaxGroupWindows : 16; };
+  // (and EOWQS, which computes no norm) may hold kMaxGroupWindows.  With
+  // big_half (OWQS), a pass of only such windows that mark_half will run
+  // without a reduction may hold kMaxHalfWindows: `run` follows mark_half's
+  // count of such windows since the last reduction, step by step.
+  int run = 0;
+  auto win_cap = [mode, big_half, &run](bool even) {
+    if (mode == OWQS_MODE_EOWQS) return kMaxGroupWindows;
+    if (even) return 16;
+    return big_half && run + kMaxHalfWindows <= kHalfRun ? kMaxHalfWindows : kMaxGroupWindows;
+  };
+  auto follow = [&run](const Step &x, const TileGroup *tg) {  // mark_half's rule
+    if (tg) {
+      if (tg->ta.nwin == 0) return;
+      run = tg->half && run + tg->ta.nwin <= kHalfRun ? run + tg->ta.nwin : 0;
+    } else if (x.kind == S_M) {
+      run = 0;
+    } else if (x.kind == S_J) {
+      run = !x.win.vw_even && run + 1 <= kHalfRun ? run + 1 : 0;
+    }
+  };
   auto groupable = [](int k) { return k == S_J || k == S_E || k == S_X || k == S_Z; };
   std::vector<char> done(ns, 0);
   std::vector<size_t> taken, skipped;
@@ -137,6 +155,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     const Step &x0 = steps[i];
     if (!groupable(x0.kind) || x0.n < kTileMinWidth) {
       out.push_back(x0);
+      follow(x0, nullptr);
       done[i] = 1;
       continue;
     }
@@ -179,6 +198,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     }
     if (taken.size() < 2) {
       out.push_back(x0);
+      follow(x0, nullptr);
       done[i] = 1;
       continue;
     }
@@ -263,6 +283,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     gs.group = (int)groups.size();
     groups.push_back(tg);
     out.push_back(gs);
+    follow(gs, &groups.back());
   }
 }
 
@@ -275,7 +296,8 @@ void group_tiles(owqs_pattern *p) {
     p->xsteps = p->steps;
     return;
   }
-  group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m);
+  group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m,
+              p->mode == OWQS_MODE_OWQS);
   if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups);
   else
     for (TileGroup &tg : p->groups) tg.half = false;

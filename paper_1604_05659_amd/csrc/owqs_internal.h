@@ -91,6 +91,9 @@ constexpr int kDefaultTileBits = 12;   // 32 KiB tiles: four workgroups per CU
 constexpr int kMinTileBits = 10;       // smallest tile the kernels take
 constexpr int kTileMinWidth = 15;      // at least 2^5 tiles of 2^10; narrower runs stay one kernel per step
 constexpr int kMaxGroupWindows = 32;
+// A group that runs without a reduction (OWQS windows with p = 1/2 exactly)
+// may hold more windows: the per-window sums only serve groups that reduce.
+constexpr int kMaxHalfWindows = 64;
 constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
 
 // One command of a fused group, with its slots mapped into the tile.

@@ -820,6 +820,8 @@ hipError_t tile_prepare() {
 
 hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const MeasureArgs &a, hipStream_t s,
                        unsigned *grid) {
+  // the per-window sums hold kMaxGroupWindows; larger groups only run without them
+  if (ta.nwin > (a.reduce != kReduceNone ? kMaxGroupWindows : kMaxHalfWindows)) return hipErrorInvalidValue;
   const size_t bytes = sizeof(float2) << ta.k;
   const unsigned g = tile_grid(ta);
   switch (ta.k) {
@@ -880,6 +882,7 @@ hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta0, const FuseOp *ops,
 hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta0, const FuseOp *ops, int nsets,
                            size_t set_stride, const float2 *coefs, double *partials, int q_first, unsigned nblk,
                            hipStream_t s) {
+  if (ta0.nwin > kMaxGroupWindows) return hipErrorInvalidValue;  // its per-window sums hold that many
   TileArgs ta = ta0;
   ta.set_stride = set_stride;
   ta.coefs = coefs;
