@@ -189,6 +189,7 @@ struct owqs_pattern {
     SigRef s, t;
     Window win;             // S_J: the window's sign masks (its folds are resolved on the device)
     int fold_off, fold_len; // S_J: its corrections in s_folds
+    bool half;              // S_J: p = 1/2 recorded without the sum (at most kHalfRun in a row)
   };
   bool sampling = false;
   std::vector<double> uniforms;

@@ -137,6 +137,23 @@ void compile_sampled(owqs_pattern *p) {
     }
     p->s_steps.push_back(st);
   }
+  // drawn windows have p = 1/2 exactly: like the fused plans (half_prob),
+  // they record it without the sum, their FP32 factors chosen with error
+  // feedback (rounded_factor), at most kHalfRun in a row
+  {
+    double e = 1.0;
+    int run = 0;
+    for (owqs_pattern::SStep &x : p->s_steps) {
+      if (x.kind == S_J) {
+        x.host_factor = rounded_factor(x.host_factor, e);
+        x.half = run + 1 <= kHalfRun;
+        run = x.half ? run + 1 : 0;
+      } else if (x.kind == S_M) {
+        e = 1.0;
+        run = 0;
+      }
+    }
+  }
   p->s_final_where.assign(p->outputs.size(), 0);
   for (size_t k = 0; k < p->outputs.size(); ++k) p->s_final_where[k] = slot_of[p->outputs[k]];
   p->s_final_factor = pending;
@@ -197,7 +214,8 @@ hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
         a.coef_dev = sm.coef;
         a.fold_dev = sm.fold;
         a.host_factor = x.host_factor;
-        a.reduce = kReduceRenorm;
+        a.reduce = x.half ? kReduceNone : kReduceRenorm;  // p = 1/2 exactly: sigma waits for the next sum
+        a.prob_half = x.half ? 1 : 0;
         a.m_index = x.m;
         a.book = p->book;
         if (e == hipSuccess) e = launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &g);
