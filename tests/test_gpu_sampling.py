@@ -144,3 +144,24 @@ def test_drawn_windows_on_the_fused_plan(ctx, nl, nj, ncz):
                 assert np.max(np.abs(got - want)) <= AMP_TOL, (draw, ex, rep)
                 np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
             p.close()
+
+
+@pytest.mark.parametrize("exec_", [owqs.EXEC_PLAIN, owqs.EXEC_FUSED])
+def test_long_runs_of_drawn_windows(ctx, exec_):
+    """300 drawn windows (p = 1/2 exactly) in a row, more than the 128 that
+    may skip their sum before one renormalises: outcomes, output, norm and
+    probabilities against the oracle, for the device-drawn plain plan and
+    the fused plan."""
+    wl = W.plain_large(index=5, n_logical=10, n_j=300, n_cz=30)
+    g = np.random.default_rng(300)
+    u, want, pw, ow = safe_uniforms(wl.pattern, wl.input_state, g)
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_exec(exec_)
+    p.set_uniforms(u)
+    p.run(torch.as_tensor(wl.input_state).cuda())
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    np.testing.assert_array_equal(p.read_outcomes(), ow)
+    assert float(np.max(np.abs(got - want))) <= AMP_TOL
+    assert abs(np.linalg.norm(got) - 1) <= 1e-5
+    np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+    p.close()
