@@ -700,6 +700,9 @@ def main():
             # HBM round trip: the plain executor's algorithmic bytes for the
             # same result, over the fused run time
             result["fused"]["commands_per_pass"] = round(n_nontriv / max(fused_passes, 1), 1)
+            result["fused"]["bound_note"] = ("a tile pass applies all its steps between one HBM read and write of the "
+                                             "vector; its time is the steps' VALU work and LDS rounds, so the HBM "
+                                             "fraction of a pass is not its limit")
             result["fused"]["plain_equivalent_GBs"] = round(step_bytes / (ms_f / 1e3) / 1e9, 1)
     if not args.no_sampled:
         log("[bench] drawn outcomes")
