@@ -522,7 +522,8 @@ def copy_ceiling(torch):
 
 def bench_small(owqs, torch, W, ctx, steps):
     """The small plain pattern (4 logical qubits, 106 commands): latency of
-    one run plus read-out through the C ABI (fused plan replayed as a graph)."""
+    one run plus read-out through the C ABI, host calls included (the default
+    executor runs a pattern this narrow in one workgroup's LDS)."""
     wl = W.plain_small()
     p = owqs.Pattern(ctx, wl.pattern)
     p.set_mode(owqs.MODE_OWQS)
@@ -539,7 +540,8 @@ def bench_small(owqs, torch, W, ctx, steps):
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / reps
     p.close()
-    return {"workload": "plain_small: 4 logical qubits, 20 J + 6 CZ, 106 commands, OWQS, fused + graph",
+    return {"workload": "plain_small: 4 logical qubits, 20 J + 6 CZ, 106 commands, OWQS, one workgroup in LDS "
+                        "(default executor), run + read-out through the Python binding",
             "us_per_pattern": round(1e6 * t, 2)}
 
 
