@@ -574,6 +574,26 @@ def pmc_probe():
     print(json.dumps({"pmc_probe": "done", "commands": len(pat_def.cmds), "counts": pat_def.counts()}), flush=True)
 
 
+def tile_probe():
+    """One fused run of the large workload (OWQS, tile bits 12) after one
+    warm-up run: the dispatches hardware-counter passes over k_tile read."""
+    import torch
+    import owqs_workloads as W
+    import paper_1604_05659_amd as owqs
+    wl = W.plain_large(**WORKLOAD)
+    ctx = owqs.Context(0)
+    p = owqs.Pattern(ctx, wl.pattern)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_outcomes(wl.outcomes)
+    p.set_exec(owqs.EXEC_FUSED)
+    p.set_tile_bits(12)
+    inp = torch.as_tensor(wl.input_state).cuda()
+    p.run(inp)
+    torch.cuda.synchronize()
+    log(f"[bench] tile probe: plan {p.plan_info()}")
+    p.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -590,11 +610,17 @@ def main():
                     help="skip the extra event-timed step (for counter collection runs)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one short run at full width, few dispatches: for rocprofv3 --pmc passes")
+    ap.add_argument("--tile-probe", action="store_true",
+                    help="one fused run of the large workload at tile bits 12 (40 tile passes): for rocprofv3 "
+                         "--pmc passes over the tile kernel")
     ap.add_argument("--only-plain", action="store_true",
                     help="run only the plain executor on the large workload (for counter collection runs)")
     args = ap.parse_args()
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.tile_probe:
+        tile_probe()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a pattern on a single MI355X "
