@@ -552,7 +552,10 @@ owqs_status ensure_device(owqs_pattern *p, bool need_psi) {
   if (p->ctx->device < 0) return fail(p->ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
   hipError_t e = hipSetDevice(p->ctx->device);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "hipSetDevice");
-  const size_t need = std::max<size_t>(size_t(1) << p->max_live, 4);
+  // max_live may exceed the width limit (and 63) for sub-state patterns,
+  // which never ask for the one-vector buffer
+  if (need_psi && p->max_live > OWQS_MAX_WIDTH) return fail(p->ctx, OWQS_E_WIDTH, "live width over the limit");
+  const size_t need = need_psi ? std::max<size_t>(size_t(1) << p->max_live, 4) : 0;
   if (need_psi && p->psi_cap < need) {
     if (p->psi) (void)hipFree(p->psi);
     p->psi = nullptr;
@@ -1506,14 +1509,19 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     e = hipEventRecord(ctx->fork, s);
     for (size_t k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamWaitEvent(ctx->side[k], ctx->fork, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "fork");
-    for (size_t j = 0; j < wide.size(); ++j) {
+    owqs_status r = OWQS_OK;
+    for (size_t j = 0; j < wide.size() && r == OWQS_OK; ++j) {
       owqs_pattern *p = pats[wide[j]];
       hipStream_t st = ctx->side[j % nside];
-      owqs_status r = run_impl(p, inputs ? inputs[wide[j]] : nullptr, size_t(1) << p->inputs.size(), 1, st,
-                               nullptr);
-      if (r != OWQS_OK) return r;
-      r = owqs_read_state(p, outputs[wide[j]], size_t(1) << p->outputs.size(), 1, st);
-      if (r != OWQS_OK) return r;
+      r = run_impl(p, inputs ? inputs[wide[j]] : nullptr, size_t(1) << p->inputs.size(), 1, st, nullptr);
+      if (r == OWQS_OK) r = owqs_read_state(p, outputs[wide[j]], size_t(1) << p->outputs.size(), 1, st);
+    }
+    if (r != OWQS_OK) {
+      // work already queued on the side streams still writes caller outputs:
+      // join it into the caller's stream before reporting the error
+      for (size_t k = 0; k < nside; ++k)
+        if (hipEventRecord(ctx->join[k], ctx->side[k]) == hipSuccess) (void)hipStreamWaitEvent(s, ctx->join[k], 0);
+      return r;
     }
   }
   if (!items.empty()) {
