@@ -245,6 +245,45 @@ owqs_status owqs_run_basis(owqs_pattern *pat, uint32_t first, uint32_t count, vo
 owqs_status owqs_run_states(owqs_pattern *pat, const void *in_c64, uint32_t count, void *out_c64,
                             double *probs, void *stream);
 
+/* Allocation-free run, for callers that cannot allocate device memory:
+ * code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc.  It runs the pattern's plan (the same kernels as owqs_run, in the
+ * same order, launched on `stream` without a graph) and writes the read-out,
+ * but its working memory is a fixed array inside the library instead of the
+ * pattern's buffers:
+ *   the live vector, at most 2^OWQS_NOALLOC_MAX_WIDTH complex64 (32 MiB),
+ *   the FP64 scale, the FP64 block partials, and (when `probs` or `err` is
+ *   NULL) the probabilities and the error word.
+ * The array is static device memory of about 33 MiB on each GPU the library
+ * runs on, held until the process ends; its address is resolved when a
+ * context is created on that device.  Every call on one GPU shares it and
+ * overwrites what the previous call left: calls that overlap on one GPU
+ * (different streams, or different host threads) race and give undefined
+ * results.  Nothing is allocated or freed: no hipMalloc, hipFree or graph.
+ *   input_c64:  device, 2^nin complex64 (n_in_amps = 2^nin; NULL with
+ *               n_in_amps = 1 when nin = 0 for the empty product state)
+ *   output_c64: device, 2^nout complex64 (n_out_amps = 2^nout), outputs[k]
+ *               at bit k, scaled to the true state as owqs_read_state does
+ *   probs:      device, n_meas FP64 (per M, Eq. 13; written in OWQS and
+ *               EOWQS_CHECK modes; EOWQS assumes 1/2 and writes none), or
+ *               NULL to keep them in the array (then n_meas <= 65536)
+ *   err:        device, 2 int32 {first M index that failed or 0x7fffffff,
+ *               kind: 1 zero probability, 2 |p - 1/2| > 1e-4}, cleared by
+ *               the call, or NULL (kept in the array, not reported)
+ * Preconditions: forced outcomes (no uniforms), not the SUBSTATES executor,
+ * and the plan compiled and its command table on the device: run the pattern
+ * once with owqs_run after its last change (mode, exec, angles, outcomes,
+ * tile size), outside the allocation-free region; else OWQS_E_STATE.
+ * OWQS_E_WIDTH when the pattern's live width exceeds OWQS_NOALLOC_MAX_WIDTH
+ * (checked first, also on a host-only context), or when probs is NULL and
+ * the pattern has more than 65536 M commands.  The call does not change what
+ * owqs_read_state, owqs_read_probs and owqs_check report (they refer to the
+ * last owqs_run). */
+#define OWQS_NOALLOC_MAX_WIDTH 22
+owqs_status owqs_run_noalloc(owqs_pattern *pat, const void *input_c64, size_t n_in_amps,
+                             void *output_c64, size_t n_out_amps, double *probs, int32_t *err,
+                             void *stream);
+
 /* Run `npat` independent patterns of one context as one batch.  inputs[i]
  * (2^nin_i complex64; may be NULL for a pattern without inputs) and
  * outputs[i] (2^nout_i complex64) are device pointers.  Patterns whose plan

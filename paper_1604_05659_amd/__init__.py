@@ -60,6 +60,7 @@ assert ctypes.sizeof(OwqsCmd) == 40
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 MAX_WIDTH = 34  # OWQS_MAX_WIDTH
+NOALLOC_MAX_WIDTH = 22  # OWQS_NOALLOC_MAX_WIDTH
 _sig = {
     "owqs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "owqs_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -93,6 +94,7 @@ _sig = {
     "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "owqs_run_basis": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_states": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]),
+    "owqs_run_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     "owqs_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
                                       ctypes.POINTER(_vp), _vp]),
     "owqs_adjoint": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _i32p,
@@ -347,6 +349,29 @@ class Pattern:
         pp = None if probs is None else probs.data_ptr()
         self.ctx.check(_lib.owqs_run_states(self._h, states.data_ptr(), int(count), out.data_ptr(), pp,
                                             _stream_handle(stream)))
+        return out
+
+    def run_noalloc(self, psi_in, out, probs=None, err=None, stream=None):
+        """owqs_run_noalloc: the whole run with the library's fixed working
+        array (no device allocation).  psi_in: complex64 CUDA tensor of
+        2^n_in amplitudes or None (n_in = 0); out: complex64 CUDA tensor of
+        2^n_out; probs: float64 CUDA tensor of n_meas or None; err: int32
+        CUDA tensor of 2 or None.  Returns out."""
+        import torch
+        self._check_out(out, 1 << self.n_out)
+        if psi_in is None:
+            ip, n_in = None, 1
+        else:
+            if psi_in.dtype != torch.complex64 or not psi_in.is_cuda or not psi_in.is_contiguous():
+                raise TypeError("input must be a contiguous complex64 CUDA tensor")
+            ip, n_in = psi_in.data_ptr(), psi_in.numel()
+        if probs is not None and (probs.dtype != torch.float64 or not probs.is_cuda or probs.numel() != self.n_meas):
+            raise TypeError("probs must be a float64 CUDA tensor of n_meas entries")
+        if err is not None and (err.dtype != torch.int32 or not err.is_cuda or err.numel() != 2):
+            raise TypeError("err must be an int32 CUDA tensor of 2 entries")
+        self.ctx.check(_lib.owqs_run_noalloc(self._h, ip, n_in, out.data_ptr(), out.numel(),
+                                             None if probs is None else probs.data_ptr(),
+                                             None if err is None else err.data_ptr(), _stream_handle(stream)))
         return out
 
     @staticmethod

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libowqs.so")
-SOURCES = ["owqs_host.cpp", "owqs_substate_host.cpp", "owqs_sample_host.cpp", "owqs_adjoint_host.cpp", "owqs_kernels.hip", "owqs_batch.hip", "owqs_adjoint.hip", "owqs_tile.hip", "owqs_sample.hip", "owqs_proa.cpp", "owqs_substate.hip", "owqs_gflow.cpp"]
+SOURCES = ["owqs_host.cpp", "owqs_substate_host.cpp", "owqs_sample_host.cpp", "owqs_adjoint_host.cpp", "owqs_kernels.hip", "owqs_batch.hip", "owqs_adjoint.hip", "owqs_tile.hip", "owqs_sample.hip", "owqs_proa.cpp", "owqs_substate.hip", "owqs_gflow.cpp", "owqs_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wl,-z,defs",

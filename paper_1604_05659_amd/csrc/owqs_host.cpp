@@ -716,20 +716,23 @@ void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups) {
 }
 
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
-                        hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab, const int *ftab) {
+                        hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab, const int *ftab,
+                        float2 *psi_over, const DevBook *book_over) {
+  float2 *const psi = psi_over ? psi_over : p->psi;
+  const DevBook book = book_over ? *book_over : p->book;
   hipError_t e = hipSuccess;
   for (size_t i = i0; i < i1 && e == hipSuccess; ++i) {
     const Step &x = xs[i];
     MeasureArgs a{};
     a.reduce = reduce;
-    a.book = p->book;
+    a.book = book;
     unsigned grid = 0;
     const FuseOp *ops = nullptr;
     switch (x.kind) {
-      case S_N: e = launch_prepare(p->psi, x.n, s); break;
-      case S_E: e = launch_cz(p->psi, x.n, x.b0, x.b1, s); break;
-      case S_X: e = launch_pauli_x(p->psi, x.n, x.b0, s); break;
-      case S_Z: e = launch_pauli_z(p->psi, x.n, x.b0, s); break;
+      case S_N: e = launch_prepare(psi, x.n, s); break;
+      case S_E: e = launch_cz(psi, x.n, x.b0, x.b1, s); break;
+      case S_X: e = launch_pauli_x(psi, x.n, x.b0, s); break;
+      case S_Z: e = launch_pauli_z(psi, x.n, x.b0, s); break;
       case S_M:
       case S_J:
         a.coef = x.coef;
@@ -743,8 +746,8 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
           a.coef_dev = ctab + x.m_index;
           a.fold_dev = ftab + 3 * x.m_index;
         }
-        e = x.kind == S_M ? launch_measure(p->psi, x.n, x.b0, a, s, &grid)
-                          : launch_jwindow(p->psi, x.n, x.b0, a, x.win, s, &grid);
+        e = x.kind == S_M ? launch_measure(psi, x.n, x.b0, a, s, &grid)
+                          : launch_jwindow(psi, x.n, x.b0, a, x.win, s, &grid);
         break;
       case S_F: {
         const TileGroup &tg = p->groups[x.group];
@@ -759,7 +762,7 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
           a.reduce = kReduceNone;
           ta.half_m = fuse_m_dev(p) + tg.m_off;
         }
-        e = launch_tile(p->psi, ta, ops, a, s, &grid);
+        e = launch_tile(psi, ta, ops, a, s, &grid);
         break;
       }
       default: break;
@@ -1156,8 +1159,20 @@ owqs_status owqs_ctx_create(int device, owqs_ctx **out) {
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || device < 0 || device >= count) return OWQS_E_INVALID_ARG;
   }
+  void *scratch = nullptr;
+  if (device >= 0) {
+    // resolve the allocation-free entry point's array once per device, with
+    // that device current (then restore the caller's current device)
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    if (e == hipSuccess) e = noalloc_scratch(device, &scratch);
+    if (e == hipSuccess) e = hipSetDevice(prev);
+    if (e != hipSuccess) return OWQS_E_HIP;
+  }
   auto *c = new owqs_ctx();
   c->device = device;
+  c->noalloc = scratch;
   *out = c;
   return OWQS_OK;
 }

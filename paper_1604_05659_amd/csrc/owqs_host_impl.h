@@ -32,6 +32,9 @@ struct owqs_ctx {
   owqs::LdsItem *dev_items = nullptr;  // device copy of an LDS batch's item table
   size_t dev_items_cap = 0;
   hipEvent_t items_done = nullptr;     // recorded after the kernel that reads dev_items
+  // the allocation-free entry point's device array on this device (its
+  // address from hipGetSymbolAddress, resolved when the context is created)
+  void *noalloc = nullptr;
 };
 
 namespace owqs {
@@ -288,9 +291,15 @@ struct Profile {
 };
 // With ctab / ftab: the windows take their coefficient and folds from these
 // per-run device tables (coefficient of M m at ctab[m], folds at ftab[3 m]).
+// psi_over / book_over (non-null): run on that live vector and bookkeeping
+// instead of the pattern's own (the allocation-free entry point).
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
                         hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab = nullptr,
-                        const int *ftab = nullptr);
+                        const int *ftab = nullptr, float2 *psi_over = nullptr, const DevBook *book_over = nullptr);
+LdsItem lds_proto(const owqs_pattern *p);
+// Address of the allocation-free entry point's device array on `device`
+// (resolved once per device with that device current; owqs_noalloc.hip).
+hipError_t noalloc_scratch(int device, void **out);
 
 // ---- owqs_substate_host.cpp
 void compile_substates(owqs_pattern *p);

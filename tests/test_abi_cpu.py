@@ -213,3 +213,22 @@ def test_uniforms_argument_checks(host_ctx):
     p.set_outcomes(wl.outcomes)
     np.testing.assert_array_equal(p.read_outcomes(), wl.outcomes)
     p.close()
+
+
+def test_noalloc_rejects_width_and_host_context(host_ctx):
+    """owqs_run_noalloc checks the live width against its fixed array before
+    anything else (a clear OWQS_E_WIDTH), and a host-only context cannot run."""
+    wide = W.plain_large(n_logical=owqs.NOALLOC_MAX_WIDTH, n_j=4, n_cz=1)   # live width 23
+    p = owqs.Pattern(host_ctx, wide.pattern)
+    assert p.max_live == owqs.NOALLOC_MAX_WIDTH + 1
+    st = owqs._lib.owqs_run_noalloc(p._h, None, 1 << p.n_in, None, 1 << p.n_out, None, None, None)
+    assert st == owqs.E_WIDTH
+    assert b"allocation-free limit 22" in owqs._lib.owqs_last_error(host_ctx._h)
+    ok = W.plain_small()
+    q = owqs.Pattern(host_ctx, ok.pattern)
+    st = owqs._lib.owqs_run_noalloc(q._h, None, 1, None, 1 << q.n_out, None, None, None)
+    assert st == owqs.E_INVALID_ARG          # no output buffer
+    st = owqs._lib.owqs_run_noalloc(q._h, None, 1, 1234, 1 << q.n_out, None, None, None)
+    assert st == owqs.E_STATE                # host-only context
+    p.close()
+    q.close()
