@@ -143,8 +143,9 @@ def cpu_baseline(wl_gates, psi_in, seconds_hint):
 
 def bench_batched(owqs, torch, W, ctx, steps):
     """512 random J/CZ patterns (live widths 8..20, 50..800 commands each):
-    one owqs_run_batch call versus the same patterns run one after another
-    with the plain executor."""
+    one owqs_run_batch call (one captured graph) versus the same plans run
+    one pattern after another, and versus the plain executor one pattern
+    after another."""
     wls = [W.batched_random(i) for i in range(512)]
     pats, ins, outs = [], [], []
     for wl in wls:
@@ -167,6 +168,17 @@ def bench_batched(owqs, torch, W, ctx, steps):
     for p in pats:
         p.check()
     batched_out = [o.clone() for o in outs]
+    # the same plans (default executor, captured graphs), one pattern after another
+    for p, x, o in zip(pats, ins, outs):
+        p.run(x)
+        p.read_state(o, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, x, o in zip(pats, ins, outs):
+        p.run(x)
+        p.read_state(o, check=False)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
     # plain, one pattern after another
     for p in pats:
         p.set_exec(owqs.EXEC_PLAIN)
@@ -191,8 +203,13 @@ def bench_batched(owqs, torch, W, ctx, steps):
         "lds_resident": int(sum(w <= 14 for w in widths)),
         "batched_patterns_per_s": round(len(pats) / t_batch, 1),
         "batched_ms": round(1e3 * t_batch, 3),
+        "sequential_patterns_per_s": round(len(pats) / t_seq, 1),
+        "sequential_ms": round(1e3 * t_seq, 3),
+        "sequential_note": "the same plans (default executor, graphs on) run one pattern after another",
+        "speedup_vs_sequential": round(t_seq / t_batch, 2),
         "plain_patterns_per_s": round(len(pats) / t_plain, 1),
         "plain_ms": round(1e3 * t_plain, 3),
+        "plain_note": "plain executor (one kernel per command, no graph), one pattern after another",
         "speedup": round(t_plain / t_batch, 2),
         "max_abs_diff_batched_vs_plain": diff,
     }

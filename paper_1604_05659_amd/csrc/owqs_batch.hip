@@ -185,13 +185,61 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
 }
 
 template <int kT>
-__global__ __launch_bounds__(kT) void k_lds_batch(const LdsItem *__restrict__ items, int count, int reduce) {
+__global__ __launch_bounds__(kT) void k_lds_batch(const LdsItem *__restrict__ items, int count) {
   extern __shared__ float2 lds[];
   __shared__ double red[kT / 64];
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
     const LdsItem *x = items + it;
     run_item<kT>(x->steps, x->nsteps, x->nin, x->nout, x->where, x->final_factor, lds, x->in, x->basis, x->out,
-             x->probs, reduce, x->err, -1, red);
+             x->probs, x->reduce, x->err, -1, red);
+  }
+}
+
+// A row of the batch table (read-only, uniform index): scalar loads.
+__device__ __forceinline__ BatchIo load_io(const BatchIo *ios, uint32_t i) {
+  static_assert(sizeof(BatchIo) % 4 == 0, "BatchIo is whole dwords");
+  constexpr int kW = sizeof(BatchIo) / 4;
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(ios)) +
+               size_t(kW) * __builtin_amdgcn_readfirstlane(i);
+  uint32_t w[kW];
+#pragma unroll
+  for (int k = 0; k < kW; ++k) w[k] = src[k];
+  BatchIo b;
+  __builtin_memcpy(&b, w, sizeof(b));
+  return b;
+}
+
+constexpr int kIoThreads = 256;
+
+// Start of pattern blockIdx.y of a batched run: sigma = 1, its error word
+// cleared, and (rows with a live vector) its input, or the empty product
+// state psi[0] = 1, in the first 2^nin amplitudes of that vector.
+__global__ __launch_bounds__(kIoThreads) void k_batch_start(const BatchIo *__restrict__ ios) {
+  const BatchIo b = load_io(ios, blockIdx.y);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *b.book.sigma = 1.0;
+    b.book.err[0] = kErrNone;
+    b.book.err[1] = 0;
+  }
+  if (!b.psi) return;  // an LDS-resident pattern: only its error word
+  const size_t n = size_t(1) << b.nin;
+  for (size_t i = size_t(blockIdx.x) * kIoThreads + threadIdx.x; i < n; i += size_t(gridDim.x) * kIoThreads)
+    b.psi[i] = b.in ? b.in[i] : make_float2(i == 0 ? 1.f : 0.f, 0.f);
+}
+
+// Read-out of pattern blockIdx.y: output x (bit k = outputs[k]) is the live
+// amplitude at the slots where[k], times sigma and the host factor.
+__global__ __launch_bounds__(kIoThreads) void k_batch_read(const BatchIo *__restrict__ ios) {
+  const BatchIo b = load_io(ios, blockIdx.y);
+  const double sg = b.reduce == kReduceRenorm ? *b.book.sigma : 1.0;
+  const float sc = float(sg * b.final_factor);
+  const size_t n = size_t(1) << b.nout;
+  for (size_t x = size_t(blockIdx.x) * kIoThreads + threadIdx.x; x < n; x += size_t(gridDim.x) * kIoThreads) {
+    size_t src = 0;
+    for (int k = 0; k < b.nout; ++k) src |= ((x >> k) & 1) << b.where[k];
+    const float2 v = b.psi[src];
+    b.out[x] = make_float2(sc * v.x, sc * v.y);
   }
 }
 
@@ -211,13 +259,18 @@ __global__ __launch_bounds__(kT) void k_lds_shared(LdsItem proto, int count, int
 
 unsigned lds_grid(int count) { return unsigned(count < 16384 ? count : 16384); }
 
+// (the LDS limit of k_lds_batch is raised once by lds_batch_prepare, before
+// any capture)
 template <int kT>
-hipError_t lds_batch_t(const LdsItem *items, int count, size_t bytes, int reduce, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch<kT>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lds_batch<kT>, dim3(lds_grid(count)), dim3(kT), bytes, s, items, count, reduce);
+hipError_t lds_batch_t(const LdsItem *items, int count, size_t bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_lds_batch<kT>, dim3(lds_grid(count)), dim3(kT), bytes, s, items, count);
   return hipGetLastError();
+}
+
+unsigned io_grid(int max_bits) {
+  const size_t n = size_t(1) << max_bits;
+  const size_t g = (n + kIoThreads - 1) / kIoThreads;
+  return unsigned(g < 256 ? g : 256);
 }
 
 template <int kT>
@@ -233,14 +286,39 @@ hipError_t lds_shared_t(const LdsItem &proto, int count, size_t bytes, int reduc
 
 }  // namespace
 
-hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int reduce, hipStream_t s) {
+hipError_t lds_batch_prepare() {
+  const int bytes = int(sizeof(float2) << kLdsMaxWidth);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch<64>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch<256>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_lds_batch<512>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
+
+hipError_t launch_lds_batch(const LdsItem *items, int count, int width, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const size_t bytes = sizeof(float2) << width;
   switch (threads_for(width)) {
-    case 64: return lds_batch_t<64>(items, count, bytes, reduce, s);
-    case 256: return lds_batch_t<256>(items, count, bytes, reduce, s);
-    default: return lds_batch_t<512>(items, count, bytes, reduce, s);
+    case 64: return lds_batch_t<64>(items, count, bytes, s);
+    case 256: return lds_batch_t<256>(items, count, bytes, s);
+    default: return lds_batch_t<512>(items, count, bytes, s);
   }
+}
+
+hipError_t launch_batch_start(const BatchIo *ios, int count, int max_nin, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_start, dim3(io_grid(max_nin), unsigned(count)), dim3(kIoThreads), 0, s, ios);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_read(const BatchIo *ios, int count, int max_nout, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_read, dim3(io_grid(max_nout), unsigned(count)), dim3(kIoThreads), 0, s, ios);
+  return hipGetLastError();
 }
 
 hipError_t launch_lds_shared(const LdsItem &proto, int count, int width, int reduce, uint32_t first,

@@ -12,6 +12,8 @@
 //     zero signal emit nothing;
 //   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
 //     into its pass (with the device FP64 sigma in OWQS mode).
+#include <atomic>
+
 #include "owqs_host_impl.h"
 #include "owqs_pattern_access.h"
 
@@ -519,6 +521,8 @@ void compile(owqs_pattern *p) {
   for (const Step &x : p->steps) w = std::max(w, x.n + (x.kind == S_N ? 1 : 0));
   p->plan_width = std::max(w, 1);
   group_tiles(p);
+  static std::atomic<uint64_t> generation{0};
+  p->plan_gen = ++generation;
   p->dirty = false;
   p->dev_steps_valid = false;
   p->dev_fuse_valid = false;
@@ -1179,14 +1183,18 @@ owqs_status owqs_ctx_create(int device, owqs_ctx **out) {
 
 void owqs_ctx_destroy(owqs_ctx *ctx) {
   if (!ctx) return;
-  if (ctx->device >= 0 && (ctx->fork || ctx->dev_items || ctx->items_done || !ctx->side.empty())) {
+  owqs_ctx::Batch &b = ctx->batch;
+  if (ctx->device >= 0 && (b.exec || b.graph || b.dev || b.cap || b.side || b.done)) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto st : ctx->side) (void)hipStreamDestroy(st);
-    for (auto ev : ctx->join) (void)hipEventDestroy(ev);
-    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
-    if (ctx->items_done) (void)hipEventDestroy(ctx->items_done);
-    if (ctx->dev_items) (void)hipFree(ctx->dev_items);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.cap) (void)hipStreamDestroy(b.cap);
+    if (b.side) (void)hipStreamDestroy(b.side);
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    if (b.join) (void)hipEventDestroy(b.join);
+    if (b.done) (void)hipEventDestroy(b.done);
   }
   delete ctx;
 }
@@ -1451,6 +1459,62 @@ owqs_status owqs_run_states(owqs_pattern *p, const void *in_c64, uint32_t count,
   return run_shared(p, in_c64, 0, count, out_c64, probs, stream, 0);
 }
 
+// ---- batched runs
+//
+// A batch is captured once as a graph and replayed while the call's arguments
+// and every pattern's plan stay the same.  Patterns whose plan fits one
+// workgroup's LDS (plan width <= 14) run whole in k_lds_batch, one launch per
+// width class sized for that class; the others run level by level: level s
+// applies the s-th step of every wide plan, with the tile groups of all
+// patterns at that level in one k_tile_multi launch per tile shape and their
+// group finishes in one k_finish_multi launch (other steps, and groups too
+// large for the per-tile partials, launch per pattern).  One launch starts
+// every wide pattern (input, sigma, error word) and one reads every output.
+// The LDS-resident launches run on a branch of the graph beside the levels.
+
+namespace owqs {
+namespace {
+
+// Width classes of the LDS-resident items: their launches size LDS and
+// threads for the widest item of the class.
+int lds_class(int width) { return width <= 8 ? 0 : width <= 11 ? 1 : width - 10; }  // 0..4
+constexpr int kLdsClasses = 5;
+
+struct Region {
+  size_t off = 0;
+  size_t bytes = 0;
+};
+
+size_t place(size_t &top, size_t bytes) {
+  const size_t off = (top + 255) & ~size_t(255);
+  top = off + bytes;
+  return off;
+}
+
+void drop_batch_graph(owqs_ctx *ctx) {
+  owqs_ctx::Batch &b = ctx->batch;
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.key.clear();
+  b.nodes = 0;
+}
+
+hipError_t batch_streams(owqs_ctx *ctx) {
+  owqs_ctx::Batch &b = ctx->batch;
+  hipError_t e = hipSuccess;
+  if (!b.cap) e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking);
+  if (e == hipSuccess && !b.side) e = hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking);
+  if (e == hipSuccess && !b.fork) e = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming);
+  if (e == hipSuccess && !b.join) e = hipEventCreateWithFlags(&b.join, hipEventDisableTiming);
+  if (e == hipSuccess && !b.done) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+  return e;
+}
+
+}  // namespace
+}  // namespace owqs
+
 owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat, const void *const *inputs,
                            void *const *outputs, void *stream) {
   if (!ctx || (npat && (!pats || !outputs))) return fail(ctx, OWQS_E_INVALID_ARG, "null argument");
@@ -1458,19 +1522,20 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     if (pats[i] && pats[i]->sampling)
       return fail(ctx, OWQS_E_STATE, "batched runs take forced outcomes (pattern " + std::to_string(i) + " draws them)");
   if (ctx->device < 0) return fail(ctx, OWQS_E_STATE, "host-only context");
+  if (npat == 0) return OWQS_OK;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // split: LDS-resident items (one workgroup each) and wide patterns
-  std::vector<LdsItem> items;
-  std::vector<size_t> wide;
-  int width = 1, reduce = -1;
   {
     std::vector<const owqs_pattern *> seen(pats, pats + npat);
     std::sort(seen.begin(), seen.end());
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
       return fail(ctx, OWQS_E_INVALID_ARG, "a pattern appears twice in one batch");
   }
+  // compile, place and upload every plan; the key of the call
+  std::vector<size_t> lds, wide;
+  std::vector<uint64_t> key;
+  key.reserve(npat * 8);
   for (size_t i = 0; i < npat; ++i) {
     owqs_pattern *p = pats[i];
     if (!p || p->ctx != ctx || !outputs[i]) return fail(ctx, OWQS_E_INVALID_ARG, "pattern " + std::to_string(i));
@@ -1478,109 +1543,245 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     if (substates(p)) return refuse_substates(p, "owqs_run_batch");
     if (owqs_status w = width_guard(p)) return w;
     if (p->dirty) compile(p);
-    owqs_status st = ensure_device(p, p->plan_width > kLdsMaxWidth);
+    const bool in_lds = p->plan_width <= kLdsMaxWidth;
+    owqs_status st = ensure_device(p, !in_lds);
+    if (st == OWQS_OK) st = in_lds ? upload_steps(p) : upload_fuse(p);
     if (st != OWQS_OK) return st;
-    if (p->plan_width <= kLdsMaxWidth && (reduce < 0 || reduce == reduce_of(p))) {
-      reduce = reduce_of(p);
-      st = upload_steps(p);
-      if (st != OWQS_OK) return st;
-      end_ranged(p);
-      e = launch_init(p->psi, p->book, s, 0);  // clears the pattern's error slot
-      if (e != hipSuccess) return hip_fail(ctx, e, "init");
+    (in_lds ? lds : wide).push_back(i);
+    const uint64_t k[] = {uint64_t(uintptr_t(p)), p->plan_gen, uint64_t(uintptr_t(p->psi)),
+                          uint64_t(uintptr_t(p->book_mem)), uint64_t(uintptr_t(in_lds ? (void *)p->dev_steps
+                                                                                        : (void *)p->dev_fuse)),
+                          uint64_t(uintptr_t(inputs ? inputs[i] : nullptr)), uint64_t(uintptr_t(outputs[i])),
+                          uint64_t(reduce_of(p))};
+    key.insert(key.end(), k, k + 8);
+  }
+  owqs_ctx::Batch &B = ctx->batch;
+  if (!(B.exec && key == B.key)) {
+    // ---- build: tables on the host, then one capture
+    if (B.done) {
+      e = hipEventSynchronize(B.done);  // a replay in flight still reads the old tables
+      if (e != hipSuccess) return hip_fail(ctx, e, "previous batch");
+    }
+    drop_batch_graph(ctx);
+    e = batch_streams(ctx);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch streams");
+    static const hipError_t lds_prep = lds_batch_prepare();  // once per process, outside any capture
+    if (lds_prep != hipSuccess) return hip_fail(ctx, lds_prep, "LDS batch kernel attribute");
+    // LDS-resident items by width class, longest first within a class
+    std::vector<LdsItem> cls_items[kLdsClasses];
+    int cls_width[kLdsClasses] = {0, 0, 0, 0, 0};
+    for (size_t i : lds) {
+      owqs_pattern *p = pats[i];
       LdsItem it = lds_proto(p);
       it.in = inputs ? static_cast<const float2 *>(inputs[i]) : nullptr;
       if (p->inputs.empty() && !it.in) it.basis = 0;  // empty product state
       it.out = static_cast<float2 *>(outputs[i]);
       it.probs = p->book.probs;
       it.err = p->book.err;
-      items.push_back(it);
-      width = std::max(width, p->plan_width);
-      p->ran = false;
-  p->ss_ran = false;
-      p->batch_ran = true;
-    } else {
-      wide.push_back(i);
+      it.reduce = reduce_of(p);
+      const int c = lds_class(p->plan_width);
+      cls_items[c].push_back(it);
+      cls_width[c] = std::max(cls_width[c], p->plan_width);
     }
+    for (auto &v : cls_items)
+      std::stable_sort(v.begin(), v.end(), [](const LdsItem &a, const LdsItem &b) {
+        return ((size_t)a.nsteps << std::max(a.nin, a.nout)) > ((size_t)b.nsteps << std::max(b.nin, b.nout));
+      });
+    // start / read rows: wide patterns first (they are read out), then the
+    // LDS-resident ones (only their error word is cleared)
+    std::vector<BatchIo> ios;
+    int max_nin = 0, max_nout = 0;
+    for (size_t i : wide) {
+      owqs_pattern *p = pats[i];
+      BatchIo b{};
+      b.psi = p->psi;
+      b.in = inputs ? static_cast<const float2 *>(inputs[i]) : nullptr;
+      b.out = static_cast<float2 *>(outputs[i]);
+      b.book = p->book;
+      b.final_factor = p->final_factor;
+      b.nin = (int)p->inputs.size();
+      b.nout = (int)p->outputs.size();
+      b.reduce = reduce_of(p);
+      for (size_t k = 0; k < p->final_where.size(); ++k) b.where[k] = p->final_where[k];
+      max_nin = std::max(max_nin, b.nin);
+      max_nout = std::max(max_nout, b.nout);
+      ios.push_back(b);
+    }
+    for (size_t i : lds) {
+      BatchIo b{};
+      b.book = pats[i]->book;
+      ios.push_back(b);
+    }
+    // levels of the wide plans
+    struct Bucket {
+      int k;
+      bool runs;
+      std::vector<MultiTile> ents;
+      uint32_t total = 0;
+    };
+    struct Level {
+      std::vector<Bucket> buckets;
+      std::vector<MultiFinish> fins;
+      int maxwin = 0;
+      std::vector<size_t> solo;  // wide patterns whose step runs on its own launches
+    };
+    size_t depth = 0;
+    for (size_t i : wide) depth = std::max(depth, pats[i]->xsteps.size());
+    std::vector<Level> levels(depth);
+    for (size_t lv = 0; lv < depth; ++lv) {
+      Level &L = levels[lv];
+      for (size_t i : wide) {
+        owqs_pattern *p = pats[i];
+        if (lv >= p->xsteps.size()) continue;
+        const Step &x = p->xsteps[lv];
+        const int reduce = reduce_of(p);
+        bool multi = false;
+        if (x.kind == S_F) {
+          const TileGroup &tg = p->groups[x.group];
+          const uint64_t ntiles = uint64_t(1) << (tg.ta.n - tg.ta.k);
+          const int r = (reduce == kReduceRenorm && tg.half) ? kReduceNone : reduce;
+          multi = ntiles <= kTileGridCap && tg.ta.nwin <= (r != kReduceNone ? kMaxGroupWindows : kMaxHalfWindows);
+          if (multi) {
+            MultiTile m{};
+            m.psi = p->psi;
+            m.ops = p->dev_fuse + tg.op_off;
+            m.partials = p->book.partials;
+            m.sigma = p->book.sigma;
+            m.probs = p->book.probs;
+            m.ta = tg.ta;
+            if (r == kReduceNone && reduce == kReduceRenorm) m.ta.half_m = fuse_m_dev(p) + tg.m_off;
+            m.reduce = r;
+            Bucket *bk = nullptr;
+            for (Bucket &b : L.buckets)
+              if (b.k == tg.ta.k && b.runs == (tg.ta.runs != 0)) bk = &b;
+            if (!bk) {
+              L.buckets.push_back(Bucket{tg.ta.k, tg.ta.runs != 0, {}, 0});
+              bk = &L.buckets.back();
+            }
+            m.first_tile = bk->total;
+            bk->total += uint32_t(ntiles);
+            bk->ents.push_back(m);
+            if (r != kReduceNone && tg.ta.nwin > 0) {
+              MultiFinish f{};
+              f.book = p->book;
+              f.m_of_window = fuse_m_dev(p) + tg.m_off;
+              f.nwin = tg.ta.nwin;
+              f.reduce = r;
+              f.ntiles = uint32_t(ntiles);
+              L.fins.push_back(f);
+              L.maxwin = std::max(L.maxwin, f.nwin);
+            }
+          }
+        }
+        if (!multi) L.solo.push_back(i);
+      }
+    }
+    // one device image of every table
+    size_t top = 0;
+    size_t cls_off[kLdsClasses];
+    for (int c = 0; c < kLdsClasses; ++c) cls_off[c] = place(top, cls_items[c].size() * sizeof(LdsItem));
+    const size_t io_off = place(top, ios.size() * sizeof(BatchIo));
+    std::vector<std::vector<size_t>> bk_off(depth);
+    std::vector<size_t> fin_off(depth);
+    for (size_t lv = 0; lv < depth; ++lv) {
+      for (Bucket &b : levels[lv].buckets) bk_off[lv].push_back(place(top, b.ents.size() * sizeof(MultiTile)));
+      fin_off[lv] = place(top, levels[lv].fins.size() * sizeof(MultiFinish));
+    }
+    std::vector<char> image(std::max<size_t>(top, 1), 0);
+    for (int c = 0; c < kLdsClasses; ++c)
+      if (!cls_items[c].empty())
+        std::memcpy(image.data() + cls_off[c], cls_items[c].data(), cls_items[c].size() * sizeof(LdsItem));
+    if (!ios.empty()) std::memcpy(image.data() + io_off, ios.data(), ios.size() * sizeof(BatchIo));
+    for (size_t lv = 0; lv < depth; ++lv) {
+      for (size_t q = 0; q < levels[lv].buckets.size(); ++q) {
+        const Bucket &b = levels[lv].buckets[q];
+        std::memcpy(image.data() + bk_off[lv][q], b.ents.data(), b.ents.size() * sizeof(MultiTile));
+      }
+      if (!levels[lv].fins.empty())
+        std::memcpy(image.data() + fin_off[lv], levels[lv].fins.data(), levels[lv].fins.size() * sizeof(MultiFinish));
+    }
+    if (B.dev_cap < image.size()) {
+      if (B.dev) (void)hipFree(B.dev);
+      B.dev = nullptr;
+      B.dev_cap = 0;
+      e = hipMalloc(&B.dev, image.size());
+      if (e != hipSuccess) return fail(ctx, OWQS_E_NOMEM, "batch tables");
+      B.dev_cap = image.size();
+    }
+    e = hipMemcpy(B.dev, image.data(), image.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch table upload");
+    char *dev = static_cast<char *>(B.dev);
+    // ---- capture
+    e = hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
+    size_t nodes = 0;
+    const BatchIo *dios = reinterpret_cast<const BatchIo *>(dev + io_off);
+    hipError_t le = launch_batch_start(dios, (int)wide.size(), max_nin, B.cap);
+    if (le == hipSuccess) le = launch_batch_start(dios + wide.size(), (int)lds.size(), 0, B.cap);
+    nodes += (wide.empty() ? 0 : 1) + (lds.empty() ? 0 : 1);
+    if (!lds.empty()) {
+      if (le == hipSuccess) le = hipEventRecord(B.fork, B.cap);
+      if (le == hipSuccess) le = hipStreamWaitEvent(B.side, B.fork, 0);
+      for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c) {
+        if (cls_items[c].empty()) continue;
+        le = launch_lds_batch(reinterpret_cast<const LdsItem *>(dev + cls_off[c]), (int)cls_items[c].size(),
+                              cls_width[c], B.side);
+        ++nodes;
+      }
+      if (le == hipSuccess) le = hipEventRecord(B.join, B.side);
+    }
+    for (size_t lv = 0; lv < depth && le == hipSuccess; ++lv) {
+      const Level &L = levels[lv];
+      for (size_t q = 0; q < L.buckets.size() && le == hipSuccess; ++q) {
+        const Bucket &b = L.buckets[q];
+        le = launch_tile_multi(reinterpret_cast<const MultiTile *>(dev + bk_off[lv][q]), (int)b.ents.size(), b.total,
+                               b.k, b.runs, B.cap);
+        ++nodes;
+      }
+      if (le == hipSuccess && !L.fins.empty()) {
+        le = launch_finish_multi(reinterpret_cast<const MultiFinish *>(dev + fin_off[lv]), (int)L.fins.size(),
+                                 L.maxwin, B.cap);
+        ++nodes;
+      }
+      for (size_t j = 0; j < L.solo.size() && le == hipSuccess; ++j) {
+        owqs_pattern *p = pats[L.solo[j]];
+        le = launch_range(p, p->xsteps, lv, lv + 1, reduce_of(p), B.cap, nullptr);
+        nodes += 2;
+      }
+    }
+    if (le == hipSuccess) le = launch_batch_read(dios, (int)wide.size(), max_nout, B.cap);
+    if (le == hipSuccess && !lds.empty()) le = hipStreamWaitEvent(B.cap, B.join, 0);
+    nodes += wide.empty() ? 0 : 1;
+    e = hipStreamEndCapture(B.cap, &B.graph);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_batch_graph(ctx);
+      return hip_fail(ctx, e, "batch capture");
+    }
+    B.key = key;
+    B.nodes = nodes;
   }
-  // wide patterns go to the side streams, longest plan first
-  std::sort(wide.begin(), wide.end(), [&](size_t a, size_t b) {
-    return (pats[a]->steps.size() << pats[a]->plan_width) > (pats[b]->steps.size() << pats[b]->plan_width);
-  });
-  const size_t nside = std::min<size_t>(wide.size(), 4);
-  if (nside) {
-    if (!ctx->fork) {
-      e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(ctx, e, "event");
-    }
-    while (ctx->side.size() < 4) {
-      hipStream_t st;
-      hipEvent_t ev;
-      e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(ctx, e, "side stream");
-      ctx->side.push_back(st);
-      ctx->join.push_back(ev);
-    }
-    e = hipEventRecord(ctx->fork, s);
-    for (size_t k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamWaitEvent(ctx->side[k], ctx->fork, 0);
-    if (e != hipSuccess) return hip_fail(ctx, e, "fork");
-    owqs_status r = OWQS_OK;
-    for (size_t j = 0; j < wide.size() && r == OWQS_OK; ++j) {
-      owqs_pattern *p = pats[wide[j]];
-      hipStream_t st = ctx->side[j % nside];
-      r = run_impl(p, inputs ? inputs[wide[j]] : nullptr, size_t(1) << p->inputs.size(), 1, st, nullptr);
-      if (r == OWQS_OK) r = owqs_read_state(p, outputs[wide[j]], size_t(1) << p->outputs.size(), 1, st);
-    }
-    if (r != OWQS_OK) {
-      // work already queued on the side streams still writes caller outputs:
-      // join it into the caller's stream before reporting the error
-      for (size_t k = 0; k < nside; ++k)
-        if (hipEventRecord(ctx->join[k], ctx->side[k]) == hipSuccess) (void)hipStreamWaitEvent(s, ctx->join[k], 0);
-      return r;
-    }
+  e = hipGraphLaunch(B.exec, s);
+  if (e == hipSuccess) e = hipEventRecord(B.done, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "batch launch");
+  for (size_t i : lds) {
+    owqs_pattern *p = pats[i];
+    end_ranged(p);
+    p->ran = false;
+    p->ss_ran = false;
+    p->sampled_ran = false;
+    p->batch_ran = true;  // outputs went straight to the caller
   }
-  if (!items.empty()) {
-    const size_t bytes = items.size() * sizeof(LdsItem);
-    // the previous batch kernel may still read the item table
-    if (ctx->items_done) {
-      e = hipEventSynchronize(ctx->items_done);
-      if (e != hipSuccess) return hip_fail(ctx, e, "previous batch");
-    }
-    if (ctx->dev_items_cap < items.size()) {
-      if (ctx->dev_items) (void)hipFree(ctx->dev_items);
-      ctx->dev_items = nullptr;
-      ctx->dev_items_cap = 0;
-      e = hipMalloc(&ctx->dev_items, bytes);
-      if (e != hipSuccess) return fail(ctx, OWQS_E_NOMEM, "batch item table");
-      ctx->dev_items_cap = items.size();
-    }
-    // longest first, so the biggest items start early
-    std::vector<size_t> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-      return ((size_t)items[a].nsteps << std::max(items[a].nin, items[a].nout)) >
-             ((size_t)items[b].nsteps << std::max(items[b].nin, items[b].nout));
-    });
-    std::vector<LdsItem> sorted(items.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
-    e = hipMemcpyAsync(ctx->dev_items, sorted.data(), bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host table is released on return
-    if (e != hipSuccess) return hip_fail(ctx, e, "batch item upload");
-    e = launch_lds_batch(ctx->dev_items, (int)sorted.size(), width, reduce, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "LDS batch kernel");
-    if (!ctx->items_done) {
-      e = hipEventCreateWithFlags(&ctx->items_done, hipEventDisableTiming);
-      if (e != hipSuccess) return hip_fail(ctx, e, "event");
-    }
-    e = hipEventRecord(ctx->items_done, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "event");
-  }
-  if (nside) {
-    for (size_t k = 0; k < nside && e == hipSuccess; ++k) {
-      e = hipEventRecord(ctx->join[k], ctx->side[k]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->join[k], 0);
-    }
-    if (e != hipSuccess) return hip_fail(ctx, e, "join");
+  for (size_t i : wide) {
+    owqs_pattern *p = pats[i];
+    end_ranged(p);
+    p->ran = true;  // the live vector holds the result: owqs_read_state reads it again
+    p->ss_ran = false;
+    p->sampled_ran = false;
+    p->batch_ran = false;
+    p->out_in_order = false;
+    p->ran_mode = reduce_of(p);
   }
   return OWQS_OK;
 }

@@ -25,13 +25,21 @@
 struct owqs_ctx {
   int device = 0;
   std::string last_error;
-  // batch runs: side streams (default priority) for patterns too wide for LDS
-  std::vector<hipStream_t> side;
-  hipEvent_t fork = nullptr;
-  std::vector<hipEvent_t> join;
-  owqs::LdsItem *dev_items = nullptr;  // device copy of an LDS batch's item table
-  size_t dev_items_cap = 0;
-  hipEvent_t items_done = nullptr;     // recorded after the kernel that reads dev_items
+  // batched runs (owqs_run_batch): the last batch captured as one graph, with
+  // the device tables its kernels read, replayed while the call's arguments
+  // and the patterns' plans stay the same
+  struct Batch {
+    std::vector<uint64_t> key;      // what the graph was built for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *dev = nullptr;            // device tables (items, start/read rows, tile and finish entries)
+    size_t dev_cap = 0;
+    hipStream_t cap = nullptr;      // capture stream
+    hipStream_t side = nullptr;     // the LDS-resident branch of the graph (default priority)
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t done = nullptr;      // recorded after every replay
+    size_t nodes = 0;               // kernels captured
+  } batch;
   // the allocation-free entry point's device array on this device (its
   // address from hipGetSymbolAddress, resolved when the context is created)
   void *noalloc = nullptr;
@@ -245,6 +253,7 @@ struct owqs_pattern {
   int ss_graph_reduce = -1;
   bool ss_ran = false;
 
+  uint64_t plan_gen = 0;  // process-wide number of the last compile (batched runs key their graph on it)
   bool ran = false;
   bool out_in_order = false;  // the last run left the read-out (ordered, scaled) at psi[0 .. 2^nout)
   bool batch_ran = false;  // the last run was an LDS batch (outputs went straight to the caller)

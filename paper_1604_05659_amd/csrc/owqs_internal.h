@@ -134,6 +134,41 @@ struct TileArgs {
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
 };
 
+// One pattern's tile group inside a multi-pattern tile launch (batched runs):
+// the launch covers the tiles of every entry, entry e owning global tiles
+// first_tile .. first_tile + 2^(ta.n - ta.k) - 1.
+struct MultiTile {
+  float2 *psi;            // the pattern's live vector
+  const FuseOp *ops;      // the group's commands
+  double *partials;       // reduce: window w of tile t at partials[w * ntiles + t]
+  const double *sigma;    // the pattern's FP64 scale (read when reduce == kReduceRenorm)
+  double *probs;          // the pattern's probabilities (ta.half_m: 1/2 written by tile 0)
+  TileArgs ta;
+  int reduce;             // ReduceMode of this group (kReduceNone for groups of p = 1/2 windows)
+  uint32_t first_tile;
+};
+
+// One pattern's group finish inside a multi-pattern finishing launch.
+struct MultiFinish {
+  DevBook book;
+  const int *m_of_window;  // measurement index of each window of the group
+  int nwin;
+  int reduce;
+  uint32_t ntiles;         // partials per window
+  uint32_t pad;
+};
+
+// Start and read-out of one pattern of a batched run.
+struct BatchIo {
+  float2 *psi;             // live vector
+  const float2 *in;        // 2^nin input amplitudes, or null (empty product state)
+  float2 *out;             // 2^nout output amplitudes
+  DevBook book;
+  double final_factor;
+  int nin, nout, reduce;
+  int where[kWhereMax];    // slot of output k
+};
+
 // One pattern of an LDS-resident batch.
 struct LdsItem {
   const DevStep *steps;
@@ -143,6 +178,7 @@ struct LdsItem {
   int *err;             // {first failing M (or item), kind}: this item's error slot
   double final_factor;
   int nsteps, nin, nout, basis;  // basis >= 0: input is |basis>
+  int reduce;                    // ReduceMode of this item (k_lds_batch)
   int where[kWhereMax];
 };
 
@@ -172,7 +208,18 @@ hipError_t launch_read(const float2 *psi, float2 *out, int nout, const int *wher
 // workgroup (live width <= kLdsMaxWidth).  `width` is the largest live width
 // of any item (sets the dynamic LDS size).  Errors (zero probability, failed
 // determinism check) go to each item's err slot: err[0] = first failing M.
-hipError_t launch_lds_batch(const LdsItem *items, int count, int width, int reduce, hipStream_t s);
+hipError_t launch_lds_batch(const LdsItem *items, int count, int width, hipStream_t s);
+// Raise k_lds_batch's dynamic LDS limit to 2^kLdsMaxWidth amplitudes (once,
+// outside any graph capture).
+hipError_t lds_batch_prepare();
+// Batched runs: start every wide pattern (sigma, error word, input into its
+// live vector) and read every output (gather and scale), one launch each.
+hipError_t launch_batch_start(const BatchIo *ios, int count, int max_nin, hipStream_t s);
+hipError_t launch_batch_read(const BatchIo *ios, int count, int max_nout, hipStream_t s);
+// Tile groups of many patterns in one launch (entries sorted by first_tile,
+// all with tile bits k and the same `runs`), and their group finishes.
+hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, hipStream_t s);
+hipError_t launch_finish_multi(const MultiFinish *fins, int nfin, int maxwin, hipStream_t s);
 // Items share one command table and differ only by input: item k runs on
 // basis state |first + k> (basis_mode = 1) or on in + k * 2^nin, and writes
 // out + k * 2^nout.  Errors go to proto.err with err[0] = first failing item.

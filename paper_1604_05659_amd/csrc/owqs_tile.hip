@@ -426,6 +426,155 @@ __device__ __forceinline__ void window_triple_any(char *lds, uint32_t tid, const
   }
 }
 
+// The global bit of each tile bit above the thread index (tile bits
+// log2(threads) .. kTB-1, lowest first).
+template <int kTB>
+__device__ __forceinline__ void tile_high_bits(uint64_t tmask, uint64_t *hp) {
+  constexpr int kLogT = log2_threads(tile_threads(kTB));
+  uint64_t m = tmask;
+  for (int i = 0; i < kLogT; ++i) m &= m - 1;
+#pragma unroll
+  for (int j = 0; j < kTB - kLogT; ++j) {
+    hp[j] = m & (~m + 1);
+    m &= m - 1;
+  }
+}
+
+// One tile of a group (tile t of the 2^(n-k)): load it into LDS, apply the
+// group's commands, store it back.  With `reduce`, every window adds its
+// FP32 norm per wave into wacc (summed in FP64 across lanes).  g_tid and hp
+// hold the thread's part of the global index and the global bits of the tile
+// bits above the thread index (see k_tile).
+template <int kTB, bool kRuns>
+__device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArgs &ta, const FuseOp *__restrict__ ops,
+                                         bool reduce, double sg, uint64_t t, uint64_t g_tid, const uint64_t *hp,
+                                         float2 *tile, double (*wacc)[tile_threads(kTB) / 64]) {
+  constexpr int kT = tile_threads(kTB);
+  constexpr int kLogT = log2_threads(kT);
+  constexpr int kPer = (1 << kTB) / kT;
+  constexpr int kHi = kTB - kLogT;  // tile bits above the thread index
+  char *const lds = reinterpret_cast<char *>(tile);
+  const uint32_t tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const uint64_t ob = pdep64(t, ta.omask);
+  const uint64_t gb = ob | g_tid;
+  {
+    float2 v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      uint64_t g = gb;
+#pragma unroll
+      for (int j = 0; j < kHi; ++j)
+        if ((r >> j) & 1) g |= hp[j];
+      v[r] = psi[g];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) tile[tid + r * kT] = v[r];
+  }
+  __syncthreads();
+  for (int o = 0; o < ta.nops; ++o) {
+    const FuseOp op = load_op(ops, o);
+    if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
+      const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
+      if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
+          n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
+        const WinP A = prep_window(op, ob, sg, ta), B = prep_window(n1, ob, sg, ta), C = prep_window(n2, ob, sg, ta);
+        float acc[3] = {0.f, 0.f, 0.f};
+        if (reduce) {
+          window_triple_any<true, kTB, kT>(lds, tid, A, B, C, acc);
+          const double da = wave_sum_to_last(acc[0]), db = wave_sum_to_last(acc[1]), dc = wave_sum_to_last(acc[2]);
+          if (lane == 63) {
+            wacc[A.widx][wave] += da;
+            wacc[B.widx][wave] += db;
+            wacc[C.widx][wave] += dc;
+          }
+        } else {
+          window_triple_any<false, kTB, kT>(lds, tid, A, B, C, acc);
+        }
+        __syncthreads();
+        o += 2;
+        continue;
+      }
+    }
+    if (kRuns && op.kind == DK_J && o + 1 < ta.nops) {
+      FuseOp nx = load_op(ops, o + 1);
+      // an E or Z between two windows joins them (applied in registers)
+      int skip = 1;
+      bool has_mid = false;
+      uint32_t mid = 0;
+      if ((nx.kind == DK_E || nx.kind == DK_Z) && o + 2 < ta.nops) {
+        const FuseOp n2 = load_op(ops, o + 2);
+        if (n2.kind == DK_J && n2.lb != op.lb) {
+          has_mid = (ob & nx.omask_b) == nx.omask_b;
+          mid = nx.lmask_b;
+          nx = n2;
+          skip = 2;
+        }
+      }
+      if (nx.kind == DK_J && nx.lb != op.lb) {
+        const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
+        float acc_a = 0.f, acc_b = 0.f;
+        if (reduce) {
+          window_pair_any<true, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
+          const double da = wave_sum_to_last(acc_a), db = wave_sum_to_last(acc_b);
+          if (lane == 63) {
+            wacc[A.widx][wave] += da;
+            wacc[B.widx][wave] += db;
+          }
+        } else {
+          window_pair_any<false, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
+        }
+        __syncthreads();
+        o += skip;
+        continue;
+      }
+    }
+    if (op.kind == DK_E || op.kind == DK_Z) {
+      if ((ob & op.omask_b) == op.omask_b) diag_flip<kTB, kT>(lds, tid, op.lmask_b);
+    } else if (op.kind == DK_X) {
+      pair_swap<kTB, kT>(lds, tid, op.lb);
+    } else {  // window: fold the tile-constant signs and the corrections
+      const uint32_t fl = op_flags(op, ta);
+      const float f = float((fl & 16u) ? sg * op.f : double(op.f));
+      const bool sw = fl & 1u;
+      float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
+      if (fl & 2u) { if (sw) fb = -fb; else fa = -fa; }
+      if (fl & 4u) { if (sw) fa = -fa; else fb = -fb; }
+      float2 cw = make_float2(op.coef.x, op.coef.y);
+      if (ta.coefs) cw = set_coef(ta, op.m_index);
+      const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
+      const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
+      // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
+      const bool s1neg = !(fl & 8u);
+      const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
+      const bool masked = (op.lmask_b | op.lmask_o1) != 0;
+      if (reduce) {
+        const float acc =
+            window_any<true, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
+        const double d = wave_sum_to_last(acc);  // FP64 from the wave sum on
+        if (lane == 63) wacc[op.widx][wave] += d;
+      } else {
+        window_any<false, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
+      }
+    }
+    __syncthreads();
+  }
+  {
+    float2 v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) v[r] = tile[tid + r * kT];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      uint64_t g = gb;
+#pragma unroll
+      for (int j = 0; j < kHi; ++j)
+        if ((r >> j) & 1) g |= hp[j];
+      psi[g] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
 // kTB = tile bits (ta.k).  Global memory <-> LDS: each thread moves
 // kPer = 2^kTB / kT amplitudes per tile, all loads issued before the first
 // LDS store (and all LDS reads before the first global store), so the memory
@@ -440,157 +589,97 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
                                                             const FuseOp *__restrict__ ops, MeasureArgs ma,
                                                             double *__restrict__ partials) {
   constexpr int kT = tile_threads(kTB);
-  constexpr int kLogT = log2_threads(kT);
-  constexpr int kPer = (1 << kTB) / kT;
-  constexpr int kHi = kTB - kLogT;  // tile bits above the thread index
+  constexpr int kHi = kTB - log2_threads(kT);  // tile bits above the thread index
   extern __shared__ float2 tile[];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
-  char *const lds = reinterpret_cast<char *>(tile);
   const uint32_t tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
   const bool reduce = ma.reduce != kReduceNone;
   if (reduce)
     for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
   const double sg = (ma.reduce == kReduceRenorm) ? *ma.book.sigma : 1.0;
   const uint64_t g_tid = pdep64(tid, ta.tmask);
-  uint64_t hp[kHi];  // global bit of tile bits 8 .. kTB-1
-  {
-    uint64_t m = ta.tmask;
-    for (int i = 0; i < kLogT; ++i) m &= m - 1;
-#pragma unroll
-    for (int j = 0; j < kHi; ++j) {
-      hp[j] = m & (~m + 1);
-      m &= m - 1;
-    }
-  }
+  uint64_t hp[kHi];
+  tile_high_bits<kTB>(ta.tmask, hp);
   psi += size_t(blockIdx.y) * ta.set_stride;
   if (ta.half_m && blockIdx.x == 0 && blockIdx.y == 0)  // windows with p = 1/2 exactly
     for (int i = tid; i < ta.nwin; i += kT) ma.book.probs[ta.half_m[i]] = 0.5;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t ob = pdep64(t, ta.omask);
-    const uint64_t gb = ob | g_tid;
-    {
-      float2 v[kPer];
-#pragma unroll
-      for (int r = 0; r < kPer; ++r) {
-        uint64_t g = gb;
-#pragma unroll
-        for (int j = 0; j < kHi; ++j)
-          if ((r >> j) & 1) g |= hp[j];
-        v[r] = psi[g];
-      }
-#pragma unroll
-      for (int r = 0; r < kPer; ++r) tile[tid + r * kT] = v[r];
-    }
-    __syncthreads();
-    for (int o = 0; o < ta.nops; ++o) {
-      const FuseOp op = load_op(ops, o);
-      if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
-        const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
-        if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
-            n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
-          const WinP A = prep_window(op, ob, sg, ta), B = prep_window(n1, ob, sg, ta), C = prep_window(n2, ob, sg, ta);
-          float acc[3] = {0.f, 0.f, 0.f};
-          if (reduce) {
-            window_triple_any<true, kTB, kT>(lds, tid, A, B, C, acc);
-            const double da = wave_sum_to_last(acc[0]), db = wave_sum_to_last(acc[1]), dc = wave_sum_to_last(acc[2]);
-            if (lane == 63) {
-              wacc[A.widx][wave] += da;
-              wacc[B.widx][wave] += db;
-              wacc[C.widx][wave] += dc;
-            }
-          } else {
-            window_triple_any<false, kTB, kT>(lds, tid, A, B, C, acc);
-          }
-          __syncthreads();
-          o += 2;
-          continue;
-        }
-      }
-      if (kRuns && op.kind == DK_J && o + 1 < ta.nops) {
-        FuseOp nx = load_op(ops, o + 1);
-        // an E or Z between two windows joins them (applied in registers)
-        int skip = 1;
-        bool has_mid = false;
-        uint32_t mid = 0;
-        if ((nx.kind == DK_E || nx.kind == DK_Z) && o + 2 < ta.nops) {
-          const FuseOp n2 = load_op(ops, o + 2);
-          if (n2.kind == DK_J && n2.lb != op.lb) {
-            has_mid = (ob & nx.omask_b) == nx.omask_b;
-            mid = nx.lmask_b;
-            nx = n2;
-            skip = 2;
-          }
-        }
-        if (nx.kind == DK_J && nx.lb != op.lb) {
-          const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
-          float acc_a = 0.f, acc_b = 0.f;
-          if (reduce) {
-            window_pair_any<true, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
-            const double da = wave_sum_to_last(acc_a), db = wave_sum_to_last(acc_b);
-            if (lane == 63) {
-              wacc[A.widx][wave] += da;
-              wacc[B.widx][wave] += db;
-            }
-          } else {
-            window_pair_any<false, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
-          }
-          __syncthreads();
-          o += skip;
-          continue;
-        }
-      }
-      if (op.kind == DK_E || op.kind == DK_Z) {
-        if ((ob & op.omask_b) == op.omask_b) diag_flip<kTB, kT>(lds, tid, op.lmask_b);
-      } else if (op.kind == DK_X) {
-        pair_swap<kTB, kT>(lds, tid, op.lb);
-      } else {  // window: fold the tile-constant signs and the corrections
-        const uint32_t fl = op_flags(op, ta);
-        const float f = float((fl & 16u) ? sg * op.f : double(op.f));
-        const bool sw = fl & 1u;
-        float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
-        if (fl & 2u) { if (sw) fb = -fb; else fa = -fa; }
-        if (fl & 4u) { if (sw) fa = -fa; else fb = -fb; }
-        float2 cw = make_float2(op.coef.x, op.coef.y);
-        if (ta.coefs) cw = set_coef(ta, op.m_index);
-        const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
-        const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
-        // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
-        const bool s1neg = !(fl & 8u);
-        const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
-        const bool masked = (op.lmask_b | op.lmask_o1) != 0;
-        if (reduce) {
-          const float acc =
-              window_any<true, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
-          const double d = wave_sum_to_last(acc);  // FP64 from the wave sum on
-          if (lane == 63) wacc[op.widx][wave] += d;
-        } else {
-          window_any<false, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
-        }
-      }
-      __syncthreads();
-    }
-    {
-      float2 v[kPer];
-#pragma unroll
-      for (int r = 0; r < kPer; ++r) v[r] = tile[tid + r * kT];
-#pragma unroll
-      for (int r = 0; r < kPer; ++r) {
-        uint64_t g = gb;
-#pragma unroll
-        for (int j = 0; j < kHi; ++j)
-          if ((r >> j) & 1) g |= hp[j];
-        psi[g] = v[r];
-      }
-    }
-    __syncthreads();
-  }
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+    tile_one<kTB, kRuns>(psi, ta, ops, reduce, sg, t, g_tid, hp, tile, wacc);
   if (reduce) {
     for (int w = tid; w < ta.nwin; w += kT) {
       double s = 0.0;
       for (int k = 0; k < kT / 64; ++k) s += wacc[w][k];
       partials[size_t(w) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// A row of a read-only device table, loaded whole through scalar loads (the
+// index is uniform over the workgroup; the table is never written by a
+// kernel, so the constant address space may be used).
+template <typename T>
+__device__ __forceinline__ T load_row(const T *tab, uint32_t i) {
+  static_assert(sizeof(T) % 4 == 0, "table rows are whole dwords");
+  constexpr int kW = sizeof(T) / 4;
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(tab)) +
+               size_t(kW) * __builtin_amdgcn_readfirstlane(i);
+  uint32_t w[kW];
+#pragma unroll
+  for (int k = 0; k < kW; ++k) w[k] = src[k];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(v));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t first_tile_of(const MultiTile *ents, int e) {
+  typedef const __attribute__((address_space(4))) uint32_t cword;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(ents + __builtin_amdgcn_readfirstlane(e)) +
+                      offsetof(MultiTile, first_tile);
+  return *reinterpret_cast<cword *>(a);
+}
+
+// Tile groups of many patterns in one launch (batched runs): the grid walks
+// the concatenated tiles of all entries; a workgroup finds the entry that
+// owns its tile (binary search on first_tile), runs that tile as k_tile
+// does, and stores its windows' sums per tile (partials[w * ntiles + t]), so
+// that k_finish_multi sums them in tile order.
+template <int kTB, bool kRuns>
+__global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTile *__restrict__ ents, int nent,
+                                                                  uint32_t total) {
+  constexpr int kT = tile_threads(kTB);
+  constexpr int kHi = kTB - log2_threads(kT);
+  extern __shared__ float2 tile[];
+  __shared__ double wacc[kMaxGroupWindows][kT / 64];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t gt = blockIdx.x; gt < total; gt += gridDim.x) {
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (first_tile_of(ents, mid) <= gt) lo = mid;
+      else hi = mid - 1;
+    }
+    const MultiTile e = load_row(ents, uint32_t(lo));
+    const uint64_t t = gt - e.first_tile;
+    const bool reduce = e.reduce != kReduceNone;
+    if (reduce)
+      for (int i = tid; i < e.ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
+    const double sg = e.reduce == kReduceRenorm ? *e.sigma : 1.0;
+    const uint64_t g_tid = pdep64(tid, e.ta.tmask);
+    uint64_t hp[kHi];
+    tile_high_bits<kTB>(e.ta.tmask, hp);
+    if (e.ta.half_m && t == 0)  // windows with p = 1/2 exactly
+      for (int i = tid; i < e.ta.nwin; i += kT) e.probs[e.ta.half_m[i]] = 0.5;
+    tile_one<kTB, kRuns>(e.psi, e.ta, e.ops, reduce, sg, t, g_tid, hp, tile, wacc);
+    if (reduce) {
+      const uint64_t ntiles = uint64_t(1) << (e.ta.n - kTB);
+      for (int w = tid; w < e.ta.nwin; w += kT) {
+        double sum = 0.0;
+        for (int k = 0; k < kT / 64; ++k) sum += wacc[w][k];
+        e.partials[size_t(w) * ntiles + t] = sum;
+      }
+      __syncthreads();  // wacc is cleared for the next tile
     }
   }
 }
@@ -791,6 +880,28 @@ __global__ __launch_bounds__(kTT) void k_finish_group(DevBook book, const int *_
   if (reduce == kReduceRenorm && g == nwin - 1) *book.sigma = n > 1e-300 ? 1.0 / sqrt(n) : 0.0;
 }
 
+// The group finish of many patterns at once: block (g, e) does for window
+// g of entry e what k_finish_group does, with the entry's per-tile partials.
+__global__ __launch_bounds__(kTT) void k_finish_multi(const MultiFinish *__restrict__ fins) {
+  const MultiFinish f = load_row(fins, blockIdx.y);
+  const int g = blockIdx.x;
+  if (g >= f.nwin) return;  // uniform over the block
+  const double n = sum_partials(f.book.partials + size_t(g) * f.ntiles, f.ntiles);
+  const double prev = g > 0 ? sum_partials(f.book.partials + size_t(g - 1) * f.ntiles, f.ntiles) : 1.0;
+  if (threadIdx.x != 0) return;
+  const double p = prev > 0.0 ? 0.5 * n / prev : 0.0;
+  const int m = f.m_of_window[g];
+  f.book.probs[m] = p;
+  if (f.reduce == kReduceRenorm && p < 1e-10) {
+    atomicMin(&f.book.err[0], m);
+    f.book.err[1] = kErrZeroProb;
+  } else if (f.reduce == kReduceCheck && fabs(p - 0.5) > 1e-4) {
+    atomicMin(&f.book.err[0], m);
+    f.book.err[1] = kErrNotDet;
+  }
+  if (f.reduce == kReduceRenorm && g == f.nwin - 1) *f.book.sigma = n > 1e-300 ? 1.0 / sqrt(n) : 0.0;
+}
+
 }  // namespace
 
 unsigned tile_grid(const TileArgs &ta) {
@@ -808,6 +919,19 @@ hipError_t tile_prepare() {
                        reinterpret_cast<const void *>(k_tile<12, true>), reinterpret_cast<const void *>(k_tile<13, true>)};
   const void *rev[] = {reinterpret_cast<const void *>(k_tile_rev<10>), reinterpret_cast<const void *>(k_tile_rev<11>),
                        reinterpret_cast<const void *>(k_tile_rev<12>), reinterpret_cast<const void *>(k_tile_rev<13>)};
+  const void *mul[] = {reinterpret_cast<const void *>(k_tile_multi<10, false>),
+                       reinterpret_cast<const void *>(k_tile_multi<11, false>),
+                       reinterpret_cast<const void *>(k_tile_multi<12, false>),
+                       reinterpret_cast<const void *>(k_tile_multi<13, false>)};
+  const void *mur[] = {reinterpret_cast<const void *>(k_tile_multi<10, true>),
+                       reinterpret_cast<const void *>(k_tile_multi<11, true>),
+                       reinterpret_cast<const void *>(k_tile_multi<12, true>),
+                       reinterpret_cast<const void *>(k_tile_multi<13, true>)};
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    e = hipFuncSetAttribute(mul[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(mur[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
+  }
   for (int i = 0; i < 4 && e == hipSuccess; ++i) {
     e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
     if (e == hipSuccess)
@@ -897,6 +1021,38 @@ hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta0, const 
     case 13: hipLaunchKernelGGL(k_tile_rev<13>, grid, dim3(tile_threads(13)), bytes, s, psi, lam, ta, ops, partials, q_first, nblk); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, hipStream_t s) {
+  if (nent <= 0 || total == 0) return hipGetLastError();
+  const size_t bytes = sizeof(float2) << k;
+  const dim3 grid(total < 65535u ? total : 65535u);
+  switch (k) {
+    case 10:
+      if (runs) hipLaunchKernelGGL((k_tile_multi<10, true>), grid, dim3(tile_threads(10)), bytes, s, ents, nent, total);
+      else hipLaunchKernelGGL((k_tile_multi<10, false>), grid, dim3(tile_threads(10)), bytes, s, ents, nent, total);
+      break;
+    case 11:
+      if (runs) hipLaunchKernelGGL((k_tile_multi<11, true>), grid, dim3(tile_threads(11)), bytes, s, ents, nent, total);
+      else hipLaunchKernelGGL((k_tile_multi<11, false>), grid, dim3(tile_threads(11)), bytes, s, ents, nent, total);
+      break;
+    case 12:
+      if (runs) hipLaunchKernelGGL((k_tile_multi<12, true>), grid, dim3(tile_threads(12)), bytes, s, ents, nent, total);
+      else hipLaunchKernelGGL((k_tile_multi<12, false>), grid, dim3(tile_threads(12)), bytes, s, ents, nent, total);
+      break;
+    case 13:
+      if (runs) hipLaunchKernelGGL((k_tile_multi<13, true>), grid, dim3(tile_threads(13)), bytes, s, ents, nent, total);
+      else hipLaunchKernelGGL((k_tile_multi<13, false>), grid, dim3(tile_threads(13)), bytes, s, ents, nent, total);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_multi(const MultiFinish *fins, int nfin, int maxwin, hipStream_t s) {
+  if (nfin <= 0 || maxwin <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_finish_multi, dim3(unsigned(maxwin), unsigned(nfin)), dim3(kTT), 0, s, fins);
   return hipGetLastError();
 }
 
