@@ -284,14 +284,21 @@ owqs_status owqs_run_noalloc(owqs_pattern *pat, const void *input_c64, size_t n_
                              void *output_c64, size_t n_out_amps, double *probs, int32_t *err,
                              void *stream);
 
-/* Run `npat` independent patterns of one context as one batch.  inputs[i]
- * (2^nin_i complex64; may be NULL for a pattern without inputs) and
- * outputs[i] (2^nout_i complex64) are device pointers.  Patterns whose plan
- * width is <= 14 run in one launch, one workgroup per pattern with its
- * vector in LDS (they must share one mode; others of a different mode are
- * run like the wide ones); wider patterns run their plans (as graphs) on up
- * to four side streams joined back into `stream`.  Each pattern keeps its own
- * probabilities and error state (owqs_read_probs, owqs_check). */
+/* Run `npat` independent patterns of one context as one batch (the paper runs
+ * patterns one at a time, Sec. 5; batching is this library's addition).
+ * inputs[i] (2^nin_i complex64; may be NULL for a pattern without inputs)
+ * and outputs[i] (2^nout_i complex64) are device pointers.  The whole batch
+ * is one graph launched on `stream`: patterns whose plan width is <= 14 run
+ * whole in one workgroup's LDS (one launch per width class); wider plans run
+ * level by level, the s-th tile pass of every pattern in one multi-pattern
+ * launch.  The graph is kept by the context and replayed while the same
+ * patterns (unchanged since their last compile), inputs and outputs are
+ * passed again; any change rebuilds it, which waits for the previous batch
+ * of this context to finish.  Each pattern keeps its own probabilities and
+ * error state (owqs_read_probs, owqs_check); the outputs of patterns wider
+ * than 14 can also be read again with owqs_read_state.  Every mode may be
+ * mixed in one batch; sub-state patterns and drawn outcomes are refused
+ * (OWQS_E_STATE). */
 owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat,
                            const void *const *inputs, void *const *outputs, void *stream);
 
