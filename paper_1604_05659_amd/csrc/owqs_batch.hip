@@ -11,6 +11,9 @@
 // Used for batches of many small patterns (each item its own command table)
 // and for the recognition problem (one table, every computational-basis
 // input: column k of the unitary is the output for |k>).
+#include <algorithm>
+
+#include "owqs_gather.h"
 #include "owqs_internal.h"
 
 namespace owqs {
@@ -230,17 +233,14 @@ __global__ __launch_bounds__(kIoThreads) void k_batch_start(const BatchIo *__res
 
 // Read-out of pattern blockIdx.y: output x (bit k = outputs[k]) is the live
 // amplitude at the slots where[k], times sigma and the host factor.
-__global__ __launch_bounds__(kIoThreads) void k_batch_read(const BatchIo *__restrict__ ios) {
+__global__ __launch_bounds__(kGatherThreads) void k_batch_read(const BatchIo *__restrict__ ios) {
+  __shared__ uint64_t tab[1 << kGatherLo];
   const BatchIo b = load_io(ios, blockIdx.y);
   const double sg = b.reduce == kReduceRenorm ? *b.book.sigma : 1.0;
-  const float sc = float(sg * b.final_factor);
-  const size_t n = size_t(1) << b.nout;
-  for (size_t x = size_t(blockIdx.x) * kIoThreads + threadIdx.x; x < n; x += size_t(gridDim.x) * kIoThreads) {
-    size_t src = 0;
-    for (int k = 0; k < b.nout; ++k) src |= ((x >> k) & 1) << b.where[k];
-    const float2 v = b.psi[src];
-    b.out[x] = make_float2(sc * v.x, sc * v.y);
-  }
+  // the slots straight from the read-only table (scalar loads)
+  typedef const __attribute__((address_space(4))) int cint;
+  cint *where = reinterpret_cast<cint *>(reinterpret_cast<uintptr_t>(ios + blockIdx.y) + offsetof(BatchIo, where));
+  gather_chunks(b.psi, b.out, b.nout, where, float(sg * b.final_factor), tab, blockIdx.x, gridDim.x);
 }
 
 template <int kT>
@@ -317,7 +317,10 @@ hipError_t launch_batch_start(const BatchIo *ios, int count, int max_nin, hipStr
 
 hipError_t launch_batch_read(const BatchIo *ios, int count, int max_nout, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_read, dim3(io_grid(max_nout), unsigned(count)), dim3(kIoThreads), 0, s, ios);
+  // one chunk of 2^kGatherLo outputs per workgroup and trip, for the widest
+  const int lo = max_nout < kGatherLo ? max_nout : kGatherLo;
+  const unsigned g = unsigned(std::min<uint64_t>(uint64_t(1) << (max_nout - lo), 64));
+  hipLaunchKernelGGL(k_batch_read, dim3(g, unsigned(count)), dim3(kGatherThreads), 0, s, ios);
   return hipGetLastError();
 }
 

@@ -1184,16 +1184,18 @@ owqs_status owqs_ctx_create(int device, owqs_ctx **out) {
 void owqs_ctx_destroy(owqs_ctx *ctx) {
   if (!ctx) return;
   owqs_ctx::Batch &b = ctx->batch;
-  if (ctx->device >= 0 && (b.exec || b.graph || b.dev || b.cap || b.side || b.done)) {
+  if (ctx->device >= 0 && (b.exec || b.graph || b.dev || b.cap || b.done)) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
     if (b.dev) (void)hipFree(b.dev);
     if (b.cap) (void)hipStreamDestroy(b.cap);
-    if (b.side) (void)hipStreamDestroy(b.side);
+    for (int c = 0; c < 5; ++c) {
+      if (b.side[c]) (void)hipStreamDestroy(b.side[c]);
+      if (b.join[c]) (void)hipEventDestroy(b.join[c]);
+    }
     if (b.fork) (void)hipEventDestroy(b.fork);
-    if (b.join) (void)hipEventDestroy(b.join);
     if (b.done) (void)hipEventDestroy(b.done);
   }
   delete ctx;
@@ -1479,6 +1481,7 @@ namespace {
 // threads for the widest item of the class.
 int lds_class(int width) { return width <= 8 ? 0 : width <= 11 ? 1 : width - 10; }  // 0..4
 constexpr int kLdsClasses = 5;
+static_assert(sizeof(owqs_ctx::Batch::side) / sizeof(hipStream_t) == kLdsClasses, "one branch per class");
 
 struct Region {
   size_t off = 0;
@@ -1505,9 +1508,11 @@ hipError_t batch_streams(owqs_ctx *ctx) {
   owqs_ctx::Batch &b = ctx->batch;
   hipError_t e = hipSuccess;
   if (!b.cap) e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking);
-  if (e == hipSuccess && !b.side) e = hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking);
+  for (int c = 0; c < kLdsClasses && e == hipSuccess; ++c) {
+    if (!b.side[c]) e = hipStreamCreateWithFlags(&b.side[c], hipStreamNonBlocking);
+    if (e == hipSuccess && !b.join[c]) e = hipEventCreateWithFlags(&b.join[c], hipEventDisableTiming);
+  }
   if (e == hipSuccess && !b.fork) e = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming);
-  if (e == hipSuccess && !b.join) e = hipEventCreateWithFlags(&b.join, hipEventDisableTiming);
   if (e == hipSuccess && !b.done) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
   return e;
 }
@@ -1719,16 +1724,15 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     hipError_t le = launch_batch_start(dios, (int)wide.size(), max_nin, B.cap);
     if (le == hipSuccess) le = launch_batch_start(dios + wide.size(), (int)lds.size(), 0, B.cap);
     nodes += (wide.empty() ? 0 : 1) + (lds.empty() ? 0 : 1);
-    if (!lds.empty()) {
-      if (le == hipSuccess) le = hipEventRecord(B.fork, B.cap);
-      if (le == hipSuccess) le = hipStreamWaitEvent(B.side, B.fork, 0);
-      for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c) {
-        if (cls_items[c].empty()) continue;
+    if (!lds.empty() && le == hipSuccess) le = hipEventRecord(B.fork, B.cap);
+    for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c) {  // each class a branch of its own
+      if (cls_items[c].empty()) continue;
+      le = hipStreamWaitEvent(B.side[c], B.fork, 0);
+      if (le == hipSuccess)
         le = launch_lds_batch(reinterpret_cast<const LdsItem *>(dev + cls_off[c]), (int)cls_items[c].size(),
-                              cls_width[c], B.side);
-        ++nodes;
-      }
-      if (le == hipSuccess) le = hipEventRecord(B.join, B.side);
+                              cls_width[c], B.side[c]);
+      if (le == hipSuccess) le = hipEventRecord(B.join[c], B.side[c]);
+      ++nodes;
     }
     for (size_t lv = 0; lv < depth && le == hipSuccess; ++lv) {
       const Level &L = levels[lv];
@@ -1750,7 +1754,8 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
       }
     }
     if (le == hipSuccess) le = launch_batch_read(dios, (int)wide.size(), max_nout, B.cap);
-    if (le == hipSuccess && !lds.empty()) le = hipStreamWaitEvent(B.cap, B.join, 0);
+    for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c)
+      if (!cls_items[c].empty()) le = hipStreamWaitEvent(B.cap, B.join[c], 0);
     nodes += wide.empty() ? 0 : 1;
     e = hipStreamEndCapture(B.cap, &B.graph);
     if (le != hipSuccess) e = le;

@@ -35,8 +35,9 @@ struct owqs_ctx {
     void *dev = nullptr;            // device tables (items, start/read rows, tile and finish entries)
     size_t dev_cap = 0;
     hipStream_t cap = nullptr;      // capture stream
-    hipStream_t side = nullptr;     // the LDS-resident branch of the graph (default priority)
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t side[5] = {};       // one branch of the graph per LDS width class (default priority)
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[5] = {};
     hipEvent_t done = nullptr;      // recorded after every replay
     size_t nodes = 0;               // kernels captured
   } batch;

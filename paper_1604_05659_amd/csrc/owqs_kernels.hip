@@ -24,6 +24,7 @@
 //            FP64 factor.
 #include <climits>
 
+#include "owqs_gather.h"
 #include "owqs_internal.h"
 
 namespace owqs {
@@ -78,12 +79,6 @@ __device__ __forceinline__ float4 pack(float2 a, float2 b) { return make_float4(
 __device__ __forceinline__ float2 axpc(float2 a, float2 c, float2 b, float f) {
   const float re = a.x + (c.x * b.x - c.y * b.y);
   const float im = a.y + (c.x * b.y + c.y * b.x);
-  return make_float2(f * re, f * im);
-}
-// f * (a - c * b)
-__device__ __forceinline__ float2 axmc(float2 a, float2 c, float2 b, float f) {
-  const float re = a.x - (c.x * b.x - c.y * b.y);
-  const float im = a.y - (c.x * b.y + c.y * b.x);
   return make_float2(f * re, f * im);
 }
 __device__ __forceinline__ double nrm2(float2 v) {
@@ -526,18 +521,11 @@ struct Where {
   int bit[kWhereMax];
 };
 
-__global__ __launch_bounds__(kBlock) void k_read(const float2 *__restrict__ psi, float2 *__restrict__ out,
-                                                  uint64_t count, int nout, Where w, double host_factor,
-                                                  const double *sigma) {
+__global__ __launch_bounds__(kGatherThreads) void k_read(const float2 *__restrict__ psi, float2 *__restrict__ out,
+                                                          int nout, Where w, double host_factor, const double *sigma) {
+  __shared__ uint64_t tab[1 << kGatherLo];
   const double sg = sigma ? *sigma : 1.0;
-  const float s = float(sg * host_factor);
-  for (uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x; x < count;
-       x += uint64_t(gridDim.x) * kBlock) {
-    uint64_t src = 0;
-    for (int k = 0; k < nout; ++k) src |= ((x >> k) & 1) << w.bit[k];
-    const float2 v = psi[src];
-    out[x] = make_float2(s * v.x, s * v.y);
-  }
+  gather_chunks(psi, out, nout, w.bit, float(sg * host_factor), tab, blockIdx.x, gridDim.x);
 }
 
 }  // namespace
@@ -667,11 +655,11 @@ hipError_t launch_read(const float2 *psi, float2 *out, int nout, const int *wher
                        const double *sigma, hipStream_t s) {
   Where w{};
   for (int k = 0; k < nout; ++k) w.bit[k] = where[k];
-  const uint64_t count = uint64_t(1) << nout;
-  uint64_t g = (count + kBlock - 1) / kBlock;
+  // one chunk of 2^kGatherLo outputs per workgroup and trip
+  const int lo = nout < kGatherLo ? nout : kGatherLo;
+  uint64_t g = uint64_t(1) << (nout - lo);
   if (g > kGridCap) g = kGridCap;
-  hipLaunchKernelGGL(k_read, dim3(unsigned(g)), dim3(kBlock), 0, s, psi, out, count, nout, w, host_factor,
-                     sigma);
+  hipLaunchKernelGGL(k_read, dim3(unsigned(g)), dim3(kGatherThreads), 0, s, psi, out, nout, w, host_factor, sigma);
   return hipGetLastError();
 }
 
