@@ -131,14 +131,56 @@ def cpu_baseline(wl_gates, psi_in, seconds_hint):
     oc.run(pat, outc, x, oc.MODE_OWQS)
     dt = time.perf_counter() - t0
     nt = pat.nontrivial_count(outc)
-    return {
+    # one thread, on the first two gates
+    g1 = wl_gates[:2]
+    pat1 = W.circuit_to_pattern(WORKLOAD["n_logical"], g1, prepare_zero=False)
+    out1 = W.outcome_bits(pat1.n_meas(), W.rng(2, W.P_OUTCOME, 0))
+    oc.set_threads(1)
+    t0 = time.perf_counter()
+    oc.run(pat1, out1, x, oc.MODE_OWQS)
+    dt1 = time.perf_counter() - t0
+    oc.set_threads(threads)
+    nt1 = pat1.nontrivial_count(out1)
+    res = {
         "value": round(nt / dt, 3),
         "unit": "commands/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"first {n_gates} gates ({len(pat.cmds)} commands, {nt} non-trivial) of the same circuit "
                    f"at live width 24<->25, complex128, {dt:.1f} s wall"),
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "one_thread": {"value": round(nt1 / dt1, 3), "unit": "commands/s", "cores": 1,
+                       "sample": f"first 2 gates ({len(pat1.cmds)} commands, {nt1} non-trivial), {dt1:.1f} s wall"},
     }
+    # the whole pattern, timed when the oracle wrote the stored expected values
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "plain_large_full.npz")
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        res["whole_pattern"] = {"seconds": round(float(g["seconds"]), 1), "threads": int(g["threads"]),
+                                "cpu_model": str(g["cpu"]), "commands": int(g["commands"]),
+                                "value": round(nt_all_of(wl_gates) / float(g["seconds"]), 3),
+                                "unit": "commands/s",
+                                "where": "the build container (not the GPU host), tests/golden/make_goldens.py"}
+    return res
+
+
+def nt_all_of(wl_gates):
+    """Non-trivial commands of the whole large pattern with its seeded outcomes."""
+    import owqs_workloads as W
+    pat = W.circuit_to_pattern(WORKLOAD["n_logical"], wl_gates, prepare_zero=False)
+    return pat.nontrivial_count(W.outcome_bits(pat.n_meas(), W.rng(2, W.P_OUTCOME, 0)))
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def bench_batched(owqs, torch, W, ctx, steps):
@@ -735,7 +777,28 @@ def main():
             "passes": fused_passes,
             "max_abs_diff_vs_plain": diff,
             "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
+            "probability_work": ("OWQS with windows of p = 1/2 recorded without sums (reading G24: a window whose "
+                                 "new qubit meets the measured one through an odd number of E has p = 1/2 exactly; "
+                                 "at most 128 in a row, then one sums and renormalises)"),
         }
+        # the same plan with every probability summed (the paper's OWQS work per M)
+        pat.set_sum_all(True)
+        pat.set_exec(owqs.EXEC_FUSED)
+        pat.set_tile_bits(tile_bits)
+        wall_s, _, _ = time_exec(owqs, torch, pat, inp, out, owqs.EXEC_FUSED, args.steps, args.warmup, False)
+        probs_s = pat.read_probs()
+        diff_s = float((out - fused_out).abs().max().item())
+        ms_s = 1e3 * wall_s / args.steps
+        result["fused"]["sum_every_m"] = {
+            "value": round(n_nontriv / (ms_s / 1e3), 1),
+            "unit": "commands/s",
+            "ms_per_step": round(ms_s, 3),
+            "passes": pat.plan_info()[2],
+            "max_abs_diff_vs_default_fused": diff_s,
+            "max_abs_p_minus_half": float(np.max(np.abs(probs_s - 0.5))),
+            "probability_work": "OWQS with every window's probability summed in FP64 (owqs_set_sum_all)",
+        }
+        pat.set_sum_all(False)
         if prof_f:
             _, roof_f = roofline_of(prof_f, names)
             result["fused"]["roofline"] = roof_f
@@ -766,6 +829,11 @@ def main():
     if not args.no_widths:
         log("[bench] plain kernels at widths 24..28")
         result["widths"] = bench_widths(owqs, torch, W, ctx)
+        if "roofline" in result:
+            # above the 256 MB Infinity Cache the vector streams from HBM only
+            result["roofline"]["above_cache"] = {
+                w: {k: v["frac"] for k, v in row.items()} for w, row in result["widths"].items()
+                if w in ("2^26", "2^27", "2^28")}
     if not args.no_substates:
         log("[bench] sub-state executor")
         result["substates"] = bench_substates(owqs, torch, W, ctx, args.steps)

@@ -204,6 +204,14 @@ owqs_status owqs_check(owqs_pattern *pat, void *stream);
  * the input copy stays outside it. */
 owqs_status owqs_set_graph(owqs_pattern *pat, int enable);
 
+/* OWQS mode: sum the probability of every M (on = 1), including fused
+ * windows whose new qubit meets the measured one through an odd number of E.
+ * Such a window has p = 1/2 exactly for every state and angle (Eqs. 11-13),
+ * so by default (on = 0) it records 1/2 without summing the state, at most
+ * 128 in a row before one sums and renormalises.  Both give the same
+ * results within rounding; on = 1 does the paper's OWQS work for every M. */
+owqs_status owqs_set_sum_all(owqs_pattern *pat, int32_t on);
+
 /* Tile size of the fused passes: 2^bits amplitudes per LDS tile, bits in
  * 10..13, or 0 for the default min(12, width - 8).  Larger tiles chain more
  * commands per pass; smaller ones fit more workgroups per CU. */

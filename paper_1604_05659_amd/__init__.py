@@ -89,6 +89,7 @@ _sig = {
     "owqs_read_live": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _i32p, _i32p, _vp]),
     "owqs_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
     "owqs_set_tile_bits": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "owqs_set_sum_all": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "owqs_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _i32p,
                                  ctypes.POINTER(ctypes.c_float)]),
     "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
@@ -306,6 +307,10 @@ class Pattern:
 
     def set_tile_bits(self, bits: int):
         self.ctx.check(_lib.owqs_set_tile_bits(self._h, int(bits)))
+
+    def set_sum_all(self, on: bool):
+        """OWQS: sum every M's probability, also where p = 1/2 exactly."""
+        self.ctx.check(_lib.owqs_set_sum_all(self._h, 1 if on else 0))
 
     def tune(self, psi_in=None, stream=None):
         """Pick the fastest tile size for this pattern; returns (bits, ms per run)."""

@@ -112,7 +112,7 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
       // OWQS: a window with an odd E(v, w) count has p = 1/2 exactly for every
       // state (Eqs. 11-13): it is recorded without the block sum and sigma is
       // left for the next measurement that sums (at most kHalfRun in a row)
-      const bool half = reduce == kReduceRenorm && st.kind == DK_J && !(st.pp & 8u) && half_run < kHalfRun;
+      const bool half = reduce == kReduceRenorm && st.kind == DK_J && !(st.pp & 24u) && half_run < kHalfRun;
       const float f = float((reduce == kReduceRenorm && !half ? sigma : 1.0) * st.host_factor);
       const float2 c = st.coef;
       double acc = 0.0;

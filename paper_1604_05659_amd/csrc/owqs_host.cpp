@@ -299,8 +299,8 @@ void group_tiles(owqs_pattern *p) {
     return;
   }
   group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m,
-              p->mode == OWQS_MODE_OWQS);
-  if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups);
+              p->mode == OWQS_MODE_OWQS && p->half_cap > 0);
+  if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups, p->half_cap);
   else
     for (TileGroup &tg : p->groups) tg.half = false;
 }
@@ -657,14 +657,21 @@ owqs_status build_pattern(owqs_ctx *ctx, const owqs_cmd *cmds, size_t ncmds, con
 }
 
 // Algorithmic bytes of one step (element level, complex64).
+// Algorithmic bytes of a step at line granularity (a 128-byte line holds the
+// 16 amplitudes of slots 0..3): E reads and writes the |11> quarter, or the
+// half of the lines with the high bit set when the low bit is below 4, or
+// every line when both are; Z the same for its one bit.
 double step_bytes(const Step &x) {
   const double a = std::ldexp(8.0, x.n);  // 8 bytes * 2^n
   switch (x.kind) {
     case S_N: return 2.0 * a;
-    case S_E: return 0.5 * a;
+    case S_E: {
+      const int lo = std::min(x.b0, x.b1), hi = std::max(x.b0, x.b1);
+      return hi < 4 ? 2.0 * a : lo < 4 ? 1.0 * a : 0.5 * a;
+    }
     case S_M: return 1.5 * a;
     case S_X: return 2.0 * a;
-    case S_Z: return 1.0 * a;
+    case S_Z: return x.b0 < 4 ? 2.0 * a : 1.0 * a;
     case S_J: return 2.0 * a;
     case S_F: return 2.0 * a;  // one read and one write of the vector
   }
@@ -702,18 +709,18 @@ double rounded_factor(double h, double &e) {
 // still add up over a long run without reductions, so at most kHalfRun such
 // windows follow each other: the window or group that would exceed it
 // reduces (and renormalises) as usual.  Groups are taken whole.
-void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups) {
+void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups, int cap) {
   int run = 0;
   for (Step &x : xs) {
     if (x.kind == S_M) {
       run = 0;
     } else if (x.kind == S_J) {
-      x.half = !x.win.vw_even && run + 1 <= kHalfRun;
+      x.half = !x.win.vw_even && run + 1 <= cap;
       run = x.half ? run + 1 : 0;
     } else if (x.kind == S_F) {
       TileGroup &tg = groups[x.group];
       if (tg.ta.nwin == 0) continue;  // no norm changes, no reduction
-      tg.half = tg.half && run + tg.ta.nwin <= kHalfRun;
+      tg.half = tg.half && run + tg.ta.nwin <= cap;
       run = tg.half ? run + tg.ta.nwin : 0;
     }
   }
@@ -832,7 +839,8 @@ owqs_status upload_steps(owqs_pattern *p) {
     d[i].m_index = x.m_index;
     d[i].coef = x.coef;
     d[i].host_factor = (float)x.host_factor;
-    d[i].pp = (x.win.swap ? 1u : 0u) | (x.win.neg0 ? 2u : 0u) | (x.win.neg1 ? 4u : 0u) | (x.win.vw_even ? 8u : 0u);
+    d[i].pp = (x.win.swap ? 1u : 0u) | (x.win.neg0 ? 2u : 0u) | (x.win.neg1 ? 4u : 0u) | (x.win.vw_even ? 8u : 0u) |
+              (p->half_cap == 0 ? 16u : 0u);
     d[i].mask_b = x.win.mask_b;
     d[i].mask_o1 = x.win.mask_o1;
   }
@@ -1333,6 +1341,17 @@ owqs_status owqs_set_graph(owqs_pattern *p, int enable) {
   return OWQS_OK;
 }
 
+owqs_status owqs_set_sum_all(owqs_pattern *p, int32_t on) {
+  if (!p || (on != 0 && on != 1)) return OWQS_E_INVALID_ARG;
+  const int cap = on ? 0 : kHalfRun;
+  if (p->half_cap != cap) {
+    p->half_cap = cap;
+    p->dirty = true;
+    p->s_valid = false;  // the drawn-outcome plan decides its windows' sums too
+  }
+  return OWQS_OK;
+}
+
 owqs_status owqs_set_tile_bits(owqs_pattern *p, int32_t bits) {
   if (!p || (bits != 0 && (bits < 10 || bits > kMaxTileBits))) return OWQS_E_INVALID_ARG;
   if (p->tile_bits != bits) p->dirty = true;
@@ -1620,7 +1639,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     // levels of the wide plans
     struct Bucket {
       int k;
-      bool runs;
+      bool runs, red;
       std::vector<MultiTile> ents;
       uint32_t total = 0;
     };
@@ -1657,10 +1676,11 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
             if (r == kReduceNone && reduce == kReduceRenorm) m.ta.half_m = fuse_m_dev(p) + tg.m_off;
             m.reduce = r;
             Bucket *bk = nullptr;
+            const bool red = r != kReduceNone;
             for (Bucket &b : L.buckets)
-              if (b.k == tg.ta.k && b.runs == (tg.ta.runs != 0)) bk = &b;
+              if (b.k == tg.ta.k && b.runs == (tg.ta.runs != 0) && b.red == red) bk = &b;
             if (!bk) {
-              L.buckets.push_back(Bucket{tg.ta.k, tg.ta.runs != 0, {}, 0});
+              L.buckets.push_back(Bucket{tg.ta.k, tg.ta.runs != 0, red, {}, 0});
               bk = &L.buckets.back();
             }
             m.first_tile = bk->total;
@@ -1739,7 +1759,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
       for (size_t q = 0; q < L.buckets.size() && le == hipSuccess; ++q) {
         const Bucket &b = L.buckets[q];
         le = launch_tile_multi(reinterpret_cast<const MultiTile *>(dev + bk_off[lv][q]), (int)b.ents.size(), b.total,
-                               b.k, b.runs, B.cap);
+                               b.k, b.runs, b.red, B.cap);
         ++nodes;
       }
       if (le == hipSuccess && !L.fins.empty()) {

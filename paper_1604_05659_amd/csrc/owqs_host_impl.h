@@ -146,6 +146,9 @@ struct owqs_pattern {
   int plan_width = 0;            // largest live width the plan reaches
 
   int tile_bits = 0;  // 0: automatic (max(10, min(12, n - 8))); else 10..13
+  // OWQS: windows with p = 1/2 exactly recorded without a sum, at most this
+  // many in a row (kHalfRun; 0 after owqs_set_sum_all(p, 1): every M sums)
+  int half_cap = kHalfRun;
   // execution steps of the global-memory path: the plan with runs of
   // window/E/X/Z steps grouped into tile passes (S_F)
   std::vector<Step> xsteps;
@@ -292,7 +295,7 @@ bool half_prob(const Step &x, int reduce);
 // Error feedback for the FP32 rounding of the factors of such windows.
 double rounded_factor(double h, double &e);
 // Decide which windows and tile groups with p = 1/2 skip their reduction.
-void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups);
+void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups, int cap);
 int reduce_of(const owqs_pattern *p);
 struct Profile {
   int64_t *counts;

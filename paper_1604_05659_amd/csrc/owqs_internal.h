@@ -66,7 +66,8 @@ struct DevStep {
   int32_t m_index;          // M / window: index of the measurement
   float2 coef;              // M / window: (-1)^o e^{-i theta}
   float host_factor;        // M / window: (1/sqrt 2)^(pending N)
-  uint32_t pp;              // window: bit 0 swap, bit 1 negate 0, bit 2 negate 1, bit 3 vw_even
+  uint32_t pp;              // window: bit 0 swap, bit 1 negate 0, bit 2 negate 1, bit 3 vw_even,
+                            // bit 4 sum its probability even when p = 1/2 exactly
   uint64_t mask_b;          // window: see Window
   uint64_t mask_o1;
 };  // 40 bytes
@@ -217,8 +218,10 @@ hipError_t lds_batch_prepare();
 hipError_t launch_batch_start(const BatchIo *ios, int count, int max_nin, hipStream_t s);
 hipError_t launch_batch_read(const BatchIo *ios, int count, int max_nout, hipStream_t s);
 // Tile groups of many patterns in one launch (entries sorted by first_tile,
-// all with tile bits k and the same `runs`), and their group finishes.
-hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, hipStream_t s);
+// all with tile bits k, the same `runs` and, as `red`, all with or all
+// without the FP64 window sums), and their group finishes.
+hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, bool red,
+                             hipStream_t s);
 hipError_t launch_finish_multi(const MultiFinish *fins, int nfin, int maxwin, hipStream_t s);
 // Items share one command table and differ only by input: item k runs on
 // basis state |first + k> (basis_mode = 1) or on in + k * 2^nin, and writes

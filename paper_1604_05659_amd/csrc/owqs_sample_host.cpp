@@ -146,7 +146,7 @@ void compile_sampled(owqs_pattern *p) {
     for (owqs_pattern::SStep &x : p->s_steps) {
       if (x.kind == S_J) {
         x.host_factor = rounded_factor(x.host_factor, e);
-        x.half = run + 1 <= kHalfRun;
+        x.half = run + 1 <= p->half_cap;
         run = x.half ? run + 1 : 0;
       } else if (x.kind == S_M) {
         e = 1.0;

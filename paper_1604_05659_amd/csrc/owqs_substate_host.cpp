@@ -65,7 +65,7 @@ void group_substates(owqs_pattern *p) {
     if (r.group >= 0) {
       TileGroup &tg = p->ss_groups[r.group];
       if (tg.ta.nwin == 0) continue;
-      tg.half = p->mode == OWQS_MODE_OWQS && tg.half && run[r.chain] + tg.ta.nwin <= kHalfRun;
+      tg.half = p->mode == OWQS_MODE_OWQS && tg.half && run[r.chain] + tg.ta.nwin <= p->half_cap;
       run[r.chain] = tg.half ? run[r.chain] + tg.ta.nwin : 0;
       continue;
     }
@@ -73,7 +73,7 @@ void group_substates(owqs_pattern *p) {
     if (x.kind == SS_M) {
       run[r.chain] = 0;
     } else if (x.kind == SS_J) {
-      x.half = p->mode == OWQS_MODE_OWQS && !x.win.vw_even && run[r.chain] + 1 <= kHalfRun;
+      x.half = p->mode == OWQS_MODE_OWQS && !x.win.vw_even && run[r.chain] + 1 <= p->half_cap;
       run[r.chain] = x.half ? run[r.chain] + 1 : 0;
     } else if (x.kind == SS_KRON) {
       run[r.chain] += run[x.top];

@@ -38,6 +38,13 @@ __device__ __forceinline__ uint32_t par64(uint64_t x) { return uint32_t(__popcll
 __device__ __forceinline__ uint32_t par32(uint32_t x) { return uint32_t(__popc(x) & 1); }
 __device__ __forceinline__ float xsign(float x, uint32_t s) { return __uint_as_float(__float_as_uint(x) ^ s); }
 __device__ __forceinline__ float2 xsign2(float2 v, uint32_t s) { return make_float2(xsign(v.x, s), xsign(v.y, s)); }
+// |a|^2 + |b|^2 of one pair: four FP32 products summed in FP32 (relative
+// error below 3 ulp), returned as FP64, so that a thread's, a wave's, a
+// workgroup's and the tiles' sums over pairs accumulate in FP64 and the
+// error stays that of one pair sum however many pairs there are
+__device__ __forceinline__ double nrm2d(float2 a, float2 b) {
+  return double(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+}
 __device__ __forceinline__ float2 &at(char *lds, uint32_t byte_off) { return *reinterpret_cast<float2 *>(lds + byte_off); }
 
 // One command of the group, read as whole dwords from a uniform address so
@@ -164,16 +171,16 @@ __device__ __forceinline__ void pair_swap(char *lds, uint32_t tid, int lb) {
 //   t = fc0 b,  o0 = fa a + t,  o1 = fb a + r t   (r = +-1, sign bit rsign),
 // with b negated where the local bits lmb have odd parity and o1 negated
 // where the local bits lmo have odd parity (kMasked), and the outputs
-// exchanged by the folded X correction (kSw).  Returns this thread's FP32
-// sum of |o0|^2 + |o1|^2 (kAcc).
+// exchanged by the folded X correction (kSw).  Returns this thread's sum of
+// |o0|^2 + |o1|^2 in FP64 (kAcc).
 template <bool kMasked, bool kSw, bool kAcc, int kTB, int kT>
-__device__ __forceinline__ float window_pass(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0,
+__device__ __forceinline__ double window_pass(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0,
                                              uint32_t rsign, uint32_t lmb, uint32_t lmo) {
   constexpr int kPairs = (1 << kTB) / kT / 2;
   const uint32_t et = ins0u(tid, lb), bit8 = 8u << lb;
   const uint32_t sbt = kMasked ? par32(et & lmb) << 31 : 0u;
   const uint32_t sot = kMasked ? par32(et & lmo) << 31 : 0u;
-  float acc = 0.f;
+  double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < kPairs; ++r) {
     const uint32_t ur = ins0u(uint32_t(r) * kT, lb);
@@ -194,7 +201,7 @@ __device__ __forceinline__ float window_pass(char *lds, uint32_t tid, int lb, fl
     const float2 p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
     at(lds, a0) = kSw ? p1 : p0;
     at(lds, a1) = kSw ? p0 : p1;
-    if (kAcc) acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
+    if (kAcc) acc += nrm2d(p0, p1);
   }
   return acc;
 }
@@ -204,11 +211,11 @@ __device__ __forceinline__ float window_pass(char *lds, uint32_t tid, int lb, fl
 // the thread's first pair, and the sign of t in o1 is an instruction
 // modifier.
 template <bool kSw, bool kAcc, bool kRneg, int kTB, int kT>
-__device__ __forceinline__ float window_low(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0) {
+__device__ __forceinline__ double window_low(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0) {
   constexpr int kPairs = (1 << kTB) / kT / 2;
   constexpr int kLogT = log2_threads(kT);
   const uint32_t a0t = ins0u(tid, lb) << 3, a1t = a0t | (8u << lb);
-  float acc = 0.f;
+  double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < kPairs; ++r) {
     // pair index tid + r kT with lb < log2 kT: insertion shifts r kT up by one
@@ -220,13 +227,13 @@ __device__ __forceinline__ float window_low(char *lds, uint32_t tid, int lb, flo
                             : make_float2(fmaf(fb, a.x, t.x), fmaf(fb, a.y, t.y));
     at(lds, a0t + off) = kSw ? p1 : p0;
     at(lds, a1t + off) = kSw ? p0 : p1;
-    if (kAcc) acc += p0.x * p0.x + p0.y * p0.y + p1.x * p1.x + p1.y * p1.y;
+    if (kAcc) acc += nrm2d(p0, p1);
   }
   return acc;
 }
 
 template <bool kAcc, int kTB, int kT>
-__device__ __forceinline__ float window_any(bool masked, bool sw, char *lds, uint32_t tid, int lb, float fa, float fb,
+__device__ __forceinline__ double window_any(bool masked, bool sw, char *lds, uint32_t tid, int lb, float fa, float fb,
                                             float2 fc0, uint32_t rsign, uint32_t lmb, uint32_t lmo) {
   constexpr int kLogT = log2_threads(kT);
   if (masked)
@@ -301,8 +308,8 @@ __device__ __forceinline__ void win_apply(const WinP &w, uint32_t e0, float2 &a,
   b = kSw ? p0 : p1;
 }
 
-__device__ __forceinline__ float nrm4(float2 a, float2 b, float2 c, float2 d) {
-  return a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + c.x * c.x + c.y * c.y + d.x * d.x + d.y * d.y;
+__device__ __forceinline__ double nrm4(float2 a, float2 b, float2 c, float2 d) {
+  return nrm2d(a, b) + nrm2d(c, d);
 }
 
 // Two consecutive unmasked windows A, B on different local bits in one LDS
@@ -311,7 +318,7 @@ __device__ __forceinline__ float nrm4(float2 a, float2 b, float2 c, float2 d) {
 // the LDS traffic and barriers of two passes.
 template <bool kAcc, bool kSwA, bool kSwB, bool kMA, bool kMB, bool kMid, int kTB, int kT>
 __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
-                                            float &acc_a, float &acc_b) {
+                                            double &acc_a, double &acc_b) {
   constexpr int kQuads = (1 << kTB) / kT / 4;
   const int lo = A.lb < B.lb ? A.lb : B.lb, hi = A.lb < B.lb ? B.lb : A.lb;
   const uint32_t ba = 8u << A.lb, bb = 8u << B.lb;
@@ -340,7 +347,7 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
 
 template <bool kAcc, bool kMA, bool kMB, bool kMid, int kTB, int kT>
 __device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
-                                               float &acc_a, float &acc_b) {
+                                               double &acc_a, double &acc_b) {
   if (A.sw) {
     if (B.sw) window_pair<kAcc, true, true, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
     else window_pair<kAcc, true, false, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
@@ -352,7 +359,7 @@ __device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const Wi
 
 template <bool kAcc, bool kMid, int kTB, int kT>
 __device__ __forceinline__ void window_pair_m(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
-                                              float &acc_a, float &acc_b) {
+                                              double &acc_a, double &acc_b) {
   if (A.masked) {
     if (B.masked) window_pair_sw<kAcc, true, true, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
     else window_pair_sw<kAcc, true, false, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
@@ -366,7 +373,7 @@ __device__ __forceinline__ void window_pair_m(char *lds, uint32_t tid, const Win
 // local bits `mid`, applied when has_mid: the tile's outer bits satisfy it).
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, bool has_mid,
-                                                uint32_t mid, float &acc_a, float &acc_b) {
+                                                uint32_t mid, double &acc_a, double &acc_b) {
   if (has_mid) window_pair_m<kAcc, true, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
   else window_pair_m<kAcc, false, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
 }
@@ -376,7 +383,7 @@ __device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const W
 // window applied to its four pairs in turn; one LDS round for three commands.
 template <bool kAcc, bool kSwA, bool kSwB, bool kSwC, int kTB, int kT>
 __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const WinP &A, const WinP &B, const WinP &C,
-                                              float *acc) {
+                                              double *acc) {
   constexpr int kOcts = (1 << kTB) / kT / 8;
   int b0 = A.lb, b1 = B.lb, b2 = C.lb;  // sorted copy for the zero insertions
   if (b0 > b1) { const int t = b0; b0 = b1; b1 = t; }
@@ -412,7 +419,7 @@ __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const Win
 
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ void window_triple_any(char *lds, uint32_t tid, const WinP &A, const WinP &B,
-                                                  const WinP &C, float *acc) {
+                                                  const WinP &C, double *acc) {
   const int sel = (A.sw ? 1 : 0) | (B.sw ? 2 : 0) | (C.sw ? 4 : 0);
   switch (sel) {
     case 0: window_triple<kAcc, false, false, false, kTB, kT>(lds, tid, A, B, C, acc); break;
@@ -442,13 +449,14 @@ __device__ __forceinline__ void tile_high_bits(uint64_t tmask, uint64_t *hp) {
 
 // One tile of a group (tile t of the 2^(n-k)): load it into LDS, apply the
 // group's commands, store it back.  With `reduce`, every window adds its
-// FP32 norm per wave into wacc (summed in FP64 across lanes).  g_tid and hp
+// norm per wave into wacc (FP64 from each thread's sum of squares on).  g_tid and hp
 // hold the thread's part of the global index and the global bits of the tile
 // bits above the thread index (see k_tile).
-template <int kTB, bool kRuns>
+template <int kTB, bool kRuns, bool kRed>
 __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArgs &ta, const FuseOp *__restrict__ ops,
-                                         bool reduce, double sg, uint64_t t, uint64_t g_tid, const uint64_t *hp,
-                                         float2 *tile, double (*wacc)[tile_threads(kTB) / 64]) {
+                                         double sg, uint64_t t, uint64_t g_tid, const uint64_t *hp, float2 *tile,
+                                         double (*wacc)[tile_threads(kTB) / 64]) {
+  constexpr bool reduce = kRed;  // a compile-time variant: the FP64 sums cost registers
   constexpr int kT = tile_threads(kTB);
   constexpr int kLogT = log2_threads(kT);
   constexpr int kPer = (1 << kTB) / kT;
@@ -479,7 +487,7 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
       if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
           n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
         const WinP A = prep_window(op, ob, sg, ta), B = prep_window(n1, ob, sg, ta), C = prep_window(n2, ob, sg, ta);
-        float acc[3] = {0.f, 0.f, 0.f};
+        double acc[3] = {0.0, 0.0, 0.0};
         if (reduce) {
           window_triple_any<true, kTB, kT>(lds, tid, A, B, C, acc);
           const double da = wave_sum_to_last(acc[0]), db = wave_sum_to_last(acc[1]), dc = wave_sum_to_last(acc[2]);
@@ -513,7 +521,7 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
       }
       if (nx.kind == DK_J && nx.lb != op.lb) {
         const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
-        float acc_a = 0.f, acc_b = 0.f;
+        double acc_a = 0.0, acc_b = 0.0;
         if (reduce) {
           window_pair_any<true, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
           const double da = wave_sum_to_last(acc_a), db = wave_sum_to_last(acc_b);
@@ -549,7 +557,7 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
       const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
       const bool masked = (op.lmask_b | op.lmask_o1) != 0;
       if (reduce) {
-        const float acc =
+        const double acc =
             window_any<true, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
         const double d = wave_sum_to_last(acc);  // FP64 from the wave sum on
         if (lane == 63) wacc[op.widx][wave] += d;
@@ -584,7 +592,7 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
 // Every command of the group is then one pass over the tile in LDS.
 // kRuns: the run-in-registers paths are compiled in (they raise the VGPR
 // count, which lowers occupancy for groups that cannot use them).
-template <int kTB, bool kRuns>
+template <int kTB, bool kRuns, bool kRed>
 __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__ psi, TileArgs ta,
                                                             const FuseOp *__restrict__ ops, MeasureArgs ma,
                                                             double *__restrict__ partials) {
@@ -593,7 +601,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
   extern __shared__ float2 tile[];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
   const uint32_t tid = threadIdx.x;
-  const bool reduce = ma.reduce != kReduceNone;
+  constexpr bool reduce = kRed;  // ma.reduce != kReduceNone
   if (reduce)
     for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
   const double sg = (ma.reduce == kReduceRenorm) ? *ma.book.sigma : 1.0;
@@ -605,7 +613,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     for (int i = tid; i < ta.nwin; i += kT) ma.book.probs[ta.half_m[i]] = 0.5;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-    tile_one<kTB, kRuns>(psi, ta, ops, reduce, sg, t, g_tid, hp, tile, wacc);
+    tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc);
   if (reduce) {
     for (int w = tid; w < ta.nwin; w += kT) {
       double s = 0.0;
@@ -645,7 +653,7 @@ __device__ __forceinline__ uint32_t first_tile_of(const MultiTile *ents, int e) 
 // owns its tile (binary search on first_tile), runs that tile as k_tile
 // does, and stores its windows' sums per tile (partials[w * ntiles + t]), so
 // that k_finish_multi sums them in tile order.
-template <int kTB, bool kRuns>
+template <int kTB, bool kRuns, bool kRed>
 __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTile *__restrict__ ents, int nent,
                                                                   uint32_t total) {
   constexpr int kT = tile_threads(kTB);
@@ -662,7 +670,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
     }
     const MultiTile e = load_row(ents, uint32_t(lo));
     const uint64_t t = gt - e.first_tile;
-    const bool reduce = e.reduce != kReduceNone;
+    constexpr bool reduce = kRed;  // every entry of the launch: e.reduce != kReduceNone
     if (reduce)
       for (int i = tid; i < e.ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
     const double sg = e.reduce == kReduceRenorm ? *e.sigma : 1.0;
@@ -671,7 +679,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
     tile_high_bits<kTB>(e.ta.tmask, hp);
     if (e.ta.half_m && t == 0)  // windows with p = 1/2 exactly
       for (int i = tid; i < e.ta.nwin; i += kT) e.probs[e.ta.half_m[i]] = 0.5;
-    tile_one<kTB, kRuns>(e.psi, e.ta, e.ops, reduce, sg, t, g_tid, hp, tile, wacc);
+    tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc);
     if (reduce) {
       const uint64_t ntiles = uint64_t(1) << (e.ta.n - kTB);
       for (int w = tid; w < e.ta.nwin; w += kT) {
@@ -909,62 +917,79 @@ unsigned tile_grid(const TileArgs &ta) {
   return unsigned(ntiles < kTileGridCap ? ntiles : kTileGridCap);
 }
 
-hipError_t tile_prepare() {
+namespace {
+
+// Dynamic LDS limits of every tile kernel with 2^kTB-amplitude tiles.
+template <int kTB>
+hipError_t prepare_bits() {
+  const int one = int(sizeof(float2) << kTB), two = 2 * one;
+  const void *fns[] = {
+      reinterpret_cast<const void *>(k_tile<kTB, false, false>), reinterpret_cast<const void *>(k_tile<kTB, false, true>),
+      reinterpret_cast<const void *>(k_tile<kTB, true, false>), reinterpret_cast<const void *>(k_tile<kTB, true, true>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, false, false>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, false, true>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, true, false>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, true, true>)};
   hipError_t e = hipSuccess;
-  const void *fns[] = {reinterpret_cast<const void *>(k_tile<10, false>),
-                       reinterpret_cast<const void *>(k_tile<11, false>),
-                       reinterpret_cast<const void *>(k_tile<12, false>),
-                       reinterpret_cast<const void *>(k_tile<13, false>)};
-  const void *fnr[] = {reinterpret_cast<const void *>(k_tile<10, true>), reinterpret_cast<const void *>(k_tile<11, true>),
-                       reinterpret_cast<const void *>(k_tile<12, true>), reinterpret_cast<const void *>(k_tile<13, true>)};
-  const void *rev[] = {reinterpret_cast<const void *>(k_tile_rev<10>), reinterpret_cast<const void *>(k_tile_rev<11>),
-                       reinterpret_cast<const void *>(k_tile_rev<12>), reinterpret_cast<const void *>(k_tile_rev<13>)};
-  const void *mul[] = {reinterpret_cast<const void *>(k_tile_multi<10, false>),
-                       reinterpret_cast<const void *>(k_tile_multi<11, false>),
-                       reinterpret_cast<const void *>(k_tile_multi<12, false>),
-                       reinterpret_cast<const void *>(k_tile_multi<13, false>)};
-  const void *mur[] = {reinterpret_cast<const void *>(k_tile_multi<10, true>),
-                       reinterpret_cast<const void *>(k_tile_multi<11, true>),
-                       reinterpret_cast<const void *>(k_tile_multi<12, true>),
-                       reinterpret_cast<const void *>(k_tile_multi<13, true>)};
-  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
-    e = hipFuncSetAttribute(mul[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(mur[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
+  for (const void *f : fns)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, one);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tile_rev<kTB>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, two);
+  return e;
+}
+
+// One tile pass: the instance compiled for these tile bits, register runs
+// (ta.runs) and reduction (FP64 window sums).
+template <int kTB>
+void tile_launch(bool runs, bool red, dim3 grid, hipStream_t s, float2 *psi, const TileArgs &ta, const FuseOp *ops,
+                 const MeasureArgs &a, double *partials) {
+  const dim3 block(tile_threads(kTB));
+  const size_t bytes = sizeof(float2) << kTB;
+  if (runs) {
+    if (red) hipLaunchKernelGGL((k_tile<kTB, true, true>), grid, block, bytes, s, psi, ta, ops, a, partials);
+    else hipLaunchKernelGGL((k_tile<kTB, true, false>), grid, block, bytes, s, psi, ta, ops, a, partials);
+  } else {
+    if (red) hipLaunchKernelGGL((k_tile<kTB, false, true>), grid, block, bytes, s, psi, ta, ops, a, partials);
+    else hipLaunchKernelGGL((k_tile<kTB, false, false>), grid, block, bytes, s, psi, ta, ops, a, partials);
   }
-  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
-    e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(fnr[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(sizeof(float2) << (10 + i)));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(rev[i], hipFuncAttributeMaxDynamicSharedMemorySize, int(2 * sizeof(float2) << (10 + i)));
+}
+
+template <int kTB>
+void tile_multi_launch(bool runs, bool red, dim3 grid, hipStream_t s, const MultiTile *ents, int nent,
+                       uint32_t total) {
+  const dim3 block(tile_threads(kTB));
+  const size_t bytes = sizeof(float2) << kTB;
+  if (runs) {
+    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, true, true>), grid, block, bytes, s, ents, nent, total);
+    else hipLaunchKernelGGL((k_tile_multi<kTB, true, false>), grid, block, bytes, s, ents, nent, total);
+  } else {
+    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, false, true>), grid, block, bytes, s, ents, nent, total);
+    else hipLaunchKernelGGL((k_tile_multi<kTB, false, false>), grid, block, bytes, s, ents, nent, total);
   }
+}
+
+}  // namespace
+
+hipError_t tile_prepare() {
+  hipError_t e = prepare_bits<10>();
+  if (e == hipSuccess) e = prepare_bits<11>();
+  if (e == hipSuccess) e = prepare_bits<12>();
+  if (e == hipSuccess) e = prepare_bits<13>();
   return e;
 }
 
 hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const MeasureArgs &a, hipStream_t s,
                        unsigned *grid) {
   // the per-window sums hold kMaxGroupWindows; larger groups only run without them
-  if (ta.nwin > (a.reduce != kReduceNone ? kMaxGroupWindows : kMaxHalfWindows)) return hipErrorInvalidValue;
-  const size_t bytes = sizeof(float2) << ta.k;
+  const bool red = a.reduce != kReduceNone;
+  if (ta.nwin > (red ? kMaxGroupWindows : kMaxHalfWindows)) return hipErrorInvalidValue;
   const unsigned g = tile_grid(ta);
   switch (ta.k) {
-    case 10:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<10, true>), dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials);
-      else hipLaunchKernelGGL((k_tile<10, false>), dim3(g), dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, a.book.partials);
-      break;
-    case 11:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<11, true>), dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials);
-      else hipLaunchKernelGGL((k_tile<11, false>), dim3(g), dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, a.book.partials);
-      break;
-    case 12:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<12, true>), dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials);
-      else hipLaunchKernelGGL((k_tile<12, false>), dim3(g), dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, a.book.partials);
-      break;
-    case 13:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<13, true>), dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials);
-      else hipLaunchKernelGGL((k_tile<13, false>), dim3(g), dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, a.book.partials);
-      break;
+    case 10: tile_launch<10>(ta.runs, red, dim3(g), s, psi, ta, ops, a, a.book.partials); break;
+    case 11: tile_launch<11>(ta.runs, red, dim3(g), s, psi, ta, ops, a, a.book.partials); break;
+    case 12: tile_launch<12>(ta.runs, red, dim3(g), s, psi, ta, ops, a, a.book.partials); break;
+    case 13: tile_launch<13>(ta.runs, red, dim3(g), s, psi, ta, ops, a, a.book.partials); break;
     default: return hipErrorInvalidValue;
   }
   *grid = g;
@@ -979,25 +1004,12 @@ hipError_t launch_tile_sets(float2 *psi, const TileArgs &ta0, const FuseOp *ops,
   ta.nsets = nsets;
   MeasureArgs a{};
   a.reduce = kReduceNone;
-  const size_t bytes = sizeof(float2) << ta.k;
   const dim3 grid(tile_grid(ta), unsigned(nsets));
   switch (ta.k) {
-    case 10:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<10, true>), grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr);
-      else hipLaunchKernelGGL((k_tile<10, false>), grid, dim3(tile_threads(10)), bytes, s, psi, ta, ops, a, nullptr);
-      break;
-    case 11:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<11, true>), grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr);
-      else hipLaunchKernelGGL((k_tile<11, false>), grid, dim3(tile_threads(11)), bytes, s, psi, ta, ops, a, nullptr);
-      break;
-    case 12:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<12, true>), grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr);
-      else hipLaunchKernelGGL((k_tile<12, false>), grid, dim3(tile_threads(12)), bytes, s, psi, ta, ops, a, nullptr);
-      break;
-    case 13:
-      if (ta.runs) hipLaunchKernelGGL((k_tile<13, true>), grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr);
-      else hipLaunchKernelGGL((k_tile<13, false>), grid, dim3(tile_threads(13)), bytes, s, psi, ta, ops, a, nullptr);
-      break;
+    case 10: tile_launch<10>(ta.runs, false, grid, s, psi, ta, ops, a, nullptr); break;
+    case 11: tile_launch<11>(ta.runs, false, grid, s, psi, ta, ops, a, nullptr); break;
+    case 12: tile_launch<12>(ta.runs, false, grid, s, psi, ta, ops, a, nullptr); break;
+    case 13: tile_launch<13>(ta.runs, false, grid, s, psi, ta, ops, a, nullptr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1024,27 +1036,15 @@ hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta0, const 
   return hipGetLastError();
 }
 
-hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, hipStream_t s) {
+hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, bool red,
+                             hipStream_t s) {
   if (nent <= 0 || total == 0) return hipGetLastError();
-  const size_t bytes = sizeof(float2) << k;
   const dim3 grid(total < 65535u ? total : 65535u);
   switch (k) {
-    case 10:
-      if (runs) hipLaunchKernelGGL((k_tile_multi<10, true>), grid, dim3(tile_threads(10)), bytes, s, ents, nent, total);
-      else hipLaunchKernelGGL((k_tile_multi<10, false>), grid, dim3(tile_threads(10)), bytes, s, ents, nent, total);
-      break;
-    case 11:
-      if (runs) hipLaunchKernelGGL((k_tile_multi<11, true>), grid, dim3(tile_threads(11)), bytes, s, ents, nent, total);
-      else hipLaunchKernelGGL((k_tile_multi<11, false>), grid, dim3(tile_threads(11)), bytes, s, ents, nent, total);
-      break;
-    case 12:
-      if (runs) hipLaunchKernelGGL((k_tile_multi<12, true>), grid, dim3(tile_threads(12)), bytes, s, ents, nent, total);
-      else hipLaunchKernelGGL((k_tile_multi<12, false>), grid, dim3(tile_threads(12)), bytes, s, ents, nent, total);
-      break;
-    case 13:
-      if (runs) hipLaunchKernelGGL((k_tile_multi<13, true>), grid, dim3(tile_threads(13)), bytes, s, ents, nent, total);
-      else hipLaunchKernelGGL((k_tile_multi<13, false>), grid, dim3(tile_threads(13)), bytes, s, ents, nent, total);
-      break;
+    case 10: tile_multi_launch<10>(runs, red, grid, s, ents, nent, total); break;
+    case 11: tile_multi_launch<11>(runs, red, grid, s, ents, nent, total); break;
+    case 12: tile_multi_launch<12>(runs, red, grid, s, ents, nent, total); break;
+    case 13: tile_multi_launch<13>(runs, red, grid, s, ents, nent, total); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

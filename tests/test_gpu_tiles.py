@@ -230,3 +230,39 @@ def test_half_probability_windows(ctx, n, kind, graph):
     got = p.read_state().cpu().numpy().astype(np.complex128)
     assert np.max(np.abs(got - want)) <= AMP_TOL
     p.close()
+
+
+@pytest.mark.parametrize("n,exec_", [(10, owqs.EXEC_AUTO), (10, owqs.EXEC_FUSED), (16, owqs.EXEC_FUSED),
+                                     (16, owqs.EXEC_SUBSTATES)])
+def test_sum_all_sums_every_window(ctx, n, exec_):
+    """owqs_set_sum_all(1): windows with p = 1/2 exactly are summed like every
+    other M (no 1/2 recorded without a sum, every pass with windows has a
+    finishing reduction); the state and every probability still match the
+    oracle, and switching back restores the default plan."""
+    g = np.random.default_rng(2600 + n + exec_)
+    pat, odd = odd_even_window_pattern(g, n, 90, even=False)
+    inp = W.gaussian_state(n, g)
+    outc = g.integers(0, 2, size=pat.n_meas()).astype(np.uint8)
+    want, pw = oc.run(pat, outc, inp.astype(np.complex128), oc.MODE_OWQS)
+    p = owqs.Pattern(ctx, pat)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_exec(exec_)
+    p.set_outcomes(outc)
+    x = torch.as_tensor(inp).cuda()
+    p.set_sum_all(True)
+    p.run(x)
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    probs = p.read_probs()
+    assert np.max(np.abs(got - want)) <= AMP_TOL
+    np.testing.assert_allclose(probs, pw, atol=1e-5)
+    assert np.all(odd) and not np.any(probs == 0.5), "every window summed"
+    if exec_ == owqs.EXEC_FUSED:
+        prof = p.run_profiled(x)
+        assert prof.get("finish(FP64)", {"launches": 0})["launches"] > 0
+    p.set_sum_all(False)
+    p.run(x)
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - want)) <= AMP_TOL
+    if exec_ != owqs.EXEC_SUBSTATES:
+        assert np.all(p.read_probs() == 0.5)
+    p.close()
