@@ -728,7 +728,7 @@ void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups, int cap) {
 
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
                         hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab, const int *ftab,
-                        float2 *psi_over, const DevBook *book_over) {
+                        float2 *psi_over, const DevBook *book_over, bool groups_patched) {
   float2 *const psi = psi_over ? psi_over : p->psi;
   const DevBook book = book_over ? *book_over : p->book;
   hipError_t e = hipSuccess;
@@ -764,7 +764,7 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
         const TileGroup &tg = p->groups[x.group];
         ops = p->dev_fuse + tg.op_off;
         TileArgs ta = tg.ta;
-        if (ctab) {
+        if (ctab && !groups_patched) {
           ta.coefs = ctab;
           ta.nsets = 1;
           ta.folds = ftab;
@@ -820,9 +820,12 @@ owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, co
 }
 
 owqs_status upload_fuse(owqs_pattern *p) {
-  if (p->dev_fuse_valid) return OWQS_OK;
+  if (p->dev_fuse_valid && !p->fuse_patched) return OWQS_OK;
   const owqs_status st = upload_fuse_table(p->ctx, p->fuse_ops, p->fuse_m, p->dev_fuse, p->dev_fuse_cap);
-  if (st == OWQS_OK) p->dev_fuse_valid = true;
+  if (st == OWQS_OK) {
+    p->dev_fuse_valid = true;
+    p->fuse_patched = false;
+  }
   return st;
 }
 

@@ -216,8 +216,10 @@ struct owqs_pattern {
   // from the uniforms alone, so a run is the fused plan with its window
   // coefficients and folds taken from a per-run device table
   bool s_analytic = false;
-  void *a_mem = nullptr;            // coefficients (float2 per M), then folds (3 int per M)
+  void *a_mem = nullptr;            // coefficients (float2 per M), folds (3 int per M), then the drawn windows
   size_t a_cap = 0;
+  bool a_wins_valid = false;        // the drawn-window table in a_mem matches s_steps
+  bool fuse_patched = false;        // drawn runs wrote coefficients into dev_fuse: forced runs upload it again
   hipGraph_t a_graph = nullptr;
   hipGraphExec_t a_exec = nullptr;
   bool an_ran = false;
@@ -306,9 +308,12 @@ struct Profile {
 // per-run device tables (coefficient of M m at ctab[m], folds at ftab[3 m]).
 // psi_over / book_over (non-null): run on that live vector and bookkeeping
 // instead of the pattern's own (the allocation-free entry point).
+// groups_patched: the tile passes take their windows' coefficients and folds
+// from their own command rows (written on the device) rather than ctab/ftab.
 hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0, size_t i1, int reduce,
                         hipStream_t s, std::vector<hipEvent_t> *ev, const float2 *ctab = nullptr,
-                        const int *ftab = nullptr, float2 *psi_over = nullptr, const DevBook *book_over = nullptr);
+                        const int *ftab = nullptr, float2 *psi_over = nullptr, const DevBook *book_over = nullptr,
+                        bool groups_patched = false);
 LdsItem lds_proto(const owqs_pattern *p);
 // Address of the allocation-free entry point's device array on `device`
 // (resolved once per device with that device current; owqs_noalloc.hip).

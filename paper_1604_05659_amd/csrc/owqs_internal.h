@@ -294,6 +294,22 @@ struct FoldRef {
   int x;
   SigRef sig;
 };
+// A drawn window of a plan whose every M is such a window (p = 1/2 for every
+// state): its outcome is u[m] <= 1/2, known before the run, like every
+// outcome its signals read.
+struct DrawWin {
+  double alpha;
+  SigRef s, t;
+  int m, fold_off, fold_len;
+  int fop;  // the window's row in the pattern's tile-pass command table, or -1
+};
+// All drawn windows at once, one thread each: outc[m], the collapse
+// coefficient ctab[m] and the folded corrections ftab[3 m .. 3 m + 2] (swap,
+// negate o0, negate o1), every signal taken from the uniforms directly; a
+// window inside a tile pass also gets them in its command row (fops[fop]:
+// coef and flag bits 0-2), so that the pass runs like a forced one.
+hipError_t launch_s_resolve(const DrawWin *wins, int nwin, const double *u, const int *dom, const FoldRef *folds,
+                            int *outc, float2 *ctab, int *ftab, FuseOp *fops, hipStream_t s);
 // One thread, for a window whose E count between v and w is odd (outcome
 // probability exactly 1/2, Sec. 4.5): o = (u[m] <= 1/2 ? 0 : 1) into outc[m],
 // the coefficient into *coef, then the folded corrections folds[0 .. nf)

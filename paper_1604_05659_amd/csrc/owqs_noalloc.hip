@@ -76,7 +76,7 @@ extern "C" owqs_status owqs_run_noalloc(owqs_pattern *p, const void *input, size
   if (ctx->device < 0) return fail(ctx, OWQS_E_STATE, "host-only context (device -1) cannot run patterns");
   if (!ctx->noalloc) return fail(ctx, OWQS_E_STATE, "the allocation-free array was not resolved on this device");
   const bool lds = p->exec == OWQS_EXEC_AUTO && p->plan_width <= kLdsMaxWidth;
-  if (p->dirty || (lds ? !p->dev_steps_valid : !p->dev_fuse_valid))
+  if (p->dirty || (lds ? !p->dev_steps_valid : (!p->dev_fuse_valid || p->fuse_patched)))
     return fail(ctx, OWQS_E_STATE,
                 "the plan is not on the device: run the pattern once with owqs_run after its last change");
   hipError_t e = hipSetDevice(ctx->device);

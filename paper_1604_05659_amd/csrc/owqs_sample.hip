@@ -141,6 +141,50 @@ __global__ void k_s_jdecide(const double *__restrict__ u, int m, double alpha, S
   fold[2] = s1 < 0;
 }
 
+// Every drawn window of a plan in which every M is such a window: thread i
+// resolves window i.  Each outcome is (u <= 1/2 ? 0 : 1) (p = 1/2 exactly),
+// so a signal (Eq. 2) is the XOR of those bits over its domain, read from the
+// uniforms without waiting for any other thread.
+__global__ __launch_bounds__(kB) void k_s_resolve(const DrawWin *__restrict__ wins, int nwin,
+                                                   const double *__restrict__ u, const int *__restrict__ dom,
+                                                   const FoldRef *__restrict__ folds, int *outc, float2 *ctab,
+                                                   int *ftab, FuseOp *fops) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= nwin) return;
+  const DrawWin w = wins[i];
+  auto sig = [&](SigRef r) {
+    int v = 0;
+    for (int k = 0; k < r.len; ++k) v ^= u[dom[r.off + k]] <= 0.5 ? 0 : 1;
+    return v;
+  };
+  const int o = u[w.m] <= 0.5 ? 0 : 1;
+  double2 c = c_of(w.alpha, sig(w.s), sig(w.t));
+  if (o) c = make_double2(-c.x, -c.y);
+  outc[w.m] = o;
+  ctab[w.m] = make_float2(float(c.x), float(c.y));
+  int i0 = 0, s0 = 1, s1 = 1;  // the corrections on w as a signed permutation
+  for (int k = 0; k < w.fold_len; ++k) {
+    const FoldRef f = folds[w.fold_off + k];
+    if (!sig(f.sig)) continue;
+    if (f.x) {
+      i0 ^= 1;
+      const int t = s0;
+      s0 = s1;
+      s1 = t;
+    } else {
+      s1 = -s1;
+    }
+  }
+  ftab[3 * w.m] = i0;
+  ftab[3 * w.m + 1] = s0 < 0;
+  ftab[3 * w.m + 2] = s1 < 0;
+  if (w.fop >= 0) {  // vector stores; the next kernel's scalar loads read them after the launch boundary
+    FuseOp *op = fops + w.fop;
+    op->coef = make_float2(float(c.x), float(c.y));
+    op->flags = uint8_t((op->flags & ~7u) | uint32_t(i0) | (s0 < 0 ? 2u : 0u) | (s1 < 0 ? 4u : 0u));
+  }
+}
+
 unsigned grid_of(uint64_t units) {
   uint64_t g = (units + kB - 1) / kB;
   if (g < 1) g = 1;
@@ -175,6 +219,14 @@ hipError_t launch_s_decide(const double *partials, unsigned nparts, const double
 hipError_t launch_s_jdecide(const double *u, int m, double alpha, SigRef sg, SigRef tg, const int *dom, int *outc,
                             float2 *coef, const FoldRef *folds, int nf, int *fold, hipStream_t s) {
   hipLaunchKernelGGL(k_s_jdecide, dim3(1), dim3(64), 0, s, u, m, alpha, sg, tg, dom, outc, coef, folds, nf, fold);
+  return hipGetLastError();
+}
+
+hipError_t launch_s_resolve(const DrawWin *wins, int nwin, const double *u, const int *dom, const FoldRef *folds,
+                            int *outc, float2 *ctab, int *ftab, FuseOp *fops, hipStream_t s) {
+  if (nwin <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_s_resolve, dim3(unsigned((nwin + kB - 1) / kB)), dim3(kB), 0, s, wins, nwin, u, dom, folds,
+                     outc, ctab, ftab, fops);
   return hipGetLastError();
 }
 

@@ -162,6 +162,7 @@ void compile_sampled(owqs_pattern *p) {
     if (x.kind != S_N && x.kind != S_E && x.kind != S_J) p->s_analytic = false;
   p->s_valid = true;
   p->s_uploaded = false;
+  p->a_wins_valid = false;
   if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
   if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
 }
@@ -230,10 +231,11 @@ hipError_t launch_sampled(owqs_pattern *p, hipStream_t s) {
 
 // Drawn outcomes when every M is a window with p = 1/2 (s_analytic): each
 // outcome is u[m] <= 1/2, known before the run, so the signals, coefficients
-// and folded corrections are resolved on the host in measurement order and
-// the fused plan (tile passes) runs with them from a device table.  Returns
-// false (nothing done) when the fused plan has steps whose form depends on
-// the outcomes (a separate M, X or Z).
+// and folded corrections of all windows are resolved at once by one device
+// kernel (k_s_resolve) from the uploaded uniforms, and the fused plan (tile
+// passes) runs with them from device tables; the run is one graph and needs
+// no host synchronisation.  Returns false (nothing done) when the fused plan
+// has steps whose form depends on the outcomes (a separate M, X or Z).
 bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_device, hipStream_t s,
                   owqs_status &st) {
   st = OWQS_OK;
@@ -243,39 +245,18 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
   for (const FuseOp &op : p->fuse_ops)
     if (op.kind == DK_X || op.kind == DK_Z) return false;
   const size_t nm = std::max<size_t>(p->n_meas, 1);
-  std::vector<int> outc(nm, 0), fold(3 * nm, 0);
-  std::vector<float2> coef(nm, make_float2(1.f, 0.f));
-  auto sig = [&](SigRef r) {
-    int v = 0;
-    for (int k = 0; k < r.len; ++k) v ^= outc[p->s_dom[r.off + k]];
-    return v & 1;
-  };
-  for (const owqs_pattern::SStep &x : p->s_steps) {
-    if (x.kind != S_J) continue;
-    const int o = p->uniforms[x.m] <= 0.5 ? 0 : 1;
-    const double theta = (sig(x.s) ? -x.alpha : x.alpha) + (sig(x.t) ? M_PI : 0.0);  // Eq. 2
-    double cr = std::cos(theta), ci = -std::sin(theta);                                // Eqs. 11-12
-    if (o) { cr = -cr; ci = -ci; }
-    outc[x.m] = o;
-    coef[x.m] = make_float2((float)cr, (float)ci);
-    int i0 = 0, s0 = 1, s1 = 1;
-    for (int k = 0; k < x.fold_len; ++k) {
-      const FoldRef &f = p->s_folds[x.fold_off + k];
-      if (!sig(f.sig)) continue;
-      if (f.x) {
-        i0 ^= 1;
-        std::swap(s0, s1);
-      } else {
-        s1 = -s1;
-      }
-    }
-    fold[3 * x.m] = i0;
-    fold[3 * x.m + 1] = s0 < 0;
-    fold[3 * x.m + 2] = s1 < 0;
-  }
+  // each window's row in the tile-pass command table (its coefficient and
+  // folds are written there by the resolving kernel)
+  std::vector<int> fop_of(std::max<size_t>(p->n_meas, 1), -1);
+  for (size_t i = 0; i < p->fuse_ops.size(); ++i)
+    if (p->fuse_ops[i].kind == DK_J) fop_of[p->fuse_ops[i].m_index] = (int)i;
+  std::vector<DrawWin> wins;
+  for (const owqs_pattern::SStep &x : p->s_steps)
+    if (x.kind == S_J) wins.push_back(DrawWin{x.alpha, x.s, x.t, x.m, x.fold_off, x.fold_len, fop_of[x.m]});
   hipError_t e = hipSuccess;
   const size_t cbytes = (nm * sizeof(float2) + 255) & ~size_t(255);
-  const size_t need = cbytes + 3 * nm * sizeof(int);
+  const size_t fbytes = (3 * nm * sizeof(int) + 255) & ~size_t(255);
+  const size_t need = cbytes + fbytes + std::max<size_t>(wins.size(), 1) * sizeof(DrawWin);
   if (p->a_cap < need) {
     if (p->a_mem) {
       (void)hipDeviceSynchronize();
@@ -285,21 +266,30 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
     if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
     p->a_mem = nullptr;
     p->a_cap = 0;
+    p->a_wins_valid = false;
     e = hipMalloc(&p->a_mem, need);
     if (e != hipSuccess) { st = fail(p->ctx, OWQS_E_NOMEM, "drawn-window tables"); return true; }
     p->a_cap = need;
   }
   float2 *ctab = static_cast<float2 *>(p->a_mem);
   int *ftab = reinterpret_cast<int *>(static_cast<char *>(p->a_mem) + cbytes);
-  // synchronous: the previous run may still read the tables
-  e = hipStreamSynchronize(s);
-  if (e == hipSuccess) e = hipMemcpy(ctab, coef.data(), nm * sizeof(float2), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ftab, fold.data(), 3 * nm * sizeof(int), hipMemcpyHostToDevice);
-  if (e == hipSuccess && p->n_meas)
-    e = hipMemcpy(sample_mem(p).outc, outc.data(), p->n_meas * sizeof(int), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { st = hip_fail(p->ctx, e, "drawn-window tables"); return true; }
-  st = upload_fuse(p);
+  DrawWin *dwins = reinterpret_cast<DrawWin *>(static_cast<char *>(p->a_mem) + cbytes + fbytes);
+  if (!p->a_wins_valid) {
+    // once per plan (synchronous: a run in flight may still read the table)
+    if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
+    if (p->a_graph) { (void)hipGraphDestroy(p->a_graph); p->a_graph = nullptr; }
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !wins.empty())
+      e = hipMemcpy(dwins, wins.data(), wins.size() * sizeof(DrawWin), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { st = hip_fail(p->ctx, e, "drawn-window table"); return true; }
+    p->a_wins_valid = true;
+  }
+  const SampleMem sm = sample_mem(p);
+  // the window rows are rewritten by every drawn run (no upload per run); a
+  // forced run uploads the table again
+  if (!p->dev_fuse_valid) st = upload_fuse(p);
   if (st != OWQS_OK) return true;
+  p->fuse_patched = true;
   end_ranged(p);
   const size_t nin = p->inputs.size();
   e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
@@ -315,7 +305,11 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
       }
       e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) { st = hip_fail(p->ctx, e, "begin capture"); return true; }
-      hipError_t le = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, p->cap_stream, nullptr, ctab, ftab);
+      hipError_t le = launch_s_resolve(dwins, (int)wins.size(), sm.u, sm.dom, sm.folds, sm.outc, ctab, ftab,
+                                       p->dev_fuse, p->cap_stream);
+      if (le == hipSuccess)
+        le = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, p->cap_stream, nullptr, ctab, ftab,
+                          nullptr, nullptr, true);
       e = hipStreamEndCapture(p->cap_stream, &p->a_graph);
       if (le != hipSuccess) e = le;
       if (e == hipSuccess) e = hipGraphInstantiate(&p->a_exec, p->a_graph, nullptr, nullptr, 0);
@@ -328,7 +322,10 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
     }
     e = hipGraphLaunch(p->a_exec, s);
   } else {
-    e = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, s, nullptr, ctab, ftab);
+    e = launch_s_resolve(dwins, (int)wins.size(), sm.u, sm.dom, sm.folds, sm.outc, ctab, ftab, p->dev_fuse, s);
+    if (e == hipSuccess)
+      e = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, s, nullptr, ctab, ftab, nullptr, nullptr,
+                       true);
   }
   if (e != hipSuccess) { st = hip_fail(p->ctx, e, "kernel launch"); return true; }
   p->ran = true;
@@ -368,6 +365,7 @@ owqs_status run_sampled(owqs_pattern *p, const void *input, size_t n_amps, int i
     if (e != hipSuccess) return fail(p->ctx, OWQS_E_NOMEM, "sampling tables");
     p->s_cap = need;
     p->s_uploaded = false;
+    p->a_wins_valid = false;  // the drawn-window graph reads these tables
     if (p->s_exec) { (void)hipGraphExecDestroy(p->s_exec); p->s_exec = nullptr; }
     if (p->s_graph) { (void)hipGraphDestroy(p->s_graph); p->s_graph = nullptr; }
   }

@@ -124,9 +124,10 @@ def test_sampling_state_rules(ctx):
 @pytest.mark.parametrize("nl,nj,ncz", [(6, 60, 12), (17, 80, 16)])
 def test_drawn_windows_on_the_fused_plan(ctx, nl, nj, ncz):
     """Every M of a J/CZ circuit is a window with p = 1/2, so with the fused
-    executors the outcomes are resolved on the host and the fused plan (tile
-    passes at width 17) runs with per-run coefficient and fold tables; the
-    plain executor draws on the device.  Both give the oracle's outcome
+    executors one device kernel resolves every outcome, coefficient and
+    folded correction from the uniforms and the fused plan (tile passes at
+    width 17) runs with those tables, all in one graph; the plain executor
+    draws window by window on the device.  Both give the oracle's outcome
     string and output, on two draws in a row."""
     g = np.random.default_rng(nl)
     pat = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, nj, ncz, g))
@@ -164,4 +165,33 @@ def test_long_runs_of_drawn_windows(ctx, exec_):
     assert float(np.max(np.abs(got - want))) <= AMP_TOL
     assert abs(np.linalg.norm(got) - 1) <= 1e-5
     np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+    p.close()
+
+
+def test_fused_drawn_plan_replays_with_new_uniforms(ctx, parity_report):
+    """The fused drawn plan (tile passes at width 18) is captured once and
+    replayed with a new set of uniforms before every run, with unrelated
+    eager work in between; every replay gives the oracle's outcomes,
+    output and probabilities for its uniforms."""
+    g = np.random.default_rng(1818)
+    nl = 18
+    pat = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, 90, 14, g))
+    inp = W.gaussian_state(nl, g)
+    x = torch.as_tensor(inp).cuda()
+    p = owqs.Pattern(ctx, pat)
+    p.set_exec(owqs.EXEC_FUSED)
+    worst = 0.0
+    for draw in range(4):
+        u, want, pw, ow = safe_uniforms(pat, inp, g)
+        p.set_uniforms(u)
+        junk = torch.randn(1 << 18, device="cuda").cumsum(0)   # unrelated eager work
+        p.run(x)
+        got = p.read_state().cpu().numpy().astype(np.complex128)
+        assert np.array_equal(p.read_outcomes(), ow), draw
+        err = float(np.max(np.abs(got - want)))
+        worst = max(worst, err)
+        assert err <= AMP_TOL, (draw, err)
+        np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+        del junk
+    parity_report("drawn_fused_replays_width18", max_amp_err=worst)
     p.close()
