@@ -669,6 +669,9 @@ def main():
                     help="skip the extra event-timed step (for counter collection runs)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one short run at full width, few dispatches: for rocprofv3 --pmc passes")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="only the batched leg (512 patterns, one graph per call, 3 calls after a warm-up): for "
+                         "rocprofv3 kernel traces of the batch")
     ap.add_argument("--tile-probe", action="store_true",
                     help="one fused run of the large workload at tile bits 12 (40 tile passes): for rocprofv3 "
                          "--pmc passes over the tile kernel")
@@ -680,6 +683,13 @@ def main():
         return
     if args.tile_probe:
         tile_probe()
+        return
+    if args.batch_probe:
+        import torch
+        import owqs_workloads as W
+        import paper_1604_05659_amd as owqs
+        ctx = owqs.Context(0)
+        print(json.dumps({"batch_probe": bench_batched(owqs, torch, W, ctx, 3)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a pattern on a single MI355X "
