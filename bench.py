@@ -199,7 +199,8 @@ def bench_batched(owqs, torch, W, ctx, steps):
         outs.append(torch.empty(1 << len(wl.pattern.outputs), dtype=torch.complex64, device="cuda"))
     n_cmds = sum(len(wl.pattern.cmds) for wl in wls)
     widths = [p.plan_info()[0] for p in pats]
-    # batched
+    # batched: the tile size of the wide plans picked for the batch
+    tile_bits, _ = owqs.tune_batch(ctx, pats, ins, outs)
     owqs.run_batch(ctx, pats, ins, outs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -243,6 +244,7 @@ def bench_batched(owqs, torch, W, ctx, steps):
         "patterns": len(pats),
         "commands": n_cmds,
         "lds_resident": int(sum(w <= 14 for w in widths)),
+        "tile_bits": tile_bits,
         "batched_patterns_per_s": round(len(pats) / t_batch, 1),
         "batched_ms": round(1e3 * t_batch, 3),
         "sequential_patterns_per_s": round(len(pats) / t_seq, 1),

@@ -225,6 +225,18 @@ owqs_status owqs_set_tile_bits(owqs_pattern *pat, int32_t bits);
 owqs_status owqs_tune(owqs_pattern *pat, const void *input_c64, size_t n_amps, int input_on_device,
                       void *stream, int32_t *best_bits, float *best_ms);
 
+/* Autotuner for a batch (owqs_run_batch with the same arguments): time the
+ * whole batch (3 calls after a warm-up, HIP events on `stream`) with every
+ * tile size 10..13 given to all of its patterns whose plans have tile passes
+ * (plan width above 14, executor not PLAIN), and keep the fastest on each of
+ * them (owqs_set_tile_bits).  In a batch the passes of many patterns share a
+ * launch, so the best size is often larger than the one a pattern run alone
+ * prefers.  Without such patterns it returns at once with *best_bits = 0 and
+ * *best_ms = 0.  The runs write the outputs.  Either output pointer may be
+ * NULL. */
+owqs_status owqs_tune_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat, const void *const *inputs,
+                            void *const *outputs, void *stream, int32_t *best_bits, float *best_ms);
+
 /* Compile the plan for the current settings (if needed) and report the
  * largest live width it reaches (plain plans: max_live; fused windows keep
  * the width of the window's input), its number of steps (one per

@@ -98,6 +98,8 @@ _sig = {
     "owqs_run_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     "owqs_run_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
                                       ctypes.POINTER(_vp), _vp]),
+    "owqs_tune_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_size_t, ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_vp), _vp, _i32p, ctypes.POINTER(ctypes.c_float)]),
     "owqs_adjoint": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, _i32p,
                                     ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp]),
     "owqs_pattern_commands": (ctypes.c_int, [_vp, ctypes.POINTER(OwqsCmd), ctypes.c_size_t, _i32p, ctypes.c_size_t,
@@ -571,6 +573,19 @@ class Pattern:
             self.close()
         except Exception:
             pass
+
+
+def tune_batch(ctx: Context, patterns: Sequence["Pattern"], inputs, outputs, stream=None):
+    """owqs_tune_batch: the fastest tile size for a batch; returns (bits, ms per call)."""
+    n = len(patterns)
+    ph = (_vp * max(n, 1))(*[p._h for p in patterns])
+    ih = (_vp * max(n, 1))(*[None if x is None else x.data_ptr() for x in inputs])
+    oh = (_vp * max(n, 1))(*[o.data_ptr() for o in outputs])
+    bits = ctypes.c_int32(0)
+    ms = ctypes.c_float(0.0)
+    ctx.check(_lib.owqs_tune_batch(ctx._h, ph, n, ih, oh, _stream_handle(stream), ctypes.byref(bits),
+                                   ctypes.byref(ms)))
+    return int(bits.value), float(ms.value)
 
 
 def run_batch(ctx: Context, patterns: Sequence["Pattern"], inputs, outputs, stream=None):

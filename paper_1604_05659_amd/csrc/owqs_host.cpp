@@ -1421,6 +1421,65 @@ owqs_status owqs_tune(owqs_pattern *p, const void *input, size_t n_amps, int inp
   return OWQS_OK;
 }
 
+owqs_status owqs_tune_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat, const void *const *inputs,
+                            void *const *outputs, void *stream, int32_t *best_bits, float *best_ms) {
+  if (!ctx || (npat && (!pats || !outputs))) return fail(ctx, OWQS_E_INVALID_ARG, "null argument");
+  if (ctx->device < 0) return fail(ctx, OWQS_E_STATE, "host-only context");
+  // the patterns whose plans have tile passes in a batch (plan width > 14)
+  std::vector<owqs_pattern *> wide;
+  std::vector<int> keep;
+  for (size_t i = 0; i < npat; ++i) {
+    owqs_pattern *p = pats[i];
+    if (!p || p->ctx != ctx) return fail(ctx, OWQS_E_INVALID_ARG, "pattern " + std::to_string(i));
+    if (substates(p)) return refuse_substates(p, "owqs_tune_batch");
+    if (owqs_status w = width_guard(p)) return w;
+    if (p->dirty) compile(p);
+    if (p->plan_width > kLdsMaxWidth && p->exec != OWQS_EXEC_PLAIN) {
+      wide.push_back(p);
+      keep.push_back(p->tile_bits);
+    }
+  }
+  if (wide.empty()) {
+    if (best_bits) *best_bits = 0;
+    if (best_ms) *best_ms = 0.f;
+    return OWQS_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(ctx, e, "tune events");
+  int best = -1;
+  float best_t = 0.f;
+  owqs_status st = OWQS_OK;
+  for (int bits = 10; bits <= kMaxTileBits && st == OWQS_OK && e == hipSuccess; ++bits) {
+    for (owqs_pattern *p : wide) owqs_set_tile_bits(p, bits);
+    st = owqs_run_batch(ctx, pats, npat, inputs, outputs, stream);  // compile, capture, warm up
+    if (st != OWQS_OK) break;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && st == OWQS_OK && e == hipSuccess; ++r)
+      st = owqs_run_batch(ctx, pats, npat, inputs, outputs, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess && st == OWQS_OK && (best < 0 || t < best_t)) {
+      best_t = t;
+      best = bits;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != OWQS_OK || e != hipSuccess) {
+    for (size_t k = 0; k < wide.size(); ++k) owqs_set_tile_bits(wide[k], keep[k]);
+    return st != OWQS_OK ? st : hip_fail(ctx, e, "tune");
+  }
+  for (owqs_pattern *p : wide) owqs_set_tile_bits(p, best);
+  if (best_bits) *best_bits = best;
+  if (best_ms) *best_ms = best_t / 3.f;
+  return OWQS_OK;
+}
+
 owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps, size_t *npasses) {
   if (!p) return OWQS_E_INVALID_ARG;
   if (owqs_status w = width_guard(p)) return w;

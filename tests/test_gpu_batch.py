@@ -187,3 +187,28 @@ def test_graph_replay_matches_eager(ctx):
         want, _ = oc.run(wl.pattern, other, wl.input_state.astype(np.complex128))
         np.testing.assert_allclose(got, want, atol=AMP_TOL)
         p.close()
+
+
+def test_tune_batch_keeps_results(ctx):
+    """owqs_tune_batch times the batch at every tile size and keeps the
+    fastest on the wide patterns; the batch then still gives the oracle's
+    outputs and probabilities."""
+    wls = [W.batched_random(i, w_lo=12, w_hi=19, c_lo=40, c_hi=200) for i in range(24)]
+    pats, ins, outs = [], [], []
+    for wl in wls:
+        p = _load(ctx, wl.pattern, wl.outcomes)
+        pats.append(p)
+        ins.append(torch.as_tensor(wl.input_state).cuda())
+        outs.append(torch.empty(1 << len(wl.pattern.outputs), dtype=torch.complex64, device="cuda"))
+    assert max(p.plan_info()[0] for p in pats) > 14
+    bits, ms = owqs.tune_batch(ctx, pats, ins, outs)
+    assert 10 <= bits <= 13 and ms > 0.0
+    owqs.run_batch(ctx, pats, ins, outs)
+    torch.cuda.synchronize()
+    for wl, p, o in zip(wls, pats, outs):
+        p.check()
+        want, pw = oc.run(wl.pattern, wl.outcomes, wl.input_state.astype(np.complex128))
+        np.testing.assert_allclose(o.cpu().numpy().astype(np.complex128), want, atol=AMP_TOL)
+        np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+    for p in pats:
+        p.close()
