@@ -128,24 +128,13 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
   // keep it in range down to p ~ 1e-4 per window; windows with p = 1/2
   // exactly (an odd E(v, w) count) keep the norm, so a pass of only those
   // (and EOWQS, which computes no norm) may hold kMaxGroupWindows.  With
-  // big_half (OWQS), a pass of only such windows that mark_half will run
-  // without a reduction may hold kMaxHalfWindows: `run` follows mark_half's
-  // count of such windows since the last reduction, step by step.
-  int run = 0;
-  auto win_cap = [mode, big_half, &run](bool even) {
+  // big_half (OWQS), a pass of only such windows runs without window sums
+  // (mark_half makes it half, at most renormalising its output), so it may
+  // hold kMaxHalfWindows.
+  auto win_cap = [mode, big_half](bool even) {
     if (mode == OWQS_MODE_EOWQS) return kMaxGroupWindows;
     if (even) return 16;
-    return big_half && run + kMaxHalfWindows <= kHalfRun ? kMaxHalfWindows : kMaxGroupWindows;
-  };
-  auto follow = [&run](const Step &x, const TileGroup *tg) {  // mark_half's rule
-    if (tg) {
-      if (tg->ta.nwin == 0) return;
-      run = tg->half && run + tg->ta.nwin <= kHalfRun ? run + tg->ta.nwin : 0;
-    } else if (x.kind == S_M) {
-      run = 0;
-    } else if (x.kind == S_J) {
-      run = !x.win.vw_even && run + 1 <= kHalfRun ? run + 1 : 0;
-    }
+    return big_half ? kMaxHalfWindows : kMaxGroupWindows;
   };
   auto groupable = [](int k) { return k == S_J || k == S_E || k == S_X || k == S_Z; };
   std::vector<char> done(ns, 0);
@@ -157,7 +146,6 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     const Step &x0 = steps[i];
     if (!groupable(x0.kind) || x0.n < kTileMinWidth) {
       out.push_back(x0);
-      follow(x0, nullptr);
       done[i] = 1;
       continue;
     }
@@ -200,7 +188,6 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     }
     if (taken.size() < 2) {
       out.push_back(x0);
-      follow(x0, nullptr);
       done[i] = 1;
       continue;
     }
@@ -285,7 +272,6 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     gs.group = (int)groups.size();
     groups.push_back(tg);
     out.push_back(gs);
-    follow(gs, &groups.back());
   }
 }
 
@@ -706,22 +692,60 @@ double rounded_factor(double h, double &e) {
 
 // What the FP32 arithmetic of a window leaves in |psi|^2 beyond its factor
 // (the rounding of the coefficient, at most a few 1e-8 per window) would
-// still add up over a long run without reductions, so at most kHalfRun such
-// windows follow each other: the window or group that would exceed it
-// reduces (and renormalises) as usual.  Groups are taken whole.
+// still add up over a long run without reductions, so at most cap such
+// windows pass between two renormalisations.  When the next window or group
+// would exceed cap, the last tile group of the run so far sums the norm of
+// its output (renorm: sigma is reset from it, its windows still record
+// p = 1/2 without sums) and the run restarts after it; with no such group
+// to take it, a single window reduces as usual and a group renormalises its
+// own output.  cap = 0: every window and group reduces.
 void mark_half(std::vector<Step> &xs, std::vector<TileGroup> &groups, int cap) {
-  int run = 0;
+  int run = 0;     // windows with p = 1/2 since the last renormalisation
+  int last = -1;   // the run's last half group, which may still take the renormalisation
+  int after = 0;   // windows of the run after that group
+  auto restart = [&] {
+    run = 0;
+    last = -1;
+    after = 0;
+  };
+  auto make_room = [&](int need) {
+    if (run + need > cap && last >= 0) {
+      groups[size_t(last)].renorm = true;
+      run = after;
+      last = -1;
+      after = 0;
+    }
+  };
+  for (TileGroup &tg : groups) tg.renorm = false;
   for (Step &x : xs) {
     if (x.kind == S_M) {
-      run = 0;
+      restart();
     } else if (x.kind == S_J) {
+      if (!x.win.vw_even) make_room(1);
       x.half = !x.win.vw_even && run + 1 <= cap;
-      run = x.half ? run + 1 : 0;
+      if (x.half) {
+        ++run;
+        ++after;
+      } else {
+        restart();
+      }
     } else if (x.kind == S_F) {
       TileGroup &tg = groups[x.group];
       if (tg.ta.nwin == 0) continue;  // no norm changes, no reduction
-      tg.half = tg.half && run + tg.ta.nwin <= cap;
-      run = tg.half ? run + tg.ta.nwin : 0;
+      tg.half = tg.half && cap > 0;
+      if (!tg.half) {
+        restart();
+        continue;
+      }
+      make_room(tg.ta.nwin);
+      if (run + tg.ta.nwin > cap) {
+        tg.renorm = true;
+        restart();
+      } else {
+        run += tg.ta.nwin;
+        last = x.group;
+        after = 0;
+      }
     }
   }
 }
@@ -772,6 +796,7 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
         if (reduce == kReduceRenorm && tg.half) {  // every window has p = 1/2 exactly
           a.reduce = kReduceNone;
           ta.half_m = fuse_m_dev(p) + tg.m_off;
+          ta.renorm = tg.renorm ? 1 : 0;
         }
         e = launch_tile(psi, ta, ops, a, s, &grid);
         break;
@@ -782,7 +807,8 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
     if ((x.kind == S_M || x.kind == S_J) && e == hipSuccess) e = launch_finish(a, grid, s);
     if (x.kind == S_F && e == hipSuccess) {
       const TileGroup &tg = p->groups[x.group];
-      e = launch_finish_group(a, fuse_m_dev(p) + tg.m_off, tg.ta.nwin, grid, s);
+      if (reduce == kReduceRenorm && tg.half && tg.renorm) e = launch_finish_renorm(a.book, grid, s);
+      else e = launch_finish_group(a, fuse_m_dev(p) + tg.m_off, tg.ta.nwin, grid, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
   }
@@ -996,8 +1022,10 @@ owqs_status run_impl(owqs_pattern *p, const void *input, size_t n_amps, int inpu
       prof->counts[k] += 1;
       prof->ms[k] += t;
       prof->bytes[k] += step_bytes(p->xsteps[i]);
+      // a half group without renorm launches no finishing kernel
       const bool half = half_prob(p->xsteps[i], reduce) ||
-                        (k == S_F && reduce == kReduceRenorm && p->groups[p->xsteps[i].group].half);
+                        (k == S_F && reduce == kReduceRenorm && p->groups[p->xsteps[i].group].half &&
+                         !p->groups[p->xsteps[i].group].renorm);
       if ((k == S_M || k == S_J || k == S_F) && reduce != kReduceNone && !half) {
         prof->counts[OWQS_KIND_FINISH] += 1;
         prof->ms[OWQS_KIND_FINISH] += f;
@@ -1735,7 +1763,9 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
             m.sigma = p->book.sigma;
             m.probs = p->book.probs;
             m.ta = tg.ta;
+            const bool renorm = r == kReduceNone && reduce == kReduceRenorm && tg.renorm;
             if (r == kReduceNone && reduce == kReduceRenorm) m.ta.half_m = fuse_m_dev(p) + tg.m_off;
+            m.ta.renorm = renorm ? 1 : 0;
             m.reduce = r;
             Bucket *bk = nullptr;
             const bool red = r != kReduceNone;
@@ -1748,13 +1778,14 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
             m.first_tile = bk->total;
             bk->total += uint32_t(ntiles);
             bk->ents.push_back(m);
-            if (r != kReduceNone && tg.ta.nwin > 0) {
+            if ((r != kReduceNone || renorm) && tg.ta.nwin > 0) {
               MultiFinish f{};
               f.book = p->book;
               f.m_of_window = fuse_m_dev(p) + tg.m_off;
-              f.nwin = tg.ta.nwin;
+              f.nwin = renorm ? 1 : tg.ta.nwin;
               f.reduce = r;
               f.ntiles = uint32_t(ntiles);
+              f.renorm = renorm ? 1 : 0;
               L.fins.push_back(f);
               L.maxwin = std::max(L.maxwin, f.nwin);
             }

@@ -69,6 +69,7 @@ struct TileGroup {
   size_t m_off;   // first window's measurement index in the pattern's m table
   bool half;      // OWQS mode: it has windows, each with an odd E(v, w) count (p = 1/2 exactly), and
                   // runs without a reduction (mark_half)
+  bool renorm;    // half, and it ends a run of such windows: its output norm resets sigma (mark_half)
 };
 
 // Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's

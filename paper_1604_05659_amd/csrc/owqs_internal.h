@@ -131,6 +131,10 @@ struct TileArgs {
   int nsets;
   int n, k, nops, nwin;
   int runs;          // 1: some consecutive unmasked windows run in registers (see k_tile)
+  // 1 (set per launch): the pass sums the squared norm of its output into
+  // partials (k_tile: one per block; k_tile_multi: one per tile), from which
+  // k_finish_renorm / k_finish_multi reset sigma
+  int renorm;
   uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
 };
@@ -156,7 +160,7 @@ struct MultiFinish {
   int nwin;
   int reduce;
   uint32_t ntiles;         // partials per window
-  uint32_t pad;
+  int renorm;              // 1: the group's output norm resets sigma (nwin = 1, one partial per tile)
 };
 
 // Start and read-out of one pattern of a batched run.
@@ -252,6 +256,8 @@ hipError_t launch_b_reduce(const double *partials, int nq, int nsets, int nblk, 
 // block count, which launch_finish_group needs to reduce the partials.
 hipError_t launch_tile(float2 *psi, const TileArgs &ta, const FuseOp *ops, const MeasureArgs &a, hipStream_t s,
                        unsigned *grid);
+// sigma = 1 / sqrt(sum of partials[0 .. nblk)) after a pass with TileArgs::renorm.
+hipError_t launch_finish_renorm(const DevBook &book, unsigned nblk, hipStream_t s);
 hipError_t launch_finish_group(const MeasureArgs &a, const int *m_of_window, int nwin, unsigned nblk,
                                hipStream_t s);
 // Raise k_tile's dynamic LDS limit to 64 KiB; call outside stream capture.

@@ -449,13 +449,14 @@ __device__ __forceinline__ void tile_high_bits(uint64_t tmask, uint64_t *hp) {
 
 // One tile of a group (tile t of the 2^(n-k)): load it into LDS, apply the
 // group's commands, store it back.  With `reduce`, every window adds its
-// norm per wave into wacc (FP64 from each thread's sum of squares on).  g_tid and hp
-// hold the thread's part of the global index and the global bits of the tile
-// bits above the thread index (see k_tile).
+// norm per wave into wacc (FP64 from each thread's sum of squares on); with
+// ta.renorm, the squared norm of the stored tile is added per wave into
+// rn.  g_tid and hp hold the thread's part of the global index and the
+// global bits of the tile bits above the thread index (see k_tile).
 template <int kTB, bool kRuns, bool kRed>
 __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArgs &ta, const FuseOp *__restrict__ ops,
                                          double sg, uint64_t t, uint64_t g_tid, const uint64_t *hp, float2 *tile,
-                                         double (*wacc)[tile_threads(kTB) / 64]) {
+                                         double (*wacc)[tile_threads(kTB) / 64], double *rn) {
   constexpr bool reduce = kRed;  // a compile-time variant: the FP64 sums cost registers
   constexpr int kT = tile_threads(kTB);
   constexpr int kLogT = log2_threads(kT);
@@ -571,6 +572,13 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
     float2 v[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) v[r] = tile[tid + r * kT];
+    if (ta.renorm) {  // uniform: the group's output norm resets sigma
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kPer; r += 2) acc += nrm2d(v[r], v[r + 1]);
+      const double d = wave_sum_to_last(acc);
+      if (lane == 63) rn[wave] += d;
+    }
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       uint64_t g = gb;
@@ -600,10 +608,12 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
   constexpr int kHi = kTB - log2_threads(kT);  // tile bits above the thread index
   extern __shared__ float2 tile[];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
+  __shared__ double rn[kT / 64];
   const uint32_t tid = threadIdx.x;
   constexpr bool reduce = kRed;  // ma.reduce != kReduceNone
   if (reduce)
     for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
+  if (tid < kT / 64) rn[tid] = 0.0;  // read after the barriers of tile_one
   const double sg = (ma.reduce == kReduceRenorm) ? *ma.book.sigma : 1.0;
   const uint64_t g_tid = pdep64(tid, ta.tmask);
   uint64_t hp[kHi];
@@ -613,7 +623,12 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
     for (int i = tid; i < ta.nwin; i += kT) ma.book.probs[ta.half_m[i]] = 0.5;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-    tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc);
+    tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc, rn);
+  if (ta.renorm && tid == 0) {  // the block's share of the output norm (tile_one ends with a barrier)
+    double sum = 0.0;
+    for (int k = 0; k < kT / 64; ++k) sum += rn[k];
+    partials[blockIdx.x] = sum;
+  }
   if (reduce) {
     for (int w = tid; w < ta.nwin; w += kT) {
       double s = 0.0;
@@ -660,7 +675,9 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
   constexpr int kHi = kTB - log2_threads(kT);
   extern __shared__ float2 tile[];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
+  __shared__ double rn[kT / 64];
   const uint32_t tid = threadIdx.x;
+  if (tid < kT / 64) rn[tid] = 0.0;  // read after the barriers of tile_one
   for (uint32_t gt = blockIdx.x; gt < total; gt += gridDim.x) {
     int lo = 0, hi = nent - 1;
     while (lo < hi) {
@@ -679,7 +696,15 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
     tile_high_bits<kTB>(e.ta.tmask, hp);
     if (e.ta.half_m && t == 0)  // windows with p = 1/2 exactly
       for (int i = tid; i < e.ta.nwin; i += kT) e.probs[e.ta.half_m[i]] = 0.5;
-    tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc);
+    tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc, rn);
+    if (e.ta.renorm && tid == 0) {  // the tile's output norm; rn starts again at 0 for the next tile
+      double sum = 0.0;
+      for (int k = 0; k < kT / 64; ++k) {
+        sum += rn[k];
+        rn[k] = 0.0;
+      }
+      e.partials[t] = sum;
+    }
     if (reduce) {
       const uint64_t ntiles = uint64_t(1) << (e.ta.n - kTB);
       for (int w = tid; w < e.ta.nwin; w += kT) {
@@ -888,12 +913,26 @@ __global__ __launch_bounds__(kTT) void k_finish_group(DevBook book, const int *_
   if (reduce == kReduceRenorm && g == nwin - 1) *book.sigma = n > 1e-300 ? 1.0 / sqrt(n) : 0.0;
 }
 
+// After a group whose windows all have p = 1/2 and which ends a run of
+// them (TileArgs::renorm): sigma = 1 / sqrt(n), n the squared norm of the
+// group's output summed from the per-block partials in block order.
+__global__ __launch_bounds__(kTT) void k_finish_renorm(DevBook book, unsigned nblk) {
+  const double n = sum_partials(book.partials, nblk);
+  if (threadIdx.x == 0) *book.sigma = n > 1e-300 ? 1.0 / sqrt(n) : 0.0;
+}
+
 // The group finish of many patterns at once: block (g, e) does for window
-// g of entry e what k_finish_group does, with the entry's per-tile partials.
+// g of entry e what k_finish_group does, with the entry's per-tile partials
+// (an entry with renorm: block (0, e) does what k_finish_renorm does).
 __global__ __launch_bounds__(kTT) void k_finish_multi(const MultiFinish *__restrict__ fins) {
   const MultiFinish f = load_row(fins, blockIdx.y);
   const int g = blockIdx.x;
   if (g >= f.nwin) return;  // uniform over the block
+  if (f.renorm) {
+    const double n = sum_partials(f.book.partials, f.ntiles);
+    if (threadIdx.x == 0) *f.book.sigma = n > 1e-300 ? 1.0 / sqrt(n) : 0.0;
+    return;
+  }
   const double n = sum_partials(f.book.partials + size_t(g) * f.ntiles, f.ntiles);
   const double prev = g > 0 ? sum_partials(f.book.partials + size_t(g - 1) * f.ntiles, f.ntiles) : 1.0;
   if (threadIdx.x != 0) return;
@@ -1053,6 +1092,12 @@ hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, in
 hipError_t launch_finish_multi(const MultiFinish *fins, int nfin, int maxwin, hipStream_t s) {
   if (nfin <= 0 || maxwin <= 0) return hipGetLastError();
   hipLaunchKernelGGL(k_finish_multi, dim3(unsigned(maxwin), unsigned(nfin)), dim3(kTT), 0, s, fins);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_renorm(const DevBook &book, unsigned nblk, hipStream_t s) {
+  if (nblk == 0 || nblk > kTileGridCap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finish_renorm, dim3(1), dim3(kTT), 0, s, book, nblk);
   return hipGetLastError();
 }
 

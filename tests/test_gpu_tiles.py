@@ -232,6 +232,67 @@ def test_half_probability_windows(ctx, n, kind, graph):
     p.close()
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_half_windows_renormalise_long_runs(ctx, graph):
+    """OWQS mode, 600 windows that all have p = 1/2 exactly (odd E(v, w)
+    counts) at width 16: far more than may pass without a renormalisation,
+    so tile passes of them now and then sum the norm of their output alone
+    and reset sigma from it (one finishing kernel each, no window sums).
+    Every probability is exactly 1/2 and the state matches the oracle, on
+    the fused executor, on two runs in a row, in a batched run of two
+    inputs (the multi-pattern tile and finishing kernels), and in the
+    allocation-free run."""
+    g = np.random.default_rng(2401 + graph)
+    pat, odd = odd_even_window_pattern(g, 16, 600, even=False)
+    assert odd.all()
+    outc = g.integers(0, 2, size=pat.n_meas()).astype(np.uint8)
+    inps = [W.gaussian_state(16, g) for _ in range(2)]
+    wants = [oc.run(pat, outc, x.astype(np.complex128), oc.MODE_OWQS) for x in inps]
+    for want, pw in wants:   # 1/2 up to the rounding of the complex64 input
+        np.testing.assert_allclose(pw, 0.5, rtol=0, atol=1e-8)
+    p = owqs.Pattern(ctx, pat)
+    p.set_mode(owqs.MODE_OWQS)
+    p.set_exec(owqs.EXEC_FUSED)
+    p.set_graph(graph)
+    p.set_outcomes(outc)
+    x = torch.as_tensor(inps[0]).cuda()
+    for rep in range(2):
+        p.run(x)
+        got = p.read_state().cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(got - wants[0][0])) <= AMP_TOL, rep
+        assert np.all(p.read_probs() == 0.5), rep
+    prof = p.run_profiled(x)
+    width, nsteps, npasses = p.plan_info()
+    assert width == 16 and npasses < nsteps
+    assert prof["tile(group)"]["launches"] >= 600 // 64
+    # renormalisations happen, far fewer than the passes
+    fin = prof.get("finish(FP64)", {"launches": 0})["launches"]
+    assert 0 < fin < prof["tile(group)"]["launches"]
+    got = p.read_state().cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - wants[0][0])) <= AMP_TOL
+    # a batched run: both inputs through the multi-pattern kernels
+    q = owqs.Pattern(ctx, pat)
+    q.set_mode(owqs.MODE_OWQS)
+    q.set_exec(owqs.EXEC_FUSED)
+    q.set_outcomes(outc)
+    ins = [torch.as_tensor(v).cuda() for v in inps]
+    outs = [torch.empty(1 << 16, dtype=torch.complex64, device="cuda") for _ in inps]
+    owqs.run_batch(ctx, [p, q], ins, outs)
+    torch.cuda.synchronize()
+    for o, (want, _) in zip(outs, wants):
+        assert np.max(np.abs(o.cpu().numpy().astype(np.complex128) - want)) <= AMP_TOL
+    # the allocation-free run of the same plan (uploaded by the runs above)
+    p.run(x)
+    out = torch.empty(1 << 16, dtype=torch.complex64, device="cuda")
+    probs = torch.empty(pat.n_meas(), dtype=torch.float64, device="cuda")
+    p.run_noalloc(x, out, probs)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(out.cpu().numpy().astype(np.complex128) - wants[0][0])) <= AMP_TOL
+    assert np.all(probs.cpu().numpy() == 0.5)
+    p.close()
+    q.close()
+
+
 @pytest.mark.parametrize("n,exec_", [(10, owqs.EXEC_AUTO), (10, owqs.EXEC_FUSED), (16, owqs.EXEC_FUSED),
                                      (16, owqs.EXEC_SUBSTATES)])
 def test_sum_all_sums_every_window(ctx, n, exec_):
