@@ -113,6 +113,129 @@ bool commute_steps(const Step &a, const Step &b) {
   return !(a.kind == S_J && b.kind == S_J && a.win.vw_even && b.win.vw_even);
 }
 
+// Order the commands of a tile group (local bits < k) into rounds over
+// register cubes of tile_cube_bits(k) bits (see k_tile): a round holds
+// windows without local masks on at most that many distinct mixing bits
+// and E / Z on any bits,
+// in an order that keeps every pair of commands that do not commute (a
+// mixing bit of one meets a bit the other mixes or reads) as it was, and,
+// unless free_windows, all windows in their order.  Ready commands are taken
+// first come first served, each round growing while any ready command fits
+// it.  X and masked windows run on their own, and so do E / Z that meet no
+// window of a round.
+struct RoundItem {
+  int op;         // >= 0: a command of the group; -1: a round header; -2: a sweep header
+  int count;      // round header: the entries of the round (they follow it); sweep: its E / Z
+  uint32_t bits;  // round header: the cube's local bits, one per byte, ascending; sweep: its
+                  // window positions (bit p: a window on cube bit p)
+};
+
+std::vector<RoundItem> schedule_rounds(const std::vector<FuseOp> &g, int k, bool free_windows) {
+  const int kc = tile_cube_bits(k);
+  const int n = int(g.size());
+  auto mix = [](const FuseOp &o) -> uint32_t { return (o.kind == DK_J || o.kind == DK_X) ? 1u << o.lb : 0u; };
+  auto diag = [](const FuseOp &o) -> uint32_t {
+    if (o.kind == DK_J) return o.lmask_b | o.lmask_o1;
+    if (o.kind == DK_E || o.kind == DK_Z) return o.lmask_b;
+    return 0u;
+  };
+  // windows with local masks run outside rounds (the single and paired
+  // window paths), like X
+  auto masked = [](const FuseOp &o) { return o.kind == DK_J && (o.lmask_b | o.lmask_o1) != 0; };
+  std::vector<std::vector<int>> pred(static_cast<size_t>(n));
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < j; ++i) {
+      const bool conflict = (mix(g[i]) & (mix(g[j]) | diag(g[j]))) || (mix(g[j]) & (mix(g[i]) | diag(g[i])));
+      if (conflict || (!free_windows && g[i].kind == DK_J && g[j].kind == DK_J)) pred[size_t(j)].push_back(i);
+    }
+  std::vector<char> done(size_t(n), 0);
+  auto ready = [&](int j) {
+    for (int i : pred[size_t(j)])
+      if (!done[size_t(i)]) return false;
+    return true;
+  };
+  std::vector<RoundItem> out;
+  int left = n;
+  while (left > 0) {
+    int i0 = 0;
+    while (done[size_t(i0)] || !ready(i0)) ++i0;
+    if (g[size_t(i0)].kind == DK_X || masked(g[size_t(i0)])) {
+      out.push_back(RoundItem{i0, 0, 0});
+      done[size_t(i0)] = 1;
+      --left;
+      continue;
+    }
+    uint32_t S = 0;
+    std::vector<int> rnd;
+    for (bool grew = true; grew;) {
+      grew = false;
+      for (int j = 0; j < n && !grew; ++j) {
+        if (done[size_t(j)] || g[size_t(j)].kind == DK_X || masked(g[size_t(j)]) || !ready(j)) continue;
+        const uint32_t m = mix(g[size_t(j)]);
+        if (m && !(S & m) && __builtin_popcount(S) == kc) continue;
+        S |= m;
+        rnd.push_back(j);
+        done[size_t(j)] = 1;
+        --left;
+        grew = true;
+      }
+    }
+    if (S == 0) {  // E / Z only: each runs on its own
+      for (int j : rnd) out.push_back(RoundItem{j, 0, 0});
+      continue;
+    }
+    // fill the cube with the highest free bits: lanes then run over the low
+    // bits, which keeps the LDS accesses of a cube free of bank conflicts
+    for (int b = k - 1; __builtin_popcount(S) < kc && b >= 0; --b) S |= 1u << b;
+    uint32_t bits = 0;
+    int pos_of[32];
+    for (int b = 0, i = 0; b < k; ++b)
+      if (S & (1u << b)) {
+        pos_of[b] = i;
+        bits |= uint32_t(b) << (8 * i++);
+      }
+    // the round as sweeps: each applies its E / Z, then at most one window
+    // per cube position in position order (a fixed code path per position);
+    // every command goes to the first sweep after the commands it depends on
+    struct Sweep {
+      std::vector<int> diag;
+      int win[4] = {-1, -1, -1, -1};
+    };
+    std::vector<Sweep> sweeps;
+    std::vector<int> sweep_of(size_t(n), -1), slot_of(size_t(n), -2);  // slot -1: E / Z, else the position
+    for (int j : rnd) {
+      const bool win = g[size_t(j)].kind == DK_J;
+      const int pj = win ? pos_of[g[size_t(j)].lb] : -1;
+      int first = 0;
+      for (int i : pred[size_t(j)]) {
+        if (sweep_of[size_t(i)] < 0) continue;  // done in an earlier round
+        const int si = sweep_of[size_t(i)], slot = slot_of[size_t(i)];
+        const bool before = slot == -1 ? true : (win && slot < pj);  // runs earlier within the same sweep
+        first = std::max(first, before ? si : si + 1);
+      }
+      int sw = first;
+      if (win)
+        while (sw < int(sweeps.size()) && sweeps[size_t(sw)].win[pj] >= 0) ++sw;
+      if (sw >= int(sweeps.size())) sweeps.resize(size_t(sw) + 1);
+      if (win) sweeps[size_t(sw)].win[pj] = j;
+      else sweeps[size_t(sw)].diag.push_back(j);
+      sweep_of[size_t(j)] = sw;
+      slot_of[size_t(j)] = pj;
+    }
+    out.push_back(RoundItem{-1, int(rnd.size() + sweeps.size()), bits});
+    for (const Sweep &w : sweeps) {
+      uint32_t pm = 0;
+      for (int p = 0; p < kc; ++p)
+        if (w.win[p] >= 0) pm |= 1u << p;
+      out.push_back(RoundItem{-2, int(w.diag.size()), pm});
+      for (int j : w.diag) out.push_back(RoundItem{j, 0, 0});
+      for (int p = 0; p < kc; ++p)
+        if (w.win[p] >= 0) out.push_back(RoundItem{w.win[p], 0, 0});
+    }
+  }
+  return out;
+}
+
 // Group runs of window/E/X/Z steps at one width >= kTileMinWidth into tile
 // passes (see owqs_tile.hip).  A pass ends at N or M steps and at a width
 // change; steps whose mixing slot would not fit the tile, or windows beyond
@@ -224,20 +347,18 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     };
     tg.op_off = fops.size();
     tg.m_off = fm.size();
-    int widx = 0;
+    std::vector<FuseOp> gops;
     for (size_t q : taken) {
       const Step &x = steps[q];
       FuseOp op{};
       op.kind = (uint8_t)x.kind;
       if (x.kind == S_J) {
         op.lb = (uint8_t)local_of[x.b0];
-        op.flags = (x.win.swap ? 1 : 0) | (x.win.neg0 ? 2 : 0) | (x.win.neg1 ? 4 : 0) | (x.win.vw_even ? 8 : 0) |
-                   (widx == 0 ? 16 : 0);
-        op.widx = (uint8_t)widx++;
+        op.flags = (x.win.swap ? 1 : 0) | (x.win.neg0 ? 2 : 0) | (x.win.neg1 ? 4 : 0) | (x.win.vw_even ? 8 : 0);
         op.m_index = x.m_index;
-        fm.push_back(x.m_index);
-        op.coef = x.coef;
         op.f = (float)x.host_factor;
+        // the factor times the coefficient (exact product of the two FP32 values, rounded once)
+        op.coef = make_float2(float(double(op.f) * double(x.coef.x)), float(double(op.f) * double(x.coef.y)));
         split(x.win.mask_b, op.lmask_b, op.omask_b);
         split(x.win.mask_o1, op.lmask_o1, op.omask_o1);
       } else if (x.kind == S_X) {
@@ -247,24 +368,62 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
       } else {  // S_Z
         split(uint64_t(1) << x.b0, op.lmask_b, op.omask_b);
       }
+      gops.push_back(op);
+    }
+    // rounds over register cubes; windows keep their order where their
+    // probabilities depend on it (a window with an even E(v, w) count)
+    int widx = 0;
+    for (const RoundItem &it : schedule_rounds(gops, k, !even)) {
+      if (it.op == -1) {  // a round: its entries follow
+        FuseOp h{};
+        h.kind = DK_R;
+        h.m_index = it.count;
+        h.lmask_b = it.bits;
+        fops.push_back(h);
+        continue;
+      }
+      if (it.op == -2) {  // a sweep of the round: its E / Z, then its windows by position
+        FuseOp h{};
+        h.kind = DK_S;
+        h.m_index = it.count;
+        h.flags = uint8_t(it.bits);
+        fops.push_back(h);
+        continue;
+      }
+      FuseOp op = gops[size_t(it.op)];
+      if (op.kind == S_J) {
+        op.flags |= widx == 0 ? 16 : 0;  // the first window to run applies sigma
+        op.widx = (uint8_t)widx++;
+        fm.push_back(op.m_index);
+      }
       fops.push_back(op);
     }
-    tg.ta.nops = (int)taken.size();
+    tg.ta.nops = int(fops.size() - tg.op_off);
     tg.ta.nwin = widx;
-    tg.half = widx > 0;
-    for (size_t q : taken)
-      if (steps[q].kind == S_J && steps[q].win.vw_even) tg.half = false;
+    tg.half = widx > 0 && !even;
     // compile the register runs in only where two windows on different bits
-    // follow each other, possibly with an E or Z between (they cost occupancy
-    // elsewhere)
+    // follow each other outside rounds, possibly with an E or Z between
+    // (they cost occupancy elsewhere)
     tg.ta.runs = 0;
-    for (size_t q = tg.op_off; q + 1 < fops.size(); ++q) {
-      const FuseOp &a = fops[q], &b = fops[q + 1];
-      if (a.kind == S_J && b.kind == S_J && a.lb != b.lb) tg.ta.runs = 1;
-      // a window, an E or Z, a window (the E / Z is applied between them)
-      if (q + 2 < fops.size() && a.kind == S_J && (b.kind == S_E || b.kind == S_Z) &&
-          fops[q + 2].kind == S_J && fops[q + 2].lb != a.lb)
-        tg.ta.runs = 1;
+    {
+      std::vector<const FuseOp *> top;  // the commands outside rounds, in order
+      for (size_t q = tg.op_off; q < fops.size(); ++q) {
+        if (fops[q].kind == DK_R) {
+          top.push_back(nullptr);  // a round separates its neighbours
+          q += size_t(fops[q].m_index);
+          continue;
+        }
+        top.push_back(&fops[q]);
+      }
+      for (size_t q = 0; q + 1 < top.size(); ++q) {
+        const FuseOp *a = top[q], *b = top[q + 1];
+        if (!a || !b) continue;
+        if (a->kind == S_J && b->kind == S_J && a->lb != b->lb) tg.ta.runs = 1;
+        // a window, an E or Z, a window (the E / Z is applied between them)
+        if (q + 2 < top.size() && top[q + 2] && a->kind == S_J && (b->kind == S_E || b->kind == S_Z) &&
+            top[q + 2]->kind == S_J && top[q + 2]->lb != a->lb)
+          tg.ta.runs = 1;
+      }
     }
     Step gs{};
     gs.kind = S_F;

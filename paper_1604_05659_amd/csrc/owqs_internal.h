@@ -83,7 +83,7 @@ __host__ __device__ inline Window window_of(const DevStep &st) {
   return w;
 }
 
-enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5 };
+enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5, DK_R = 6, DK_S = 7 };
 
 // ---- tile fusion (owqs_tile.hip)
 constexpr int kLowBits = 5;            // slots 0..4 are always in a tile (256-byte runs)
@@ -96,17 +96,25 @@ constexpr int kMaxGroupWindows = 32;
 // may hold more windows: the per-window sums only serve groups that reduce.
 constexpr int kMaxHalfWindows = 64;
 constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
+// Threads of a tile pass over 2^k-amplitude tiles, and the bits of the
+// register cube each thread holds in a round (2^k / threads amplitudes).
+constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : tile_bits <= 11 ? 128 : 256; }
+constexpr int tile_cube_bits(int tile_bits) {
+  return tile_bits - (tile_bits >= 13 ? 9 : tile_bits <= 11 ? 7 : 8);
+}
 
 // One command of a fused group, with its slots mapped into the tile.
 struct FuseOp {
-  uint8_t kind;      // DK_J, DK_X, DK_E, DK_Z
+  uint8_t kind;      // DK_J, DK_X, DK_E, DK_Z; DK_R, DK_S: round and sweep headers (see k_tile)
   uint8_t lb;        // J, X: local (tile) bit of the mixing slot
-  uint8_t flags;     // J: bit 0 swap, 1 negate o0, 2 negate o1, 3 vw_even, 4 apply sigma
+  uint8_t flags;     // J: bit 0 swap, 1 negate o0, 2 negate o1, 3 vw_even, 4 apply sigma;
+                     // S: bit p set: the sweep has a window on cube position p
   uint8_t widx;      // J: index of the window inside its group
-  int32_t m_index;   // J: measurement index
-  float2 coef;       // J
+  int32_t m_index;   // J: measurement index; R: entries of the round (they follow it); S: its E / Z
+  float2 coef;       // J: the factor f times the coefficient
   float f;           // J: host factor
-  uint32_t lmask_b;  // J: local bits of mask_b;  E/Z: local bits that must all be 1
+  uint32_t lmask_b;  // J: local bits of mask_b;  E/Z: local bits that must all be 1;
+                     // R: the cube's local bits, one per byte, ascending
   uint32_t lmask_o1; // J: local bits of mask_o1
   uint32_t pad;
   uint64_t omask_b;  // J: outer bits of mask_b;  E/Z: outer bits that must all be 1

@@ -180,7 +180,9 @@ __global__ __launch_bounds__(kB) void k_s_resolve(const DrawWin *__restrict__ wi
   ftab[3 * w.m + 2] = s1 < 0;
   if (w.fop >= 0) {  // vector stores; the next kernel's scalar loads read them after the launch boundary
     FuseOp *op = fops + w.fop;
-    op->coef = make_float2(float(c.x), float(c.y));
+    // the row holds the window's factor times its coefficient (as the host writes it)
+    const double f = double(op->f);
+    op->coef = make_float2(float(f * double(float(c.x))), float(f * double(float(c.y))));
     op->flags = uint8_t((op->flags & ~7u) | uint32_t(i0) | (s0 < 0 ? 2u : 0u) | (s1 < 0 ? 4u : 0u));
   }
 }

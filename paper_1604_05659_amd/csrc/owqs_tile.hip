@@ -19,6 +19,8 @@
 // windows all have p = 1/2 exactly (an odd E(v, w) count) runs without the
 // sums when the host says so (TileArgs::half_m): it records p = 1/2, keeps
 // the norm of its input, and leaves sigma as it is.
+#include <type_traits>
+
 #include "owqs_internal.h"
 
 namespace owqs {
@@ -26,11 +28,11 @@ namespace {
 
 constexpr int kTT = 256;  // threads per workgroup of the finishing kernel
 
-// Threads per workgroup of a tile pass: 512 (8 waves) for 2^13-amplitude
-// tiles, so that a CU holding two such tiles still runs 16 waves; 128 for
-// 2^10 and 2^11 tiles, so that every thread has 8 or 16 amplitudes to work
-// on per command (the per-command decoding is paid once per wave).
-constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : tile_bits <= 11 ? 128 : 256; }
+// Threads per workgroup of a tile pass (tile_threads): 512 (8 waves) for
+// 2^13-amplitude tiles, so that a CU holding two such tiles still runs 16
+// waves; 128 for 2^10 and 2^11 tiles, so that every thread has 8 or 16
+// amplitudes to work on per command (the per-command decoding is paid once
+// per wave).
 constexpr int log2_threads(int t) { return t == 512 ? 9 : t == 256 ? 8 : 7; }
 
 __device__ __forceinline__ uint32_t ins0u(uint32_t x, int b) { return ((x >> b) << (b + 1)) | (x & ((1u << b) - 1)); }
@@ -44,6 +46,19 @@ __device__ __forceinline__ float2 xsign2(float2 v, uint32_t s) { return make_flo
 // error stays that of one pair sum however many pairs there are
 __device__ __forceinline__ double nrm2d(float2 a, float2 b) {
   return double(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+}
+// An empty asm statement that the compiler must assume changes x: values
+// computed from x before it are not reused after it (no instructions).
+__device__ __forceinline__ void opaque(uint64_t &x) {
+  uint32_t lo = uint32_t(x), hi = uint32_t(x >> 32);
+  asm volatile("" : "+v"(lo), "+v"(hi));
+  x = (uint64_t(hi) << 32) | lo;
+}
+__device__ __forceinline__ void opaque32(uint32_t &x) { asm volatile("" : "+v"(x)); }
+// x in a vector register (an empty asm statement that takes it as one).
+__device__ __forceinline__ float in_vgpr(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
 }
 __device__ __forceinline__ float2 &at(char *lds, uint32_t byte_off) { return *reinterpret_cast<float2 *>(lds + byte_off); }
 
@@ -167,133 +182,86 @@ __device__ __forceinline__ void pair_swap(char *lds, uint32_t tid, int lb) {
   }
 }
 
-// A window on the element pairs (a, b) that differ in local bit lb:
-//   t = fc0 b,  o0 = fa a + t,  o1 = fb a + r t   (r = +-1, sign bit rsign),
-// with b negated where the local bits lmb have odd parity and o1 negated
-// where the local bits lmo have odd parity (kMasked), and the outputs
-// exchanged by the folded X correction (kSw).  Returns this thread's sum of
-// |o0|^2 + |o1|^2 in FP64 (kAcc).
-template <bool kMasked, bool kSw, bool kAcc, int kTB, int kT>
-__device__ __forceinline__ double window_pass(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0,
-                                             uint32_t rsign, uint32_t lmb, uint32_t lmo) {
-  constexpr int kPairs = (1 << kTB) / kT / 2;
-  const uint32_t et = ins0u(tid, lb), bit8 = 8u << lb;
-  const uint32_t sbt = kMasked ? par32(et & lmb) << 31 : 0u;
-  const uint32_t sot = kMasked ? par32(et & lmo) << 31 : 0u;
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < kPairs; ++r) {
-    const uint32_t ur = ins0u(uint32_t(r) * kT, lb);
-    const uint32_t a0 = (et << 3) | (ur << 3), a1 = a0 | bit8;
-    const float2 a = at(lds, a0);
-    float2 b = at(lds, a1);
-    float fbe = fb;
-    uint32_t ts = rsign;
-    if (kMasked) {
-      b = xsign2(b, sbt ^ (par32(ur & lmb) << 31));
-      const uint32_t so = sot ^ (par32(ur & lmo) << 31);
-      fbe = xsign(fb, so);
-      ts ^= so;
-    }
-    const float2 t = make_float2(fc0.x * b.x - fc0.y * b.y, fc0.x * b.y + fc0.y * b.x);
-    const float2 p0 = make_float2(fmaf(fa, a.x, t.x), fmaf(fa, a.y, t.y));
-    const float2 te = xsign2(t, ts);
-    const float2 p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
-    at(lds, a0) = kSw ? p1 : p0;
-    at(lds, a1) = kSw ? p0 : p1;
-    if (kAcc) acc += nrm2d(p0, p1);
-  }
-  return acc;
-}
-
-// The unmasked window with compile-time r and a mixing bit below the thread
-// index bits: element pair r of the thread is then at a fixed offset from
-// the thread's first pair, and the sign of t in o1 is an instruction
-// modifier.
-template <bool kSw, bool kAcc, bool kRneg, int kTB, int kT>
-__device__ __forceinline__ double window_low(char *lds, uint32_t tid, int lb, float fa, float fb, float2 fc0) {
-  constexpr int kPairs = (1 << kTB) / kT / 2;
-  constexpr int kLogT = log2_threads(kT);
-  const uint32_t a0t = ins0u(tid, lb) << 3, a1t = a0t | (8u << lb);
-  double acc = 0.0;
-#pragma unroll
-  for (int r = 0; r < kPairs; ++r) {
-    // pair index tid + r kT with lb < log2 kT: insertion shifts r kT up by one
-    const uint32_t off = uint32_t(r) << (kLogT + 4);
-    const float2 a = at(lds, a0t + off), b = at(lds, a1t + off);
-    const float2 t = make_float2(fc0.x * b.x - fc0.y * b.y, fc0.x * b.y + fc0.y * b.x);
-    const float2 p0 = make_float2(fmaf(fa, a.x, t.x), fmaf(fa, a.y, t.y));
-    const float2 p1 = kRneg ? make_float2(fmaf(fb, a.x, -t.x), fmaf(fb, a.y, -t.y))
-                            : make_float2(fmaf(fb, a.x, t.x), fmaf(fb, a.y, t.y));
-    at(lds, a0t + off) = kSw ? p1 : p0;
-    at(lds, a1t + off) = kSw ? p0 : p1;
-    if (kAcc) acc += nrm2d(p0, p1);
-  }
-  return acc;
-}
-
-template <bool kAcc, int kTB, int kT>
-__device__ __forceinline__ double window_any(bool masked, bool sw, char *lds, uint32_t tid, int lb, float fa, float fb,
-                                            float2 fc0, uint32_t rsign, uint32_t lmb, uint32_t lmo) {
-  constexpr int kLogT = log2_threads(kT);
-  if (masked)
-    return sw ? window_pass<true, true, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo)
-              : window_pass<true, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, lmb, lmo);
-  if (lb < kLogT) {
-    if (rsign)
-      return sw ? window_low<true, kAcc, true, kTB, kT>(lds, tid, lb, fa, fb, fc0)
-                : window_low<false, kAcc, true, kTB, kT>(lds, tid, lb, fa, fb, fc0);
-    return sw ? window_low<true, kAcc, false, kTB, kT>(lds, tid, lb, fa, fb, fc0)
-              : window_low<false, kAcc, false, kTB, kT>(lds, tid, lb, fa, fb, fc0);
-  }
-  return sw ? window_pass<false, true, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, 0u, 0u)
-            : window_pass<false, false, kAcc, kTB, kT>(lds, tid, lb, fa, fb, fc0, rsign, 0u, 0u);
-}
+// How a window's pair update is compiled (WinP::kind).  A window maps the
+// element pair (a, b) that differs in its local bit to
+//   t = fc0 b,  o0 = fa a + t,  o1 = fb a + r t   (r = +-1),
+// the outputs exchanged by a folded X correction.  Without local masks the
+// exchange is folded into the parameters (o1 = fb a + r fc0 b in place of
+// o0 is the same form with fa and fb exchanged and fc0 -> r fc0, r kept),
+// and r is compiled in: kWinPlus, kWinMinus.  With local masks (b negated
+// where the local bits lmb have odd parity, o1 where lmo has) the signs are
+// applied at run time and the exchange is compiled in: kWinMasked,
+// kWinMaskedSw.
+enum : int { kWinPlus = 0, kWinMinus = 1, kWinMasked = 2, kWinMaskedSw = 3 };
 
 // A window's per-tile parameters: the tile-constant signs and the folded
 // corrections resolved into fa, fb, fc0 and the sign of t in o1.
 struct WinP {
   float fa, fb;
   float2 fc0;
-  uint32_t rsign, lmb, lmo;
-  int lb, widx;
-  bool sw, masked;
+  uint32_t rsign, lmb, lmo;  // rsign: sign bit of r
+  int lb, widx, kind;
 };
 
+// All of it is sign-bit work on uniform words (scalar instructions) except
+// for the group's first window, which applies sigma, and runs with one
+// coefficient per set: FuseOp::coef holds the window's factor times its
+// coefficient, so fc0 = fa c0 is that product with a sign.
 __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, double sg, const TileArgs &ta) {
+  constexpr uint32_t kS = 0x80000000u;
   WinP w;
   const uint32_t fl = op_flags(op, ta);
-  const float f = float((fl & 16u) ? sg * op.f : double(op.f));
-  w.sw = fl & 1u;
-  float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
-  if (fl & 2u) { if (w.sw) fb = -fb; else fa = -fa; }
-  if (fl & 4u) { if (w.sw) fa = -fa; else fb = -fb; }
-  float2 cw = make_float2(op.coef.x, op.coef.y);
-  if (ta.coefs) cw = set_coef(ta, op.m_index);
-  const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
-  w.fa = fa;
-  w.fb = fb;
-  w.fc0 = make_float2(fa * c0.x, fa * c0.y);
+  const bool sw = fl & 1u;
+  // signs of fa, fb (the factor) and of c0 (the coefficient) on this tile
+  uint32_t sa = 0u, sb = par64(ob & op.omask_o1) << 31;
+  if (fl & 2u) { if (sw) sb ^= kS; else sa ^= kS; }
+  if (fl & 4u) { if (sw) sa ^= kS; else sb ^= kS; }
+  const uint32_t sc = par64(ob & op.omask_b) << 31;
+  float f = op.f;
+  float2 fc = op.coef;
+  if (ta.coefs) {  // one coefficient per set
+    const float2 cw = set_coef(ta, op.m_index);
+    fc = make_float2(f * cw.x, f * cw.y);
+  }
+  if (fl & 16u) {  // the group's first window applies sigma
+    const float g = float(sg);
+    f = float(sg * double(op.f));
+    fc = make_float2(g * fc.x, g * fc.y);
+  }
+  float fa = xsign(f, sa), fb = xsign(f, sb);
+  float2 fc0 = xsign2(fc, sa ^ sc);
   // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
   const bool s1neg = !(fl & 8u);
-  w.rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
+  const bool rneg = s1neg != (sa != sb);
+  const bool masked = (op.lmask_b | op.lmask_o1) != 0;
+  if (!masked && sw) {
+    const float t = fa;
+    fa = fb;
+    fb = t;
+    if (rneg) fc0 = xsign2(fc0, kS);
+  }
+  // the factors go to vector registers: the window arithmetic then takes the
+  // short (VOP2) encodings, which the scalar operands would rule out
+  w.fa = in_vgpr(fa);
+  w.fb = in_vgpr(fb);
+  w.fc0 = make_float2(in_vgpr(fc0.x), in_vgpr(fc0.y));
+  w.rsign = rneg ? kS : 0u;
   w.lmb = op.lmask_b;
   w.lmo = op.lmask_o1;
-  w.masked = (op.lmask_b | op.lmask_o1) != 0;
   w.lb = op.lb;
   w.widx = op.widx;
+  w.kind = masked ? (sw ? kWinMaskedSw : kWinMasked) : (rneg ? kWinMinus : kWinPlus);
   return w;
 }
 
-// A window on one pair in registers (a: local index e0 with bit lb = 0, b:
-// the same with bit lb = 1).  For a masked window (kMasked) b is negated
-// where e0 has odd parity under lmb, and o1 where it has odd parity under
-// lmo.
-template <bool kSw, bool kMasked = false>
+// A window on one pair in registers: a at local index e0 (bit lb = 0), b at
+// e0 with bit lb set.
+template <int kKind>
 __device__ __forceinline__ void win_apply(const WinP &w, uint32_t e0, float2 &a, float2 &b) {
+  constexpr bool kMasked = kKind >= kWinMasked;
+  float2 bb = b;
   float fbe = w.fb;
   uint32_t ts = w.rsign;
-  float2 bb = b;
   if (kMasked) {
     bb = xsign2(bb, par32(e0 & w.lmb) << 31);
     const uint32_t so = par32(e0 & w.lmo) << 31;
@@ -302,21 +270,86 @@ __device__ __forceinline__ void win_apply(const WinP &w, uint32_t e0, float2 &a,
   }
   const float2 t = make_float2(w.fc0.x * bb.x - w.fc0.y * bb.y, w.fc0.x * bb.y + w.fc0.y * bb.x);
   const float2 p0 = make_float2(fmaf(w.fa, a.x, t.x), fmaf(w.fa, a.y, t.y));
-  const float2 te = xsign2(t, ts);
-  const float2 p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
+  float2 p1;
+  if (kKind == kWinPlus) {
+    p1 = make_float2(fmaf(w.fb, a.x, t.x), fmaf(w.fb, a.y, t.y));
+  } else if (kKind == kWinMinus) {
+    p1 = make_float2(fmaf(w.fb, a.x, -t.x), fmaf(w.fb, a.y, -t.y));
+  } else {
+    const float2 te = xsign2(t, ts);
+    p1 = make_float2(fmaf(fbe, a.x, te.x), fmaf(fbe, a.y, te.y));
+  }
+  constexpr bool kSw = kKind == kWinMaskedSw;
   a = kSw ? p1 : p0;
   b = kSw ? p0 : p1;
+}
+
+// One window over the tile: every element pair that differs in local bit
+// lb.  Returns this thread's sum of |o0|^2 + |o1|^2 in FP64 (kAcc).
+template <int kKind, bool kAcc, int kTB, int kT>
+__device__ __forceinline__ double window_pass(char *lds, uint32_t tid, const WinP &w) {
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  const uint32_t et = ins0u(tid, w.lb), bit8 = 8u << w.lb;
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    const uint32_t e0 = et | ins0u(uint32_t(r) * kT, w.lb);
+    const uint32_t a0 = e0 << 3, a1 = a0 | bit8;
+    float2 a = at(lds, a0), b = at(lds, a1);
+    win_apply<kKind>(w, e0, a, b);
+    at(lds, a0) = a;
+    at(lds, a1) = b;
+    if (kAcc) acc += nrm2d(a, b);
+  }
+  return acc;
+}
+
+// The unmasked window with a mixing bit below the thread index bits: pair r
+// of the thread is then at a fixed offset from the thread's first pair.
+template <int kKind, bool kAcc, int kTB, int kT>
+__device__ __forceinline__ double window_low(char *lds, uint32_t tid, const WinP &w) {
+  static_assert(kKind == kWinPlus || kKind == kWinMinus, "unmasked windows only");
+  constexpr int kPairs = (1 << kTB) / kT / 2;
+  constexpr int kLogT = log2_threads(kT);
+  const uint32_t a0t = ins0u(tid, w.lb) << 3, a1t = a0t | (8u << w.lb);
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < kPairs; ++r) {
+    // pair index tid + r kT with lb < log2 kT: insertion shifts r kT up by one
+    const uint32_t off = uint32_t(r) << (kLogT + 4);
+    float2 a = at(lds, a0t + off), b = at(lds, a1t + off);
+    win_apply<kKind>(w, 0u, a, b);
+    at(lds, a0t + off) = a;
+    at(lds, a1t + off) = b;
+    if (kAcc) acc += nrm2d(a, b);
+  }
+  return acc;
+}
+
+template <bool kAcc, int kTB, int kT>
+__device__ __forceinline__ double window_single(char *lds, uint32_t tid, const WinP &w) {
+  constexpr int kLogT = log2_threads(kT);
+  switch (w.kind) {
+    case kWinMasked: return window_pass<kWinMasked, kAcc, kTB, kT>(lds, tid, w);
+    case kWinMaskedSw: return window_pass<kWinMaskedSw, kAcc, kTB, kT>(lds, tid, w);
+    case kWinMinus:
+      return w.lb < kLogT ? window_low<kWinMinus, kAcc, kTB, kT>(lds, tid, w)
+                          : window_pass<kWinMinus, kAcc, kTB, kT>(lds, tid, w);
+    default:
+      return w.lb < kLogT ? window_low<kWinPlus, kAcc, kTB, kT>(lds, tid, w)
+                          : window_pass<kWinPlus, kAcc, kTB, kT>(lds, tid, w);
+  }
 }
 
 __device__ __forceinline__ double nrm4(float2 a, float2 b, float2 c, float2 d) {
   return nrm2d(a, b) + nrm2d(c, d);
 }
 
-// Two consecutive unmasked windows A, B on different local bits in one LDS
-// pass: each thread takes quads of elements (all values of the two bits),
-// applies A to its two pairs, then B to its two pairs, in registers.  Half
-// the LDS traffic and barriers of two passes.
-template <bool kAcc, bool kSwA, bool kSwB, bool kMA, bool kMB, bool kMid, int kTB, int kT>
+// Two consecutive windows A, B on different local bits in one LDS pass:
+// each thread takes quads of elements (all values of the two bits), applies
+// A to its two pairs, then B to its two pairs, in registers.  Half the LDS
+// traffic and barriers of two passes.
+template <bool kAcc, int kKA, int kKB, bool kMid, int kTB, int kT>
 __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
                                             double &acc_a, double &acc_b) {
   constexpr int kQuads = (1 << kTB) / kT / 4;
@@ -326,8 +359,8 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
   for (int r = 0; r < kQuads; ++r) {
     const uint32_t el = ins0u(ins0u(tid + uint32_t(r) * kT, lo), hi), e = el << 3;
     float2 x00 = at(lds, e), x10 = at(lds, e | ba), x01 = at(lds, e | bb), x11 = at(lds, e | ba | bb);
-    win_apply<kSwA, kMA>(A, el, x00, x10);
-    win_apply<kSwA, kMA>(A, el | (bb >> 3), x01, x11);
+    win_apply<kKA>(A, el, x00, x10);
+    win_apply<kKA>(A, el | (bb >> 3), x01, x11);
     if (kAcc) acc_a += nrm4(x00, x10, x01, x11);
     if (kMid) {  // an E / Z between the windows: negate where its local bits are all set
       if ((el & mid) == mid) x00 = xsign2(x00, 0x80000000u);
@@ -335,8 +368,8 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
       if (((el | (bb >> 3)) & mid) == mid) x01 = xsign2(x01, 0x80000000u);
       if (((el | ((ba | bb) >> 3)) & mid) == mid) x11 = xsign2(x11, 0x80000000u);
     }
-    win_apply<kSwB, kMB>(B, el, x00, x01);
-    win_apply<kSwB, kMB>(B, el | (ba >> 3), x10, x11);
+    win_apply<kKB>(B, el, x00, x01);
+    win_apply<kKB>(B, el | (ba >> 3), x10, x11);
     if (kAcc) acc_b += nrm4(x00, x10, x01, x11);
     at(lds, e) = x00;
     at(lds, e | ba) = x10;
@@ -345,27 +378,25 @@ __device__ __forceinline__ void window_pair(char *lds, uint32_t tid, const WinP 
   }
 }
 
-template <bool kAcc, bool kMA, bool kMB, bool kMid, int kTB, int kT>
-__device__ __forceinline__ void window_pair_sw(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
-                                               double &acc_a, double &acc_b) {
-  if (A.sw) {
-    if (B.sw) window_pair<kAcc, true, true, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-    else window_pair<kAcc, true, false, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-  } else {
-    if (B.sw) window_pair<kAcc, false, true, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-    else window_pair<kAcc, false, false, kMA, kMB, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+template <bool kAcc, int kKA, bool kMid, int kTB, int kT>
+__device__ __forceinline__ void window_pair_b(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
+                                              double &acc_a, double &acc_b) {
+  switch (B.kind) {
+    case kWinPlus: window_pair<kAcc, kKA, kWinPlus, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    case kWinMinus: window_pair<kAcc, kKA, kWinMinus, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    case kWinMasked: window_pair<kAcc, kKA, kWinMasked, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    default: window_pair<kAcc, kKA, kWinMaskedSw, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
   }
 }
 
 template <bool kAcc, bool kMid, int kTB, int kT>
-__device__ __forceinline__ void window_pair_m(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
+__device__ __forceinline__ void window_pair_a(char *lds, uint32_t tid, const WinP &A, const WinP &B, uint32_t mid,
                                               double &acc_a, double &acc_b) {
-  if (A.masked) {
-    if (B.masked) window_pair_sw<kAcc, true, true, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-    else window_pair_sw<kAcc, true, false, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-  } else {
-    if (B.masked) window_pair_sw<kAcc, false, true, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-    else window_pair_sw<kAcc, false, false, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+  switch (A.kind) {
+    case kWinPlus: window_pair_b<kAcc, kWinPlus, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    case kWinMinus: window_pair_b<kAcc, kWinMinus, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    case kWinMasked: window_pair_b<kAcc, kWinMasked, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
+    default: window_pair_b<kAcc, kWinMaskedSw, kMid, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b); break;
   }
 }
 
@@ -374,14 +405,14 @@ __device__ __forceinline__ void window_pair_m(char *lds, uint32_t tid, const Win
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ void window_pair_any(char *lds, uint32_t tid, const WinP &A, const WinP &B, bool has_mid,
                                                 uint32_t mid, double &acc_a, double &acc_b) {
-  if (has_mid) window_pair_m<kAcc, true, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
-  else window_pair_m<kAcc, false, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+  if (has_mid) window_pair_a<kAcc, true, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
+  else window_pair_a<kAcc, false, kTB, kT>(lds, tid, A, B, mid, acc_a, acc_b);
 }
 
 // Three consecutive unmasked windows A, B, C on three different local bits:
 // octets of elements (all values of the three bits) in registers, each
 // window applied to its four pairs in turn; one LDS round for three commands.
-template <bool kAcc, bool kSwA, bool kSwB, bool kSwC, int kTB, int kT>
+template <bool kAcc, int kKA, int kKB, int kKC, int kTB, int kT>
 __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const WinP &A, const WinP &B, const WinP &C,
                                               double *acc) {
   constexpr int kOcts = (1 << kTB) / kT / 8;
@@ -393,24 +424,24 @@ __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const Win
 #pragma unroll
   for (int r = 0; r < kOcts; ++r) {
     const uint32_t el = ins0u(ins0u(ins0u(tid + uint32_t(r) * kT, b0), b1), b2), e = el << 3;
-    const uint32_t la = ba >> 3, lb_ = bb >> 3, lc = bc >> 3;
     float2 x[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) x[q] = at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u));
-    win_apply<kSwA>(A, el, x[0], x[1]);
-    win_apply<kSwA>(A, el | lb_, x[2], x[3]);
-    win_apply<kSwA>(A, el | lc, x[4], x[5]);
-    win_apply<kSwA>(A, el | lb_ | lc, x[6], x[7]);
+    // unmasked windows: the element index does not enter
+    win_apply<kKA>(A, 0u, x[0], x[1]);
+    win_apply<kKA>(A, 0u, x[2], x[3]);
+    win_apply<kKA>(A, 0u, x[4], x[5]);
+    win_apply<kKA>(A, 0u, x[6], x[7]);
     if (kAcc) acc[0] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
-    win_apply<kSwB>(B, el, x[0], x[2]);
-    win_apply<kSwB>(B, el | la, x[1], x[3]);
-    win_apply<kSwB>(B, el | lc, x[4], x[6]);
-    win_apply<kSwB>(B, el | la | lc, x[5], x[7]);
+    win_apply<kKB>(B, 0u, x[0], x[2]);
+    win_apply<kKB>(B, 0u, x[1], x[3]);
+    win_apply<kKB>(B, 0u, x[4], x[6]);
+    win_apply<kKB>(B, 0u, x[5], x[7]);
     if (kAcc) acc[1] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
-    win_apply<kSwC>(C, el, x[0], x[4]);
-    win_apply<kSwC>(C, el | la, x[1], x[5]);
-    win_apply<kSwC>(C, el | lb_, x[2], x[6]);
-    win_apply<kSwC>(C, el | la | lb_, x[3], x[7]);
+    win_apply<kKC>(C, 0u, x[0], x[4]);
+    win_apply<kKC>(C, 0u, x[1], x[5]);
+    win_apply<kKC>(C, 0u, x[2], x[6]);
+    win_apply<kKC>(C, 0u, x[3], x[7]);
     if (kAcc) acc[2] += nrm4(x[0], x[1], x[2], x[3]) + nrm4(x[4], x[5], x[6], x[7]);
 #pragma unroll
     for (int q = 0; q < 8; ++q) at(lds, e | ((q & 1) ? ba : 0u) | ((q & 2) ? bb : 0u) | ((q & 4) ? bc : 0u)) = x[q];
@@ -420,17 +451,152 @@ __device__ __forceinline__ void window_triple(char *lds, uint32_t tid, const Win
 template <bool kAcc, int kTB, int kT>
 __device__ __forceinline__ void window_triple_any(char *lds, uint32_t tid, const WinP &A, const WinP &B,
                                                   const WinP &C, double *acc) {
-  const int sel = (A.sw ? 1 : 0) | (B.sw ? 2 : 0) | (C.sw ? 4 : 0);
+  // unmasked windows: kind kWinPlus (0) or kWinMinus (1)
+  const int sel = A.kind | (B.kind << 1) | (C.kind << 2);
+  constexpr int P = kWinPlus, M = kWinMinus;
   switch (sel) {
-    case 0: window_triple<kAcc, false, false, false, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 1: window_triple<kAcc, true, false, false, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 2: window_triple<kAcc, false, true, false, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 3: window_triple<kAcc, true, true, false, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 4: window_triple<kAcc, false, false, true, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 5: window_triple<kAcc, true, false, true, kTB, kT>(lds, tid, A, B, C, acc); break;
-    case 6: window_triple<kAcc, false, true, true, kTB, kT>(lds, tid, A, B, C, acc); break;
-    default: window_triple<kAcc, true, true, true, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 0: window_triple<kAcc, P, P, P, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 1: window_triple<kAcc, M, P, P, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 2: window_triple<kAcc, P, M, P, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 3: window_triple<kAcc, M, M, P, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 4: window_triple<kAcc, P, P, M, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 5: window_triple<kAcc, M, P, M, kTB, kT>(lds, tid, A, B, C, acc); break;
+    case 6: window_triple<kAcc, P, M, M, kTB, kT>(lds, tid, A, B, C, acc); break;
+    default: window_triple<kAcc, M, M, M, kTB, kT>(lds, tid, A, B, C, acc); break;
   }
+}
+
+// ---- rounds: runs of commands on a register cube.
+// A round header (DK_R) names kC local bits (the cube) and the commands
+// after it that run on it: windows without local masks whose mixing bit is
+// a cube bit, E and Z on any bits.  Each thread loads the 2^kC amplitudes that share its other
+// bits (element el | qb[q], q the cube index), applies the round's commands
+// in registers in order, and stores them back: one LDS round trip and one
+// barrier for the whole run.
+//
+// The sign r of t in o1 is not applied: the stored value of o1 is r o1
+// (pend, bit j: the amplitudes with cube bit j set carry a factor -1), so
+// every window is fa a + t, r fb a + t.  Such a factor is common to both
+// amplitudes of a pair of any window on another cube bit and commutes with
+// E and Z; a window on cube bit j takes it into its coefficient (b arrives
+// as -b); the round applies what is left before it stores the cube.
+
+// The cube positions (bit i: cube bit b[i]) of the local bits in m.
+template <int kC>
+__device__ __forceinline__ uint32_t cube_part(uint32_t m, const int *b) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kC; ++i) c |= ((m >> b[i]) & 1u) << i;
+  return c;
+}
+
+// A window on cube bit J (no local masks: rounds hold no masked windows).
+// The update is in place, o1 before o0 (the last use of a writes a's own
+// register), so that the compiler keeps every amplitude in one register
+// through the round's command loop.
+template <int J, int kC, bool kAcc>
+__device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP &w, uint32_t &pend) {
+  constexpr int kPer = 1 << kC;
+  constexpr int kB = 1 << J;
+  const float2 fc = xsign2(w.fc0, ((pend >> J) & 1u) << 31);  // sign work on uniform words
+  const float fbr = xsign(w.fb, w.rsign);
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (q & kB) continue;
+    const float2 a = x[q], bb = x[q + kB];
+    const float2 t = make_float2(fc.x * bb.x - fc.y * bb.y, fc.x * bb.y + fc.y * bb.x);
+    x[q + kB] = make_float2(fmaf(fbr, a.x, t.x), fmaf(fbr, a.y, t.y));
+    x[q] = make_float2(fmaf(w.fa, a.x, t.x), fmaf(w.fa, a.y, t.y));
+    if (kAcc) acc += nrm2d(x[q], x[q + kB]);
+  }
+  pend = w.rsign ? (pend | (1u << J)) : (pend & ~(1u << J));
+  return acc;
+}
+
+// E or Z in a round: negate the amplitudes whose local bits m are all set
+// (the bits outside the cube decide per thread, the cube bits per q).
+template <int kC>
+__device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t el, uint32_t m, uint32_t cmask,
+                                           const int *b) {
+  const uint32_t mr = m & ~cmask, cm = cube_part<kC>(m, b);
+  const uint32_t neg = (el & mr) == mr ? 0x80000000u : 0u;
+#pragma unroll
+  for (int q = 0; q < (1 << kC); ++q) {
+    const uint32_t on = (uint32_t(q) & cm) == cm ? 0xFFFFFFFFu : 0u;  // uniform
+    x[q] = xsign2(x[q], neg & on);
+  }
+}
+
+// The round whose header holds `bits` (entries ops[o0 .. o0 + n)): a
+// sequence of sweeps, each a header (DK_S: the count of its E / Z and the
+// positions of its windows), its E / Z, then its windows in position order.
+// Each position has its own code path, so the amplitudes stay in their
+// registers through the round.
+template <int kTB, bool kRed>
+__device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp *__restrict__ ops, int o0, int n,
+                                           uint32_t bits, uint64_t ob, double sg, const TileArgs &ta,
+                                           double (*wacc)[tile_threads(kTB) / 64]) {
+  constexpr int kC = tile_cube_bits(kTB);
+  constexpr int kPer = 1 << kC;
+  static_assert(kPer * tile_threads(kTB) == (1 << kTB), "a thread holds one cube per round");
+  const int lane = tid & 63, wave = tid >> 6;
+  int b[kC];
+  uint32_t cmask = 0;
+#pragma unroll
+  for (int i = 0; i < kC; ++i) {
+    b[i] = int((bits >> (8 * i)) & 0xFFu);
+    cmask |= 1u << b[i];
+  }
+  uint32_t el = tid;
+#pragma unroll
+  for (int i = 0; i < kC; ++i) el = ins0u(el, b[i]);  // ascending bits
+  uint32_t qb[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kC; ++i) v |= uint32_t((q >> i) & 1) << b[i];
+    qb[q] = v;
+  }
+  float2 x[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) x[q] = at(lds, (el | qb[q]) << 3);
+  uint32_t pend = 0;
+  // one window of the sweep on position J: its norm into wacc (kRed)
+  auto window = [&](auto jc, const FuseOp &op) {
+    constexpr int J = decltype(jc)::value;
+    const WinP w = prep_window(op, ob, sg, ta);
+    if (kRed) {
+      const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
+      if (lane == 63) wacc[w.widx][wave] += d;
+    } else {
+      round_window<J, kC, false>(x, w, pend);
+    }
+  };
+  for (int o = o0; o < o0 + n;) {
+    const FuseOp h = load_op(ops, o++);
+    const uint32_t pm = h.flags;
+    for (int d = 0; d < h.m_index; ++d) {
+      const FuseOp e = load_op(ops, o++);
+      if ((ob & e.omask_b) == e.omask_b) round_diag<kC>(x, el, e.lmask_b, cmask, b);
+    }
+    if (pm & 1u) window(std::integral_constant<int, 0>(), load_op(ops, o++));
+    if (pm & 2u) window(std::integral_constant<int, 1>(), load_op(ops, o++));
+    if (pm & 4u) window(std::integral_constant<int, 2>(), load_op(ops, o++));
+    if (kC > 3 && (pm & 8u)) window(std::integral_constant<int, (kC > 3 ? 3 : 0)>(), load_op(ops, o++));
+  }
+#pragma unroll
+  for (int j = 0; j < kC; ++j) {
+    if ((pend >> j) & 1u) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q)
+        if (q & (1 << j)) x[q] = xsign2(x[q], 0x80000000u);
+    }
+  }
+  opaque32(el);  // the store recomputes its addresses: they are not held over the commands
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) at(lds, (el | qb[q]) << 3) = x[q];
 }
 
 // The global bit of each tile bit above the thread index (tile bits
@@ -449,14 +615,15 @@ __device__ __forceinline__ void tile_high_bits(uint64_t tmask, uint64_t *hp) {
 
 // One tile of a group (tile t of the 2^(n-k)): load it into LDS, apply the
 // group's commands, store it back.  With `reduce`, every window adds its
-// norm per wave into wacc (FP64 from each thread's sum of squares on); with
-// ta.renorm, the squared norm of the stored tile is added per wave into
-// rn.  g_tid and hp hold the thread's part of the global index and the
-// global bits of the tile bits above the thread index (see k_tile).
+// norm per wave into wacc (FP64 from each thread's sum of squares on).
+// Returns, with ta.renorm, this thread's part of the squared norm of the
+// stored tile (else 0).  g_tid and hp hold the thread's part of the global
+// index and the global bits of the tile bits above the thread index (see
+// k_tile).  Ends with a barrier: the tile's LDS is free after it.
 template <int kTB, bool kRuns, bool kRed>
-__device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArgs &ta, const FuseOp *__restrict__ ops,
-                                         double sg, uint64_t t, uint64_t g_tid, const uint64_t *hp, float2 *tile,
-                                         double (*wacc)[tile_threads(kTB) / 64], double *rn) {
+__device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileArgs &ta,
+                                           const FuseOp *__restrict__ ops, double sg, uint64_t t, uint64_t g_tid,
+                                           const uint64_t *hp, float2 *tile, double (*wacc)[tile_threads(kTB) / 64]) {
   constexpr bool reduce = kRed;  // a compile-time variant: the FP64 sums cost registers
   constexpr int kT = tile_threads(kTB);
   constexpr int kLogT = log2_threads(kT);
@@ -466,7 +633,7 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
   const uint32_t tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const uint64_t ob = pdep64(t, ta.omask);
-  const uint64_t gb = ob | g_tid;
+  uint64_t gb = ob | g_tid;
   {
     float2 v[kPer];
 #pragma unroll
@@ -483,6 +650,12 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
   __syncthreads();
   for (int o = 0; o < ta.nops; ++o) {
     const FuseOp op = load_op(ops, o);
+    if (op.kind == DK_R) {  // a round: its commands in registers
+      tile_round<kTB, kRed>(lds, tid, ops, o + 1, op.m_index, op.lmask_b, ob, sg, ta, wacc);
+      __syncthreads();
+      o += op.m_index;
+      continue;
+    }
     if (kRuns && op.kind == DK_J && (op.lmask_b | op.lmask_o1) == 0 && o + 2 < ta.nops) {
       const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
       if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
@@ -543,42 +716,26 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
     } else if (op.kind == DK_X) {
       pair_swap<kTB, kT>(lds, tid, op.lb);
     } else {  // window: fold the tile-constant signs and the corrections
-      const uint32_t fl = op_flags(op, ta);
-      const float f = float((fl & 16u) ? sg * op.f : double(op.f));
-      const bool sw = fl & 1u;
-      float fa = f, fb = par64(ob & op.omask_o1) ? -f : f;
-      if (fl & 2u) { if (sw) fb = -fb; else fa = -fa; }
-      if (fl & 4u) { if (sw) fa = -fa; else fb = -fb; }
-      float2 cw = make_float2(op.coef.x, op.coef.y);
-      if (ta.coefs) cw = set_coef(ta, op.m_index);
-      const float2 c0 = par64(ob & op.omask_b) ? make_float2(-cw.x, -cw.y) : cw;
-      const float2 fc0 = make_float2(fa * c0.x, fa * c0.y);
-      // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
-      const bool s1neg = !(fl & 8u);
-      const uint32_t rsign = (s1neg != ((fa < 0.f) != (fb < 0.f))) ? 0x80000000u : 0u;
-      const bool masked = (op.lmask_b | op.lmask_o1) != 0;
+      const WinP w = prep_window(op, ob, sg, ta);
       if (reduce) {
-        const double acc =
-            window_any<true, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
-        const double d = wave_sum_to_last(acc);  // FP64 from the wave sum on
-        if (lane == 63) wacc[op.widx][wave] += d;
+        const double d = wave_sum_to_last(window_single<true, kTB, kT>(lds, tid, w));  // FP64 from the wave sum on
+        if (lane == 63) wacc[w.widx][wave] += d;
       } else {
-        window_any<false, kTB, kT>(masked, sw, lds, tid, op.lb, fa, fb, fc0, rsign, op.lmask_b, op.lmask_o1);
+        window_single<false, kTB, kT>(lds, tid, w);
       }
     }
     __syncthreads();
   }
+  double rsum = 0.0;
   {
     float2 v[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) v[r] = tile[tid + r * kT];
     if (ta.renorm) {  // uniform: the group's output norm resets sigma
-      double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < kPer; r += 2) acc += nrm2d(v[r], v[r + 1]);
-      const double d = wave_sum_to_last(acc);
-      if (lane == 63) rn[wave] += d;
+      for (int r = 0; r < kPer; r += 2) rsum += nrm2d(v[r], v[r + 1]);
     }
+    opaque(gb);  // the load's addresses are not kept live over the commands: recomputed here
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
       uint64_t g = gb;
@@ -589,6 +746,21 @@ __device__ __forceinline__ void tile_one(float2 *__restrict__ psi, const TileArg
     }
   }
   __syncthreads();
+  return rsum;
+}
+
+// Sum of x over the workgroup, valid in thread 0, through `scratch` (one
+// double per wave of LDS that no thread uses meanwhile).
+template <int kT>
+__device__ __forceinline__ double block_sum0(double x, double *scratch) {
+  const uint32_t tid = threadIdx.x;
+  const double d = wave_sum_to_last(x);
+  if ((tid & 63) == 63) scratch[tid >> 6] = d;
+  __syncthreads();
+  double s = 0.0;
+  if (tid == 0)
+    for (int k = 0; k < kT / 64; ++k) s += scratch[k];
+  return s;
 }
 
 // kTB = tile bits (ta.k).  Global memory <-> LDS: each thread moves
@@ -606,14 +778,12 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
                                                             double *__restrict__ partials) {
   constexpr int kT = tile_threads(kTB);
   constexpr int kHi = kTB - log2_threads(kT);  // tile bits above the thread index
-  extern __shared__ float2 tile[];
+  __shared__ float2 tile[1 << kTB];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
-  __shared__ double rn[kT / 64];
   const uint32_t tid = threadIdx.x;
   constexpr bool reduce = kRed;  // ma.reduce != kReduceNone
   if (reduce)
     for (int i = tid; i < ta.nwin * (kT / 64); i += kT) wacc[i / (kT / 64)][i % (kT / 64)] = 0.0;
-  if (tid < kT / 64) rn[tid] = 0.0;  // read after the barriers of tile_one
   const double sg = (ma.reduce == kReduceRenorm) ? *ma.book.sigma : 1.0;
   const uint64_t g_tid = pdep64(tid, ta.tmask);
   uint64_t hp[kHi];
@@ -622,12 +792,12 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
   if (ta.half_m && blockIdx.x == 0 && blockIdx.y == 0)  // windows with p = 1/2 exactly
     for (int i = tid; i < ta.nwin; i += kT) ma.book.probs[ta.half_m[i]] = 0.5;
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
+  double rsum = 0.0;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-    tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc, rn);
-  if (ta.renorm && tid == 0) {  // the block's share of the output norm (tile_one ends with a barrier)
-    double sum = 0.0;
-    for (int k = 0; k < kT / 64; ++k) sum += rn[k];
-    partials[blockIdx.x] = sum;
+    rsum += tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc);
+  if (ta.renorm) {  // the block's share of the output norm, summed through the free tile LDS
+    const double sum = block_sum0<kT>(rsum, reinterpret_cast<double *>(tile));
+    if (tid == 0) partials[blockIdx.x] = sum;
   }
   if (reduce) {
     for (int w = tid; w < ta.nwin; w += kT) {
@@ -673,11 +843,9 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
                                                                   uint32_t total) {
   constexpr int kT = tile_threads(kTB);
   constexpr int kHi = kTB - log2_threads(kT);
-  extern __shared__ float2 tile[];
+  __shared__ float2 tile[1 << kTB];
   __shared__ double wacc[kMaxGroupWindows][kT / 64];
-  __shared__ double rn[kT / 64];
   const uint32_t tid = threadIdx.x;
-  if (tid < kT / 64) rn[tid] = 0.0;  // read after the barriers of tile_one
   for (uint32_t gt = blockIdx.x; gt < total; gt += gridDim.x) {
     int lo = 0, hi = nent - 1;
     while (lo < hi) {
@@ -696,14 +864,11 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
     tile_high_bits<kTB>(e.ta.tmask, hp);
     if (e.ta.half_m && t == 0)  // windows with p = 1/2 exactly
       for (int i = tid; i < e.ta.nwin; i += kT) e.probs[e.ta.half_m[i]] = 0.5;
-    tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc, rn);
-    if (e.ta.renorm && tid == 0) {  // the tile's output norm; rn starts again at 0 for the next tile
-      double sum = 0.0;
-      for (int k = 0; k < kT / 64; ++k) {
-        sum += rn[k];
-        rn[k] = 0.0;
-      }
-      e.partials[t] = sum;
+    const double rsum = tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc);
+    if (e.ta.renorm) {  // the tile's output norm, summed through the free tile LDS
+      const double sum = block_sum0<kT>(rsum, reinterpret_cast<double *>(tile));
+      if (tid == 0) e.partials[t] = sum;
+      __syncthreads();  // the next tile's loads overwrite the LDS
     }
     if (reduce) {
       const uint64_t ntiles = uint64_t(1) << (e.ta.n - kTB);
@@ -824,6 +989,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_rev(float2 *__restri
     __syncthreads();
     for (int o = ta.nops - 1; o >= 0; --o) {
       const FuseOp op = load_op(ops, o);
+      if (op.kind == DK_R || op.kind == DK_S) continue;  // round and sweep headers: one command at a time here
       if (op.kind == DK_E || op.kind == DK_Z) {
         if ((ob & op.omask_b) == op.omask_b) {
           diag_flip<kTB, kT>(lp, tid, op.lmask_b);
@@ -984,13 +1150,12 @@ template <int kTB>
 void tile_launch(bool runs, bool red, dim3 grid, hipStream_t s, float2 *psi, const TileArgs &ta, const FuseOp *ops,
                  const MeasureArgs &a, double *partials) {
   const dim3 block(tile_threads(kTB));
-  const size_t bytes = sizeof(float2) << kTB;
   if (runs) {
-    if (red) hipLaunchKernelGGL((k_tile<kTB, true, true>), grid, block, bytes, s, psi, ta, ops, a, partials);
-    else hipLaunchKernelGGL((k_tile<kTB, true, false>), grid, block, bytes, s, psi, ta, ops, a, partials);
+    if (red) hipLaunchKernelGGL((k_tile<kTB, true, true>), grid, block, 0, s, psi, ta, ops, a, partials);
+    else hipLaunchKernelGGL((k_tile<kTB, true, false>), grid, block, 0, s, psi, ta, ops, a, partials);
   } else {
-    if (red) hipLaunchKernelGGL((k_tile<kTB, false, true>), grid, block, bytes, s, psi, ta, ops, a, partials);
-    else hipLaunchKernelGGL((k_tile<kTB, false, false>), grid, block, bytes, s, psi, ta, ops, a, partials);
+    if (red) hipLaunchKernelGGL((k_tile<kTB, false, true>), grid, block, 0, s, psi, ta, ops, a, partials);
+    else hipLaunchKernelGGL((k_tile<kTB, false, false>), grid, block, 0, s, psi, ta, ops, a, partials);
   }
 }
 
@@ -998,13 +1163,12 @@ template <int kTB>
 void tile_multi_launch(bool runs, bool red, dim3 grid, hipStream_t s, const MultiTile *ents, int nent,
                        uint32_t total) {
   const dim3 block(tile_threads(kTB));
-  const size_t bytes = sizeof(float2) << kTB;
   if (runs) {
-    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, true, true>), grid, block, bytes, s, ents, nent, total);
-    else hipLaunchKernelGGL((k_tile_multi<kTB, true, false>), grid, block, bytes, s, ents, nent, total);
+    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, true, true>), grid, block, 0, s, ents, nent, total);
+    else hipLaunchKernelGGL((k_tile_multi<kTB, true, false>), grid, block, 0, s, ents, nent, total);
   } else {
-    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, false, true>), grid, block, bytes, s, ents, nent, total);
-    else hipLaunchKernelGGL((k_tile_multi<kTB, false, false>), grid, block, bytes, s, ents, nent, total);
+    if (red) hipLaunchKernelGGL((k_tile_multi<kTB, false, true>), grid, block, 0, s, ents, nent, total);
+    else hipLaunchKernelGGL((k_tile_multi<kTB, false, false>), grid, block, 0, s, ents, nent, total);
   }
 }
 
