@@ -287,7 +287,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     for (size_t j = i; j < ns && j - i < kGroupLookahead; ++j) {
       if (done[j]) continue;
       const Step &x = steps[j];
-      if (!groupable(x.kind) || x.n != n || taken.size() == 128) break;
+      if (!groupable(x.kind) || x.n != n || taken.size() == 255) break;
       bool ok = !(x.kind == S_J && nwin >= win_cap(even || x.win.vw_even));
       uint64_t bit = 0;
       if (ok && (x.kind == S_J || x.kind == S_X)) {

@@ -94,7 +94,7 @@ constexpr int kTileMinWidth = 15;      // at least 2^5 tiles of 2^10; narrower r
 constexpr int kMaxGroupWindows = 32;
 // A group that runs without a reduction (OWQS windows with p = 1/2 exactly)
 // may hold more windows: the per-window sums only serve groups that reduce.
-constexpr int kMaxHalfWindows = 64;
+constexpr int kMaxHalfWindows = 128;
 constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
 // Threads of a tile pass over 2^k-amplitude tiles, and the bits of the
 // register cube each thread holds in a round (2^k / threads amplitudes).

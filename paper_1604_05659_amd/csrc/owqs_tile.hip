@@ -14,8 +14,8 @@
 //
 // Probabilities (Eq. 13): windows inside a group do not renormalise; each
 // workgroup sums the squared norm after every window, and the finishing
-// kernel chains p_g = n_g / (2 n_{g-1}) (n_0 = 1: the first window of the
-// group applies sigma) and sets sigma = 1 / sqrt(n_last).  A group whose
+// kernel chains p_g = n_g / (2 n_{g-1}) (n_0 = 1: a group with windows
+// scales its tile by sigma as it loads it) and sets sigma = 1 / sqrt(n_last).  A group whose
 // windows all have p = 1/2 exactly (an odd E(v, w) count) runs without the
 // sums when the host says so (TileArgs::half_m): it records p = 1/2, keeps
 // the norm of its input, and leaves sigma as it is.
@@ -204,10 +204,11 @@ struct WinP {
 };
 
 // All of it is sign-bit work on uniform words (scalar instructions) except
-// for the group's first window, which applies sigma, and runs with one
-// coefficient per set: FuseOp::coef holds the window's factor times its
-// coefficient, so fc0 = fa c0 is that product with a sign.
-__device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, double sg, const TileArgs &ta) {
+// for runs with one coefficient per set: FuseOp::coef holds the window's
+// factor times its coefficient, so fc0 = fa c0 is that product with a sign.
+// Sigma, which the group's first window applies (flag bit 4), is applied to
+// the tile as it is loaded (see tile_one).
+__device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const TileArgs &ta) {
   constexpr uint32_t kS = 0x80000000u;
   WinP w;
   const uint32_t fl = op_flags(op, ta);
@@ -217,16 +218,11 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, doubl
   if (fl & 2u) { if (sw) sb ^= kS; else sa ^= kS; }
   if (fl & 4u) { if (sw) sa ^= kS; else sb ^= kS; }
   const uint32_t sc = par64(ob & op.omask_b) << 31;
-  float f = op.f;
+  const float f = op.f;
   float2 fc = op.coef;
   if (ta.coefs) {  // one coefficient per set
     const float2 cw = set_coef(ta, op.m_index);
     fc = make_float2(f * cw.x, f * cw.y);
-  }
-  if (fl & 16u) {  // the group's first window applies sigma
-    const float g = float(sg);
-    f = float(sg * double(op.f));
-    fc = make_float2(g * fc.x, g * fc.y);
   }
   float fa = xsign(f, sa), fb = xsign(f, sb);
   float2 fc0 = xsign2(fc, sa ^ sc);
@@ -535,7 +531,7 @@ __device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t el, ui
 // registers through the round.
 template <int kTB, bool kRed>
 __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp *__restrict__ ops, int o0, int n,
-                                           uint32_t bits, uint64_t ob, double sg, const TileArgs &ta,
+                                           uint32_t bits, uint64_t ob, const TileArgs &ta,
                                            double (*wacc)[tile_threads(kTB) / 64]) {
   constexpr int kC = tile_cube_bits(kTB);
   constexpr int kPer = 1 << kC;
@@ -566,7 +562,7 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
   // one window of the sweep on position J: its norm into wacc (kRed)
   auto window = [&](auto jc, const FuseOp &op) {
     constexpr int J = decltype(jc)::value;
-    const WinP w = prep_window(op, ob, sg, ta);
+    const WinP w = prep_window(op, ob, ta);
     if (kRed) {
       const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
       if (lane == 63) wacc[w.widx][wave] += d;
@@ -644,6 +640,11 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
         if ((r >> j) & 1) g |= hp[j];
       v[r] = psi[g];
     }
+    if (ta.nwin > 0 && sg != 1.0) {  // sigma, for the group's first window: applied to the whole tile
+      const float gs = float(sg);
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) v[r] = make_float2(gs * v[r].x, gs * v[r].y);
+    }
 #pragma unroll
     for (int r = 0; r < kPer; ++r) tile[tid + r * kT] = v[r];
   }
@@ -651,7 +652,7 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
   for (int o = 0; o < ta.nops; ++o) {
     const FuseOp op = load_op(ops, o);
     if (op.kind == DK_R) {  // a round: its commands in registers
-      tile_round<kTB, kRed>(lds, tid, ops, o + 1, op.m_index, op.lmask_b, ob, sg, ta, wacc);
+      tile_round<kTB, kRed>(lds, tid, ops, o + 1, op.m_index, op.lmask_b, ob, ta, wacc);
       __syncthreads();
       o += op.m_index;
       continue;
@@ -660,7 +661,7 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
       const FuseOp n1 = load_op(ops, o + 1), n2 = load_op(ops, o + 2);
       if (n1.kind == DK_J && n2.kind == DK_J && (n1.lmask_b | n1.lmask_o1 | n2.lmask_b | n2.lmask_o1) == 0 &&
           n1.lb != op.lb && n2.lb != op.lb && n2.lb != n1.lb) {
-        const WinP A = prep_window(op, ob, sg, ta), B = prep_window(n1, ob, sg, ta), C = prep_window(n2, ob, sg, ta);
+        const WinP A = prep_window(op, ob, ta), B = prep_window(n1, ob, ta), C = prep_window(n2, ob, ta);
         double acc[3] = {0.0, 0.0, 0.0};
         if (reduce) {
           window_triple_any<true, kTB, kT>(lds, tid, A, B, C, acc);
@@ -694,7 +695,7 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
         }
       }
       if (nx.kind == DK_J && nx.lb != op.lb) {
-        const WinP A = prep_window(op, ob, sg, ta), B = prep_window(nx, ob, sg, ta);
+        const WinP A = prep_window(op, ob, ta), B = prep_window(nx, ob, ta);
         double acc_a = 0.0, acc_b = 0.0;
         if (reduce) {
           window_pair_any<true, kTB, kT>(lds, tid, A, B, has_mid, mid, acc_a, acc_b);
@@ -716,7 +717,7 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
     } else if (op.kind == DK_X) {
       pair_swap<kTB, kT>(lds, tid, op.lb);
     } else {  // window: fold the tile-constant signs and the corrections
-      const WinP w = prep_window(op, ob, sg, ta);
+      const WinP w = prep_window(op, ob, ta);
       if (reduce) {
         const double d = wave_sum_to_last(window_single<true, kTB, kT>(lds, tid, w));  // FP64 from the wave sum on
         if (lane == 63) wacc[w.widx][wave] += d;
