@@ -236,8 +236,8 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const
     fb = t;
     if (rneg) fc0 = xsign2(fc0, kS);
   }
-  // the factors go to vector registers: the window arithmetic then takes the
-  // short (VOP2) encodings, which the scalar operands would rule out
+  // the factors go to vector registers: the window arithmetic of the other
+  // paths then takes the short (VOP2) encodings, which scalar operands rule out
   w.fa = in_vgpr(fa);
   w.fb = in_vgpr(fb);
   w.fc0 = make_float2(in_vgpr(fc0.x), in_vgpr(fc0.y));
@@ -486,10 +486,27 @@ __device__ __forceinline__ uint32_t cube_part(uint32_t m, const int *b) {
   return c;
 }
 
+// A window on one pair in place: t = fc b, b <- fbr a + t, a <- fa a + t.
+// Written as one asm statement with the amplitudes as read-write operands:
+// the compiler then keeps every amplitude of the cube in one register
+// through the round's command loop (with plain C++ it moves half the cube
+// between registers after each window).  Two FP32 products and six FMAs,
+// no packed instructions.
+__device__ __forceinline__ void pair_update(float2 &a, float2 &b, float2 fc, float fa, float fbr) {
+  float t0, t1;
+  asm("v_mul_f32 %[t0], %[cy], %[by]\n\t"
+      "v_mul_f32 %[t1], %[cy], %[bx]\n\t"
+      "v_fma_f32 %[t0], %[cx], %[bx], -%[t0]\n\t"
+      "v_fma_f32 %[t1], %[cx], %[by], %[t1]\n\t"
+      "v_fma_f32 %[bx], %[fb], %[ax], %[t0]\n\t"
+      "v_fma_f32 %[by], %[fb], %[ay], %[t1]\n\t"
+      "v_fma_f32 %[ax], %[fa], %[ax], %[t0]\n\t"
+      "v_fma_f32 %[ay], %[fa], %[ay], %[t1]"
+      : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t0] "=&v"(t0), [t1] "=&v"(t1)
+      : [cx] "v"(fc.x), [cy] "v"(fc.y), [fa] "v"(fa), [fb] "v"(fbr));
+}
+
 // A window on cube bit J (no local masks: rounds hold no masked windows).
-// The update is in place, o1 before o0 (the last use of a writes a's own
-// register), so that the compiler keeps every amplitude in one register
-// through the round's command loop.
 template <int J, int kC, bool kAcc>
 __device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP &w, uint32_t &pend) {
   constexpr int kPer = 1 << kC;
@@ -500,10 +517,7 @@ __device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP 
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     if (q & kB) continue;
-    const float2 a = x[q], bb = x[q + kB];
-    const float2 t = make_float2(fc.x * bb.x - fc.y * bb.y, fc.x * bb.y + fc.y * bb.x);
-    x[q + kB] = make_float2(fmaf(fbr, a.x, t.x), fmaf(fbr, a.y, t.y));
-    x[q] = make_float2(fmaf(w.fa, a.x, t.x), fmaf(w.fa, a.y, t.y));
+    pair_update(x[q], x[q + kB], fc, w.fa, fbr);
     if (kAcc) acc += nrm2d(x[q], x[q + kB]);
   }
   pend = w.rsign ? (pend | (1u << J)) : (pend & ~(1u << J));
