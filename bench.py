@@ -791,7 +791,8 @@ def main():
             "max_abs_p_minus_half": float(np.max(np.abs(probs_f - 0.5))),
             "probability_work": ("OWQS with windows of p = 1/2 recorded without sums (reading G24: a window whose "
                                  "new qubit meets the measured one through an odd number of E has p = 1/2 exactly; "
-                                 "at most 128 in a row, then one sums and renormalises)"),
+                                 "the tile pass that ends a run of up to 128 such windows sums the norm of its "
+                                 "output and renormalises)"),
         }
         # the same plan with every probability summed (the paper's OWQS work per M)
         pat.set_sum_all(True)
