@@ -274,7 +274,7 @@ owqs_status owqs_run_states(owqs_pattern *pat, const void *in_c64, uint32_t coun
  *   the live vector, at most 2^OWQS_NOALLOC_MAX_WIDTH complex64 (32 MiB),
  *   the FP64 scale, the FP64 block partials, and (when `probs` or `err` is
  *   NULL) the probabilities and the error word.
- * The array is static device memory of about 33 MiB on each GPU the library
+ * The array is static device memory of about 34 MiB on each GPU the library
  * runs on, held until the process ends; its address is resolved when a
  * context is created on that device.  Every call on one GPU shares it and
  * overwrites what the previous call left: calls that overlap on one GPU

@@ -17,7 +17,7 @@ struct DevBook {
   int *err;           // [2] {first failing M index or INT_MAX, error kind}
 };
 
-constexpr int kMaxPartials = 1 << 16;
+constexpr int kMaxPartials = 1 << 17;
 // OWQS: windows with p = 1/2 exactly (an odd E(v, w) count) recorded in a row
 // without summing the state; the next one sums and renormalises.
 constexpr int kHalfRun = 128;
@@ -95,7 +95,7 @@ constexpr int kMaxGroupWindows = 32;
 // A group that runs without a reduction (OWQS windows with p = 1/2 exactly)
 // may hold more windows: the per-window sums only serve groups that reduce.
 constexpr int kMaxHalfWindows = 128;
-constexpr unsigned kTileGridCap = 2048;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
+constexpr unsigned kTileGridCap = 4096;  // kMaxGroupWindows * kTileGridCap <= kMaxPartials
 // Threads of a tile pass over 2^k-amplitude tiles, and the bits of the
 // register cube each thread holds in a round (2^k / threads amplitudes).
 constexpr int tile_threads(int tile_bits) { return tile_bits >= 13 ? 512 : tile_bits <= 11 ? 128 : 256; }

@@ -34,7 +34,7 @@ void *g_addr[kMaxDevices];  // device address of `scratch` on each device
 
 }  // namespace
 
-// The working memory of owqs_run_noalloc (about 33 MiB on every device the
+// The working memory of owqs_run_noalloc (about 34 MiB on every device the
 // library runs on, held until the process ends).  In host code this name is a
 // host-side stand-in: kernels get the device address resolved below.
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
