@@ -525,17 +525,16 @@ __device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP 
 }
 
 // E or Z in a round: negate the amplitudes whose local bits m are all set
-// (the bits outside the cube decide per thread, the cube bits per q).
+// (the bits outside the cube decide per thread, the cube bits per q: a
+// uniform branch per q, so only the amplitudes it can flip are touched).
 template <int kC>
 __device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t el, uint32_t m, uint32_t cmask,
                                            const int *b) {
   const uint32_t mr = m & ~cmask, cm = cube_part<kC>(m, b);
   const uint32_t neg = (el & mr) == mr ? 0x80000000u : 0u;
 #pragma unroll
-  for (int q = 0; q < (1 << kC); ++q) {
-    const uint32_t on = (uint32_t(q) & cm) == cm ? 0xFFFFFFFFu : 0u;  // uniform
-    x[q] = xsign2(x[q], neg & on);
-  }
+  for (int q = 0; q < (1 << kC); ++q)
+    if ((uint32_t(q) & cm) == cm) x[q] = xsign2(x[q], neg);  // uniform condition
 }
 
 // The round whose header holds `bits` (entries ops[o0 .. o0 + n)): a
