@@ -1997,9 +1997,11 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     if (le == hipSuccess) le = launch_batch_start(dios + wide.size(), (int)lds.size(), 0, B.cap);
     nodes += (wide.empty() ? 0 : 1) + (lds.empty() ? 0 : 1);
     if (!lds.empty() && le == hipSuccess) le = hipEventRecord(B.fork, B.cap);
+    bool forked[kLdsClasses] = {};
     for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c) {  // each class a branch of its own
       if (cls_items[c].empty()) continue;
       le = hipStreamWaitEvent(B.side[c], B.fork, 0);
+      forked[c] = le == hipSuccess;
       if (le == hipSuccess)
         le = launch_lds_batch(reinterpret_cast<const LdsItem *>(dev + cls_off[c]), (int)cls_items[c].size(),
                               cls_width[c], B.side[c]);
@@ -2028,6 +2030,10 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     if (le == hipSuccess) le = launch_batch_read(dios, (int)wide.size(), max_nout, B.cap);
     for (int c = 0; c < kLdsClasses && le == hipSuccess; ++c)
       if (!cls_items[c].empty()) le = hipStreamWaitEvent(B.cap, B.join[c], 0);
+    if (le != hipSuccess)  // join every forked branch, so that the capture ends whole (the graph is dropped)
+      for (int c = 0; c < kLdsClasses; ++c)
+        if (forked[c] && hipEventRecord(B.join[c], B.side[c]) == hipSuccess)
+          (void)hipStreamWaitEvent(B.cap, B.join[c], 0);
     nodes += wide.empty() ? 0 : 1;
     e = hipStreamEndCapture(B.cap, &B.graph);
     if (le != hipSuccess) e = le;
