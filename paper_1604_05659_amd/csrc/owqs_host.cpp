@@ -361,6 +361,7 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
         op.coef = make_float2(float(double(op.f) * double(x.coef.x)), float(double(op.f) * double(x.coef.y)));
         split(x.win.mask_b, op.lmask_b, op.omask_b);
         split(x.win.mask_o1, op.lmask_o1, op.omask_o1);
+        round_words(op);
       } else if (x.kind == S_X) {
         op.lb = (uint8_t)local_of[x.b0];
       } else if (x.kind == S_E) {

@@ -116,10 +116,48 @@ struct FuseOp {
   uint32_t lmask_b;  // J: local bits of mask_b;  E/Z: local bits that must all be 1;
                      // R: the cube's local bits, one per byte, ascending
   uint32_t lmask_o1; // J: local bits of mask_o1
-  uint32_t pad;
+  uint32_t rw_rs;    // J: sign bit of r (round_words)
   uint64_t omask_b;  // J: outer bits of mask_b;  E/Z: outer bits that must all be 1
   uint64_t omask_o1; // J: outer bits of mask_o1
-};  // 48 bytes
+  // J, for register rounds (round_words): fa, r fb and the sign of c0 as words
+  // on a tile where the outer bits of both masks have even parity, and the
+  // sign mask (0 or bit 31) of the folded exchange
+  uint32_t rw_fa, rw_fbr, rw_cs, rw_fold;
+};  // 64 bytes
+
+// A window's parameters with its tile-independent signs resolved, as a
+// register round takes them: the window maps the pair (a, b) to
+// o0 = fa a + t, o1 = fb a + r t with t = fa c0 b, the outputs exchanged by a
+// folded X correction (flag bit 0).  Flag bits 1 and 2 negate o0 and o1;
+// without flag bit 3, s1 = -1 (r = s1 fb / fa).  A window without local
+// masks takes the exchange into its parameters (fa and fb exchanged, c0 ->
+// r c0).  On a tile where the outer bits of mask_o1 have odd parity, fb and
+// r change sign: with the exchange folded in, so do fa, r fb and c0, which is
+// what rw_fold masks; an odd parity of mask_b's outer bits negates c0.
+// Called wherever a window's flags, factor or coefficient are written (the
+// plan compiler, and the kernel that resolves drawn outcomes).
+__host__ __device__ inline void round_words(FuseOp &op) {
+  const uint32_t kS = 0x80000000u, fl = op.flags;
+  const bool sw = fl & 1u;
+  const uint32_t n0 = (fl & 2u) ? kS : 0u, n1 = (fl & 4u) ? kS : 0u;
+  const uint32_t sa = sw ? n1 : n0, sb = sw ? n0 : n1;
+  const uint32_t rs = ((fl & 8u) ? 0u : kS) ^ sa ^ sb;
+  uint32_t f;
+  __builtin_memcpy(&f, &op.f, sizeof(f));
+  uint32_t fa = f ^ sa, fb = f ^ sb, cs = sa;
+  const bool fold = sw && (op.lmask_b | op.lmask_o1) == 0;
+  if (fold) {
+    const uint32_t t = fa;
+    fa = fb;
+    fb = t;
+    cs ^= rs;
+  }
+  op.rw_fa = fa;
+  op.rw_fbr = fb ^ rs;
+  op.rw_cs = cs;
+  op.rw_rs = rs;
+  op.rw_fold = fold ? kS : 0u;
+}
 
 struct TileArgs {
   uint64_t tmask;    // global slots in the tile (tile bit i = the i-th lowest)

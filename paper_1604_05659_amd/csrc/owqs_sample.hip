@@ -184,6 +184,7 @@ __global__ __launch_bounds__(kB) void k_s_resolve(const DrawWin *__restrict__ wi
     const double f = double(op->f);
     op->coef = make_float2(float(f * double(float(c.x))), float(f * double(float(c.y))));
     op->flags = uint8_t((op->flags & ~7u) | uint32_t(i0) | (s0 < 0 ? 2u : 0u) | (s1 < 0 ? 4u : 0u));
+    round_words(*op);
   }
 }
 

@@ -60,19 +60,36 @@ __device__ __forceinline__ float in_vgpr(float x) {
   asm volatile("" : "+v"(x));
   return x;
 }
+// The vector as a buffer resource, for vectors whose byte offsets all fit
+// 32 bits (live width 29 or less): a load or store then takes the
+// uniform part of its offset in a scalar register and the thread's part in a
+// vector one, with no vector instruction to form the address.  Word 3 is the
+// format CDNA's untyped buffer access takes (32-bit data).
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(float2 *psi) {
+  return __builtin_amdgcn_make_buffer_rsrc(psi, 0, 0xFFFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__uint_as_float(w[0]), __uint_as_float(w[1]));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float2 v) {
+  const u32x2 w = {__float_as_uint(v.x), __float_as_uint(v.y)};
+  __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
+}
 __device__ __forceinline__ float2 &at(char *lds, uint32_t byte_off) { return *reinterpret_cast<float2 *>(lds + byte_off); }
 
 // One command of the group, read as whole dwords from a uniform address so
 // that it comes through scalar loads (its byte fields are unpacked after).
 __device__ __forceinline__ FuseOp load_op(const FuseOp *__restrict__ ops, int o) {
-  static_assert(sizeof(FuseOp) == 48, "FuseOp is 12 dwords");
+  static_assert(sizeof(FuseOp) == 64, "FuseOp is 16 dwords");
   // the command table is never written by the kernels: read it through the
   // constant address space, which the scalar unit may always load
   typedef const __attribute__((address_space(4))) uint32_t cword;
-  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(ops)) + 12 * __builtin_amdgcn_readfirstlane(o);
-  uint32_t w[12];
+  cword *src = reinterpret_cast<cword *>(reinterpret_cast<uintptr_t>(ops)) + 16 * __builtin_amdgcn_readfirstlane(o);
+  uint32_t w[16];
 #pragma unroll
-  for (int i = 0; i < 12; ++i) w[i] = src[i];
+  for (int i = 0; i < 16; ++i) w[i] = src[i];
   FuseOp op;
   __builtin_memcpy(&op, w, sizeof(op));
   return op;
@@ -207,46 +224,75 @@ struct WinP {
 // for runs with one coefficient per set: FuseOp::coef holds the window's
 // factor times its coefficient, so fc0 = fa c0 is that product with a sign.
 // Sigma, which the group's first window applies (flag bit 4), is applied to
-// the tile as it is loaded (see tile_one).
-__device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const TileArgs &ta) {
+// the tile as it is loaded (see tile_one).  A register round passes two more
+// signs: cs, a sign of fc0 (the pending sign of the window's position), and
+// fold_r, which makes fb carry r (the round stores r o1).  Every sign is
+// applied to the words before they move to vector registers: a sign applied
+// after the move would cost a vector instruction per word and window.
+__device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const TileArgs &ta, uint32_t cs = 0u,
+                                            bool fold_r = false) {
   constexpr uint32_t kS = 0x80000000u;
   WinP w;
   const uint32_t fl = op_flags(op, ta);
   const bool sw = fl & 1u;
-  // signs of fa, fb (the factor) and of c0 (the coefficient) on this tile
-  uint32_t sa = 0u, sb = par64(ob & op.omask_o1) << 31;
-  if (fl & 2u) { if (sw) sb ^= kS; else sa ^= kS; }
-  if (fl & 4u) { if (sw) sa ^= kS; else sb ^= kS; }
+  // signs of fa, fb (the factor) and of c0 (the coefficient) on this tile:
+  // flag bits 1 and 2 negate o0 and o1, which are exchanged by the swap
+  const uint32_t n0 = (fl << 30) & kS, n1 = (fl << 29) & kS;
+  const uint32_t sa = sw ? n1 : n0;
+  const uint32_t sb = (par64(ob & op.omask_o1) << 31) ^ (sw ? n0 : n1);
   const uint32_t sc = par64(ob & op.omask_b) << 31;
-  const float f = op.f;
-  float2 fc = op.coef;
-  if (ta.coefs) {  // one coefficient per set
+  uint32_t cx = __float_as_uint(op.coef.x), cy = __float_as_uint(op.coef.y);
+  if (ta.coefs) {  // one coefficient per set: uniform, back to scalar words
     const float2 cw = set_coef(ta, op.m_index);
-    fc = make_float2(f * cw.x, f * cw.y);
+    cx = __builtin_amdgcn_readfirstlane(__float_as_uint(op.f * cw.x));
+    cy = __builtin_amdgcn_readfirstlane(__float_as_uint(op.f * cw.y));
   }
-  float fa = xsign(f, sa), fb = xsign(f, sb);
-  float2 fc0 = xsign2(fc, sa ^ sc);
+  const uint32_t f = __float_as_uint(op.f);
+  uint32_t fa = f ^ sa, fb = f ^ sb;
+  uint32_t c0 = sa ^ sc ^ cs;  // the sign of fc0 = fa c0
   // o1 = fb a + fb s1 c0 b = fb a + r fc0 b, r = s1 fb / fa (|fa| = |fb|)
-  const bool s1neg = !(fl & 8u);
-  const bool rneg = s1neg != (sa != sb);
+  const uint32_t rs = ((fl & 8u) ? 0u : kS) ^ sa ^ sb;  // sign bit of r
   const bool masked = (op.lmask_b | op.lmask_o1) != 0;
   if (!masked && sw) {
-    const float t = fa;
+    const uint32_t t = fa;
     fa = fb;
     fb = t;
-    if (rneg) fc0 = xsign2(fc0, kS);
+    c0 ^= rs;
   }
+  if (fold_r) fb ^= rs;
   // the factors go to vector registers: the window arithmetic of the other
   // paths then takes the short (VOP2) encodings, which scalar operands rule out
-  w.fa = in_vgpr(fa);
-  w.fb = in_vgpr(fb);
-  w.fc0 = make_float2(in_vgpr(fc0.x), in_vgpr(fc0.y));
-  w.rsign = rneg ? kS : 0u;
+  w.fa = in_vgpr(__uint_as_float(fa));
+  w.fb = in_vgpr(__uint_as_float(fb));
+  w.fc0 = make_float2(in_vgpr(__uint_as_float(cx ^ c0)), in_vgpr(__uint_as_float(cy ^ c0)));
+  w.rsign = rs;
   w.lmb = op.lmask_b;
   w.lmo = op.lmask_o1;
   w.lb = op.lb;
   w.widx = op.widx;
-  w.kind = masked ? (sw ? kWinMaskedSw : kWinMasked) : (rneg ? kWinMinus : kWinPlus);
+  w.kind = masked ? (sw ? kWinMaskedSw : kWinMasked) : (rs ? kWinMinus : kWinPlus);
+  return w;
+}
+
+// A window of a register round from its resolved words (round_words): on
+// this tile, p1 and p2 are the parities of the outer bits of mask_o1 and
+// mask_b; pj is the pending sign of the window's position, applied to c0
+// (b arrives as -b); fb carries r.  A dozen scalar instructions.
+__device__ __forceinline__ WinP prep_round(const FuseOp &op, uint64_t ob, uint32_t pj) {
+  const uint32_t p1 = par64(ob & op.omask_o1) << 31, p2 = par64(ob & op.omask_b) << 31;
+  const uint32_t x = p1 & op.rw_fold;
+  const uint32_t cs = op.rw_cs ^ x ^ p2 ^ (pj << 31);
+  WinP w;
+  w.fa = in_vgpr(__uint_as_float(op.rw_fa ^ x));
+  w.fb = in_vgpr(__uint_as_float(op.rw_fbr ^ x));
+  w.fc0 = make_float2(in_vgpr(__uint_as_float(__float_as_uint(op.coef.x) ^ cs)),
+                      in_vgpr(__uint_as_float(__float_as_uint(op.coef.y) ^ cs)));
+  w.rsign = op.rw_rs ^ p1;
+  w.lmb = 0u;
+  w.lmo = 0u;
+  w.lb = op.lb;
+  w.widx = op.widx;
+  w.kind = w.rsign ? kWinMinus : kWinPlus;
   return w;
 }
 
@@ -506,32 +552,33 @@ __device__ __forceinline__ void pair_update(float2 &a, float2 &b, float2 fc, flo
       : [cx] "v"(fc.x), [cy] "v"(fc.y), [fa] "v"(fa), [fb] "v"(fbr));
 }
 
-// A window on cube bit J (no local masks: rounds hold no masked windows).
+// A window on cube bit J (no local masks: rounds hold no masked windows),
+// its parameters prepared with the pending sign of position J in fc0 and r
+// in fb (prep_window's cs and fold_r).
 template <int J, int kC, bool kAcc>
 __device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP &w, uint32_t &pend) {
   constexpr int kPer = 1 << kC;
   constexpr int kB = 1 << J;
-  const float2 fc = xsign2(w.fc0, ((pend >> J) & 1u) << 31);  // sign work on uniform words
-  const float fbr = xsign(w.fb, w.rsign);
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     if (q & kB) continue;
-    pair_update(x[q], x[q + kB], fc, w.fa, fbr);
+    pair_update(x[q], x[q + kB], w.fc0, w.fa, w.fb);
     if (kAcc) acc += nrm2d(x[q], x[q + kB]);
   }
-  pend = w.rsign ? (pend | (1u << J)) : (pend & ~(1u << J));
+  pend = (pend & ~(1u << J)) | ((w.rsign >> 31) << J);
   return acc;
 }
 
 // E or Z in a round: negate the amplitudes whose local bits m are all set
 // (the bits outside the cube decide per thread, the cube bits per q: a
 // uniform branch per q, so only the amplitudes it can flip are touched).
+// e8: the thread's byte offset in the tile (its local index times 8).
 template <int kC>
-__device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t el, uint32_t m, uint32_t cmask,
+__device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t e8, uint32_t m, uint32_t cmask,
                                            const int *b) {
-  const uint32_t mr = m & ~cmask, cm = cube_part<kC>(m, b);
-  const uint32_t neg = (el & mr) == mr ? 0x80000000u : 0u;
+  const uint32_t mr8 = (m & ~cmask) << 3, cm = cube_part<kC>(m, b);
+  const uint32_t neg = (e8 & mr8) == mr8 ? 0x80000000u : 0u;
 #pragma unroll
   for (int q = 0; q < (1 << kC); ++q)
     if ((uint32_t(q) & cm) == cm) x[q] = xsign2(x[q], neg);  // uniform condition
@@ -568,14 +615,22 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
     for (int i = 0; i < kC; ++i) v |= uint32_t((q >> i) & 1) << b[i];
     qb[q] = v;
   }
+  // the thread's byte offset, hidden from the compiler so that each
+  // amplitude's address stays one OR with a uniform word (it would fold the
+  // shift back into every address otherwise)
+  uint32_t e8 = el << 3;
+  opaque32(e8);
   float2 x[kPer];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) x[q] = at(lds, (el | qb[q]) << 3);
+  for (int q = 0; q < kPer; ++q) x[q] = at(lds, e8 | (qb[q] << 3));
   uint32_t pend = 0;
   // one window of the sweep on position J: its norm into wacc (kRed)
   auto window = [&](auto jc, const FuseOp &op) {
     constexpr int J = decltype(jc)::value;
-    const WinP w = prep_window(op, ob, ta);
+    // coefficients per set or corrections read per run: the words of the
+    // command table do not hold them
+    const WinP w = (ta.coefs || ta.folds) ? prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true)
+                                          : prep_round(op, ob, (pend >> J) & 1u);
     if (kRed) {
       const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
       if (lane == 63) wacc[w.widx][wave] += d;
@@ -588,7 +643,7 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
     const uint32_t pm = h.flags;
     for (int d = 0; d < h.m_index; ++d) {
       const FuseOp e = load_op(ops, o++);
-      if ((ob & e.omask_b) == e.omask_b) round_diag<kC>(x, el, e.lmask_b, cmask, b);
+      if ((ob & e.omask_b) == e.omask_b) round_diag<kC>(x, e8, e.lmask_b, cmask, b);
     }
     if (pm & 1u) window(std::integral_constant<int, 0>(), load_op(ops, o++));
     if (pm & 2u) window(std::integral_constant<int, 1>(), load_op(ops, o++));
@@ -603,9 +658,9 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
         if (q & (1 << j)) x[q] = xsign2(x[q], 0x80000000u);
     }
   }
-  opaque32(el);  // the store recomputes its addresses: they are not held over the commands
+  opaque32(e8);  // the store recomputes its addresses: they are not held over the commands
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) at(lds, (el | qb[q]) << 3) = x[q];
+  for (int q = 0; q < kPer; ++q) at(lds, e8 | (qb[q] << 3)) = x[q];
 }
 
 // The global bit of each tile bit above the thread index (tile bits
@@ -643,15 +698,31 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
   const int lane = tid & 63, wave = tid >> 6;
   const uint64_t ob = pdep64(t, ta.omask);
   uint64_t gb = ob | g_tid;
+  // every byte offset of the vector below 2^32 (live width 29 or less): the
+  // tile moves through buffer loads and stores (see vec_rsrc)
+  const bool narrow = ((ta.tmask | ta.omask) >> 29) == 0;
+  const __amdgpu_buffer_rsrc_t rsrc = vec_rsrc(psi);
   {
     float2 v[kPer];
+    if (narrow) {
+      const uint32_t toff = uint32_t(g_tid) << 3;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      uint64_t g = gb;
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t u = ob;
 #pragma unroll
-      for (int j = 0; j < kHi; ++j)
-        if ((r >> j) & 1) g |= hp[j];
-      v[r] = psi[g];
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) u |= hp[j];
+        v[r] = buf_ld(rsrc, toff, uint32_t(u) << 3);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
+#pragma unroll
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        v[r] = psi[g];
+      }
     }
     if (ta.nwin > 0 && sg != 1.0) {  // sigma, for the group's first window: applied to the whole tile
       const float gs = float(sg);
@@ -750,13 +821,25 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
       for (int r = 0; r < kPer; r += 2) rsum += nrm2d(v[r], v[r + 1]);
     }
     opaque(gb);  // the load's addresses are not kept live over the commands: recomputed here
+    if (narrow) {
+      const uint32_t toff = uint32_t(g_tid) << 3;
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      uint64_t g = gb;
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t u = ob;
 #pragma unroll
-      for (int j = 0; j < kHi; ++j)
-        if ((r >> j) & 1) g |= hp[j];
-      psi[g] = v[r];
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) u |= hp[j];
+        buf_st(rsrc, toff, uint32_t(u) << 3, v[r]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) {
+        uint64_t g = gb;
+#pragma unroll
+        for (int j = 0; j < kHi; ++j)
+          if ((r >> j) & 1) g |= hp[j];
+        psi[g] = v[r];
+      }
     }
   }
   __syncthreads();
