@@ -233,6 +233,27 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const
                                             bool fold_r = false) {
   constexpr uint32_t kS = 0x80000000u;
   WinP w;
+  if (!ta.coefs && !ta.folds) {
+    // the words of the command table (round_words) hold every sign but those
+    // of this tile: p1 and p2, the parities of the outer bits of mask_o1 and
+    // mask_b (a dozen scalar instructions)
+    const uint32_t p1 = par64(ob & op.omask_o1) << 31, p2 = par64(ob & op.omask_b) << 31;
+    const uint32_t x = p1 & op.rw_fold;
+    const uint32_t rs = op.rw_rs ^ p1, fbr = op.rw_fbr ^ x, c = op.rw_cs ^ x ^ p2 ^ cs;
+    w.fa = in_vgpr(__uint_as_float(op.rw_fa ^ x));
+    w.fb = in_vgpr(__uint_as_float(fold_r ? fbr : fbr ^ rs));
+    w.fc0 = make_float2(in_vgpr(__uint_as_float(__float_as_uint(op.coef.x) ^ c)),
+                        in_vgpr(__uint_as_float(__float_as_uint(op.coef.y) ^ c)));
+    w.rsign = rs;
+    w.lmb = op.lmask_b;
+    w.lmo = op.lmask_o1;
+    w.lb = op.lb;
+    w.widx = op.widx;
+    const bool masked = (op.lmask_b | op.lmask_o1) != 0;
+    w.kind = masked ? ((op.flags & 1u) ? kWinMaskedSw : kWinMasked) : (rs ? kWinMinus : kWinPlus);
+    return w;
+  }
+  // coefficients per set, or corrections read per run: every sign from the flags
   const uint32_t fl = op_flags(op, ta);
   const bool sw = fl & 1u;
   // signs of fa, fb (the factor) and of c0 (the coefficient) on this tile:
@@ -271,28 +292,6 @@ __device__ __forceinline__ WinP prep_window(const FuseOp &op, uint64_t ob, const
   w.lb = op.lb;
   w.widx = op.widx;
   w.kind = masked ? (sw ? kWinMaskedSw : kWinMasked) : (rs ? kWinMinus : kWinPlus);
-  return w;
-}
-
-// A window of a register round from its resolved words (round_words): on
-// this tile, p1 and p2 are the parities of the outer bits of mask_o1 and
-// mask_b; pj is the pending sign of the window's position, applied to c0
-// (b arrives as -b); fb carries r.  A dozen scalar instructions.
-__device__ __forceinline__ WinP prep_round(const FuseOp &op, uint64_t ob, uint32_t pj) {
-  const uint32_t p1 = par64(ob & op.omask_o1) << 31, p2 = par64(ob & op.omask_b) << 31;
-  const uint32_t x = p1 & op.rw_fold;
-  const uint32_t cs = op.rw_cs ^ x ^ p2 ^ (pj << 31);
-  WinP w;
-  w.fa = in_vgpr(__uint_as_float(op.rw_fa ^ x));
-  w.fb = in_vgpr(__uint_as_float(op.rw_fbr ^ x));
-  w.fc0 = make_float2(in_vgpr(__uint_as_float(__float_as_uint(op.coef.x) ^ cs)),
-                      in_vgpr(__uint_as_float(__float_as_uint(op.coef.y) ^ cs)));
-  w.rsign = op.rw_rs ^ p1;
-  w.lmb = 0u;
-  w.lmo = 0u;
-  w.lb = op.lb;
-  w.widx = op.widx;
-  w.kind = w.rsign ? kWinMinus : kWinPlus;
   return w;
 }
 
@@ -627,10 +626,7 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
   // one window of the sweep on position J: its norm into wacc (kRed)
   auto window = [&](auto jc, const FuseOp &op) {
     constexpr int J = decltype(jc)::value;
-    // coefficients per set or corrections read per run: the words of the
-    // command table do not hold them
-    const WinP w = (ta.coefs || ta.folds) ? prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true)
-                                          : prep_round(op, ob, (pend >> J) & 1u);
+    const WinP w = prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true);
     if (kRed) {
       const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
       if (lane == 63) wacc[w.widx][wave] += d;
