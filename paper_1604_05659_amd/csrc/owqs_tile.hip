@@ -60,11 +60,13 @@ __device__ __forceinline__ float in_vgpr(float x) {
   asm volatile("" : "+v"(x));
   return x;
 }
-// The vector as a buffer resource, for vectors whose byte offsets all fit
-// 32 bits (live width 29 or less): a load or store then takes the
-// uniform part of its offset in a scalar register and the thread's part in a
-// vector one, with no vector instruction to form the address.  Word 3 is the
-// format CDNA's untyped buffer access takes (32-bit data).
+// The vector as a buffer resource, for live widths up to 28 (byte offsets
+// below 2^31): a load or store then takes the uniform part of its offset in
+// a scalar register and the thread's part in a vector one, with no vector
+// instruction to form the address.  The record count, 2^32 - 1 bytes at
+// most, leaves the last dword of a 2^29-amplitude vector outside the range
+// (read as 0, not written), so width 29 takes the global path.  Word 3 is
+// the format CDNA's untyped buffer access takes (32-bit data).
 typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(float2 *psi) {
   return __builtin_amdgcn_make_buffer_rsrc(psi, 0, 0xFFFFFFFF, 0x00020000);
@@ -694,9 +696,9 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
   const int lane = tid & 63, wave = tid >> 6;
   const uint64_t ob = pdep64(t, ta.omask);
   uint64_t gb = ob | g_tid;
-  // every byte offset of the vector below 2^32 (live width 29 or less): the
-  // tile moves through buffer loads and stores (see vec_rsrc)
-  const bool narrow = ((ta.tmask | ta.omask) >> 29) == 0;
+  // live width 28 or less: the tile moves through buffer loads and stores
+  // (see vec_rsrc)
+  const bool narrow = ((ta.tmask | ta.omask) >> 28) == 0;
   const __amdgpu_buffer_rsrc_t rsrc = vec_rsrc(psi);
   {
     float2 v[kPer];

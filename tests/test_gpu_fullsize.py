@@ -128,3 +128,29 @@ def test_plain_kernels_above_the_cache_against_oracle(ctx, nl, parity_report):
     parity_report(f"plain kernels at 2^{nl + 1}", max_err=err, infidelity=1 - _fidelity(got, want))
     assert err <= AMP_TOL
     np.testing.assert_allclose(probs, pw, atol=1e-5)
+
+
+@pytest.mark.parametrize("nl", [28, 29])
+def test_fused_at_the_buffer_offset_boundary(ctx, nl, parity_report):
+    """Tile passes at live width 28, the widest that moves its tiles through
+    buffer loads and stores (byte offsets up to 2^31 - 8), and at 29 (64-bit
+    global addresses; a buffer's record count, 2^32 - 1 bytes at most, would
+    leave the last dword of the vector out of range there): a short circuit
+    run fused and plain on the same seeded input, compared element by
+    element on the device (2^nl amplitudes, beyond what the oracle holds;
+    the plain kernels are checked against the oracle at every width above)."""
+    g = np.random.default_rng([160405659, 12, 0, nl])
+    pat = W.circuit_to_pattern(nl, W.random_jcz_circuit(nl, 4, 2, g))
+    outc = g.integers(0, 2, pat.n_meas()).astype(np.uint8)
+    gen = torch.Generator(device="cuda").manual_seed(160405659 + nl)
+    inp = torch.randn(1 << nl, dtype=torch.complex64, device="cuda", generator=gen)
+    inp /= torch.linalg.vector_norm(inp)
+    print(f"[fullsize] fused at width {nl}<->{nl + 1}, {len(pat.cmds)} commands", flush=True)
+    out_f, pf = _run(ctx, pat, outc, inp, owqs.EXEC_FUSED)
+    out_p, pp = _run(ctx, pat, outc, inp, owqs.EXEC_PLAIN)
+    err = float((out_f - out_p).abs().max().item())
+    norm = float(torch.linalg.vector_norm(out_f).item())
+    parity_report(f"fused vs plain at 2^{nl}", max_err=err, norm=norm)
+    assert err <= AMP_TOL, err
+    assert abs(norm - 1.0) <= 1e-4, norm
+    np.testing.assert_allclose(pf, pp, atol=1e-6)
