@@ -816,20 +816,32 @@ def main():
             _, roof_f = roofline_of(prof_f, names)
             result["fused"]["roofline"] = roof_f
             result["fused"]["kernels"] = kernel_table(prof_f)
-            # the tile pass against the vector ALU: a window's arithmetic is 8
-            # FP32 operations per amplitude pair (4 lane operations per
-            # amplitude), on the live width the passes run at; the peak is
-            # 256 CUs x 64 FP32 lanes x 2.4 GHz (packed FP32 is not used)
+            # the tile pass against the vector ALU, on the FP32 work it runs: a
+            # window applied alone is 8 FP32 operations per amplitude pair (4
+            # lane operations per amplitude), a composed 2x2 map 16 (8); on the
+            # live width the passes run at; the peak is 256 CUs x 64 FP32 lanes
+            # x 2.4 GHz (packed FP32 is not used)
             tile_us = roof_f.get("avg_launch_us", 0.0) * roof_f.get("launches_per_step", 0)
+            tw, tm, tc = pat.plan_tile_work()
+            result["fused"]["composition"] = {
+                "windows_alone": tw, "maps": tm, "windows_in_maps": tc,
+                "note": "windows in a row on one register-round position, with no E / Z on its bit between them, "
+                        "run as one 2x2 map (FP64 product rounded to FP32)"}
             if tile_us > 0:
-                lane_ops = 4.0 * float(1 << 24) * counts["M"]
+                lane_ops = float(1 << 24) * (4.0 * tw + 8.0 * tm)
                 achieved = lane_ops / (tile_us * 1e-6) / 1e12
                 peak = 256 * 64 * 2.4e9 / 1e12
+                per_window = 4.0 * float(1 << 24) * counts["M"] / (tile_us * 1e-6) / 1e12
                 result["fused"]["alu_roofline"] = {
                     "bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
                     "unit": "Tlane-op/s", "frac": round(achieved / peak, 4),
-                    "work": "4 FP32 lane operations per amplitude per window, %d windows at 2^24 amplitudes "
-                            "(E / Z and set-up not counted), over the tile passes' event time" % counts["M"]}
+                    "work": "executed FP32 work at 2^24 amplitudes: 4 lane operations per amplitude for each of the "
+                            "%d windows applied alone, 8 for each of the %d composed maps (E / Z, set-up and LDS "
+                            "rounds not counted), over the tile passes' event time" % (tw, tm),
+                    "per_window_equivalent": {
+                        "achieved": round(per_window, 2), "frac": round(per_window / peak, 4),
+                        "work": "4 lane operations per amplitude for every one of the %d windows, as if none "
+                                "were composed, over the same time" % counts["M"]}}
         if prof:
             # each tile pass carries about nontrivial / passes commands in one
             # HBM round trip: the plain executor's algorithmic bytes for the

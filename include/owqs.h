@@ -247,6 +247,18 @@ owqs_status owqs_tune_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npa
  * grouped into tile passes.  Any pointer may be NULL. */
 owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps, size_t *npasses);
 
+/* The tile passes of the fused plan (global-memory executor; 0s for other
+ * plans) as they run with forced outcomes and without window sums: windows
+ * applied one by one (*windows), and runs of windows on one register-round
+ * position (Sec. 4.4: each window is a fixed 2x2 map on its pair once its
+ * outcome is known) composed into one 2x2 map each (*maps, covering
+ * *composed windows).  Every window of a pass is in exactly one of the two,
+ * so *windows + *composed is the passes' window count.  A map costs the
+ * FP32 work of two windows.  Passes with window sums and runs with drawn
+ * outcomes apply every window on its own.  Compiles the plan if needed; any
+ * pointer may be NULL. */
+owqs_status owqs_plan_tile_work(owqs_pattern *pat, size_t *windows, size_t *maps, size_t *composed);
+
 /* Recognition problem (Sec. 1: which unitary does a pattern implement):
  * run the pattern on the computational-basis inputs |first>, ...,
  * |first + count - 1> and write output k (2^nout complex64) to

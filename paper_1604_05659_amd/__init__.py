@@ -93,6 +93,8 @@ _sig = {
     "owqs_tune": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, _vp, _i32p,
                                  ctypes.POINTER(ctypes.c_float)]),
     "owqs_plan_info": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "owqs_plan_tile_work": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
     "owqs_run_basis": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_states": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _vp, _vp, _vp]),
     "owqs_run_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
@@ -329,6 +331,15 @@ class Pattern:
         x = ctypes.c_size_t()
         self.ctx.check(_lib.owqs_plan_info(self._h, ctypes.byref(w), ctypes.byref(n), ctypes.byref(x)))
         return w.value, n.value, x.value
+
+    def plan_tile_work(self):
+        """(windows applied one by one, composed 2x2 maps, windows inside the
+        maps) of the fused plan's tile passes, forced outcomes, no window sums."""
+        w = ctypes.c_size_t()
+        m = ctypes.c_size_t()
+        c = ctypes.c_size_t()
+        self.ctx.check(_lib.owqs_plan_tile_work(self._h, ctypes.byref(w), ctypes.byref(m), ctypes.byref(c)))
+        return w.value, m.value, c.value
 
     def run_basis(self, first: int = 0, count: Optional[int] = None, out=None, probs=None, stream=None):
         """Outputs for basis inputs |first> .. |first+count-1> as a

@@ -13,6 +13,7 @@
 //   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
 //     into its pass (with the device FP64 sigma in OWQS mode).
 #include <atomic>
+#include <complex>
 
 #include "owqs_host_impl.h"
 #include "owqs_pattern_access.h"
@@ -236,6 +237,157 @@ std::vector<RoundItem> schedule_rounds(const std::vector<FuseOp> &g, int k, bool
   return out;
 }
 
+namespace {
+
+using cplx = std::complex<double>;
+
+float word_f(uint32_t w) {
+  float f;
+  __builtin_memcpy(&f, &w, sizeof(f));
+  return f;
+}
+
+uint32_t f_word(double x) {
+  const float f = float(x);
+  uint32_t w;
+  __builtin_memcpy(&w, &f, sizeof(w));
+  return w;
+}
+
+// A window's map on true amplitudes as a register round applies it (no
+// masks, no sign pending on its position): t = c b, o0 = fa a + t, and the
+// round stores fbr a + t for o1 = r (fbr a + t), r the sign of rw_rs (see
+// round_words).  Row-major 2x2.
+void window_map(const FuseOp &w, cplx m[4]) {
+  const uint32_t cs = w.rw_cs & 0x80000000u;
+  uint32_t cx, cy;
+  __builtin_memcpy(&cx, &w.coef.x, sizeof(cx));
+  __builtin_memcpy(&cy, &w.coef.y, sizeof(cy));
+  const cplx c(word_f(cx ^ cs), word_f(cy ^ cs));
+  const double fa = word_f(w.rw_fa), fbr = word_f(w.rw_fbr), r = (w.rw_rs & 0x80000000u) ? -1.0 : 1.0;
+  m[0] = fa;
+  m[1] = c;
+  m[2] = r * fbr;
+  m[3] = r * c;
+}
+
+// A window whose map is the same on every tile and in every order of the
+// round: no local or outer masks, and p = 1/2 exactly (an odd E(v, w) count).
+bool composable(const FuseOp &w) {
+  return w.kind == DK_J && (w.lmask_b | w.lmask_o1) == 0 && (w.omask_b | w.omask_o1) == 0 && !(w.flags & 8u);
+}
+
+}  // namespace
+
+// Windows on one position of a register round (one mixing bit) that follow
+// each other with no E / Z on that bit between them commute with everything
+// else between them (windows on other positions, E / Z on other bits), so
+// the earlier ones may move up to the last one and the run is one linear
+// map on the pair: the product of their 2x2 maps, formed in FP64 and rounded
+// once to FP32.  It replaces the last window of the run (a DK_U row); the
+// others leave their sweeps.  A DK_U costs the FP32 work of two windows.
+bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out) {
+  const int kc = tile_cube_bits(tile_bits);
+  struct Sweep {
+    FuseOp head;
+    std::vector<FuseOp> diag;
+    FuseOp win[4];
+    bool has[4] = {false, false, false, false};
+  };
+  std::vector<FuseOp> res;
+  res.reserve(size_t(nops));
+  bool any = false;
+  for (int q = 0; q < nops; ++q) {
+    if (ops[q].kind != DK_R) {
+      res.push_back(ops[q]);
+      continue;
+    }
+    const FuseOp rh = ops[q];
+    const int end = q + 1 + rh.m_index;
+    std::vector<Sweep> sw;
+    for (int o = q + 1; o < end;) {
+      Sweep w;
+      w.head = ops[o++];
+      for (int d = 0; d < w.head.m_index; ++d) w.diag.push_back(ops[o++]);
+      for (int pos = 0; pos < kc; ++pos)
+        if ((w.head.flags >> pos) & 1u) {
+          w.win[pos] = ops[o++];
+          w.has[pos] = true;
+        }
+      sw.push_back(w);
+    }
+    q = end - 1;
+    for (int pos = 0; pos < kc; ++pos) {
+      const uint32_t bit = 1u << ((rh.lmask_b >> (8 * pos)) & 0xFFu);
+      std::vector<size_t> run;
+      auto flush = [&]() {
+        if (run.size() >= 2) {
+          cplx u[4] = {1.0, 0.0, 0.0, 1.0};
+          for (size_t i : run) {  // u <- W u, in the order the windows run
+            cplx w[4];
+            window_map(sw[i].win[pos], w);
+            const cplx n0 = w[0] * u[0] + w[1] * u[2], n1 = w[0] * u[1] + w[1] * u[3];
+            const cplx n2 = w[2] * u[0] + w[3] * u[2], n3 = w[2] * u[1] + w[3] * u[3];
+            u[0] = n0;
+            u[1] = n1;
+            u[2] = n2;
+            u[3] = n3;
+          }
+          const FuseOp last = sw[run.back()].win[pos];
+          FuseOp m{};
+          m.kind = DK_U;
+          m.lb = last.lb;
+          m.widx = last.widx;
+          m.m_index = last.m_index;
+          m.coef = make_float2(float(u[0].real()), float(u[0].imag()));
+          m.lmask_o1 = f_word(u[1].real());
+          m.rw_rs = f_word(u[1].imag());
+          m.rw_fa = f_word(u[2].real());
+          m.rw_fbr = f_word(u[2].imag());
+          m.rw_cs = f_word(u[3].real());
+          m.rw_fold = f_word(u[3].imag());
+          for (size_t i = 0; i + 1 < run.size(); ++i) sw[run[i]].has[pos] = false;
+          sw[run.back()].win[pos] = m;
+          any = true;
+        }
+        run.clear();
+      };
+      for (size_t i = 0; i < sw.size(); ++i) {
+        for (const FuseOp &d : sw[i].diag)
+          if (d.lmask_b & bit) {  // an E / Z on this bit ends the run
+            flush();
+            break;
+          }
+        if (!sw[i].has[pos]) continue;
+        if (composable(sw[i].win[pos])) {
+          run.push_back(i);
+        } else {
+          flush();
+        }
+      }
+      flush();
+    }
+    const size_t at = res.size();
+    res.push_back(rh);
+    for (const Sweep &w : sw) {
+      uint32_t pm = 0;
+      for (int pos = 0; pos < kc; ++pos)
+        if (w.has[pos]) pm |= 1u << pos;
+      if (pm == 0 && w.diag.empty()) continue;
+      FuseOp h = w.head;
+      h.flags = uint8_t(pm);
+      res.push_back(h);
+      for (const FuseOp &d : w.diag) res.push_back(d);
+      for (int pos = 0; pos < kc; ++pos)
+        if (w.has[pos]) res.push_back(w.win[pos]);
+    }
+    res[at].m_index = int(res.size() - at - 1);
+  }
+  if (!any) return false;
+  out.swap(res);
+  return true;
+}
+
 // Group runs of window/E/X/Z steps at one width >= kTileMinWidth into tile
 // passes (see owqs_tile.hip).  A pass ends at N or M steps and at a width
 // change; steps whose mixing slot would not fit the tile, or windows beyond
@@ -245,7 +397,8 @@ std::vector<RoundItem> schedule_rounds(const std::vector<FuseOp> &g, int k, bool
 // `groups`, its commands to `fops` and its windows' measurement indices to
 // `fm`.
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
-                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm, bool big_half) {
+                 std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm, bool big_half,
+                 std::vector<FuseOp> *mops) {
   const size_t ns = steps.size();
   // windows of a pass chain their norms in FP32 without renormalising: 16
   // keep it in range down to p ~ 1e-4 per window; windows with p = 1/2
@@ -401,6 +554,14 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     }
     tg.ta.nops = int(fops.size() - tg.op_off);
     tg.ta.nwin = widx;
+    if (mops) {
+      std::vector<FuseOp> m;
+      if (merge_round_windows(fops.data() + tg.op_off, tg.ta.nops, k, m)) {
+        tg.mop_off = mops->size();
+        tg.mnops = int(m.size());
+        mops->insert(mops->end(), m.begin(), m.end());
+      }
+    }
     tg.half = widx > 0 && !even;
     // compile the register runs in only where two windows on different bits
     // follow each other outside rounds, possibly with an E or Z between
@@ -440,12 +601,13 @@ void group_tiles(owqs_pattern *p) {
   p->groups.clear();
   p->fuse_ops.clear();
   p->fuse_m.clear();
+  p->fuse_mops.clear();
   if (p->exec == OWQS_EXEC_PLAIN) {
     p->xsteps = p->steps;
     return;
   }
   group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m,
-              p->mode == OWQS_MODE_OWQS && p->half_cap > 0);
+              p->mode == OWQS_MODE_OWQS && p->half_cap > 0, &p->fuse_mops);
   if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups, p->half_cap);
   else
     for (TileGroup &tg : p->groups) tg.half = false;
@@ -958,6 +1120,10 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
           ta.half_m = fuse_m_dev(p) + tg.m_off;
           ta.renorm = tg.renorm ? 1 : 0;
         }
+        if (tg.mnops > 0 && !ctab && a.reduce == kReduceNone) {  // no window sums: the composed commands
+          ops = p->dev_fuse + fuse_mops_base(p->fuse_ops.size(), p->fuse_m.size()) + tg.mop_off;
+          ta.nops = tg.mnops;
+        }
         e = launch_tile(psi, ta, ops, a, s, &grid);
         break;
       }
@@ -981,12 +1147,17 @@ hipError_t launch_steps(owqs_pattern *p, int reduce, hipStream_t s, std::vector<
 
 // Upload the tile groups' command table: FuseOps, then the windows'
 // measurement indices.
+size_t fuse_mops_base(size_t nfops, size_t nfm) {
+  return nfops + (nfm * sizeof(int) + sizeof(FuseOp) - 1) / sizeof(FuseOp);
+}
+
 owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, const std::vector<int> &fm,
-                              FuseOp *&dev, size_t &cap) {
+                              FuseOp *&dev, size_t &cap, const std::vector<FuseOp> *mops) {
   static const hipError_t prep = tile_prepare();  // once per process, outside any capture
   if (prep != hipSuccess) return hip_fail(ctx, prep, "tile kernel attribute");
-  const size_t mints = (fm.size() * sizeof(int) + sizeof(FuseOp) - 1) / sizeof(FuseOp);
-  const size_t need = std::max<size_t>(fops.size() + mints, 1);
+  const size_t base = fuse_mops_base(fops.size(), fm.size());
+  const size_t nm = mops ? mops->size() : 0;
+  const size_t need = std::max<size_t>(base + nm, 1);
   hipError_t e = hipSuccess;
   if (dev) (void)hipDeviceSynchronize();  // a run in flight may still read the old table
   if (cap < need) {
@@ -1001,13 +1172,15 @@ owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, co
   if (e == hipSuccess && !fm.empty())
     e = hipMemcpy(reinterpret_cast<int *>(dev + fops.size()), fm.data(), fm.size() * sizeof(int),
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess && nm) e = hipMemcpy(dev + base, mops->data(), nm * sizeof(FuseOp), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(ctx, e, "fused command table upload");
   return OWQS_OK;
 }
 
 owqs_status upload_fuse(owqs_pattern *p) {
   if (p->dev_fuse_valid && !p->fuse_patched) return OWQS_OK;
-  const owqs_status st = upload_fuse_table(p->ctx, p->fuse_ops, p->fuse_m, p->dev_fuse, p->dev_fuse_cap);
+  const owqs_status st =
+      upload_fuse_table(p->ctx, p->fuse_ops, p->fuse_m, p->dev_fuse, p->dev_fuse_cap, &p->fuse_mops);
   if (st == OWQS_OK) {
     p->dev_fuse_valid = true;
     p->fuse_patched = false;
@@ -1675,6 +1848,33 @@ owqs_status owqs_plan_info(owqs_pattern *p, int32_t *plan_width, size_t *nsteps,
   if (plan_width) *plan_width = p->plan_width;
   if (nsteps) *nsteps = substates(p) ? p->ss_steps.size() : p->steps.size();
   if (npasses) *npasses = substates(p) ? p->ss_run.size() : p->xsteps.size();
+  return OWQS_OK;
+}
+
+owqs_status owqs_plan_tile_work(owqs_pattern *p, size_t *windows, size_t *maps, size_t *composed) {
+  if (!p) return OWQS_E_INVALID_ARG;
+  if (owqs_status w = width_guard(p)) return w;
+  if (p->dirty) compile(p);
+  size_t nw = 0, nm = 0, nc = 0;
+  const int reduce = reduce_of(p);
+  if (!substates(p))
+    for (const TileGroup &tg : p->groups) {
+      size_t gw = 0, gm = 0;
+      // the commands a forced run launches (launch_range): composed where the pass sums no window
+      const bool comp = tg.mnops > 0 && (reduce == kReduceNone || (reduce == kReduceRenorm && tg.half));
+      const FuseOp *ops = comp ? p->fuse_mops.data() + tg.mop_off : p->fuse_ops.data() + tg.op_off;
+      const int nops = comp ? tg.mnops : tg.ta.nops;
+      for (int i = 0; i < nops; ++i) {
+        gw += ops[i].kind == DK_J;
+        gm += ops[i].kind == DK_U;
+      }
+      nw += gw;
+      nm += gm;
+      nc += size_t(tg.ta.nwin) - gw;
+    }
+  if (windows) *windows = nw;
+  if (maps) *maps = nm;
+  if (composed) *composed = nc;
   return OWQS_OK;
 }
 

@@ -70,6 +70,11 @@ struct TileGroup {
   bool half;      // OWQS mode: it has windows, each with an odd E(v, w) count (p = 1/2 exactly), and
                   // runs without a reduction (mark_half)
   bool renorm;    // half, and it ends a run of such windows: its output norm resets sigma (mark_half)
+  // the group's commands with runs of windows on one round position composed
+  // (DK_U), for passes without window sums and without drawn outcomes:
+  // mnops rows from mop_off in the pattern's composed table (0: none)
+  size_t mop_off;
+  int mnops;
 };
 
 // Sub-state executor (OWQS_EXEC_SUBSTATES).  A chain is one sub-state's
@@ -156,7 +161,8 @@ struct owqs_pattern {
   std::vector<TileGroup> groups;
   std::vector<FuseOp> fuse_ops;
   std::vector<int> fuse_m;        // measurement index of every window of every group
-  FuseOp *dev_fuse = nullptr;     // fuse_ops, then fuse_m (as int) in one allocation
+  std::vector<FuseOp> fuse_mops;  // composed copies of the groups' commands (TileGroup::mop_off)
+  FuseOp *dev_fuse = nullptr;     // fuse_ops, then fuse_m (as int), then fuse_mops in one allocation
   size_t dev_fuse_cap = 0;
   bool dev_fuse_valid = false;
 
@@ -287,11 +293,18 @@ constexpr size_t kGroupSkipMax = 128;
 bool commute_steps(const Step &a, const Step &b);
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm,
-                 bool big_half = false);
+                 bool big_half = false, std::vector<FuseOp> *mops = nullptr);
+// The commands of one group (nops rows) with every run of two or more
+// windows in a row on one register-round position composed into one DK_U
+// row; false (and `out` unchanged) when nothing composes.
+bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out);
 // Copy a tile-pass command table (FuseOps, then the windows' measurement
-// indices as int) to the device, growing `dev` as needed.
+// indices as int, then the composed commands `mops` from a FuseOp boundary)
+// to the device, growing `dev` as needed.
 owqs_status upload_fuse_table(owqs_ctx *ctx, const std::vector<FuseOp> &fops, const std::vector<int> &fm,
-                              FuseOp *&dev, size_t &cap);
+                              FuseOp *&dev, size_t &cap, const std::vector<FuseOp> *mops = nullptr);
+// Rows before the composed commands in a table upload_fuse_table wrote.
+size_t fuse_mops_base(size_t nfops, size_t nfm);
 int *fuse_m_dev(owqs_pattern *p);
 // An OWQS window with an odd E(v, w) count: p = 1/2 exactly, no reduction.
 bool half_prob(const Step &x, int reduce);

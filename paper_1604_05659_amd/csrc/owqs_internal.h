@@ -83,7 +83,9 @@ __host__ __device__ inline Window window_of(const DevStep &st) {
   return w;
 }
 
-enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5, DK_R = 6, DK_S = 7 };
+// DK_U: windows in a row on one register-round position composed into one
+// 2x2 map (see merge_round_windows); it takes a window's place in a sweep.
+enum DevKind : uint8_t { DK_N = 0, DK_E = 1, DK_M = 2, DK_X = 3, DK_Z = 4, DK_J = 5, DK_R = 6, DK_S = 7, DK_U = 8 };
 
 // ---- tile fusion (owqs_tile.hip)
 constexpr int kLowBits = 5;            // slots 0..4 are always in a tile (256-byte runs)
@@ -124,6 +126,10 @@ struct FuseOp {
   // sign mask (0 or bit 31) of the folded exchange
   uint32_t rw_fa, rw_fbr, rw_cs, rw_fold;
 };  // 64 bytes
+// A DK_U row (a composed 2x2 map o0 = m00 a + m01 b, o1 = m10 a + m11 b on
+// true amplitudes) keeps lb and holds its four complex entries as FP32 words:
+// m00 in coef, m01 in (lmask_o1, rw_rs), m10 in (rw_fa, rw_fbr), m11 in
+// (rw_cs, rw_fold); lmask_b, omask_b and omask_o1 are 0.
 
 // A window's parameters with its tile-independent signs resolved, as a
 // register round takes them: the window maps the pair (a, b) to

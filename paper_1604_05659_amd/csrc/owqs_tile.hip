@@ -571,6 +571,54 @@ __device__ __forceinline__ double round_window(float2 (&x)[1 << kC], const WinP 
   return acc;
 }
 
+// A composed map on one pair in place: o0 = m00 a + m01 b, o1 = m10 a + m11 b
+// (complex entries).  m10 a goes to temporaries first, then a is updated in
+// place from the old a and b, then b from the old b: four FP32 products and
+// twelve FMAs, with no register moves (one asm statement, as pair_update).
+__device__ __forceinline__ void pair_map(float2 &a, float2 &b, float2 m00, float2 m01, float2 m10, float2 m11) {
+  float t0, t1, t2, t3;
+  asm("v_mul_f32 %[t2], %[m10y], %[ay]\n\t"
+      "v_mul_f32 %[t3], %[m10y], %[ax]\n\t"
+      "v_fma_f32 %[t2], %[m10x], %[ax], -%[t2]\n\t"
+      "v_fma_f32 %[t3], %[m10x], %[ay], %[t3]\n\t"
+      "v_mul_f32 %[t0], %[m00y], %[ay]\n\t"
+      "v_mul_f32 %[t1], %[m00y], %[ax]\n\t"
+      "v_fma_f32 %[ax], %[m00x], %[ax], -%[t0]\n\t"
+      "v_fma_f32 %[ay], %[m00x], %[ay], %[t1]\n\t"
+      "v_fma_f32 %[ax], %[m01x], %[bx], %[ax]\n\t"
+      "v_fma_f32 %[ay], %[m01x], %[by], %[ay]\n\t"
+      "v_fma_f32 %[ax], -%[m01y], %[by], %[ax]\n\t"
+      "v_fma_f32 %[ay], %[m01y], %[bx], %[ay]\n\t"
+      "v_fma_f32 %[t2], -%[m11y], %[by], %[t2]\n\t"
+      "v_fma_f32 %[t3], %[m11y], %[bx], %[t3]\n\t"
+      "v_fma_f32 %[bx], %[m11x], %[bx], %[t2]\n\t"
+      "v_fma_f32 %[by], %[m11x], %[by], %[t3]"
+      : [ax] "+v"(a.x), [ay] "+v"(a.y), [bx] "+v"(b.x), [by] "+v"(b.y), [t0] "=&v"(t0), [t1] "=&v"(t1),
+        [t2] "=&v"(t2), [t3] "=&v"(t3)
+      : [m00x] "v"(m00.x), [m00y] "v"(m00.y), [m01x] "v"(m01.x), [m01y] "v"(m01.y), [m10x] "v"(m10.x),
+        [m10y] "v"(m10.y), [m11x] "v"(m11.x), [m11y] "v"(m11.y));
+}
+
+// A composed map (DK_U) on cube bit J.  A sign pending on position J means
+// the stored b is -b: it negates the column that multiplies b.  The map
+// writes o1 whole, so nothing is pending on J after it.
+template <int J, int kC>
+__device__ __forceinline__ void round_map(float2 (&x)[1 << kC], const FuseOp &op, uint32_t &pend) {
+  constexpr int kPer = 1 << kC;
+  constexpr int kB = 1 << J;
+  const uint32_t s = ((pend >> J) & 1u) << 31;
+  const float2 m00 = make_float2(in_vgpr(op.coef.x), in_vgpr(op.coef.y));
+  const float2 m01 = make_float2(in_vgpr(__uint_as_float(op.lmask_o1 ^ s)), in_vgpr(__uint_as_float(op.rw_rs ^ s)));
+  const float2 m10 = make_float2(in_vgpr(__uint_as_float(op.rw_fa)), in_vgpr(__uint_as_float(op.rw_fbr)));
+  const float2 m11 = make_float2(in_vgpr(__uint_as_float(op.rw_cs ^ s)), in_vgpr(__uint_as_float(op.rw_fold ^ s)));
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (q & kB) continue;
+    pair_map(x[q], x[q + kB], m00, m01, m10, m11);
+  }
+  pend &= ~(1u << J);
+}
+
 // E or Z in a round: negate the amplitudes whose local bits m are all set
 // (the bits outside the cube decide per thread, the cube bits per q: a
 // uniform branch per q, so only the amplitudes it can flip are touched).
@@ -628,6 +676,10 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
   // one window of the sweep on position J: its norm into wacc (kRed)
   auto window = [&](auto jc, const FuseOp &op) {
     constexpr int J = decltype(jc)::value;
+    if (!kRed && op.kind == DK_U) {  // composed windows (passes without window sums only)
+      round_map<J, kC>(x, op, pend);
+      return;
+    }
     const WinP w = prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true);
     if (kRed) {
       const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));

@@ -327,3 +327,56 @@ def test_sum_all_sums_every_window(ctx, n, exec_):
     if exec_ != owqs.EXEC_SUBSTATES:
         assert np.all(p.read_probs() == 0.5)
     p.close()
+
+
+def runs_circuit(g, n, n_gates, hot=3, p_cz=0.08):
+    """J gates mostly on a few wires (long runs of windows on one slot, which
+    the plan composes into 2x2 maps), CZ now and then on random pairs."""
+    gates = []
+    for _ in range(n_gates):
+        if g.random() < p_cz:
+            a, b = g.choice(n, size=2, replace=False)
+            gates.append(("CZ", int(a), int(b)))
+        else:
+            q = int(g.integers(hot)) if g.random() < 0.7 else int(g.integers(n))
+            gates.append(("J", q, float(g.uniform(0, 2 * math.pi))))
+    return gates
+
+
+@pytest.mark.parametrize("n,bits", [(16, 10), (18, 12), (20, 11)])
+@pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS])
+def test_composed_window_runs(ctx, n, bits, mode, parity_report):
+    """Runs of windows on one round position composed into one 2x2 map
+    (products of the windows' maps, pending signs taken into the map):
+    state and probabilities against the oracle, on two runs in a row, and
+    the same state with every window summed (no composition)."""
+    g = np.random.default_rng(2300 + n + 5 * mode)
+    gates = runs_circuit(g, n, 260)
+    pat = W.circuit_to_pattern(n, gates)
+    inp = W.gaussian_state(n, g)
+    outc = g.integers(0, 2, size=pat.n_meas()).astype(np.uint8)
+    want, pw = oc.run(pat, outc, inp.astype(np.complex128),
+                      oc.MODE_OWQS if mode == owqs.MODE_OWQS else oc.MODE_EOWQS)
+    p = owqs.Pattern(ctx, pat)
+    p.set_mode(mode)
+    p.set_exec(owqs.EXEC_FUSED)
+    p.set_outcomes(outc)
+    p.set_tile_bits(bits)
+    alone, maps, inside = p.plan_tile_work()
+    assert maps > 0 and inside >= 2 * maps, (alone, maps, inside)
+    x = torch.as_tensor(inp).cuda()
+    for rep in range(2):
+        p.run(x)
+        got = p.read_state().cpu().numpy().astype(np.complex128)
+        err = float(np.max(np.abs(got - want)))
+        assert err <= AMP_TOL, (rep, err)
+        if mode == owqs.MODE_OWQS:
+            np.testing.assert_allclose(p.read_probs(), pw, atol=1e-5)
+    parity_report(f"composed_runs_n{n}_k{bits}_mode{mode}", max_amp_err=err, maps=maps, windows_in_maps=inside)
+    if mode == owqs.MODE_OWQS:
+        p.set_sum_all(True)
+        assert p.plan_tile_work()[1] == 0
+        p.run(x)
+        got2 = p.read_state().cpu().numpy().astype(np.complex128)
+        assert float(np.max(np.abs(got2 - want))) <= AMP_TOL
+    p.close()
