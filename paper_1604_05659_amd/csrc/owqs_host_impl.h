@@ -288,8 +288,8 @@ owqs_status upload_fuse(owqs_pattern *p);
 // Group runs of window/E/X/Z steps into tile passes (S_F steps in `out`),
 // looking up to kGroupLookahead steps ahead past at most kGroupSkipMax steps
 // left for later passes.
-constexpr size_t kGroupLookahead = 512;
-constexpr size_t kGroupSkipMax = 128;
+constexpr size_t kGroupLookahead = 2048;
+constexpr size_t kGroupSkipMax = 512;
 bool commute_steps(const Step &a, const Step &b);
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm,

@@ -151,7 +151,7 @@ def test_fused_plan_forms_windows(host_ctx):
 def test_tile_grouping_looks_ahead(host_ctx):
     """Host plan of the large circuit (24 logical qubits, 2000 J + 300 CZ):
     a step whose slot does not fit the tile no longer ends the pass, so the
-    2300 steps go into about 26 passes in OWQS mode (at most 128 windows
+    2300 steps go into about 22 passes in OWQS mode (at most 128 windows
     with p = 1/2 a pass; the tile's free slots end most passes first) and 64
     in EOWQS mode (at most 32); the sub-state plan of three 16-qubit
     circuits groups each sub-state's steps the same way."""
