@@ -286,8 +286,17 @@ bool composable(const FuseOp &w) {
 // map on the pair: the product of their 2x2 maps, formed in FP64 and rounded
 // once to FP32.  It replaces the last window of the run (a DK_U row); the
 // others leave their sweeps.  A DK_U costs the FP32 work of two windows.
+// All or nothing: when every window of the group's rounds composes, each
+// run (one window or more) becomes a map, so the kernel runs one code path
+// per round position (maps only); otherwise nothing is composed.
 bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out) {
   const int kc = tile_cube_bits(tile_bits);
+  for (int q = 0; q < nops; ++q) {
+    if (ops[q].kind != DK_R) continue;
+    for (int o = q + 1; o <= q + ops[q].m_index; ++o)
+      if (ops[o].kind == DK_J && !composable(ops[o])) return false;
+    q += ops[q].m_index;
+  }
   struct Sweep {
     FuseOp head;
     std::vector<FuseOp> diag;
@@ -321,7 +330,7 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
       const uint32_t bit = 1u << ((rh.lmask_b >> (8 * pos)) & 0xFFu);
       std::vector<size_t> run;
       auto flush = [&]() {
-        if (run.size() >= 2) {
+        if (!run.empty()) {
           cplx u[4] = {1.0, 0.0, 0.0, 1.0};
           for (size_t i : run) {  // u <- W u, in the order the windows run
             cplx w[4];
@@ -359,11 +368,7 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
             break;
           }
         if (!sw[i].has[pos]) continue;
-        if (composable(sw[i].win[pos])) {
-          run.push_back(i);
-        } else {
-          flush();
-        }
+        run.push_back(i);  // every window of the rounds composes (checked above)
       }
       flush();
     }
@@ -1123,6 +1128,7 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
         if (tg.mnops > 0 && !ctab && a.reduce == kReduceNone) {  // no window sums: the composed commands
           ops = p->dev_fuse + fuse_mops_base(p->fuse_ops.size(), p->fuse_m.size()) + tg.mop_off;
           ta.nops = tg.mnops;
+          ta.maps = 1;
         }
         e = launch_tile(psi, ta, ops, a, s, &grid);
         break;

@@ -187,6 +187,11 @@ struct TileArgs {
   // partials (k_tile: one per block; k_tile_multi: one per tile), from which
   // k_finish_renorm / k_finish_multi reset sigma
   int renorm;
+  // 1 (set per launch): every window slot of the group's rounds holds a
+  // composed map (DK_U) and the pass sums no window: the kernel variant with
+  // only the map path runs (one code path per position keeps the amplitudes
+  // in their registers)
+  int maps;
   uint8_t tpos[16];  // global slot of tile bit i (tpos[i] = i for i < kLowBits)
   uint8_t opos[48];  // global slots of the bits outside the tile, ascending (n - k of them)
 };

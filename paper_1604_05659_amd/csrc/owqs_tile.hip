@@ -638,7 +638,7 @@ __device__ __forceinline__ void round_diag(float2 (&x)[1 << kC], uint32_t e8, ui
 // positions of its windows), its E / Z, then its windows in position order.
 // Each position has its own code path, so the amplitudes stay in their
 // registers through the round.
-template <int kTB, bool kRed>
+template <int kTB, bool kRed, bool kMaps>
 __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp *__restrict__ ops, int o0, int n,
                                            uint32_t bits, uint64_t ob, const TileArgs &ta,
                                            double (*wacc)[tile_threads(kTB) / 64]) {
@@ -676,16 +676,16 @@ __device__ __forceinline__ void tile_round(char *lds, uint32_t tid, const FuseOp
   // one window of the sweep on position J: its norm into wacc (kRed)
   auto window = [&](auto jc, const FuseOp &op) {
     constexpr int J = decltype(jc)::value;
-    if (!kRed && op.kind == DK_U) {  // composed windows (passes without window sums only)
+    if constexpr (kMaps) {  // every window slot holds a composed map (passes without window sums)
       round_map<J, kC>(x, op, pend);
-      return;
-    }
-    const WinP w = prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true);
-    if (kRed) {
-      const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
-      if (lane == 63) wacc[w.widx][wave] += d;
     } else {
-      round_window<J, kC, false>(x, w, pend);
+      const WinP w = prep_window(op, ob, ta, ((pend >> J) & 1u) << 31, true);
+      if (kRed) {
+        const double d = wave_sum_to_last(round_window<J, kC, true>(x, w, pend));
+        if (lane == 63) wacc[w.widx][wave] += d;
+      } else {
+        round_window<J, kC, false>(x, w, pend);
+      }
     }
   };
   for (int o = o0; o < o0 + n;) {
@@ -734,7 +734,7 @@ __device__ __forceinline__ void tile_high_bits(uint64_t tmask, uint64_t *hp) {
 // stored tile (else 0).  g_tid and hp hold the thread's part of the global
 // index and the global bits of the tile bits above the thread index (see
 // k_tile).  Ends with a barrier: the tile's LDS is free after it.
-template <int kTB, bool kRuns, bool kRed>
+template <int kTB, bool kRuns, bool kRed, bool kMaps = false>
 __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileArgs &ta,
                                            const FuseOp *__restrict__ ops, double sg, uint64_t t, uint64_t g_tid,
                                            const uint64_t *hp, float2 *tile, double (*wacc)[tile_threads(kTB) / 64]) {
@@ -786,7 +786,7 @@ __device__ __forceinline__ double tile_one(float2 *__restrict__ psi, const TileA
   for (int o = 0; o < ta.nops; ++o) {
     const FuseOp op = load_op(ops, o);
     if (op.kind == DK_R) {  // a round: its commands in registers
-      tile_round<kTB, kRed>(lds, tid, ops, o + 1, op.m_index, op.lmask_b, ob, ta, wacc);
+      tile_round<kTB, kRed, kMaps>(lds, tid, ops, o + 1, op.m_index, op.lmask_b, ob, ta, wacc);
       __syncthreads();
       o += op.m_index;
       continue;
@@ -919,7 +919,7 @@ __device__ __forceinline__ double block_sum0(double x, double *scratch) {
 // Every command of the group is then one pass over the tile in LDS.
 // kRuns: the run-in-registers paths are compiled in (they raise the VGPR
 // count, which lowers occupancy for groups that cannot use them).
-template <int kTB, bool kRuns, bool kRed>
+template <int kTB, bool kRuns, bool kRed, bool kMaps = false>
 __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__ psi, TileArgs ta,
                                                             const FuseOp *__restrict__ ops, MeasureArgs ma,
                                                             double *__restrict__ partials) {
@@ -941,7 +941,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile(float2 *__restrict__
   const uint64_t ntiles = uint64_t(1) << (ta.n - kTB);
   double rsum = 0.0;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-    rsum += tile_one<kTB, kRuns, kRed>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc);
+    rsum += tile_one<kTB, kRuns, kRed, kMaps>(psi, ta, ops, sg, t, g_tid, hp, tile, wacc);
   if (ta.renorm) {  // the block's share of the output norm, summed through the free tile LDS
     const double sum = block_sum0<kT>(rsum, reinterpret_cast<double *>(tile));
     if (tid == 0) partials[blockIdx.x] = sum;
@@ -1282,6 +1282,8 @@ hipError_t prepare_bits() {
   const void *fns[] = {
       reinterpret_cast<const void *>(k_tile<kTB, false, false>), reinterpret_cast<const void *>(k_tile<kTB, false, true>),
       reinterpret_cast<const void *>(k_tile<kTB, true, false>), reinterpret_cast<const void *>(k_tile<kTB, true, true>),
+      reinterpret_cast<const void *>(k_tile<kTB, false, false, true>),
+      reinterpret_cast<const void *>(k_tile<kTB, true, false, true>),
       reinterpret_cast<const void *>(k_tile_multi<kTB, false, false>),
       reinterpret_cast<const void *>(k_tile_multi<kTB, false, true>),
       reinterpret_cast<const void *>(k_tile_multi<kTB, true, false>),
@@ -1301,6 +1303,11 @@ template <int kTB>
 void tile_launch(bool runs, bool red, dim3 grid, hipStream_t s, float2 *psi, const TileArgs &ta, const FuseOp *ops,
                  const MeasureArgs &a, double *partials) {
   const dim3 block(tile_threads(kTB));
+  if (ta.maps && !red) {  // rounds of composed maps only
+    if (runs) hipLaunchKernelGGL((k_tile<kTB, true, false, true>), grid, block, 0, s, psi, ta, ops, a, partials);
+    else hipLaunchKernelGGL((k_tile<kTB, false, false, true>), grid, block, 0, s, psi, ta, ops, a, partials);
+    return;
+  }
   if (runs) {
     if (red) hipLaunchKernelGGL((k_tile<kTB, true, true>), grid, block, 0, s, psi, ta, ops, a, partials);
     else hipLaunchKernelGGL((k_tile<kTB, true, false>), grid, block, 0, s, psi, ta, ops, a, partials);

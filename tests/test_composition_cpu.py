@@ -31,7 +31,7 @@ def _work(ctx, wl, mode, exec_=owqs.EXEC_FUSED, sum_all=False, bits=12):
 def test_every_window_once(host_ctx, bits):
     wl = W.plain_large(n_logical=18, n_j=400, n_cz=60)
     alone, maps, inside = _work(host_ctx, wl, owqs.MODE_OWQS, bits=bits)
-    assert maps > 0 and inside >= 2 * maps
+    assert maps > 0 and inside > maps  # some maps compose several windows
     assert alone + inside <= 400  # the circuit's 400 J windows, most of them in tile passes
     assert alone + inside >= 360
     # with every window summed nothing composes (such plans group at most 32
@@ -41,7 +41,7 @@ def test_every_window_once(host_ctx, bits):
     # EOWQS sums no window and composes; the check mode groups the same
     # passes (at most 32 windows each in both) and sums every window
     ea, em, ei = _work(host_ctx, wl, owqs.MODE_EOWQS, bits=bits)
-    assert em > 0 and ei >= 2 * em
+    assert em > 0 and ei > em
     assert _work(host_ctx, wl, owqs.MODE_EOWQS_CHECK, bits=bits) == (ea + ei, 0, 0)
 
 
@@ -52,7 +52,8 @@ def test_plain_plan_has_no_tile_work(host_ctx):
 
 def test_cz_on_every_wire_between_windows_stops_composition(host_ctx):
     """J, CZ on the same wire, J, ...: each window meets an E on its own bit
-    before the next one, so no two windows on a wire are adjacent."""
+    before the next one, so every map holds one window (the rounds still
+    run maps only: all or nothing per pass)."""
     n = 16
     gates = []
     for r in range(6):
@@ -64,4 +65,4 @@ def test_cz_on_every_wire_between_windows_stops_composition(host_ctx):
     wl = W.Workload(pat, W.outcome_bits(pat.n_meas(), W.rng(9, W.P_OUTCOME, 0)),
                     W.gaussian_state(n, W.rng(9, W.P_INPUT, 0)), {})
     alone, maps, inside = _work(host_ctx, wl, owqs.MODE_OWQS)
-    assert (maps, inside) == (0, 0) and alone > 0
+    assert maps > 0 and inside == maps

@@ -347,7 +347,8 @@ def runs_circuit(g, n, n_gates, hot=3, p_cz=0.08):
 @pytest.mark.parametrize("mode", [owqs.MODE_OWQS, owqs.MODE_EOWQS])
 def test_composed_window_runs(ctx, n, bits, mode, parity_report):
     """Runs of windows on one round position composed into one 2x2 map
-    (products of the windows' maps, pending signs taken into the map):
+    (products of the windows' maps, pending signs taken into the map; every
+    round window of a pass becomes a map, runs of one included):
     state and probabilities against the oracle, on two runs in a row, and
     the same state with every window summed (no composition)."""
     g = np.random.default_rng(2300 + n + 5 * mode)
@@ -363,7 +364,7 @@ def test_composed_window_runs(ctx, n, bits, mode, parity_report):
     p.set_outcomes(outc)
     p.set_tile_bits(bits)
     alone, maps, inside = p.plan_tile_work()
-    assert maps > 0 and inside >= 2 * maps, (alone, maps, inside)
+    assert maps > 0 and inside > maps, (alone, maps, inside)
     x = torch.as_tensor(inp).cuda()
     for rep in range(2):
         p.run(x)
