@@ -675,7 +675,7 @@ def main():
                     help="only the batched leg (512 patterns, one graph per call, 3 calls after a warm-up): for "
                          "rocprofv3 kernel traces of the batch")
     ap.add_argument("--tile-probe", action="store_true",
-                    help="one fused run of the large workload at tile bits 12 (40 tile passes): for rocprofv3 "
+                    help="one fused run of the large workload at tile bits 12 (22 tile passes): for rocprofv3 "
                          "--pmc passes over the tile kernel")
     ap.add_argument("--only-plain", action="store_true",
                     help="run only the plain executor on the large workload (for counter collection runs)")
