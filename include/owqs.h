@@ -247,8 +247,9 @@ owqs_status owqs_tune_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npa
  * grouped into tile passes.  Any pointer may be NULL. */
 owqs_status owqs_plan_info(owqs_pattern *pat, int32_t *plan_width, size_t *nsteps, size_t *npasses);
 
-/* The tile passes of the fused plan (global-memory executor; 0s for other
- * plans) as they run with forced outcomes and without window sums: windows
+/* The tile passes of the fused plan (global-memory executor) or of the
+ * sub-state plan (0s for other plans) as they run with forced outcomes and
+ * without window sums: windows
  * applied one by one (*windows), and runs of windows on one register-round
  * position (Sec. 4.4: each window is a fixed 2x2 map on its pair once its
  * outcome is known) composed into one 2x2 map each (*maps, covering

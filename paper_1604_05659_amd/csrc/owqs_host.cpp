@@ -1863,21 +1863,23 @@ owqs_status owqs_plan_tile_work(owqs_pattern *p, size_t *windows, size_t *maps, 
   if (p->dirty) compile(p);
   size_t nw = 0, nm = 0, nc = 0;
   const int reduce = reduce_of(p);
-  if (!substates(p))
-    for (const TileGroup &tg : p->groups) {
-      size_t gw = 0, gm = 0;
-      // the commands a forced run launches (launch_range): composed where the pass sums no window
-      const bool comp = tg.mnops > 0 && (reduce == kReduceNone || (reduce == kReduceRenorm && tg.half));
-      const FuseOp *ops = comp ? p->fuse_mops.data() + tg.mop_off : p->fuse_ops.data() + tg.op_off;
-      const int nops = comp ? tg.mnops : tg.ta.nops;
-      for (int i = 0; i < nops; ++i) {
-        gw += ops[i].kind == DK_J;
-        gm += ops[i].kind == DK_U;
-      }
-      nw += gw;
-      nm += gm;
-      nc += size_t(tg.ta.nwin) - gw;
+  const bool ss = substates(p);
+  const std::vector<TileGroup> &groups = ss ? p->ss_groups : p->groups;
+  const std::vector<FuseOp> &fops = ss ? p->ss_fuse_ops : p->fuse_ops, &mops = ss ? p->ss_fuse_mops : p->fuse_mops;
+  for (const TileGroup &tg : groups) {
+    size_t gw = 0, gm = 0;
+    // the commands a forced run launches (launch_range, launch_substeps): composed where the pass sums no window
+    const bool comp = tg.mnops > 0 && (reduce == kReduceNone || (reduce == kReduceRenorm && tg.half));
+    const FuseOp *ops = comp ? mops.data() + tg.mop_off : fops.data() + tg.op_off;
+    const int nops = comp ? tg.mnops : tg.ta.nops;
+    for (int i = 0; i < nops; ++i) {
+      gw += ops[i].kind == DK_J;
+      gm += ops[i].kind == DK_U;
     }
+    nw += gw;
+    nm += gm;
+    nc += size_t(tg.ta.nwin) - gw;
+  }
   if (windows) *windows = nw;
   if (maps) *maps = nm;
   if (composed) *composed = nc;

@@ -249,7 +249,8 @@ struct owqs_pattern {
   std::vector<TileGroup> ss_groups;
   std::vector<FuseOp> ss_fuse_ops;
   std::vector<int> ss_fuse_m;
-  FuseOp *ss_dev_fuse = nullptr;    // ss_fuse_ops, then ss_fuse_m (as int)
+  std::vector<FuseOp> ss_fuse_mops; // composed copies of the sub-state groups' commands (TileGroup::mop_off)
+  FuseOp *ss_dev_fuse = nullptr;    // ss_fuse_ops, then ss_fuse_m (as int), then ss_fuse_mops
   size_t ss_dev_fuse_cap = 0;
   bool ss_dev_fuse_valid = false;
   int ss_width = 0;                 // widest sub-state

@@ -16,6 +16,7 @@ void group_substates(owqs_pattern *p) {
   p->ss_run.clear();
   p->ss_groups.clear();
   p->ss_fuse_ops.clear();
+  p->ss_fuse_mops.clear();
   p->ss_fuse_m.clear();
   p->ss_dev_fuse_valid = false;
   const size_t nch = p->ss_chains.size();
@@ -40,7 +41,8 @@ void group_substates(owqs_pattern *p) {
       run.push_back(st);
     }
     std::vector<Step> out;
-    group_steps(run, p->mode, p->tile_bits, out, p->ss_groups, p->ss_fuse_ops, p->ss_fuse_m);
+    group_steps(run, p->mode, p->tile_bits, out, p->ss_groups, p->ss_fuse_ops, p->ss_fuse_m, false,
+                &p->ss_fuse_mops);
     for (const Step &x : out)
       p->ss_run.push_back(x.kind == S_F ? SubRun{-1, x.group, c} : SubRun{x.group, -1, c});
     h.clear();
@@ -389,7 +391,13 @@ hipError_t launch_substeps(owqs_pattern *p, int reduce, hipStream_t s, std::vect
         a.reduce = kReduceNone;
         ta.half_m = m_of;
       }
-      e = launch_tile(psi, ta, p->ss_dev_fuse + tg.op_off, a, s, &grid);
+      const FuseOp *ops = p->ss_dev_fuse + tg.op_off;
+      if (tg.mnops > 0 && a.reduce == kReduceNone) {  // no window sums: the composed commands
+        ops = p->ss_dev_fuse + fuse_mops_base(p->ss_fuse_ops.size(), p->ss_fuse_m.size()) + tg.mop_off;
+        ta.nops = tg.mnops;
+        ta.maps = 1;
+      }
+      e = launch_tile(psi, ta, ops, a, s, &grid);
       if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 1], s);
       if (e == hipSuccess) e = launch_finish_group(a, m_of, tg.ta.nwin, grid, s);
       if (ev && e == hipSuccess) e = hipEventRecord((*ev)[2 * i + 2], s);
@@ -495,7 +503,8 @@ owqs_status run_substates(owqs_pattern *p, const void *const *factors, const int
   }
   if (!p->ss_dev_fuse_valid) {  // before any capture: the graph holds the table's address
     drop_ss_graph(p);
-    st = upload_fuse_table(p->ctx, p->ss_fuse_ops, p->ss_fuse_m, p->ss_dev_fuse, p->ss_dev_fuse_cap);
+    st = upload_fuse_table(p->ctx, p->ss_fuse_ops, p->ss_fuse_m, p->ss_dev_fuse, p->ss_dev_fuse_cap,
+                           &p->ss_fuse_mops);
     if (st != OWQS_OK) return st;
     p->ss_dev_fuse_valid = true;
   }

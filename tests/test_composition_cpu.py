@@ -66,3 +66,20 @@ def test_cz_on_every_wire_between_windows_stops_composition(host_ctx):
                     W.gaussian_state(n, W.rng(9, W.P_INPUT, 0)), {})
     alone, maps, inside = _work(host_ctx, wl, owqs.MODE_OWQS)
     assert maps > 0 and inside == maps
+
+
+def test_substate_passes_compose(host_ctx):
+    """Sub-state plans (three 16-qubit circuits side by side) compose the
+    windows of their tile passes the same way."""
+    import numpy as np
+    g = np.random.default_rng([160405659, 9, 0])
+    parts = [W.circuit_to_pattern(16, W.random_jcz_circuit(16, 400, 60, g)) for _ in range(3)]
+    q = owqs.Pattern(host_ctx, W.disjoint_union(parts))
+    q.set_exec(owqs.EXEC_SUBSTATES)
+    q.set_input_factors([16, 16, 16])
+    alone, maps, inside = q.plan_tile_work()
+    assert maps > 0 and inside > maps, (alone, maps, inside)
+    assert alone + inside <= 3 * 400
+    q.set_sum_all(True)
+    assert q.plan_tile_work()[1:] == (0, 0)
+    q.close()
