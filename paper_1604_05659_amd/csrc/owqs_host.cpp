@@ -2097,7 +2097,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
     // levels of the wide plans
     struct Bucket {
       int k;
-      bool runs, red;
+      bool runs, red, maps;
       std::vector<MultiTile> ents;
       uint32_t total = 0;
     };
@@ -2135,12 +2135,17 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
             if (r == kReduceNone && reduce == kReduceRenorm) m.ta.half_m = fuse_m_dev(p) + tg.m_off;
             m.ta.renorm = renorm ? 1 : 0;
             m.reduce = r;
+            if (tg.mnops > 0 && r == kReduceNone) {  // no window sums: the composed commands
+              m.ops = p->dev_fuse + fuse_mops_base(p->fuse_ops.size(), p->fuse_m.size()) + tg.mop_off;
+              m.ta.nops = tg.mnops;
+              m.ta.maps = 1;
+            }
             Bucket *bk = nullptr;
-            const bool red = r != kReduceNone;
+            const bool red = r != kReduceNone, maps = m.ta.maps != 0;
             for (Bucket &b : L.buckets)
-              if (b.k == tg.ta.k && b.runs == (tg.ta.runs != 0) && b.red == red) bk = &b;
+              if (b.k == tg.ta.k && b.runs == (tg.ta.runs != 0) && b.red == red && b.maps == maps) bk = &b;
             if (!bk) {
-              L.buckets.push_back(Bucket{tg.ta.k, tg.ta.runs != 0, red, {}, 0});
+              L.buckets.push_back(Bucket{tg.ta.k, tg.ta.runs != 0, red, maps, {}, 0});
               bk = &L.buckets.back();
             }
             m.first_tile = bk->total;
@@ -2222,7 +2227,7 @@ owqs_status owqs_run_batch(owqs_ctx *ctx, owqs_pattern *const *pats, size_t npat
       for (size_t q = 0; q < L.buckets.size() && le == hipSuccess; ++q) {
         const Bucket &b = L.buckets[q];
         le = launch_tile_multi(reinterpret_cast<const MultiTile *>(dev + bk_off[lv][q]), (int)b.ents.size(), b.total,
-                               b.k, b.runs, b.red, B.cap);
+                               b.k, b.runs, b.red, b.maps, B.cap);
         ++nodes;
       }
       if (le == hipSuccess && !L.fins.empty()) {

@@ -280,9 +280,10 @@ hipError_t launch_batch_start(const BatchIo *ios, int count, int max_nin, hipStr
 hipError_t launch_batch_read(const BatchIo *ios, int count, int max_nout, hipStream_t s);
 // Tile groups of many patterns in one launch (entries sorted by first_tile,
 // all with tile bits k, the same `runs` and, as `red`, all with or all
-// without the FP64 window sums), and their group finishes.
+// without the FP64 window sums; `maps`: every entry's rounds hold composed
+// maps only, ta.maps), and their group finishes.
 hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, bool red,
-                             hipStream_t s);
+                             bool maps, hipStream_t s);
 hipError_t launch_finish_multi(const MultiFinish *fins, int nfin, int maxwin, hipStream_t s);
 // Items share one command table and differ only by input: item k runs on
 // basis state |first + k> (basis_mode = 1) or on in + k * 2^nin, and writes

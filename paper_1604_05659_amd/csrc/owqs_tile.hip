@@ -985,7 +985,7 @@ __device__ __forceinline__ uint32_t first_tile_of(const MultiTile *ents, int e) 
 // owns its tile (binary search on first_tile), runs that tile as k_tile
 // does, and stores its windows' sums per tile (partials[w * ntiles + t]), so
 // that k_finish_multi sums them in tile order.
-template <int kTB, bool kRuns, bool kRed>
+template <int kTB, bool kRuns, bool kRed, bool kMaps = false>
 __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTile *__restrict__ ents, int nent,
                                                                   uint32_t total) {
   constexpr int kT = tile_threads(kTB);
@@ -1011,7 +1011,7 @@ __global__ __launch_bounds__(tile_threads(kTB)) void k_tile_multi(const MultiTil
     tile_high_bits<kTB>(e.ta.tmask, hp);
     if (e.ta.half_m && t == 0)  // windows with p = 1/2 exactly
       for (int i = tid; i < e.ta.nwin; i += kT) e.probs[e.ta.half_m[i]] = 0.5;
-    const double rsum = tile_one<kTB, kRuns, kRed>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc);
+    const double rsum = tile_one<kTB, kRuns, kRed, kMaps>(e.psi, e.ta, e.ops, sg, t, g_tid, hp, tile, wacc);
     if (e.ta.renorm) {  // the tile's output norm, summed through the free tile LDS
       const double sum = block_sum0<kT>(rsum, reinterpret_cast<double *>(tile));
       if (tid == 0) e.partials[t] = sum;
@@ -1287,7 +1287,9 @@ hipError_t prepare_bits() {
       reinterpret_cast<const void *>(k_tile_multi<kTB, false, false>),
       reinterpret_cast<const void *>(k_tile_multi<kTB, false, true>),
       reinterpret_cast<const void *>(k_tile_multi<kTB, true, false>),
-      reinterpret_cast<const void *>(k_tile_multi<kTB, true, true>)};
+      reinterpret_cast<const void *>(k_tile_multi<kTB, true, true>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, false, false, true>),
+      reinterpret_cast<const void *>(k_tile_multi<kTB, true, false, true>)};
   hipError_t e = hipSuccess;
   for (const void *f : fns)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, one);
@@ -1318,9 +1320,14 @@ void tile_launch(bool runs, bool red, dim3 grid, hipStream_t s, float2 *psi, con
 }
 
 template <int kTB>
-void tile_multi_launch(bool runs, bool red, dim3 grid, hipStream_t s, const MultiTile *ents, int nent,
+void tile_multi_launch(bool runs, bool red, bool maps, dim3 grid, hipStream_t s, const MultiTile *ents, int nent,
                        uint32_t total) {
   const dim3 block(tile_threads(kTB));
+  if (maps && !red) {  // every entry's rounds hold composed maps only
+    if (runs) hipLaunchKernelGGL((k_tile_multi<kTB, true, false, true>), grid, block, 0, s, ents, nent, total);
+    else hipLaunchKernelGGL((k_tile_multi<kTB, false, false, true>), grid, block, 0, s, ents, nent, total);
+    return;
+  }
   if (runs) {
     if (red) hipLaunchKernelGGL((k_tile_multi<kTB, true, true>), grid, block, 0, s, ents, nent, total);
     else hipLaunchKernelGGL((k_tile_multi<kTB, true, false>), grid, block, 0, s, ents, nent, total);
@@ -1398,14 +1405,14 @@ hipError_t launch_tile_rev(float2 *psi, float2 *lam, const TileArgs &ta0, const 
 }
 
 hipError_t launch_tile_multi(const MultiTile *ents, int nent, uint32_t total, int k, bool runs, bool red,
-                             hipStream_t s) {
+                             bool maps, hipStream_t s) {
   if (nent <= 0 || total == 0) return hipGetLastError();
   const dim3 grid(total < 65535u ? total : 65535u);
   switch (k) {
-    case 10: tile_multi_launch<10>(runs, red, grid, s, ents, nent, total); break;
-    case 11: tile_multi_launch<11>(runs, red, grid, s, ents, nent, total); break;
-    case 12: tile_multi_launch<12>(runs, red, grid, s, ents, nent, total); break;
-    case 13: tile_multi_launch<13>(runs, red, grid, s, ents, nent, total); break;
+    case 10: tile_multi_launch<10>(runs, red, maps, grid, s, ents, nent, total); break;
+    case 11: tile_multi_launch<11>(runs, red, maps, grid, s, ents, nent, total); break;
+    case 12: tile_multi_launch<12>(runs, red, maps, grid, s, ents, nent, total); break;
+    case 13: tile_multi_launch<13>(runs, red, maps, grid, s, ents, nent, total); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
