@@ -13,7 +13,6 @@
 //   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
 //     into its pass (with the device FP64 sigma in OWQS mode).
 #include <atomic>
-#include <complex>
 
 #include "owqs_host_impl.h"
 #include "owqs_pattern_access.h"
@@ -239,38 +238,6 @@ std::vector<RoundItem> schedule_rounds(const std::vector<FuseOp> &g, int k, bool
 
 namespace {
 
-using cplx = std::complex<double>;
-
-float word_f(uint32_t w) {
-  float f;
-  __builtin_memcpy(&f, &w, sizeof(f));
-  return f;
-}
-
-uint32_t f_word(double x) {
-  const float f = float(x);
-  uint32_t w;
-  __builtin_memcpy(&w, &f, sizeof(w));
-  return w;
-}
-
-// A window's map on true amplitudes as a register round applies it (no
-// masks, no sign pending on its position): t = c b, o0 = fa a + t, and the
-// round stores fbr a + t for o1 = r (fbr a + t), r the sign of rw_rs (see
-// round_words).  Row-major 2x2.
-void window_map(const FuseOp &w, cplx m[4]) {
-  const uint32_t cs = w.rw_cs & 0x80000000u;
-  uint32_t cx, cy;
-  __builtin_memcpy(&cx, &w.coef.x, sizeof(cx));
-  __builtin_memcpy(&cy, &w.coef.y, sizeof(cy));
-  const cplx c(word_f(cx ^ cs), word_f(cy ^ cs));
-  const double fa = word_f(w.rw_fa), fbr = word_f(w.rw_fbr), r = (w.rw_rs & 0x80000000u) ? -1.0 : 1.0;
-  m[0] = fa;
-  m[1] = c;
-  m[2] = r * fbr;
-  m[3] = r * c;
-}
-
 // A window whose map is the same on every tile and in every order of the
 // round: no local or outer masks, and p = 1/2 exactly (an odd E(v, w) count).
 bool composable(const FuseOp &w) {
@@ -289,7 +256,8 @@ bool composable(const FuseOp &w) {
 // All or nothing: when every window of the group's rounds composes, each
 // run (one window or more) becomes a map, so the kernel runs one code path
 // per round position (maps only); otherwise nothing is composed.
-bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out) {
+bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out,
+                         std::vector<int> *src) {
   const int kc = tile_cube_bits(tile_bits);
   for (int q = 0; q < nops; ++q) {
     if (ops[q].kind != DK_R) continue;
@@ -302,8 +270,11 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
     std::vector<FuseOp> diag;
     FuseOp win[4];
     bool has[4] = {false, false, false, false};
+    int at[4] = {-1, -1, -1, -1};  // the window's row in ops
+    std::vector<int> from[4];      // a map: the rows of its windows, in order
   };
   std::vector<FuseOp> res;
+  std::vector<int> refs;
   res.reserve(size_t(nops));
   bool any = false;
   for (int q = 0; q < nops; ++q) {
@@ -320,6 +291,7 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
       for (int d = 0; d < w.head.m_index; ++d) w.diag.push_back(ops[o++]);
       for (int pos = 0; pos < kc; ++pos)
         if ((w.head.flags >> pos) & 1u) {
+          w.at[pos] = o;
           w.win[pos] = ops[o++];
           w.has[pos] = true;
         }
@@ -331,16 +303,13 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
       std::vector<size_t> run;
       auto flush = [&]() {
         if (!run.empty()) {
-          cplx u[4] = {1.0, 0.0, 0.0, 1.0};
+          double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+          std::vector<int> from;
           for (size_t i : run) {  // u <- W u, in the order the windows run
-            cplx w[4];
+            double w[8];
             window_map(sw[i].win[pos], w);
-            const cplx n0 = w[0] * u[0] + w[1] * u[2], n1 = w[0] * u[1] + w[1] * u[3];
-            const cplx n2 = w[2] * u[0] + w[3] * u[2], n3 = w[2] * u[1] + w[3] * u[3];
-            u[0] = n0;
-            u[1] = n1;
-            u[2] = n2;
-            u[3] = n3;
+            map_left(w, u);
+            from.push_back(sw[i].at[pos]);
           }
           const FuseOp last = sw[run.back()].win[pos];
           FuseOp m{};
@@ -348,15 +317,10 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
           m.lb = last.lb;
           m.widx = last.widx;
           m.m_index = last.m_index;
-          m.coef = make_float2(float(u[0].real()), float(u[0].imag()));
-          m.lmask_o1 = f_word(u[1].real());
-          m.rw_rs = f_word(u[1].imag());
-          m.rw_fa = f_word(u[2].real());
-          m.rw_fbr = f_word(u[2].imag());
-          m.rw_cs = f_word(u[3].real());
-          m.rw_fold = f_word(u[3].imag());
+          map_store(m, u);
           for (size_t i = 0; i + 1 < run.size(); ++i) sw[run[i]].has[pos] = false;
           sw[run.back()].win[pos] = m;
+          sw[run.back()].from[pos] = from;
           any = true;
         }
         run.clear();
@@ -384,12 +348,20 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
       res.push_back(h);
       for (const FuseOp &d : w.diag) res.push_back(d);
       for (int pos = 0; pos < kc; ++pos)
-        if (w.has[pos]) res.push_back(w.win[pos]);
+        if (w.has[pos]) {
+          if (w.win[pos].kind == DK_U) {  // its row here, then its windows' rows in ops
+            refs.push_back(int(res.size()));
+            refs.push_back(int(w.from[pos].size()));
+            refs.insert(refs.end(), w.from[pos].begin(), w.from[pos].end());
+          }
+          res.push_back(w.win[pos]);
+        }
     }
     res[at].m_index = int(res.size() - at - 1);
   }
   if (!any) return false;
   out.swap(res);
+  if (src) src->swap(refs);
   return true;
 }
 
@@ -403,7 +375,7 @@ bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector
 // `fm`.
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm, bool big_half,
-                 std::vector<FuseOp> *mops) {
+                 std::vector<FuseOp> *mops, std::vector<int> *msrc) {
   const size_t ns = steps.size();
   // windows of a pass chain their norms in FP32 without renormalising: 16
   // keep it in range down to p ~ 1e-4 per window; windows with p = 1/2
@@ -561,10 +533,19 @@ void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::v
     tg.ta.nwin = widx;
     if (mops) {
       std::vector<FuseOp> m;
-      if (merge_round_windows(fops.data() + tg.op_off, tg.ta.nops, k, m)) {
+      std::vector<int> refs;
+      if (merge_round_windows(fops.data() + tg.op_off, tg.ta.nops, k, m, &refs)) {
         tg.mop_off = mops->size();
         tg.mnops = int(m.size());
         mops->insert(mops->end(), m.begin(), m.end());
+        if (msrc)  // each map: its row in mops, its window count, its windows' rows in fops
+          for (size_t q = 0; q < refs.size();) {
+            const int cnt = refs[q + 1];
+            msrc->push_back(int(tg.mop_off) + refs[q]);
+            msrc->push_back(cnt);
+            for (int c = 0; c < cnt; ++c) msrc->push_back(int(tg.op_off) + refs[q + 2 + size_t(c)]);
+            q += 2 + size_t(cnt);
+          }
       }
     }
     tg.half = widx > 0 && !even;
@@ -607,12 +588,13 @@ void group_tiles(owqs_pattern *p) {
   p->fuse_ops.clear();
   p->fuse_m.clear();
   p->fuse_mops.clear();
+  p->fuse_msrc.clear();
   if (p->exec == OWQS_EXEC_PLAIN) {
     p->xsteps = p->steps;
     return;
   }
   group_steps(p->steps, p->mode, p->tile_bits, p->xsteps, p->groups, p->fuse_ops, p->fuse_m,
-              p->mode == OWQS_MODE_OWQS && p->half_cap > 0, &p->fuse_mops);
+              p->mode == OWQS_MODE_OWQS && p->half_cap > 0, &p->fuse_mops, &p->fuse_msrc);
   if (p->mode == OWQS_MODE_OWQS) mark_half(p->xsteps, p->groups, p->half_cap);
   else
     for (TileGroup &tg : p->groups) tg.half = false;
@@ -1125,7 +1107,9 @@ hipError_t launch_range(owqs_pattern *p, const std::vector<Step> &xs, size_t i0,
           ta.half_m = fuse_m_dev(p) + tg.m_off;
           ta.renorm = tg.renorm ? 1 : 0;
         }
-        if (tg.mnops > 0 && !ctab && a.reduce == kReduceNone) {  // no window sums: the composed commands
+        // no window sums: the composed commands (a drawn run that patches the
+        // rows has composed them again on the device, k_s_compose)
+        if (tg.mnops > 0 && (!ctab || groups_patched) && a.reduce == kReduceNone) {
           ops = p->dev_fuse + fuse_mops_base(p->fuse_ops.size(), p->fuse_m.size()) + tg.mop_off;
           ta.nops = tg.mnops;
           ta.maps = 1;

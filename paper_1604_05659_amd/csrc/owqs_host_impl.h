@@ -162,6 +162,9 @@ struct owqs_pattern {
   std::vector<FuseOp> fuse_ops;
   std::vector<int> fuse_m;        // measurement index of every window of every group
   std::vector<FuseOp> fuse_mops;  // composed copies of the groups' commands (TileGroup::mop_off)
+  // per map of fuse_mops: its row there, its window count, its windows' rows
+  // in fuse_ops (drawn runs compose the resolved rows on the device)
+  std::vector<int> fuse_msrc;
   FuseOp *dev_fuse = nullptr;     // fuse_ops, then fuse_m (as int), then fuse_mops in one allocation
   size_t dev_fuse_cap = 0;
   bool dev_fuse_valid = false;
@@ -294,11 +297,12 @@ constexpr size_t kGroupSkipMax = 512;
 bool commute_steps(const Step &a, const Step &b);
 void group_steps(const std::vector<Step> &steps, int mode, int tile_bits, std::vector<Step> &out,
                  std::vector<TileGroup> &groups, std::vector<FuseOp> &fops, std::vector<int> &fm,
-                 bool big_half = false, std::vector<FuseOp> *mops = nullptr);
+                 bool big_half = false, std::vector<FuseOp> *mops = nullptr, std::vector<int> *msrc = nullptr);
 // The commands of one group (nops rows) with every run of two or more
 // windows in a row on one register-round position composed into one DK_U
 // row; false (and `out` unchanged) when nothing composes.
-bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out);
+bool merge_round_windows(const FuseOp *ops, int nops, int tile_bits, std::vector<FuseOp> &out,
+                         std::vector<int> *src = nullptr);
 // Copy a tile-pass command table (FuseOps, then the windows' measurement
 // indices as int, then the composed commands `mops` from a FuseOp boundary)
 // to the device, growing `dev` as needed.

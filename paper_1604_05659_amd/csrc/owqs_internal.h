@@ -165,6 +165,61 @@ __host__ __device__ inline void round_words(FuseOp &op) {
   op.rw_fold = fold ? kS : 0u;
 }
 
+// A window's map on true amplitudes as a register round applies it (no
+// masks, no sign pending on its position): t = c b, o0 = fa a + t, and the
+// round stores fbr a + t for o1 = r (fbr a + t), r the sign of rw_rs; so
+// [[fa, c], [r fbr, r c]], row-major, as (re, im) pairs.  From the round
+// words (round_words), on the host (plan compiler) and on the device (drawn
+// outcomes).
+__host__ __device__ inline void window_map(const FuseOp &w, double m[8]) {
+  const uint32_t cs = w.rw_cs & 0x80000000u;
+  uint32_t cx, cy;
+  __builtin_memcpy(&cx, &w.coef.x, sizeof(cx));
+  __builtin_memcpy(&cy, &w.coef.y, sizeof(cy));
+  cx ^= cs;
+  cy ^= cs;
+  float fcx, fcy, fa, fbr;
+  __builtin_memcpy(&fcx, &cx, sizeof(fcx));
+  __builtin_memcpy(&fcy, &cy, sizeof(fcy));
+  __builtin_memcpy(&fa, &w.rw_fa, sizeof(fa));
+  __builtin_memcpy(&fbr, &w.rw_fbr, sizeof(fbr));
+  const double r = (w.rw_rs & 0x80000000u) ? -1.0 : 1.0;
+  m[0] = fa;
+  m[1] = 0.0;
+  m[2] = fcx;
+  m[3] = fcy;
+  m[4] = r * fbr;
+  m[5] = 0.0;
+  m[6] = r * fcx;
+  m[7] = r * fcy;
+}
+
+// u <- w u for 2x2 complex maps (row-major, (re, im) pairs), in FP64.
+__host__ __device__ inline void map_left(const double w[8], double u[8]) {
+  double n[8];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const double ar = w[4 * i], ai = w[4 * i + 1], br = w[4 * i + 2], bi = w[4 * i + 3];
+      const double cr = u[2 * j], ci = u[2 * j + 1], dr = u[4 + 2 * j], di = u[4 + 2 * j + 1];
+      n[4 * i + 2 * j] = ar * cr - ai * ci + br * dr - bi * di;
+      n[4 * i + 2 * j + 1] = ar * ci + ai * cr + br * di + bi * dr;
+    }
+  for (int k = 0; k < 8; ++k) u[k] = n[k];
+}
+
+// The entries of a composed map (DK_U row), each rounded once to FP32.
+__host__ __device__ inline void map_store(FuseOp &row, const double u[8]) {
+  float f[8];
+  for (int k = 0; k < 8; ++k) f[k] = float(u[k]);
+  row.coef = make_float2(f[0], f[1]);
+  __builtin_memcpy(&row.lmask_o1, &f[2], 4);
+  __builtin_memcpy(&row.rw_rs, &f[3], 4);
+  __builtin_memcpy(&row.rw_fa, &f[4], 4);
+  __builtin_memcpy(&row.rw_fbr, &f[5], 4);
+  __builtin_memcpy(&row.rw_cs, &f[6], 4);
+  __builtin_memcpy(&row.rw_fold, &f[7], 4);
+}
+
 struct TileArgs {
   uint64_t tmask;    // global slots in the tile (tile bit i = the i-th lowest)
   uint64_t omask;    // the other live slots (outer bit i = the i-th lowest)
@@ -372,6 +427,11 @@ struct DrawWin {
 // negate o0, negate o1), every signal taken from the uniforms directly; a
 // window inside a tile pass also gets them in its command row (fops[fop]:
 // coef and flag bits 0-2), so that the pass runs like a forced one.
+// Composed maps of a drawn run from the rows k_s_resolve wrote: map i's
+// entry starts at refs[off[i]] (its row in mrows, its window count, its
+// windows' rows in fops).
+hipError_t launch_s_compose(const FuseOp *fops, FuseOp *mrows, const int *refs, const int *off, int nmaps,
+                            hipStream_t s);
 hipError_t launch_s_resolve(const DrawWin *wins, int nwin, const double *u, const int *dom, const FoldRef *folds,
                             int *outc, float2 *ctab, int *ftab, FuseOp *fops, hipStream_t s);
 // One thread, for a window whose E count between v and w is odd (outcome

@@ -225,6 +225,40 @@ hipError_t launch_s_jdecide(const double *u, int m, double alpha, SigRef sg, Sig
   return hipGetLastError();
 }
 
+namespace {
+
+// Composed maps of a drawn run (one thread per map): the product of its
+// windows' maps from the rows k_s_resolve has just written, as the plan
+// compiler forms it for forced outcomes.  refs[off[i] ..]: the map's row in
+// mrows, its window count, its windows' rows in fops.
+__global__ __launch_bounds__(kB) void k_s_compose(const FuseOp *__restrict__ fops, FuseOp *__restrict__ mrows,
+                                                   const int *__restrict__ refs, const int *__restrict__ off,
+                                                   int nmaps) {
+  const int i = blockIdx.x * kB + threadIdx.x;
+  if (i >= nmaps) return;
+  const int *r = refs + off[i];
+  const int row = r[0], cnt = r[1];
+  double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+  for (int c = 0; c < cnt; ++c) {
+    double w[8];
+    window_map(fops[r[2 + c]], w);
+    map_left(w, u);
+  }
+  FuseOp m = mrows[row];
+  map_store(m, u);
+  mrows[row] = m;
+}
+
+}  // namespace
+
+hipError_t launch_s_compose(const FuseOp *fops, FuseOp *mrows, const int *refs, const int *off, int nmaps,
+                            hipStream_t s) {
+  if (nmaps <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_s_compose, dim3(unsigned((nmaps + kB - 1) / kB)), dim3(kB), 0, s, fops, mrows, refs, off,
+                     nmaps);
+  return hipGetLastError();
+}
+
 hipError_t launch_s_resolve(const DrawWin *wins, int nwin, const double *u, const int *dom, const FoldRef *folds,
                             int *outc, float2 *ctab, int *ftab, FuseOp *fops, hipStream_t s) {
   if (nwin <= 0) return hipGetLastError();

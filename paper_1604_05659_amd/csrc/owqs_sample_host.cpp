@@ -253,10 +253,16 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
   std::vector<DrawWin> wins;
   for (const owqs_pattern::SStep &x : p->s_steps)
     if (x.kind == S_J) wins.push_back(DrawWin{x.alpha, x.s, x.t, x.m, x.fold_off, x.fold_len, fop_of[x.m]});
+  // the composed maps (their rows are formed again from the resolved windows)
+  std::vector<int> moff;
+  for (size_t q = 0; q < p->fuse_msrc.size(); q += 2 + size_t(p->fuse_msrc[q + 1])) moff.push_back(int(q));
+  const int nmaps = int(moff.size());
   hipError_t e = hipSuccess;
   const size_t cbytes = (nm * sizeof(float2) + 255) & ~size_t(255);
   const size_t fbytes = (3 * nm * sizeof(int) + 255) & ~size_t(255);
-  const size_t need = cbytes + fbytes + std::max<size_t>(wins.size(), 1) * sizeof(DrawWin);
+  const size_t wbytes = (std::max<size_t>(wins.size(), 1) * sizeof(DrawWin) + 255) & ~size_t(255);
+  const size_t mbytes = (p->fuse_msrc.size() + moff.size() + 1) * sizeof(int);
+  const size_t need = cbytes + fbytes + wbytes + mbytes;
   if (p->a_cap < need) {
     if (p->a_mem) {
       (void)hipDeviceSynchronize();
@@ -274,6 +280,8 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
   float2 *ctab = static_cast<float2 *>(p->a_mem);
   int *ftab = reinterpret_cast<int *>(static_cast<char *>(p->a_mem) + cbytes);
   DrawWin *dwins = reinterpret_cast<DrawWin *>(static_cast<char *>(p->a_mem) + cbytes + fbytes);
+  int *mrefs = reinterpret_cast<int *>(static_cast<char *>(p->a_mem) + cbytes + fbytes + wbytes);
+  int *moffs = mrefs + p->fuse_msrc.size();
   if (!p->a_wins_valid) {
     // once per plan (synchronous: a run in flight may still read the table)
     if (p->a_exec) { (void)hipGraphExecDestroy(p->a_exec); p->a_exec = nullptr; }
@@ -281,6 +289,9 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
     e = hipStreamSynchronize(s);
     if (e == hipSuccess && !wins.empty())
       e = hipMemcpy(dwins, wins.data(), wins.size() * sizeof(DrawWin), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nmaps > 0)
+      e = hipMemcpy(mrefs, p->fuse_msrc.data(), p->fuse_msrc.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nmaps > 0) e = hipMemcpy(moffs, moff.data(), moff.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) { st = hip_fail(p->ctx, e, "drawn-window table"); return true; }
     p->a_wins_valid = true;
   }
@@ -290,6 +301,7 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
   if (!p->dev_fuse_valid) st = upload_fuse(p);
   if (st != OWQS_OK) return true;
   p->fuse_patched = true;
+  FuseOp *const mrows = p->dev_fuse + fuse_mops_base(p->fuse_ops.size(), p->fuse_m.size());
   end_ranged(p);
   const size_t nin = p->inputs.size();
   e = launch_init(p->psi, p->book, s, nin == 0 && input == nullptr ? 1 : 0);
@@ -307,6 +319,7 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
       if (e != hipSuccess) { st = hip_fail(p->ctx, e, "begin capture"); return true; }
       hipError_t le = launch_s_resolve(dwins, (int)wins.size(), sm.u, sm.dom, sm.folds, sm.outc, ctab, ftab,
                                        p->dev_fuse, p->cap_stream);
+      if (le == hipSuccess) le = launch_s_compose(p->dev_fuse, mrows, mrefs, moffs, nmaps, p->cap_stream);
       if (le == hipSuccess)
         le = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, p->cap_stream, nullptr, ctab, ftab,
                           nullptr, nullptr, true);
@@ -323,6 +336,7 @@ bool run_analytic(owqs_pattern *p, const void *input, size_t want, int input_on_
     e = hipGraphLaunch(p->a_exec, s);
   } else {
     e = launch_s_resolve(dwins, (int)wins.size(), sm.u, sm.dom, sm.folds, sm.outc, ctab, ftab, p->dev_fuse, s);
+    if (e == hipSuccess) e = launch_s_compose(p->dev_fuse, mrows, mrefs, moffs, nmaps, s);
     if (e == hipSuccess)
       e = launch_range(p, p->xsteps, 0, p->xsteps.size(), kReduceRenorm, s, nullptr, ctab, ftab, nullptr, nullptr,
                        true);
