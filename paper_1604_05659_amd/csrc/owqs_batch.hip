@@ -108,6 +108,26 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
         const uint32_t j = i0(i, b) | (1u << b);
         lds[j] = neg(lds[j]);
       }
+    } else if (st.kind == DK_U) {  // windows on slot b composed into one map (EOWQS)
+      uint32_t w[6];
+      __builtin_memcpy(&w[0], &st.host_factor, 4);
+      w[1] = st.pp;
+      w[2] = uint32_t(st.mask_b);
+      w[3] = uint32_t(st.mask_b >> 32);
+      w[4] = uint32_t(st.mask_o1);
+      w[5] = uint32_t(st.mask_o1 >> 32);
+      float e[6];
+      __builtin_memcpy(e, w, sizeof(e));
+      const float2 m00 = st.coef, m01 = make_float2(e[0], e[1]), m10 = make_float2(e[2], e[3]),
+                   m11 = make_float2(e[4], e[5]);
+      for (uint32_t i = threadIdx.x; i < (dim >> 1); i += kT) {
+        const uint32_t j = i0(i, b), st2 = 1u << b;
+        const float2 a = lds[j], bb = lds[j + st2];
+        lds[j] = make_float2(m00.x * a.x - m00.y * a.y + m01.x * bb.x - m01.y * bb.y,
+                             m00.x * a.y + m00.y * a.x + m01.x * bb.y + m01.y * bb.x);
+        lds[j + st2] = make_float2(m10.x * a.x - m10.y * a.y + m11.x * bb.x - m11.y * bb.y,
+                                   m10.x * a.y + m10.y * a.x + m11.x * bb.y + m11.y * bb.x);
+      }
     } else {  // DK_M or DK_J
       // OWQS: a window with an odd E(v, w) count has p = 1/2 exactly for every
       // state (Eqs. 11-13): it is recorded without the block sum and sigma is

@@ -12,6 +12,7 @@
 //     zero signal emit nothing;
 //   - the 1/sqrt 2 of every N stays a host factor until the next M folds it
 //     into its pass (with the device FP64 sigma in OWQS mode).
+#include <array>
 #include <atomic>
 
 #include "owqs_host_impl.h"
@@ -1179,6 +1180,84 @@ owqs_status upload_fuse(owqs_pattern *p) {
 }
 
 // Upload the plan as a DevStep table (for the LDS-resident kernels).
+namespace {
+
+// A window step's map as the LDS-resident kernel applies it without masks
+// and without renormalising (EOWQS): o0 = f (a + c b), o1 = f (a + s1 c b)
+// with s1 = +1 for an even E(v, w) count, then the folded exchange and
+// negations (run_item in owqs_batch.hip).  Row-major, (re, im) pairs.
+void lds_window_map(const DevStep &st, double m[8]) {
+  const double f = st.host_factor, cx = st.coef.x, cy = st.coef.y, s1 = (st.pp & 8u) ? 1.0 : -1.0;
+  double r0[4] = {f, 0.0, f * cx, f * cy}, r1[4] = {f, 0.0, s1 * f * cx, s1 * f * cy};
+  if (st.pp & 1u)
+    for (int k = 0; k < 4; ++k) {
+      const double t = r0[k];
+      r0[k] = r1[k];
+      r1[k] = t;
+    }
+  const double n0 = (st.pp & 2u) ? -1.0 : 1.0, n1 = (st.pp & 4u) ? -1.0 : 1.0;
+  for (int k = 0; k < 4; ++k) {
+    m[k] = n0 * r0[k];
+    m[4 + k] = n1 * r1[k];
+  }
+}
+
+// Compose runs of unmasked window steps on one slot (EOWQS LDS tables): a
+// window joins the last window on its slot when no step since then touched
+// that slot (E, X or Z on it, a window reading it as a sign) and no N or M
+// changed the layout; the steps between commute with it, so it may move up
+// to that window, whose row becomes their product (DK_U, entries as FP32
+// words: m00 in coef, m01 in host_factor and pp, m10 and m11 in mask_b and
+// mask_o1, low word re, high word im).
+std::vector<DevStep> compose_lds_steps(const std::vector<DevStep> &d) {
+  std::vector<DevStep> out;
+  std::vector<std::array<double, 8>> prod;  // the product of each composed row so far
+  std::vector<int> open(64, -1);            // per slot: the row of its open run
+  for (const DevStep &st : d) {
+    const bool win = st.kind == DK_J, masked = win && (st.mask_b | st.mask_o1) != 0;
+    if (st.kind == DK_N || st.kind == DK_M) {
+      std::fill(open.begin(), open.end(), -1);
+    } else if (st.kind == DK_E) {
+      open[st.b0] = open[st.b1] = -1;
+    } else if (st.kind == DK_X || st.kind == DK_Z) {
+      open[st.b0] = -1;
+    } else if (masked) {
+      for (int b = 0; b < 64; ++b)
+        if (((st.mask_b | st.mask_o1) >> b) & 1u) open[b] = -1;
+      open[st.b0] = -1;
+    }
+    if (win && !masked && open[st.b0] >= 0) {  // joins the run on its slot
+      const int r = open[st.b0];
+      double w[8];
+      lds_window_map(st, w);
+      map_left(w, prod[size_t(r)].data());
+      out[size_t(r)].kind = DK_U;
+      continue;
+    }
+    out.push_back(st);
+    prod.emplace_back();
+    if (win && !masked) {
+      lds_window_map(st, prod.back().data());
+      open[st.b0] = int(out.size() - 1);
+    }
+  }
+  for (size_t r = 0; r < out.size(); ++r) {
+    if (out[r].kind != DK_U) continue;
+    float f[8];
+    for (int k = 0; k < 8; ++k) f[k] = float(prod[r][size_t(k)]);
+    uint32_t w[8];
+    __builtin_memcpy(w, f, sizeof(w));
+    out[r].coef = make_float2(f[0], f[1]);
+    out[r].host_factor = f[2];
+    out[r].pp = w[3];
+    out[r].mask_b = uint64_t(w[4]) | (uint64_t(w[5]) << 32);
+    out[r].mask_o1 = uint64_t(w[6]) | (uint64_t(w[7]) << 32);
+  }
+  return out;
+}
+
+}  // namespace
+
 owqs_status upload_steps(owqs_pattern *p) {
   if (p->dev_steps_valid) return OWQS_OK;
   std::vector<DevStep> d(p->steps.size());
@@ -1196,6 +1275,9 @@ owqs_status upload_steps(owqs_pattern *p) {
     d[i].mask_b = x.win.mask_b;
     d[i].mask_o1 = x.win.mask_o1;
   }
+  // EOWQS records no window probability: runs of windows on one slot compose
+  if (reduce_of(p) == kReduceNone) d = compose_lds_steps(d);
+  p->dev_nsteps = d.size();
   const size_t need = std::max<size_t>(d.size(), 1);
   hipError_t e = hipSuccess;
   if (p->dev_steps_cap < need) {
@@ -1219,7 +1301,7 @@ int reduce_of(const owqs_pattern *p) {
 LdsItem lds_proto(const owqs_pattern *p) {
   LdsItem it{};
   it.steps = p->dev_steps;
-  it.nsteps = (int)p->steps.size();
+  it.nsteps = (int)p->dev_nsteps;
   it.nin = (int)p->inputs.size();
   it.nout = (int)p->outputs.size();
   it.final_factor = p->final_factor;

@@ -169,7 +169,9 @@ struct owqs_pattern {
   size_t dev_fuse_cap = 0;
   bool dev_fuse_valid = false;
 
-  // the plan as a device command table (LDS-resident runs)
+  // the plan as a device command table (LDS-resident runs); dev_nsteps rows
+  // (fewer than steps when window runs were composed, EOWQS)
+  size_t dev_nsteps = 0;
   DevStep *dev_steps = nullptr;
   size_t dev_steps_cap = 0;
   bool dev_steps_valid = false;
