@@ -108,7 +108,7 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
         const uint32_t j = i0(i, b) | (1u << b);
         lds[j] = neg(lds[j]);
       }
-    } else if (st.kind == DK_U) {  // windows on slot b composed into one map (EOWQS)
+    } else if (st.kind == DK_U) {  // windows on slot b composed into one map, none summed
       uint32_t w[6];
       __builtin_memcpy(&w[0], &st.host_factor, 4);
       w[1] = st.pp;
@@ -127,6 +127,12 @@ __device__ void run_item(const DevStep *__restrict__ steps, int nsteps, int nin,
                              m00.x * a.y + m00.y * a.x + m01.x * bb.y + m01.y * bb.x);
         lds[j + st2] = make_float2(m10.x * a.x - m10.y * a.y + m11.x * bb.x - m11.y * bb.y,
                                    m10.x * a.y + m10.y * a.x + m11.x * bb.y + m11.y * bb.x);
+      }
+      if (reduce == kReduceRenorm) {  // OWQS: each of its b1 windows has p = 1/2 (indices after the rows)
+        const int *ml = reinterpret_cast<const int *>(steps + nsteps) + st.m_index;
+        if (probs)
+          for (int k = threadIdx.x; k < int(st.b1); k += kT) probs[ml[k]] = 0.5;
+        half_run += int(st.b1);
       }
     } else {  // DK_M or DK_J
       // OWQS: a window with an odd E(v, w) count has p = 1/2 exactly for every

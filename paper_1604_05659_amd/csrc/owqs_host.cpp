@@ -1202,21 +1202,41 @@ void lds_window_map(const DevStep &st, double m[8]) {
   }
 }
 
-// Compose runs of unmasked window steps on one slot (EOWQS LDS tables): a
-// window joins the last window on its slot when no step since then touched
-// that slot (E, X or Z on it, a window reading it as a sign) and no N or M
-// changed the layout; the steps between commute with it, so it may move up
-// to that window, whose row becomes their product (DK_U, entries as FP32
-// words: m00 in coef, m01 in host_factor and pp, m10 and m11 in mask_b and
-// mask_o1, low word re, high word im).
-std::vector<DevStep> compose_lds_steps(const std::vector<DevStep> &d) {
+// Compose runs of unmasked window steps on one slot (LDS tables): a window
+// joins the last window on its slot when no step since then touched that
+// slot (E, X or Z on it, a window reading it as a sign) and no N or M
+// changed the layout; the steps between commute with the earlier windows,
+// so they may move down to the latest one, whose row becomes their product
+// (DK_U, entries as FP32 words: m00 in coef, m01 in host_factor and pp, m10
+// and m11 in mask_b and mask_o1, low word re, high word im).  Rows move
+// later, never earlier, so no window meets more windows recorded without a
+// sum before it than it did.
+// With `owqs` (OWQS, the kernel renormalising), only windows that run_item
+// records with p = 1/2 and no sum compose (an odd E(v, w) count, fewer than
+// kHalfRun such windows since the last sum, found by replaying its rule), a
+// window or M that sums ends every run, and a composed row lists its
+// windows' measurement indices in `mlist` (m_index: the first, b1: the
+// count), for which the kernel records 1/2.
+std::vector<DevStep> compose_lds_steps(const std::vector<DevStep> &d, bool owqs, std::vector<int> &mlist) {
   std::vector<DevStep> out;
   std::vector<std::array<double, 8>> prod;  // the product of each composed row so far
+  std::vector<std::vector<int>> ms;         // the measurement indices of each row's windows
+  std::vector<char> dead;                   // rows whose windows moved down into a later row
   std::vector<int> open(64, -1);            // per slot: the row of its open run
+  int half_run = 0;
   for (const DevStep &st : d) {
-    const bool win = st.kind == DK_J, masked = win && (st.mask_b | st.mask_o1) != 0;
-    if (st.kind == DK_N || st.kind == DK_M) {
+    bool win = st.kind == DK_J;
+    const bool masked = win && (st.mask_b | st.mask_o1) != 0;
+    bool sums = st.kind == DK_M;
+    if (owqs && win) {
+      const bool half = !(st.pp & 24u) && half_run < kHalfRun;
+      if (half) ++half_run;
+      else sums = true;
+    }
+    if (owqs && sums) half_run = 0;
+    if (st.kind == DK_N || st.kind == DK_M || (owqs && sums)) {
       std::fill(open.begin(), open.end(), -1);
+      if (sums) win = false;  // a window that sums stays as it is
     } else if (st.kind == DK_E) {
       open[st.b0] = open[st.b1] = -1;
     } else if (st.kind == DK_X || st.kind == DK_Z) {
@@ -1226,34 +1246,53 @@ std::vector<DevStep> compose_lds_steps(const std::vector<DevStep> &d) {
         if (((st.mask_b | st.mask_o1) >> b) & 1u) open[b] = -1;
       open[st.b0] = -1;
     }
-    if (win && !masked && open[st.b0] >= 0) {  // joins the run on its slot
-      const int r = open[st.b0];
+    if (win && !masked && open[st.b0] >= 0) {  // joins the run on its slot, in its own place
+      const size_t r = size_t(open[st.b0]);
       double w[8];
       lds_window_map(st, w);
-      map_left(w, prod[size_t(r)].data());
-      out[size_t(r)].kind = DK_U;
+      std::array<double, 8> u = prod[r];
+      map_left(w, u.data());
+      std::vector<int> m = std::move(ms[r]);
+      m.push_back(st.m_index);
+      dead[r] = 1;
+      DevStep row = st;
+      row.kind = DK_U;
+      out.push_back(row);
+      prod.push_back(u);
+      ms.push_back(std::move(m));
+      dead.push_back(0);
+      open[st.b0] = ms.back().size() < 255 ? int(out.size() - 1) : -1;
       continue;
     }
     out.push_back(st);
     prod.emplace_back();
+    ms.emplace_back(1, st.m_index);
+    dead.push_back(0);
     if (win && !masked) {
       lds_window_map(st, prod.back().data());
       open[st.b0] = int(out.size() - 1);
     }
   }
+  std::vector<DevStep> kept;
   for (size_t r = 0; r < out.size(); ++r) {
+    if (dead[r]) continue;
+    kept.push_back(out[r]);
     if (out[r].kind != DK_U) continue;
+    DevStep &k = kept.back();
+    k.m_index = int(mlist.size());
+    k.b1 = uint8_t(ms[r].size());
+    mlist.insert(mlist.end(), ms[r].begin(), ms[r].end());
     float f[8];
-    for (int k = 0; k < 8; ++k) f[k] = float(prod[r][size_t(k)]);
+    for (int q = 0; q < 8; ++q) f[q] = float(prod[r][size_t(q)]);
     uint32_t w[8];
     __builtin_memcpy(w, f, sizeof(w));
-    out[r].coef = make_float2(f[0], f[1]);
-    out[r].host_factor = f[2];
-    out[r].pp = w[3];
-    out[r].mask_b = uint64_t(w[4]) | (uint64_t(w[5]) << 32);
-    out[r].mask_o1 = uint64_t(w[6]) | (uint64_t(w[7]) << 32);
+    k.coef = make_float2(f[0], f[1]);
+    k.host_factor = f[2];
+    k.pp = w[3];
+    k.mask_b = uint64_t(w[4]) | (uint64_t(w[5]) << 32);
+    k.mask_o1 = uint64_t(w[6]) | (uint64_t(w[7]) << 32);
   }
-  return out;
+  return kept;
 }
 
 }  // namespace
@@ -1275,10 +1314,14 @@ owqs_status upload_steps(owqs_pattern *p) {
     d[i].mask_b = x.win.mask_b;
     d[i].mask_o1 = x.win.mask_o1;
   }
-  // EOWQS records no window probability: runs of windows on one slot compose
-  if (reduce_of(p) == kReduceNone) d = compose_lds_steps(d);
+  // runs of windows on one slot compose where no window of the run sums
+  // (EOWQS; OWQS windows recorded with p = 1/2), at most 255 to a row
+  std::vector<int> mlist;
+  const int red = reduce_of(p);
+  if (red == kReduceNone || red == kReduceRenorm) d = compose_lds_steps(d, red == kReduceRenorm, mlist);
   p->dev_nsteps = d.size();
-  const size_t need = std::max<size_t>(d.size(), 1);
+  // the composed rows' measurement indices follow the rows
+  const size_t need = std::max<size_t>(d.size() + (mlist.size() * sizeof(int) + sizeof(DevStep) - 1) / sizeof(DevStep), 1);
   hipError_t e = hipSuccess;
   if (p->dev_steps_cap < need) {
     if (p->dev_steps) (void)hipFree(p->dev_steps);
@@ -1289,6 +1332,9 @@ owqs_status upload_steps(owqs_pattern *p) {
     p->dev_steps_cap = need;
   }
   if (!d.empty()) e = hipMemcpy(p->dev_steps, d.data(), d.size() * sizeof(DevStep), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !mlist.empty())
+    e = hipMemcpy(reinterpret_cast<int *>(p->dev_steps + d.size()), mlist.data(), mlist.size() * sizeof(int),
+                  hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(p->ctx, e, "command table upload");
   p->dev_steps_valid = true;
   return OWQS_OK;
